@@ -1,0 +1,586 @@
+/*
+ * ov_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Slow on purpose: full 4x4 gamma matrices, one vector operation per loop,
+ * every shifted search direction kept explicitly.  OpenMP only splits the
+ * site loops.  Nothing here is shared with the GPU library.
+ *
+ * Paper: Chen, Dzienkowski, Giedt, "Lattice Wess-Zumino model with
+ * Ginsparg-Wilson fermions: one-loop results and GPU benchmarks" (arXiv:1005.3276).
+ *   - lattice operators A = 1 - a D_W, D = (1 - A (A^dag A)^-1/2)/a: Sec. 2.2
+ *   - gamma conventions: Sec. 2.1
+ *   - fermion matrix with Yukawa coupling g: Sec. 7.1 (Pfaffian phase)
+ *   - antiperiodic time for the fermion: Sec. 3.1 (mode analysis), Sec. 3.2
+ *   - CG on MdagM for each system: Sec. 7.2 (pseudofermions), Sec. 7.3 (preconditioning)
+ * The sign function is evaluated by Zolotarev's optimal rational approximation
+ * (Akhiezer; Chiu et al. 2002; van den Eshof et al. 2002) with a multi-shift CG
+ * (Jegerlehner 1996); the paper itself applies D exactly in momentum space.
+ */
+#include "ov_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ gamma */
+
+/* Sec. 2.1: gamma_0 = [[0,1],[1,0]], gamma_i = [[0, i sigma_i], [-i sigma_i, 0]],
+ * gamma_5 = diag(-1, 1) in 2x2 blocks.  Directions x,y,z use gamma_1,2,3 and
+ * t uses gamma_0. */
+static void build_gamma(int mu, cplx g[4][4]) {
+  const cplx Im = _Complex_I;
+  cplx s[3][2][2] = {
+      {{0, 1}, {1, 0}},
+      {{0, -Im}, {Im, 0}},
+      {{1, 0}, {0, -1}},
+  };
+  memset(g, 0, sizeof(cplx) * 16);
+  if (mu == 4) {
+    g[0][0] = -1; g[1][1] = -1; g[2][2] = 1; g[3][3] = 1;
+    return;
+  }
+  if (mu == 3) {
+    for (int i = 0; i < 2; ++i) { g[i][i + 2] = 1; g[i + 2][i] = 1; }
+    return;
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      g[i][j + 2] = Im * s[mu][i][j];
+      g[i + 2][j] = -Im * s[mu][i][j];
+    }
+}
+
+int orc_gamma(int mu, cplx *out16) {
+  if (mu < 0 || mu > 4) return 1;
+  cplx g[4][4];
+  build_gamma(mu, g);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) out16[4 * i + j] = g[i][j];
+  return 0;
+}
+
+/* ------------------------------------------------------------- Zolotarev */
+
+/* Jacobi elliptic functions by the arithmetic-geometric mean (Abramowitz &
+ * Stegun 16.4), parameter m = 1 - m1 given through its complement so that
+ * m1 ~ 1e-10 keeps full precision.  Long double throughout. */
+static void sncndn_ld(long double u, long double m1, long double *sn, long double *cn,
+                      long double *dn, long double *K) {
+  long double a[80], c[80];
+  long double A = 1.0L, B = sqrtl(m1);
+  int N = 0;
+  a[0] = 1.0L;
+  c[0] = sqrtl(1.0L - m1);
+  while (N < 70) {
+    long double An = 0.5L * (A + B);
+    long double Bn = sqrtl(A * B);
+    long double Cn = 0.5L * (A - B);
+    ++N;
+    a[N] = An; c[N] = Cn;
+    A = An; B = Bn;
+    if (fabsl(Cn) <= LDBL_EPSILON * An) break;
+  }
+  *K = 3.14159265358979323846264338327950288L / (2.0L * a[N]);
+  long double phi = ldexpl(a[N] * u, N);
+  long double phi1 = phi;
+  for (int n = N; n >= 1; --n) {
+    phi1 = phi;
+    phi = 0.5L * (phi + asinl(c[n] / a[n] * sinl(phi)));
+  }
+  *sn = sinl(phi);
+  *cn = cosl(phi);
+  *dn = cosl(phi) / cosl(phi1 - phi);
+}
+
+void orc_sncndn(double u, double m1, double *sn, double *cn, double *dn, double *K) {
+  long double s, c, d, k;
+  sncndn_ld(u, m1, &s, &c, &d, &k);
+  *sn = (double)s; *cn = (double)c; *dn = (double)d; *K = (double)k;
+}
+
+/* product form f(x) = (x/lmin) prod_{l=1}^{n-1} (Y + c_{2l}) / prod_{l=1}^{n} (Y + c_{2l-1}),
+ * Y = (x/lmin)^2; c[1..2n-1]. */
+static long double zolo_f(long double x, long double lmin, int n, const long double *c) {
+  long double y = (x / lmin) * (x / lmin);
+  long double v = x / lmin;
+  for (int l = 1; l <= n - 1; ++l) v *= (y + c[2 * l]);
+  for (int l = 1; l <= n; ++l) v /= (y + c[2 * l - 1]);
+  return v;
+}
+
+/* golden-section search for an extremum of zolo_f on [lo, hi] (log x). */
+static long double zolo_refine(long double lo, long double hi, long double lmin, int n,
+                               const long double *c, int want_max) {
+  const long double gr = 0.61803398874989484820458683436563811L;
+  long double a = logl(lo), b = logl(hi);
+  long double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
+  long double f1 = zolo_f(expl(x1), lmin, n, c), f2 = zolo_f(expl(x2), lmin, n, c);
+  for (int it = 0; it < 200 && (b - a) > 1e-15L; ++it) {
+    int left = want_max ? (f1 > f2) : (f1 < f2);
+    if (left) {
+      b = x2; x2 = x1; f2 = f1;
+      x1 = b - gr * (b - a); f1 = zolo_f(expl(x1), lmin, n, c);
+    } else {
+      a = x1; x1 = x2; f1 = f2;
+      x2 = a + gr * (b - a); f2 = zolo_f(expl(x2), lmin, n, c);
+    }
+  }
+  return zolo_f(expl(0.5L * (a + b)), lmin, n, c);
+}
+
+int orc_zolotarev(int n, double lmin_d, double lmax_d, double *a_out, double *b_out,
+                  double *delta_out, double *d0_out) {
+  if (n < 1 || n > ORC_MAX_POLES || !(lmin_d > 0) || !(lmax_d > lmin_d)) return 1;
+  long double lmin = lmin_d, lmax = lmax_d;
+  long double bb = (lmax / lmin) * (lmax / lmin); /* b = (lmax/lmin)^2 */
+  long double m1 = 1.0L / bb;                     /* complementary parameter */
+  long double c[2 * ORC_MAX_POLES + 1];
+  long double sn, cn, dn, K;
+  sncndn_ld(0.0L, m1, &sn, &cn, &dn, &K);
+  /* c_l = sn^2/cn^2 at u = l K / (2n); for l > n use c_l c_{2n-l} = b. */
+  for (int l = 1; l <= n; ++l) {
+    long double u = (long double)l * K / (2.0L * n);
+    sncndn_ld(u, m1, &sn, &cn, &dn, &K);
+    c[l] = (sn * sn) / (cn * cn);
+  }
+  for (int l = n + 1; l <= 2 * n - 1; ++l) c[l] = bb / c[2 * n - l];
+
+  /* extremes of f on [lmin, lmax]: dense log sampling, then refinement */
+  enum { NS = 8000 };
+  static long double xs[NS + 1], fs[NS + 1];
+  long double fmax = -1.0L, fmin = 1e300L;
+  for (int i = 0; i <= NS; ++i) {
+    xs[i] = expl(logl(lmin) + (logl(lmax) - logl(lmin)) * i / NS);
+    fs[i] = zolo_f(xs[i], lmin, n, c);
+    if (fs[i] > fmax) fmax = fs[i];
+    if (fs[i] < fmin) fmin = fs[i];
+  }
+  for (int i = 1; i < NS; ++i) {
+    if (fs[i] >= fs[i - 1] && fs[i] >= fs[i + 1]) {
+      long double v = zolo_refine(xs[i - 1], xs[i + 1], lmin, n, c, 1);
+      if (v > fmax) fmax = v;
+    }
+    if (fs[i] <= fs[i - 1] && fs[i] <= fs[i + 1]) {
+      long double v = zolo_refine(xs[i - 1], xs[i + 1], lmin, n, c, 0);
+      if (v < fmin) fmin = v;
+    }
+  }
+  long double d0 = 2.0L / (fmax + fmin);
+  long double delta = (fmax - fmin) / (fmax + fmin);
+
+  /* partial fractions R0(Y) = sum_k r_k / (Y + c_{2k-1}) */
+  for (int k = 1; k <= n; ++k) {
+    long double ck = c[2 * k - 1];
+    long double num = 1.0L, den = 1.0L;
+    for (int l = 1; l <= n - 1; ++l) num *= (c[2 * l] - ck);
+    for (int l = 1; l <= n; ++l)
+      if (l != k) den *= (c[2 * l - 1] - ck);
+    long double rk = num / den;
+    a_out[k - 1] = (double)(d0 * rk * lmin);
+    b_out[k - 1] = (double)(ck * lmin * lmin);
+  }
+  if (delta_out) *delta_out = (double)delta;
+  if (d0_out) *d0_out = (double)d0;
+  return 0;
+}
+
+/* --------------------------------------------------------------- geometry */
+
+static long long volume(const orc_params *p) {
+  return (long long)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
+}
+
+/* neighbour of site i in direction mu, forward (dir = +1) or backward (-1);
+ * *ph receives the boundary phase of the hop. */
+static long long neighbour(const orc_params *p, long long i, int mu, int dir, double *ph) {
+  int co[4];
+  long long r = i;
+  for (int d = 0; d < 4; ++d) { co[d] = (int)(r % p->dims[d]); r /= p->dims[d]; }
+  *ph = 1.0;
+  int L = p->dims[mu];
+  int nc = co[mu] + dir;
+  if (nc == L) { nc = 0; if (mu == 3) *ph = (double)p->bc_t; }
+  if (nc == -1) { nc = L - 1; if (mu == 3) *ph = (double)p->bc_t; }
+  co[mu] = nc;
+  return co[0] + (long long)p->dims[0] * (co[1] + (long long)p->dims[1] *
+                                          (co[2] + (long long)p->dims[2] * co[3]));
+}
+
+/* ------------------------------------------------------------ vector ops */
+
+static cplx *vec_new(long long n) { return (cplx *)calloc((size_t)n, sizeof(cplx)); }
+
+static double vec_norm2(long long n, const cplx *x) {
+  double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+  for (long long i = 0; i < n; ++i) s += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+  return s;
+}
+
+static cplx vec_dot(long long n, const cplx *x, const cplx *y) { /* x^dag y */
+  double sr = 0.0, si = 0.0;
+#pragma omp parallel for reduction(+ : sr, si) schedule(static)
+  for (long long i = 0; i < n; ++i) {
+    cplx v = conj(x[i]) * y[i];
+    sr += creal(v);
+    si += cimag(v);
+  }
+  return sr + _Complex_I * si;
+}
+
+static void vec_copy(long long n, cplx *y, const cplx *x) { memcpy(y, x, (size_t)n * sizeof(cplx)); }
+
+static void vec_axpy(long long n, cplx a, const cplx *x, cplx *y) { /* y += a x */
+#pragma omp parallel for schedule(static)
+  for (long long i = 0; i < n; ++i) y[i] += a * x[i];
+}
+
+static void vec_xpay(long long n, const cplx *x, cplx a, cplx *y) { /* y = x + a y */
+#pragma omp parallel for schedule(static)
+  for (long long i = 0; i < n; ++i) y[i] = x[i] + a * y[i];
+}
+
+static void apply_g5(long long V, const cplx *in, cplx *out) {
+  cplx g5[4][4];
+  build_gamma(4, g5);
+#pragma omp parallel for schedule(static)
+  for (long long x = 0; x < V; ++x) {
+    cplx v[4];
+    for (int s = 0; s < 4; ++s) {
+      v[s] = 0;
+      for (int t = 0; t < 4; ++t) v[s] += g5[s][t] * in[4 * x + t];
+    }
+    for (int s = 0; s < 4; ++s) out[4 * x + s] = v[s];
+  }
+}
+
+/* ------------------------------------------------------------- operators */
+
+void orc_dw(const orc_params *p, const cplx *in, cplx *out) {
+  long long V = volume(p);
+  cplx gm[4][4][4], one[4][4];
+  for (int mu = 0; mu < 4; ++mu) build_gamma(mu, gm[mu]);
+  memset(one, 0, sizeof(one));
+  for (int s = 0; s < 4; ++s) one[s][s] = 1;
+  double diag = 4.0 - p->M0;
+#pragma omp parallel for schedule(static)
+  for (long long x = 0; x < V; ++x) {
+    cplx acc[4];
+    for (int s = 0; s < 4; ++s) acc[s] = diag * in[4 * x + s];
+    for (int mu = 0; mu < 4; ++mu) {
+      double phf, phb;
+      long long xf = neighbour(p, x, mu, +1, &phf);
+      long long xb = neighbour(p, x, mu, -1, &phb);
+      for (int s = 0; s < 4; ++s) {
+        cplx v = 0;
+        for (int t = 0; t < 4; ++t) {
+          v += (one[s][t] - gm[mu][s][t]) * phf * in[4 * xf + t];
+          v += (one[s][t] + gm[mu][s][t]) * phb * in[4 * xb + t];
+        }
+        acc[s] -= 0.5 * v;
+      }
+    }
+    for (int s = 0; s < 4; ++s) out[4 * x + s] = acc[s];
+  }
+}
+
+void orc_hw(const orc_params *p, const cplx *in, cplx *out) {
+  long long V = volume(p);
+  cplx *tmp = vec_new(4 * V);
+  orc_dw(p, in, tmp);
+  apply_g5(V, tmp, out);
+  free(tmp);
+}
+
+/* -------------------------------------------------------- multi-shift CG */
+
+/* Jegerlehner's multi-shift CG: one Krylov space of H_W^2 serves every
+ * shifted system (H_W^2 + sig_k) y_k = src.  Base shift 0 (H_W^2 >= 1 for the
+ * free Wilson operator at M0 = 1). */
+int orc_multishift(const orc_params *p, int n, const double *sig, const double *coef,
+                   double tol, int maxit, const cplx *src, cplx *acc, cplx *ys,
+                   orc_ms_stats *st) {
+  long long V = volume(p), N = 4 * V;
+  if (acc) memset(acc, 0, (size_t)N * sizeof(cplx));
+  if (ys) memset(ys, 0, (size_t)n * N * sizeof(cplx));
+  double srcn = sqrt(vec_norm2(N, src));
+  if (st) { st->iters = 0; st->converged = 1; st->max_shift_res = 0.0; }
+  if (srcn == 0.0) return 0;
+
+  cplx *r = vec_new(N), *P = vec_new(N), *t = vec_new(N), *w = vec_new(N);
+  cplx **pk = (cplx **)malloc(sizeof(cplx *) * n);
+  double *zeta = malloc(sizeof(double) * n), *zeta_old = malloc(sizeof(double) * n);
+  double *zeta_new = malloc(sizeof(double) * n);
+  int *active = malloc(sizeof(int) * n);
+  vec_copy(N, r, src);
+  vec_copy(N, P, src);
+  for (int k = 0; k < n; ++k) {
+    pk[k] = vec_new(N);
+    vec_copy(N, pk[k], src);
+    zeta[k] = zeta_old[k] = 1.0;
+    active[k] = 1;
+  }
+  double alpha_old = 1.0, beta_old = 0.0;
+  double rr = vec_norm2(N, r);
+  int it = 0, nactive = n;
+  while (nactive > 0 && it < maxit) {
+    orc_hw(p, P, t);
+    orc_hw(p, t, w);
+    double pw = creal(vec_dot(N, P, w));
+    double alpha = rr / pw;
+    for (int k = 0; k < n; ++k) {
+      if (!active[k]) continue;
+      zeta_new[k] = zeta[k] * zeta_old[k] * alpha_old /
+                    (alpha_old * zeta_old[k] * (1.0 + alpha * sig[k]) +
+                     alpha * beta_old * (zeta_old[k] - zeta[k]));
+      double ak = alpha * zeta_new[k] / zeta[k];
+      if (ys) vec_axpy(N, ak, pk[k], ys + (long long)k * N);
+      if (acc) vec_axpy(N, coef[k] * ak, pk[k], acc);
+    }
+    vec_axpy(N, -alpha, w, r);
+    double rr_new = vec_norm2(N, r);
+    double beta = rr_new / rr;
+    for (int k = 0; k < n; ++k) {
+      if (!active[k]) continue;
+      double bk = beta * (zeta_new[k] / zeta[k]) * (zeta_new[k] / zeta[k]);
+      /* p_k = zeta_new r + bk p_k */
+      cplx *q = pk[k];
+#pragma omp parallel for schedule(static)
+      for (long long i = 0; i < N; ++i) q[i] = zeta_new[k] * r[i] + bk * q[i];
+    }
+    vec_xpay(N, r, beta, P);
+    for (int k = 0; k < n; ++k) {
+      if (!active[k]) continue;
+      zeta_old[k] = zeta[k];
+      zeta[k] = zeta_new[k];
+    }
+    alpha_old = alpha;
+    beta_old = beta;
+    rr = rr_new;
+    ++it;
+    for (int k = 0; k < n; ++k) {
+      if (active[k] && fabs(zeta[k]) * sqrt(rr) <= tol * srcn) {
+        active[k] = 0;
+        --nactive;
+      }
+    }
+  }
+  if (st) {
+    double mx = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double v = fabs(zeta[k]) * sqrt(rr) / srcn;
+      if (v > mx) mx = v;
+    }
+    st->iters = it;
+    st->converged = nactive == 0;
+    st->max_shift_res = mx;
+  }
+  for (int k = 0; k < n; ++k) free(pk[k]);
+  free(pk); free(zeta); free(zeta_old); free(zeta_new); free(active);
+  free(r); free(P); free(t); free(w);
+  return nactive == 0 ? 0 : 2;
+}
+
+int orc_init(orc_params *p) {
+  for (int d = 0; d < 4; ++d)
+    if (p->dims[d] < 2) return 1;
+  if (p->bc_t != 1 && p->bc_t != -1) return 1;
+  if (p->n_poles < 1 || p->n_poles > ORC_MAX_POLES) return 1;
+  if (p->inner_tol <= 0 || p->max_inner < 1) return 1;
+  return orc_zolotarev(p->n_poles, p->lambda_min, p->lambda_max, p->a, p->b, &p->delta,
+                       &p->d0);
+}
+
+int orc_sign(const orc_params *p, const cplx *in, cplx *out, orc_ms_stats *st) {
+  long long N = 4 * volume(p);
+  cplx *acc = vec_new(N);
+  int rc = orc_multishift(p, p->n_poles, p->b, p->a, p->inner_tol, p->max_inner, in, acc,
+                          NULL, st);
+  orc_hw(p, acc, out);
+  free(acc);
+  return rc;
+}
+
+/* Yukawa term added to out: c+ P+ in + c- P- in (dag = 0) or its adjoint (dag = 1). */
+static void add_yukawa(const orc_params *p, const cplx *phi, const cplx *in, cplx *out,
+                       int dag) {
+  long long V = volume(p);
+  cplx g5[4][4];
+  build_gamma(4, g5);
+  cplx m = p->m_re + _Complex_I * p->m_im;
+  cplx g = p->g_re + _Complex_I * p->g_im;
+#pragma omp parallel for schedule(static)
+  for (long long x = 0; x < V; ++x) {
+    cplx cp = m + g * phi[x];
+    cplx cm = conj(m) + conj(g) * conj(phi[x]);
+    if (dag) { cp = conj(cp); cm = conj(cm); }
+    for (int s = 0; s < 4; ++s) {
+      cplx v = 0;
+      for (int t = 0; t < 4; ++t) {
+        double id = (s == t) ? 1.0 : 0.0;
+        cplx pp = 0.5 * (id + g5[s][t]); /* P+ */
+        cplx pm = 0.5 * (id - g5[s][t]); /* P- */
+        v += (cp * pp + cm * pm) * in[4 * x + t];
+      }
+      out[4 * x + s] += v;
+    }
+  }
+}
+
+static int apply_one(const orc_params *p, int op, const cplx *phi, const cplx *in, cplx *out,
+                     long long *inner) {
+  long long V = volume(p), N = 4 * V;
+  orc_ms_stats st = {0, 1, 0.0};
+  int rc = 0;
+  cplx *tmp = vec_new(N), *eps = vec_new(N);
+  switch (op) {
+    case ORC_OP_HW:
+      orc_hw(p, in, out);
+      break;
+    case ORC_OP_DOV:
+    case ORC_OP_M:
+      rc = orc_sign(p, in, eps, &st);
+      apply_g5(V, eps, tmp);
+      for (long long i = 0; i < N; ++i) out[i] = in[i] + tmp[i];
+      if (op == ORC_OP_M) add_yukawa(p, phi, in, out, 0);
+      break;
+    case ORC_OP_DOV_DAG:
+    case ORC_OP_M_DAG:
+      apply_g5(V, in, tmp);
+      rc = orc_sign(p, tmp, eps, &st);
+      for (long long i = 0; i < N; ++i) out[i] = in[i] + eps[i];
+      if (op == ORC_OP_M_DAG) add_yukawa(p, phi, in, out, 1);
+      break;
+    default:
+      rc = 1;
+  }
+  if (inner) *inner += st.iters;
+  free(tmp);
+  free(eps);
+  return rc;
+}
+
+int orc_apply(const orc_params *p, int op, const cplx *phi, const cplx *in, cplx *out,
+              long long *inner) {
+  if (op == ORC_OP_MDAGM) {
+    long long N = 4 * volume(p);
+    cplx *u = vec_new(N);
+    int rc = apply_one(p, ORC_OP_M, phi, in, u, inner);
+    int rc2 = apply_one(p, ORC_OP_M_DAG, phi, u, out, inner);
+    free(u);
+    return rc ? rc : rc2;
+  }
+  return apply_one(p, op, phi, in, out, inner);
+}
+
+double orc_residual(const orc_params *p, const cplx *phi, const cplx *b, const cplx *x) {
+  long long N = 4 * volume(p);
+  cplx *q = vec_new(N);
+  orc_apply(p, ORC_OP_MDAGM, phi, x, q, NULL);
+  for (long long i = 0; i < N; ++i) q[i] = b[i] - q[i];
+  double res = sqrt(vec_norm2(N, q) / vec_norm2(N, b));
+  free(q);
+  return res;
+}
+
+/* CG on MdagM x = b (Sec. 7.3 states the problem), x0 = 0.  The true residual is
+ * recomputed every 25 iterations and whenever the recursive one meets tol; the
+ * iteration ends only on the true residual, restarting from it if needed. */
+int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, double tol,
+              int maxit, orc_cg_stats *st) {
+  long long N = 4 * volume(p);
+  long long inner = 0;
+  memset(x, 0, (size_t)N * sizeof(cplx));
+  double bn = sqrt(vec_norm2(N, b));
+  if (st) { st->iters = 0; st->converged = 1; st->inner_iters = 0; st->true_rel_res = 0; }
+  if (bn == 0.0) return 0;
+  cplx *r = vec_new(N), *pv = vec_new(N), *q = vec_new(N), *rt = vec_new(N);
+  vec_copy(N, r, b);
+  vec_copy(N, pv, r);
+  double rr = vec_norm2(N, r);
+  int it = 0, conv = 0;
+  double true_res = 1.0;
+  while (it < maxit) {
+    orc_apply(p, ORC_OP_MDAGM, phi, pv, q, &inner);
+    double pq = creal(vec_dot(N, pv, q));
+    double alpha = rr / pq;
+    vec_axpy(N, alpha, pv, x);
+    vec_axpy(N, -alpha, q, r);
+    double rr_new = vec_norm2(N, r);
+    ++it;
+    if (sqrt(rr_new) <= tol * bn || it % 25 == 0) {
+      orc_apply(p, ORC_OP_MDAGM, phi, x, rt, &inner);
+      for (long long i = 0; i < N; ++i) rt[i] = b[i] - rt[i];
+      double rtn = vec_norm2(N, rt);
+      true_res = sqrt(rtn) / bn;
+      if (true_res <= tol) { conv = 1; break; }
+      if (sqrt(rr_new) <= tol * bn) { /* recursive residual drifted: restart */
+        vec_copy(N, r, rt);
+        vec_copy(N, pv, r);
+        rr = rtn;
+        continue;
+      }
+    }
+    double beta = rr_new / rr;
+    vec_xpay(N, r, beta, pv);
+    rr = rr_new;
+  }
+  if (!conv) true_res = orc_residual(p, phi, b, x);
+  if (st) {
+    st->iters = it;
+    st->converged = conv;
+    st->inner_iters = inner;
+    st->true_rel_res = true_res;
+  }
+  free(r); free(pv); free(q); free(rt);
+  return conv ? 0 : 2;
+}
+
+/* HMC force of S = xi^dag (MdagM)^-1 xi.  With X = (MdagM)^-1 xi and Y = M X,
+ * dS = -2 Re[ Y^dag dM X ] and dM = g P+ dphi + g* P- dphi*, so
+ *   dS/dphi_x = -g [ Y_x^dag P+ X_x + X_x^dag P- Y_x ],
+ *   G_x = dS/dRe phi_x + i dS/dIm phi_x = 2 conj(dS/dphi_x)   (S real). */
+int orc_force(const orc_params *p, const cplx *phi, const cplx *xi, double tol, int maxit,
+              double *S, cplx *G, orc_cg_stats *st) {
+  long long V = volume(p), N = 4 * V;
+  cplx *X = vec_new(N), *Y = vec_new(N);
+  int rc = orc_solve(p, phi, xi, X, tol, maxit, st);
+  long long inner = 0;
+  orc_apply(p, ORC_OP_M, phi, X, Y, &inner);
+  if (st) st->inner_iters += inner;
+  cplx g5[4][4];
+  build_gamma(4, g5);
+  cplx g = p->g_re + _Complex_I * p->g_im;
+#pragma omp parallel for schedule(static)
+  for (long long x = 0; x < V; ++x) {
+    cplx t1 = 0, t2 = 0;
+    for (int s = 0; s < 4; ++s)
+      for (int t = 0; t < 4; ++t) {
+        double id = (s == t) ? 1.0 : 0.0;
+        cplx pp = 0.5 * (id + g5[s][t]);
+        cplx pm = 0.5 * (id - g5[s][t]);
+        t1 += conj(Y[4 * x + s]) * pp * X[4 * x + t];
+        t2 += conj(X[4 * x + s]) * pm * Y[4 * x + t];
+      }
+    cplx dS = -g * (t1 + t2);
+    G[x] = 2.0 * conj(dS);
+  }
+  *S = creal(vec_dot(N, xi, X));
+  free(X);
+  free(Y);
+  return rc;
+}
