@@ -1,0 +1,194 @@
+"""Benchmark: overlap solves/s at 16^4 (mixed FP32/FP64 vs FP64) to a 1e-10
+true residual, plus the Wilson-stencil bandwidth.
+
+One step = one solve of M^dag M x = b at 16^4 (m = 0.05, g = 0.3, phi ~ CN(0, 0.25),
+20 Zolotarev poles on [1e-3, 8], outer residual 1e-10) with the mixed-precision
+solver: every step of the hot path (pack, multi-shift sign, D_ov / M / M^dag
+epilogues, outer CG, reliable FP64 updates) runs inside it.  Inputs are seeded
+synthetic fields resident in HBM before the timed region.
+
+Prints ONE JSON line.  Only one GPU is supported: --gpus N > 1 exits.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (16, 16, 16, 16)
+CFG = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0, outer_tol=1e-10,
+           inner_tol=1e-8, truth_tol=1e-13)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stencil_bandwidth(lat, torch, nrhs, prec, reps=20):
+    """Algorithmic bytes (read + write one spinor per site) / kernel time."""
+    V = lat.V
+    dt = torch.complex64 if prec else torch.complex128
+    x = torch.randn((nrhs, 4, V), dtype=dt, device="cuda")
+    lat.stencil_bench(x, prec, reps=2)
+    _, ms = lat.stencil_bench(x, prec, reps=reps)
+    esize = 8 if prec else 16
+    gbs = 2.0 * 4 * esize * V * nrhs / (ms * 1e-3) / 1e9
+    return {"nrhs": nrhs, "prec": "fp32" if prec else "fp64", "ms": ms, "GB_s": gbs,
+            "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
+def cpu_baseline(phi, src, outer_iters):
+    """Oracle FP64 M^dag M applications at 16^4 on the host cores; scaled to one
+    solve with the GPU FP64 solver's outer-iteration count."""
+    from oracle import oracle as O
+    o = O.Oracle(DIMS, m=CFG["m"], g=CFG["g"], n_poles=CFG["n_poles"],
+                 lambda_min=CFG["lambda_min"], lambda_max=CFG["lambda_max"], inner_tol=1e-12)
+    t = time.perf_counter()
+    napp = 0
+    v = src[0]
+    while True:
+        v = o.apply(O.OP_MDAGM, v, phi)
+        v = v / (abs(v).max())
+        napp += 1
+        if time.perf_counter() - t > 10.0 or napp >= 3:
+            break
+    el = time.perf_counter() - t
+    per = el / napp
+    return {"value": 1.0 / (per * outer_iters), "unit": "solves/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{napp} MdagM applications (FP64 oracle, multi-shift tol 1e-12) at 16^4, "
+                      f"{per:.2f} s each, scaled by {outer_iters} outer CG iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip FP64 and stencil sweeps")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the batched and "
+                                   "multi-lattice work shards across GPUs without "
+                                   "communication; that path is not part of this build)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1005_3276_amd import Lattice, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    phi, src = inputs.draw(DIMS, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    dphi = torch.from_numpy(phi).cuda()
+    dsrc = torch.from_numpy(src).cuda()
+    lat = Lattice(DIMS, precision="mixed", **CFG)
+    lat.use_workspace(1)
+
+    # ---- mixed solves (the metric)
+    for _ in range(args.warmup):
+        lat.solve(dsrc, dphi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        x, stats = lat.solve(dsrc, dphi)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = args.steps / el
+    log(f"mixed: {el / args.steps * 1e3:.2f} ms/solve  {stats[0]}")
+
+    # ---- dominant kernel: live HIP-event sampling on the library's stream
+    lat.kernel_sampling(64)
+    lat.kernel_times(0, reset=True)
+    lat.kernel_times(1, reset=True)
+    lat.solve(dsrc, dphi)
+    lat.kernel_sampling(0)
+    kt = [lat.kernel_times(k) for k in (0, 1)]
+    ms_sum = kt[0][0] + kt[1][0]
+    cnt = kt[0][1] + kt[1][1]
+    bytes_sum = kt[0][2] + kt[1][2]
+    avg_us = ms_sum / cnt * 1e3
+    per_launch = bytes_sum / cnt
+    achieved = bytes_sum / (ms_sum * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_ms_t<float> + k_ms_r<float> (multi-shift Wilson passes)",
+                "avg_launch_us": avg_us, "bytes_per_launch": per_launch,
+                "t_pass_us": kt[0][0] / max(kt[0][1], 1) * 1e3,
+                "r_pass_us": kt[1][0] / max(kt[1][1], 1) * 1e3, "samples": cnt}
+    log(f"roofline: {roofline}")
+
+    extra = {}
+    fp64_outer = stats[0]["outer_iters"]
+    if not args.quick:
+        # ---- plain FP64 paths (P2: inner 1e-8 + reliable updates; P1: inner 1e-12)
+        for name, kw in (("fp64_p2", dict(inner_tol=1e-8, reliable_delta=0.1)),
+                         ("fp64_p1", dict(inner_tol=1e-12, reliable_delta=0.0))):
+            cfg = dict(CFG)
+            cfg.update(kw)
+            l64 = Lattice(DIMS, precision="fp64", **cfg)
+            l64.solve(dsrc, dphi)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x64, st64 = l64.solve(dsrc, dphi)
+            torch.cuda.synchronize()
+            e64 = time.perf_counter() - t
+            extra[name] = {"solves_per_s": 1.0 / e64, "ms_per_solve": e64 * 1e3,
+                           "outer_iters": st64[0]["outer_iters"],
+                           "inner_iters": st64[0]["inner_iters"],
+                           "true_rel_res": st64[0]["true_rel_res"]}
+            if name == "fp64_p1":
+                fp64_outer = st64[0]["outer_iters"]
+            log(f"{name}: {extra[name]}")
+            del l64
+        best64 = max(extra["fp64_p2"]["solves_per_s"], extra["fp64_p1"]["solves_per_s"])
+        extra["mixed_speedup_vs_best_fp64"] = value / best64
+        # ---- stencil bandwidth at 16^4
+        sweep = []
+        for prec in (1, 0):
+            for nrhs in (1, 12, 48):
+                sweep.append(stencil_bandwidth(lat, torch, nrhs, prec))
+                log(f"stencil {sweep[-1]}")
+        extra["stencil"] = sweep
+        extra["stencil_best_TB_s"] = max(s["GB_s"] for s in sweep) / 1e3
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(phi, src, fp64_outer)
+        log(f"cpu: {cpu}")
+
+    out = {
+        "metric": "overlap solves/sec + stencil HBM TB/s at 16^4, FP32-mixed vs FP64, 1e-10 res",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "MdagM x = b at 16^4 (config 2): M = D_ov + Yukawa, m=0.05, "
+                               "g=0.3, phi~CN(0,0.25), 20-pole Zolotarev on [1e-3,8], "
+                               "one Gaussian rhs, true residual 1e-10, mixed FP32/FP64",
+                   "lattice": list(DIMS), "nrhs": 1,
+                   "true_rel_res": stats[0]["true_rel_res"],
+                   "outer_iters": stats[0]["outer_iters"],
+                   "inner_iters": stats[0]["inner_iters"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * ov.h -- C ABI of the MI355X overlap-fermion library (libov.so).
+ *
+ * The library applies and inverts the fermion matrix of the lattice
+ * Wess-Zumino model of arXiv:1005.3276 in its overlap form
+ *
+ *     M = D_ov + (m + g phi_x) P+ + (m* + g* phi*_x) P-
+ *     D_ov = 1 + g5 sign(H_W),   H_W = g5 D_W(-M0)
+ *
+ * (lattice operators A = 1 - a D_W and D = (1 - A (A^dag A)^-1/2)/a of Sec. 2.2,
+ * with a = 1; fermion matrix as in Sec. 7.1 with coupling g).  sign(H_W) is
+ * Zolotarev's optimal rational approximation x sum_k a_k/(x^2 + b_k), evaluated
+ * by a multi-shift conjugate gradient on H_W^2; M^dag M x = b is solved by CG
+ * (Sec. 7.2 and 7.3 pose this problem), in FP64 or in mixed FP32/FP64 with
+ * reliable updates and an FP64 true residual (Sec. 7.3 names mixed-precision
+ * CG as the way to use single precision); ov_force returns the HMC force of
+ * S = xi^dag (M^dag M)^-1 xi (molecular dynamics, Sec. 7.3).
+ *
+ * Conventions (shared with every entry point):
+ *   - dims = {X, Y, Z, T}; site index i = x + X*(y + Y*(z + Z*t)).
+ *   - Every field at the ABI is complex128 device memory, C-contiguous
+ *     (nrhs, T, Z, Y, X, 4): spin innermost, then x, y, z, t, then rhs.
+ *     phi is complex128 device memory (T, Z, Y, X).
+ *   - gamma matrices in the paper's chiral basis (Sec. 2.1):
+ *     g_t = [[0,1],[1,0]], g_{x,y,z} = [[0, i s_{1,2,3}], [-i s_{1,2,3}, 0]],
+ *     g5 = diag(-1,-1,1,1); P+ = (1+g5)/2 acts on spins 2,3.
+ *   - D_W(-M0) psi_x = (4 - M0) psi_x
+ *        - 1/2 sum_mu [(1 - g_mu) ph psi_{x+mu} + (1 + g_mu) ph psi_{x-mu}],
+ *     ph = bc_t for hops across the time boundary (fermions antiperiodic in
+ *     time, Sec. 3.1), space periodic.
+ *
+ * Ownership: the caller owns every field, phi and the workspace (device
+ * memory, e.g. from torch).  The library owns only the context.  All work is
+ * enqueued on the context's HIP stream; entry points return after the result
+ * is complete on that stream unless stated otherwise.  One context per
+ * stream; contexts are not thread-safe.
+ *
+ * Errors: every function returns ov_status; no exception or abort crosses the
+ * ABI.  On OV_ERR_NOT_CONVERGED outputs hold the best iterate and the stats
+ * are filled; on any other error outputs are undefined.  ov_last_error()
+ * gives a human-readable reason.
+ */
+#ifndef OV_H
+#define OV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OV_OK = 0,
+  OV_ERR_INVALID_ARG = 1,   /* bad params, null pointer, odd or < 2 extent */
+  OV_ERR_NOT_CONVERGED = 2, /* iteration cap reached; best iterate returned */
+  OV_ERR_BREAKDOWN = 3,     /* non-finite or non-positive CG scalar (NaN input ...) */
+  OV_ERR_SPECTRUM = 4,      /* free |H_W| range not inside [lambda_min, lambda_max] */
+  OV_ERR_WORKSPACE = 5,     /* workspace missing or too small */
+  OV_ERR_DEVICE = 6         /* HIP runtime error; destroy the context */
+} ov_status;
+
+typedef enum { OV_FP64 = 0, OV_MIXED = 1 } ov_precision;
+
+typedef enum {
+  OV_OP_HW = 0,      /* H_W = g5 D_W(-M0) */
+  OV_OP_DOV = 1,     /* psi + g5 eps(psi) */
+  OV_OP_DOV_DAG = 2, /* psi + eps(g5 psi) */
+  OV_OP_M = 3,       /* D_ov psi + c+ P+ psi + c- P- psi */
+  OV_OP_M_DAG = 4,   /* D_ov^dag psi + c+* P+ psi + c-* P- psi */
+  OV_OP_MDAGM = 5    /* M^dag M psi */
+} ov_op;
+
+typedef struct {
+  int dims[4];             /* X, Y, Z, T: each even and >= 2 */
+  int bc_t;                /* -1 antiperiodic time (default), +1 periodic */
+  double M0;               /* Wilson mass in D_W(-M0); 1.0 (r = 1) */
+  double m_re, m_im;       /* fermion mass m */
+  double g_re, g_im;       /* Yukawa coupling g */
+  int n_poles;             /* Zolotarev poles, 1..32 */
+  double lambda_min;       /* [lambda_min, lambda_max] bounds |eig(H_W)| (not H_W^2) */
+  double lambda_max;
+  double inner_tol;        /* multi-shift stop |zeta_k| ||r|| <= tol ||src|| for
+                              ov_sign/ov_apply and the FP64 solver's inner sign */
+  double outer_tol;        /* solve stop: true ||b - MdagM x|| / ||b|| */
+  double truth_tol;        /* FP64 multi-shift tolerance of true residuals (1e-12) */
+  double mixed_inner_tol;  /* FP32 multi-shift tolerance of the mixed solver */
+  double reliable_delta;   /* reliable update when ||r|| drops below delta * ||r_true|| */
+  int max_inner;           /* multi-shift iteration cap (<= basis capacity) */
+  int max_outer;           /* outer CG iteration cap */
+  ov_precision precision;  /* OV_FP64 or OV_MIXED for ov_solve / ov_force */
+} ov_params;
+
+typedef struct {
+  int outer_iters;         /* CG iterations on MdagM */
+  int reliable_updates;    /* FP64 true-residual recomputations */
+  long long inner_iters;   /* multi-shift iterations summed over all sign applications */
+  long long stencil_apps;  /* H_W applications (2 per multi-shift iteration + finals) */
+  double true_rel_res;     /* last FP64 true relative residual (solves) */
+  double max_shift_res;    /* max_k |zeta_k| ||r|| / ||src|| of the last multi-shift */
+  double seconds;          /* wall time of the call (host clock, stream synchronised) */
+  double model_bytes;      /* algorithmic HBM bytes moved (byte model) */
+} ov_stats;
+
+typedef struct ov_ctx ov_ctx;
+
+/* Fill p with the defaults (4^4 antiperiodic, M0 = 1, 20 poles on [1e-3, 8], ...). */
+void ov_params_default(ov_params *p);
+
+/* Create a context on HIP stream `hip_stream` (hipStream_t; NULL = default stream)
+ * of the current device.  Computes the Zolotarev coefficients and checks the
+ * analytic free spectrum of |H_W| against [lambda_min, lambda_max]
+ * (OV_ERR_SPECTRUM).  *out receives the context (NULL on error). */
+ov_status ov_ctx_create(const ov_params *p, void *hip_stream, ov_ctx **out);
+ov_status ov_ctx_destroy(ov_ctx *ctx);
+
+/* Device bytes of workspace needed for nrhs right-hand sides. */
+size_t ov_workspace_bytes(const ov_ctx *ctx, int nrhs);
+
+/* Hand the context a caller-owned device buffer (256-byte aligned).  Without
+ * one, calls allocate and keep their own workspace (freed by ov_ctx_destroy). */
+ov_status ov_set_workspace(ov_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Zolotarev coefficients (n_poles each) and the max error delta on the interval. */
+ov_status ov_get_coeffs(const ov_ctx *ctx, double *a, double *b, double *delta);
+
+/* Host-only Zolotarev generator: sign(x) ~ x sum_k a_k/(x^2+b_k) on
+ * lmin <= |x| <= lmax with max error *delta.  No device work. */
+ov_status ov_zolotarev(int n, double lmin, double lmax, double *a, double *b, double *delta);
+
+/* out = eps(in) = H_W sum_k a_k (H_W^2 + b_k)^-1 in, FP64, for nrhs fields. */
+ov_status ov_sign(ov_ctx *ctx, void *out, const void *in, int nrhs, ov_stats *st);
+
+/* out = op(in) for nrhs fields (FP64).  phi is required for OV_OP_M* ops. */
+ov_status ov_apply(ov_ctx *ctx, ov_op op, void *out, const void *in, const void *phi,
+                   int nrhs, ov_stats *st);
+
+/* Solve MdagM x = b for nrhs right-hand sides (all in one batched launch
+ * sequence).  x is the initial guess on entry (zero it for a cold start) and
+ * the solution on exit.  st may be NULL or an array of nrhs stats. */
+ov_status ov_solve(ov_ctx *ctx, void *x, const void *b, const void *phi, int nrhs,
+                   ov_stats *st);
+
+/* Solve n systems of possibly different lattices in one batched sequence.
+ * Every context must share precision, n_poles, interval and tolerances; the
+ * first context's stream is used.  st: sum_i nrhs[i] stats (may be NULL). */
+ov_status ov_solve_batch(int n, ov_ctx *const *ctx, void *const *x, const void *const *b,
+                         const void *const *phi, const int *nrhs, ov_stats *st);
+
+/* HMC force of S = sum_rhs Re xi^dag (MdagM)^-1 xi:
+ *   grad_phi[x] = dS/dRe phi_x + i dS/dIm phi_x  (complex128 [V], device; summed over rhs)
+ *   S_host[r]   = Re xi_r^dag X_r  (host array of nrhs doubles)
+ * X = (MdagM)^-1 xi is solved with the context's precision; M X is recomputed
+ * rather than storing shifted solutions. */
+ov_status ov_force(ov_ctx *ctx, void *grad_phi, double *S_host, const void *xi,
+                   const void *phi, int nrhs, ov_stats *st);
+
+/* Single Wilson-stencil pass out = H_W in on fields already in the library's
+ * internal layout, for bandwidth measurement: prec 0 = FP64, 1 = FP32; in/out
+ * hold nrhs * 4 * V complex values in spin-planar order (see DESIGN notes in
+ * ov_pack).  reps launches back to back. */
+ov_status ov_stencil_bench(ov_ctx *ctx, int prec, void *out, const void *in, int nrhs,
+                           int reps, float *ms_per_launch);
+
+/* Convert nrhs ABI fields (complex128 AoS) to / from the internal spin-planar
+ * layout of precision prec (0 FP64, 1 FP32): plane s of rhs r holds V complex
+ * values at offset (r*4 + s)*V. */
+ov_status ov_pack(ov_ctx *ctx, int prec, void *dst, const void *src, int nrhs);
+ov_status ov_unpack(ov_ctx *ctx, int prec, void *dst, const void *src, int nrhs);
+
+/* Tuning knobs chosen by the autotuner: threads per block and sites per thread
+ * for the stencil kernels (0 = keep). */
+ov_status ov_set_launch(ov_ctx *ctx, int block, int sites_per_thread);
+ov_status ov_get_launch(const ov_ctx *ctx, int *block, int *sites_per_thread);
+
+/* Kernel-duration sampling with HIP events recorded on the context's stream.
+ * While max_per_call > 0, the first max_per_call launches of each multi-shift
+ * kernel (0 = t pass  t_n = H r_n + beta t_{n-1},  1 = r pass  r_{n+1} = r_n -
+ * alpha H t_n) in every sign/apply/solve/force call are bracketed by events.
+ * ov_kernel_times returns, per kernel, the summed duration (ms), the number of
+ * sampled launches and their summed algorithmic HBM bytes (3 spinor fields per
+ * site and launch: two read, one written).  reset != 0 clears the sums. */
+ov_status ov_kernel_sampling(ov_ctx *ctx, int max_per_call);
+ov_status ov_kernel_times(ov_ctx *ctx, int kernel, double *total_ms, long long *count,
+                          double *bytes, int reset);
+
+const char *ov_status_string(ov_status s);
+const char *ov_last_error(const ov_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OV_H */

@@ -1,0 +1,762 @@
+// ov_kernels.hpp -- HIP kernels of the overlap hot path (gfx950).
+//
+// Every kernel works on a *batch* of systems: one system is one right-hand
+// side on one lattice.  A launch covers sum_s nblk_s workgroups; workgroup b
+// is remapped XCD-contiguously to a logical block L, which belongs to system
+// s with sys[s].blk0 <= L < sys[s].blk0 + sys[s].nblk.  Systems may live on
+// lattices of different sizes (uneven batches) and carry their own scalars,
+// iteration counts and convergence flags.
+//
+// Multi-shift CG, Krylov-basis form.  For (H^2 + b_k) y_k = psi the shifted
+// solutions are linear combinations of the base residuals r_j, with scalar
+// coefficients that follow from the base CG scalars alone (Jegerlehner's
+// recurrences).  The pole sum needed by the sign function is
+//     eps = H sum_k a_k y_k = sum_j d_j t_j,   t_j = H P_j,
+// so one pass of the base CG on H^2 that keeps every t_j (HBM is 288 GB) plus
+// one combination pass replaces the n_poles shifted search directions of the
+// textbook algorithm.  Per iteration only two vectors are read and one written
+// in each of the two stencil kernels:
+//     k_ms_t:  t_n = H r_n + beta_{n-1} t_{n-1}         (= H P_n, P never stored)
+//     k_ms_r:  r_{n+1} = r_n - alpha_n H t_n
+// The scalar reductions are finished redundantly by every workgroup of the
+// next kernel (fixed summation order -> identical bits in every workgroup), so
+// no grid barrier, atomic or host round trip is needed inside an iteration.
+#pragma once
+
+#include "ov_common.hpp"
+
+namespace ov {
+
+constexpr int MAXP = 32;      // max poles
+constexpr int NTHREADS = 256; // default workgroup size (4 waves)
+
+// Device descriptor of one system for one phase of a solve.
+struct SysDev {
+  Geo g;
+  int nblk;    // workgroups of this system in a launch
+  int blk0;    // first logical workgroup
+  int spb;     // sites per workgroup
+  int pad0;
+  int* active;              // host-controlled on/off flag (batched solves); may be null
+  // multi-shift
+  void* basis;              // t_j slots, slot stride 4V complex
+  void* r;                  // r_n, n >= 1
+  const void* src;          // r_0
+  double* part_a;           // [nblk] |t_n|^2 partials
+  double* part_b;           // [nblk] |r_n|^2 partials (source partials for n = 0)
+  double* h_rho;            // [cap+1]
+  double* h_alpha;          // [cap+1]
+  double* h_zeta;           // [(cap+1) * MAXP]
+  unsigned int* h_active;   // [cap+1] shift masks
+  int* h_ctl;               // [4]: done, n_done, status, sticky error (host-reset)
+  long long* stat;          // [4]: inner iterations, multi-shift solves, max N, (unused)
+  double* dstat;            // [2]: max shift residual of the last multi-shift, (unused)
+  double* coef_term;        // [MAXP * cap]
+  double* coef_c;           // [cap+1]
+  double* coef_d;           // [cap]
+  // epilogue / CG
+  const double2* phi;       // [V] background scalar
+  const void* e_in;         // operator input psi (spin-planar, kernel precision)
+  void* e_out;              // operator output
+  void* e_out2;             // optional g5 * output (next multi-shift source)
+  double* part_c;           // [nblk] partials of |e_out|^2 or |r|^2
+  void* cg_x;               // CG vectors (kernel precision)
+  void* cg_p;
+  void* cg_r;
+  const double2* cg_b;      // FP64 right-hand side (true residual)
+  void* cg_r64;             // FP64 true residual out
+  void* cg_x64;             // FP64 solution (reliable updates)
+  double* cg_s;             // per-system CG scalars (see CG_* below)
+  double m_re, m_im;        // fermion mass
+  double g_re, g_im;        // Yukawa coupling
+};
+
+// CG scalar slots
+enum { CG_RR = 0, CG_RR_OLD, CG_PAP, CG_ALPHA, CG_BETA, CG_BB, CG_RTRUE, CG_NSLOT = 8 };
+
+struct MsParams {
+  int np;               // poles
+  int cap;              // basis capacity (max iterations)
+  double tol;           // shift tolerance
+  double diag;          // 4 - M0
+  double sigma[MAXP];   // shifts b_k
+  double coef[MAXP];    // residues a_k
+};
+
+__device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys, int L) {
+  int s = 0;
+  for (int k = 1; k < nsys; ++k)
+    if (sys[k].blk0 <= L) s = k;
+  return s;
+}
+
+// ------------------------------------------------------------------ pack
+// ABI complex128 (V,4) AoS (optionally times g5, times scale) <-> spin-planar R.
+template <class R>
+__global__ void k_pack(const SysDev* __restrict__ sys, int nsys, int nb_total,
+                       const double2* const* __restrict__ src, void* const* __restrict__ dst,
+                       double scale) {
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  const int V = S.g.V;
+  const int lb = L - S.blk0;
+  const double2* in = src[s];
+  c2<R>* out = (c2<R>*)dst[s];
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 v = in[(size_t)i * 4 + k];
+      out[(size_t)k * V + i] = c2<R>{(R)(scale * v.x), (R)(scale * v.y)};
+    }
+  }
+}
+
+template <class R>
+__global__ void k_unpack(const SysDev* __restrict__ sys, int nsys, int nb_total,
+                         void* const* __restrict__ src, double2* const* __restrict__ dst) {
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  const int V = S.g.V;
+  const int lb = L - S.blk0;
+  const c2<R>* in = (const c2<R>*)src[s];
+  double2* out = dst[s];
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const c2<R> v = in[(size_t)k * V + i];
+      out[(size_t)i * 4 + k] = double2{(double)v.x, (double)v.y};
+    }
+  }
+}
+
+// ---------------------------------------------------------- plain stencil
+// out = H_W in; optional |out|^2 partials.  in/out per system from e_in/e_out.
+template <class R>
+__global__ void __launch_bounds__(1024) k_hw(const SysDev* __restrict__ sys, int nsys,
+                                             int nb_total, double diag, int want_norm) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  const Geo g = S.g;
+  const int lb = L - S.blk0;
+  const c2<R>* in = (const c2<R>*)S.e_in;
+  c2<R>* out = (c2<R>*)S.e_out;
+  const int i0 = lb * S.spb;
+  const int i1 = min(g.V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> o[4];
+    hw_site<R>(in, g, i, (R)diag, o);
+    store_sp<R>(out, g.V, i, o);
+    if (want_norm) acc += norm2_sp(o);
+  }
+  if (want_norm) {
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) S.part_c[lb] = tot;
+  }
+}
+
+// ------------------------------------------------------- multi-shift: t pass
+// Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
+// advances the shift recurrences, decides convergence, then
+//   t_n = H r_n + beta_{n-1} t_{n-1}  -> basis slot n,  partial |t_n|^2.
+template <class R>
+__global__ void __launch_bounds__(1024) k_ms_t(const SysDev* __restrict__ sys, int nsys,
+                                               int nb_total, int n,
+                                               const MsParams mp_) {
+  __shared__ double lds[17];
+  __shared__ double sh_beta;
+  __shared__ int sh_stop;
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  if (n > 0 && S.h_ctl[0]) return;  // done in an earlier iteration
+  const int lb = L - S.blk0;
+  const MsParams* mp = &mp_;
+  const int np = mp->np;
+
+  const double rho = sum_partials(S.part_b, S.nblk, lds);
+  if (threadIdx.x < 64) {
+    // scalar recurrences, lane k of wave 0 owns shift k (identical in every
+    // workgroup of system s)
+    const int k = threadIdx.x;
+    const double rho0 = (n == 0) ? rho : S.h_rho[0];
+    const double thr = mp->tol * sqrt(rho0);
+    const double srho = sqrt(rho);
+    bool act = false;
+    double zn = 1.0;
+    if (n == 0) {
+      act = (k < np) && (srho > thr);
+    } else if (k < np) {
+      const unsigned int act_prev = S.h_active[n - 1];
+      const double zk1 = S.h_zeta[(size_t)(n - 1) * MAXP + k];  // zeta^{n-1}
+      zn = zk1;
+      if (act_prev & (1u << k)) {
+        const double a1 = S.h_alpha[n - 1];                                  // alpha_{n-1}
+        const double a2 = (n >= 2) ? S.h_alpha[n - 2] : 1.0;                 // alpha_{n-2}
+        const double b2 = (n >= 2) ? S.h_rho[n - 1] / S.h_rho[n - 2] : 0.0;  // beta_{n-2}
+        const double zk2 = (n >= 2) ? S.h_zeta[(size_t)(n - 2) * MAXP + k] : 1.0;
+        const double den = a2 * zk2 * (1.0 + a1 * mp->sigma[k]) + a1 * b2 * (zk2 - zk1);
+        zn = zk1 * zk2 * a2 / den;
+        act = fabs(zn) * srho > thr;
+      }
+    }
+    const unsigned int amask = (unsigned int)__ballot(act);
+    if (lb == 0 && k < np) S.h_zeta[(size_t)n * MAXP + k] = zn;
+    if (k == 0) {
+      int status = 0;
+      if (n > 0 && (!(rho >= 0.0) || !isfinite(rho))) status = 1;  // breakdown
+      int stop = (amask == 0) || status != 0;
+      if (!stop && n >= mp->cap) { stop = 1; status = 2; }  // basis exhausted
+      sh_beta = (n > 0) ? rho / S.h_rho[n - 1] : 0.0;
+      sh_stop = stop;
+      if (lb == 0) {
+        S.h_rho[n] = rho;
+        S.h_active[n] = amask;
+        if (stop) {
+          S.h_ctl[1] = n;
+          S.h_ctl[2] = status;
+        }
+        S.h_ctl[0] = stop;
+      }
+    }
+  }
+  __syncthreads();
+  if (sh_stop) return;
+  const double beta = sh_beta;
+
+  const Geo g = S.g;
+  const size_t slot = (size_t)4 * g.V;
+  const c2<R>* rin = (const c2<R>*)(n == 0 ? S.src : S.r);
+  c2<R>* tn = (c2<R>*)S.basis + (size_t)n * slot;
+  const c2<R>* tp = (const c2<R>*)S.basis + (size_t)(n > 0 ? n - 1 : 0) * slot;
+  const R rbeta = (R)beta;
+  const int i0 = lb * S.spb;
+  const int i1 = min(g.V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> o[4];
+    hw_site<R>(rin, g, i, (R)mp->diag, o);
+    if (n > 0) {
+      c2<R> q[4];
+      load_sp<R>(tp, g.V, i, q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[k] = c2<R>{o[k].x + rbeta * q[k].x, o[k].y + rbeta * q[k].y};
+    }
+    store_sp<R>(tn, g.V, i, o);
+    acc += norm2_sp(o);
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_a[lb] = tot;
+}
+
+// ------------------------------------------------------- multi-shift: r pass
+//   alpha_n = rho_n / |t_n|^2;  r_{n+1} = r_n - alpha_n H t_n;  partial |r_{n+1}|^2.
+template <class R>
+__global__ void __launch_bounds__(1024) k_ms_r(const SysDev* __restrict__ sys, int nsys,
+                                               int nb_total, int n,
+                                               const MsParams mp_) {
+  __shared__ double lds[17];
+  __shared__ double sh_alpha;
+  __shared__ int sh_stop;
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  if (S.h_ctl[0]) return;
+  const MsParams* mp = &mp_;
+  const int lb = L - S.blk0;
+  const double gam = sum_partials(S.part_a, S.nblk, lds);
+  if (threadIdx.x == 0) {
+    const double alpha = S.h_rho[n] / gam;
+    int stop = !(gam > 0.0) || !isfinite(alpha);
+    sh_alpha = alpha;
+    sh_stop = stop;
+    if (lb == 0) {
+      S.h_alpha[n] = alpha;
+      if (stop) {
+        S.h_ctl[1] = n;
+        S.h_ctl[2] = 1;
+        S.h_ctl[0] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (sh_stop) return;
+  const R alpha = (R)sh_alpha;
+  const Geo g = S.g;
+  const size_t slot = (size_t)4 * g.V;
+  const c2<R>* tn = (const c2<R>*)S.basis + (size_t)n * slot;
+  const c2<R>* rin = (const c2<R>*)(n == 0 ? S.src : S.r);
+  c2<R>* rout = (c2<R>*)S.r;
+  const int i0 = lb * S.spb;
+  const int i1 = min(g.V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> w[4], r[4];
+    hw_site<R>(tn, g, i, (R)mp->diag, w);
+    load_sp<R>(rin, g.V, i, r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = c2<R>{r[k].x - alpha * w[k].x, r[k].y - alpha * w[k].y};
+    store_sp<R>(rout, g.V, i, r);
+    acc += norm2_sp(r);
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_b[lb] = tot;
+}
+
+// ------------------------------------------------- multi-shift: coefficients
+// One workgroup per system.  Shift k ran N_k iterations (first n with its bit
+// clear in h_active).  With z^j = zeta_k^j, alpha_{j,k} = alpha_j z^{j+1}/z^j,
+// beta_{j,k} = beta_j (z^{j+1}/z^j)^2 and p_k^j = sum_{i<=j} z^i prod beta_{.,k} r_i:
+//   y_k = sum_j z^j S_k^j r_j,  S_k^j = alpha_{j,k} + beta_{j,k} S_k^{j+1},  S_k^{N_k} = 0,
+//   acc = sum_j c_j r_j,  c_j = sum_k a_k z^j S_k^j,
+//   eps = H acc = sum_j d_j t_j,  d_j = c_j - beta_j c_{j+1}   (H r_j = t_j - beta_{j-1} t_{j-1}).
+__global__ void k_ms_coef(const SysDev* __restrict__ sys, int nsys, int launched,
+                          const MsParams mp_) {
+  __shared__ int sh_N;
+  __shared__ double sh_res[MAXP];
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const MsParams* mp = &mp_;
+  const int np = mp->np;
+  const int cap = mp->cap;
+  if (threadIdx.x == 0) {
+    int N;
+    if (S.h_ctl[0]) {
+      N = S.h_ctl[1];
+      if (S.h_ctl[2]) S.h_ctl[3] |= 1 << S.h_ctl[2];
+    } else {  // not finished within the launched iterations: use what exists
+      N = launched > 0 ? launched - 1 : 0;
+      S.h_ctl[1] = N;
+      S.h_ctl[3] |= 1 << 2;
+    }
+    sh_N = N;
+    S.stat[0] += N;
+    S.stat[1] += 1;
+    if (N > S.stat[2]) S.stat[2] = N;
+  }
+  __syncthreads();
+  const int N = sh_N;
+  const double rho0 = S.h_rho[0];
+  for (int k = threadIdx.x; k < MAXP; k += blockDim.x) sh_res[k] = 0.0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    int Nk = N;
+    for (int j = 0; j < N; ++j)
+      if (!(S.h_active[j] & (1u << k))) { Nk = j; break; }
+    double Sk = 0.0;
+    for (int j = Nk - 1; j >= 0; --j) {
+      const double zj = S.h_zeta[(size_t)j * MAXP + k];
+      const double zr = S.h_zeta[(size_t)(j + 1) * MAXP + k] / zj;
+      const double aj = S.h_alpha[j] * zr;
+      const double bj = (S.h_rho[j + 1] / S.h_rho[j]) * zr * zr;
+      Sk = aj + bj * Sk;
+      S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zj * Sk;
+    }
+    for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
+    if (rho0 > 0.0)
+      sh_res[k] = fabs(S.h_zeta[(size_t)Nk * MAXP + k]) * sqrt(S.h_rho[Nk] / rho0);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    double c = 0.0;
+    for (int k = 0; k < np; ++k) c += S.coef_term[(size_t)k * cap + j];
+    S.coef_c[j] = c;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const double cn = (j + 1 < N) ? S.coef_c[j + 1] : 0.0;
+    S.coef_d[j] = S.coef_c[j] - (S.h_rho[j + 1] / S.h_rho[j]) * cn;
+  }
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int k = 0; k < np; ++k) mx = fmax(mx, sh_res[k]);
+    S.dstat[0] = mx;
+  }
+}
+
+// ---------------------------------------------- combination + epilogues
+enum EpiMode {
+  EPI_SIGN = 0,     // out = eps
+  EPI_DOV = 1,      // out = psi + g5 eps
+  EPI_DOVDAG = 2,   // out = psi + eps            (multi-shift source was g5 psi)
+  EPI_M = 3,        // out = psi + g5 eps + Y psi;   out2 = g5 out;  partial |out|^2
+  EPI_MDAG = 4,     // out = psi + eps + Y^dag psi
+  EPI_MDAG_CG = 5,  // q = psi + eps + Y^dag psi;  x += alpha p;  r -= alpha q;  partial |r|^2
+  EPI_MDAG_RES = 6  // r64 = b - (psi + eps + Y^dag psi) (+ low-precision copy in cg_r); partial |r64|^2
+};
+
+// c+ = m + g phi, c- = m* + g* phi*;  Y psi = c- psi_{0,1} (P-) + c+ psi_{2,3} (P+).
+template <class R>
+__global__ void __launch_bounds__(1024) k_ms_combine(const SysDev* __restrict__ sys, int nsys,
+                                                     int nb_total, int mode) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const Geo g = S.g;
+  const int V = g.V;
+  const size_t slot = (size_t)4 * V;
+  const int N = S.h_ctl[1];
+  const double* __restrict__ d = S.coef_d;
+  const c2<R>* basis = (const c2<R>*)S.basis;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double alpha = 0.0;
+  if (mode == EPI_MDAG_CG) alpha = S.cg_s[CG_ALPHA];
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = double2{0.0, 0.0};
+    int j = 0;
+    for (; j + 1 < N; j += 2) {
+      const double d0 = d[j], d1 = d[j + 1];
+      const c2<R>* b0 = basis + (size_t)j * slot;
+      const c2<R>* b1 = b0 + slot;
+      c2<R> v0[4], v1[4];
+      load_sp<R>(b0, V, i, v0);
+      load_sp<R>(b1, V, i, v1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        e[k].x += d0 * (double)v0[k].x + d1 * (double)v1[k].x;
+        e[k].y += d0 * (double)v0[k].y + d1 * (double)v1[k].y;
+      }
+    }
+    if (j < N) {
+      const double d0 = d[j];
+      c2<R> v0[4];
+      load_sp<R>(basis + (size_t)j * slot, V, i, v0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        e[k].x += d0 * (double)v0[k].x;
+        e[k].y += d0 * (double)v0[k].y;
+      }
+    }
+    if (mode == EPI_SIGN) {
+      c2<R> o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[k] = c2<R>{(R)e[k].x, (R)e[k].y};
+      store_sp<R>((c2<R>*)S.e_out, V, i, o);
+      continue;
+    }
+    c2<R> p[4];
+    load_sp<R>((const c2<R>*)S.e_in, V, i, p);
+    double2 o[4];
+    if (mode == EPI_DOV || mode == EPI_M) {
+      o[0] = double2{(double)p[0].x - e[0].x, (double)p[0].y - e[0].y};
+      o[1] = double2{(double)p[1].x - e[1].x, (double)p[1].y - e[1].y};
+      o[2] = double2{(double)p[2].x + e[2].x, (double)p[2].y + e[2].y};
+      o[3] = double2{(double)p[3].x + e[3].x, (double)p[3].y + e[3].y};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[k] = double2{(double)p[k].x + e[k].x, (double)p[k].y + e[k].y};
+    }
+    if (mode >= EPI_M) {
+      const double2 ph = S.phi[i];
+      // c+ = m + g phi ; c- = conj(m) + conj(g) conj(phi)
+      double cpr = S.m_re + S.g_re * ph.x - S.g_im * ph.y;
+      double cpi = S.m_im + S.g_re * ph.y + S.g_im * ph.x;
+      double cmr = S.m_re + S.g_re * ph.x - S.g_im * ph.y;
+      double cmi = -S.m_im - (S.g_re * ph.y + S.g_im * ph.x);
+      if (mode != EPI_M) { cpi = -cpi; cmi = -cmi; }  // adjoint: conjugate coefficients
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double cr = (k < 2) ? cmr : cpr, ci = (k < 2) ? cmi : cpi;
+        const double pr = (double)p[k].x, pi = (double)p[k].y;
+        o[k].x += cr * pr - ci * pi;
+        o[k].y += cr * pi + ci * pr;
+      }
+    }
+    if (mode == EPI_MDAG_CG) {
+      // x += alpha p ; r -= alpha q
+      c2<R> xv[4], pv[4], rv[4];
+      load_sp<R>((const c2<R>*)S.cg_x, V, i, xv);
+      load_sp<R>((const c2<R>*)S.cg_p, V, i, pv);
+      load_sp<R>((const c2<R>*)S.cg_r, V, i, rv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xv[k] = c2<R>{(R)((double)xv[k].x + alpha * (double)pv[k].x),
+                      (R)((double)xv[k].y + alpha * (double)pv[k].y)};
+        rv[k] = c2<R>{(R)((double)rv[k].x - alpha * o[k].x), (R)((double)rv[k].y - alpha * o[k].y)};
+      }
+      store_sp<R>((c2<R>*)S.cg_x, V, i, xv);
+      store_sp<R>((c2<R>*)S.cg_r, V, i, rv);
+      acc += norm2_sp(rv);
+      continue;
+    }
+    if (mode == EPI_MDAG_RES) {
+      double2 rr[4];
+      const double2* b = S.cg_b;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double2 bv = b[(size_t)i * 4 + k];
+        rr[k] = double2{bv.x - o[k].x, bv.y - o[k].y};
+      }
+      store_sp<double>((double2*)S.cg_r64, V, i, rr);
+      if (S.cg_r) {
+        c2<R> lo[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lo[k] = c2<R>{(R)rr[k].x, (R)rr[k].y};
+        store_sp<R>((c2<R>*)S.cg_r, V, i, lo);
+      }
+      acc += norm2_sp(rr);
+      continue;
+    }
+    c2<R> ov[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ov[k] = c2<R>{(R)o[k].x, (R)o[k].y};
+    store_sp<R>((c2<R>*)S.e_out, V, i, ov);
+    if (mode == EPI_M) {
+      acc += norm2_sp(ov);
+      if (S.e_out2) {
+        c2<R> g5o[4] = {c2<R>{-ov[0].x, -ov[0].y}, c2<R>{-ov[1].x, -ov[1].y}, ov[2], ov[3]};
+        store_sp<R>((c2<R>*)S.e_out2, V, i, g5o);
+      }
+    }
+  }
+  if (mode == EPI_M || mode == EPI_MDAG_CG || mode == EPI_MDAG_RES) {
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+      if (S.part_c) S.part_c[lb] = tot;
+      if (mode == EPI_M && S.part_b) S.part_b[lb] = tot;  // rho_0 of the next multi-shift
+    }
+  }
+}
+
+// ------------------------------------------------------- multi-shift setup
+// Source partials |src|^2 -> part_b (and src = g5 e_in when g5_src).
+template <class R>
+__global__ void __launch_bounds__(1024) k_ms_prep(const SysDev* __restrict__ sys, int nsys,
+                                                  int nb_total, int g5_src) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  // optional: src = g5 * e_in  (writes the multi-shift source buffer)
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> v[4];
+    if (g5_src) {
+      load_sp<R>((const c2<R>*)S.e_in, V, i, v);
+      v[0] = c2<R>{-v[0].x, -v[0].y};
+      v[1] = c2<R>{-v[1].x, -v[1].y};
+      store_sp<R>((c2<R>*)S.src, V, i, v);
+    } else {
+      load_sp<R>((const c2<R>*)S.src, V, i, v);
+    }
+    acc += norm2_sp(v);
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_b[lb] = tot;
+}
+
+// ------------------------------------------------------------ CG kernels
+// Sum part_c into cg_s[slot]; op 0: store, 1: alpha = rr/pap, 2: beta + rr update.
+__global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
+  __shared__ double lds[17];
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const double v = sum_partials(S.part_c, S.nblk, lds);
+  if (threadIdx.x == 0) {
+    double* c = S.cg_s;
+    if (op == 0) {
+      c[CG_RR] = v;
+      c[CG_RR_OLD] = v;
+      c[CG_BETA] = 0.0;
+    } else if (op == 1) {
+      c[CG_PAP] = v;
+      c[CG_ALPHA] = c[CG_RR] / v;
+    } else if (op == 2) {
+      c[CG_RR_OLD] = c[CG_RR];
+      c[CG_RR] = v;
+      c[CG_BETA] = v / c[CG_RR_OLD];
+    } else if (op == 3) {  // reliable update: replace the recursive |r|^2 by the true one
+      // Keep the search direction unless the true residual exceeds the recursive
+      // one by more than 2x (the recursion drifted): then restart with p = r.
+      const double rec = c[CG_RR];
+      c[CG_RTRUE] = v;
+      c[CG_RR] = v;
+      c[CG_BETA] = (v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
+    } else if (op == 5) {  // true residual only (no CG state change)
+      c[CG_RTRUE] = v;
+    } else if (op == 4) {  // norm of b
+      c[CG_BB] = v;
+    }
+  }
+}
+
+// p = r + beta p (beta from cg_s; use_beta = 0 -> p = r); partial |p|^2 -> part_b.
+template <class R>
+__global__ void __launch_bounds__(1024) k_cg_p(const SysDev* __restrict__ sys, int nsys,
+                                               int nb_total, int use_beta) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const double beta = use_beta ? S.cg_s[CG_BETA] : 0.0;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> r[4], p[4];
+    load_sp<R>((const c2<R>*)S.cg_r, V, i, r);
+    if (use_beta) {
+      load_sp<R>((const c2<R>*)S.cg_p, V, i, p);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        p[k] = c2<R>{(R)((double)r[k].x + beta * (double)p[k].x),
+                     (R)((double)r[k].y + beta * (double)p[k].y)};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] = r[k];
+    }
+    store_sp<R>((c2<R>*)S.cg_p, V, i, p);
+    acc += norm2_sp(p);
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_b[lb] = tot;
+}
+
+// Fill / axpy helpers used by the reliable-update solver.
+//   op 0: x64 += x (low precision), x = 0
+//   op 1: r = b (FP64 AoS -> planar R), partial |b|^2 -> part_c
+//   op 2: x = 0
+template <class R>
+__global__ void __launch_bounds__(1024) k_cg_misc(const SysDev* __restrict__ sys, int nsys,
+                                                  int nb_total, int op) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    if (op == 0) {
+      c2<R> xv[4];
+      double2 xh[4];
+      load_sp<R>((const c2<R>*)S.cg_x, V, i, xv);
+      load_sp<double>((const double2*)S.cg_x64, V, i, xh);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xh[k] = double2{xh[k].x + (double)xv[k].x, xh[k].y + (double)xv[k].y};
+        xv[k] = c2<R>{(R)0, (R)0};
+      }
+      store_sp<double>((double2*)S.cg_x64, V, i, xh);
+      store_sp<R>((c2<R>*)S.cg_x, V, i, xv);
+    } else if (op == 1) {
+      c2<R> rv[4];
+      double2 bv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        bv[k] = S.cg_b[(size_t)i * 4 + k];
+        rv[k] = c2<R>{(R)bv[k].x, (R)bv[k].y};
+      }
+      store_sp<R>((c2<R>*)S.cg_r, V, i, rv);
+      acc += norm2_sp(bv);
+    } else if (op == 2) {
+      c2<R> z[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) z[k] = c2<R>{(R)0, (R)0};
+      store_sp<R>((c2<R>*)S.cg_x, V, i, z);
+    }
+  }
+  if (op == 1) {
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) S.part_c[lb] = tot;
+  }
+}
+
+// ------------------------------------------------------------------ force
+// dS/dphi_x = -g [ Y_x^dag P+ X_x + X_x^dag P- Y_x ]  and  G_x = 2 conj(dS/dphi_x),
+// summed over the nsys right-hand sides (same lattice, same phi) in index order.
+// X = e_in, Y = e_out (FP64 planar) per system; G complex128 [V].
+__global__ void __launch_bounds__(1024) k_force(const SysDev* __restrict__ sys, int nsys,
+                                                int nb0, double2* __restrict__ G) {
+  const int L = xcd_logical_block(nb0);
+  const SysDev& S0 = sys[0];
+  const int V = S0.g.V;
+  const int i0 = L * S0.spb;
+  const int i1 = min(V, i0 + S0.spb);
+  const double g_re = S0.g_re, g_im = S0.g_im;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double gr = 0.0, gi = 0.0;
+    for (int s = 0; s < nsys; ++s) {
+      double2 X[4], Y[4];
+      load_sp<double>((const double2*)sys[s].e_in, V, i, X);
+      load_sp<double>((const double2*)sys[s].e_out, V, i, Y);
+      // t = sum_{s=2,3} conj(Y_s) X_s + sum_{s=0,1} conj(X_s) Y_s
+      double tr = 0.0, ti = 0.0;
+#pragma unroll
+      for (int k = 2; k < 4; ++k) {
+        tr += Y[k].x * X[k].x + Y[k].y * X[k].y;
+        ti += Y[k].x * X[k].y - Y[k].y * X[k].x;
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        tr += X[k].x * Y[k].x + X[k].y * Y[k].y;
+        ti += X[k].x * Y[k].y - X[k].y * Y[k].x;
+      }
+      // dS/dphi = -g t ;  G = 2 conj(dS/dphi)
+      const double fr = -(g_re * tr - g_im * ti);
+      const double fi = -(g_re * ti + g_im * tr);
+      gr += 2.0 * fr;
+      gi += -2.0 * fi;
+    }
+    G[i] = double2{gr, gi};
+  }
+}
+
+// Re <xi, X> partials (xi AoS complex128 from cg_b, X planar FP64 e_in) -> part_c
+__global__ void __launch_bounds__(1024) k_dot_re(const SysDev* __restrict__ sys, int nsys,
+                                                 int nb_total) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 X[4];
+    load_sp<double>((const double2*)S.e_in, V, i, X);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 b = S.cg_b[(size_t)i * 4 + k];
+      acc += b.x * X[k].x + b.y * X[k].y;
+    }
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_c[lb] = tot;
+}
+
+}  // namespace ov

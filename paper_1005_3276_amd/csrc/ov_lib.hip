@@ -1,0 +1,1497 @@
+// ov_lib.hip -- host orchestration and the C ABI of libov.so (gfx950).
+//
+// Layers:
+//   kernels (ov_kernels.hpp)  -> Engine (batched systems, tables, launch
+//   sequences for sign / apply / solve / force)  -> extern "C" ov_* (ov.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ov.h"
+#include "ov_kernels.hpp"
+
+namespace ov {
+int zolotarev_coeffs(int n, double lmin, double lmax, double* a, double* b, double* delta);
+}
+
+using namespace ov;
+
+struct ov_ctx {
+  ov_params p;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  double a[MAXP], b[MAXP], delta = 0;
+  double smin = 0, smax = 0;     // analytic free |H_W| range on this lattice
+  int block = NTHREADS;          // threads per workgroup
+  int spt = 0;                   // sites per thread (0 = automatic)
+  // workspace
+  void* user_ws = nullptr;
+  size_t user_ws_bytes = 0;
+  void* own_ws = nullptr;
+  size_t own_ws_bytes = 0;
+  double* pinned = nullptr;      // host staging of per-system scalars
+  int pinned_n = 0;
+  int* pinned_flags = nullptr;
+  // kernel-duration sampling (see ov_kernel_sampling)
+  int sample_max = 0;
+  std::vector<hipEvent_t> ev_pool;             // pairs
+  std::vector<std::pair<int, double>> ev_use;  // (kernel, bytes) per recorded pair
+  int ev_call_count[2] = {0, 0};
+  double ksum_ms[2] = {0, 0}, ksum_bytes[2] = {0, 0};
+  long long kcount[2] = {0, 0};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+#define HIPCHK(ctx, call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return OV_ERR_DEVICE;                                                      \
+    }                                                                            \
+  } while (0)
+
+#define TRY(x)                 \
+  do {                         \
+    ov_status s_ = (x);        \
+    if (s_ != OV_OK) return s_; \
+  } while (0)
+
+bool ov_log() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("OV_LOG");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Iterations CG on H_W^2 needs, in the worst case, to bring every shifted
+// residual |zeta_k| |r| below tol |src|: Chebyshev bound with kappa =
+// (smax/smin)^2 and the sqrt(kappa) factor between error and residual norms.
+int cg_bound(double smin, double smax, double tol) {
+  const double kap = (smax / smin) * (smax / smin);
+  const double sk = std::sqrt(kap);
+  const double q = (sk - 1.0) / (sk + 1.0);
+  if (q <= 0.0) return 2;
+  return (int)std::ceil(std::log(2.0 * sk / tol) / std::log(1.0 / q));
+}
+
+int capacity(const ov_ctx* c, double tol) {
+  const int cap = cg_bound(c->smin, c->smax, tol) + 6;
+  return std::max(4, std::min(cap, c->p.max_inner));
+}
+
+// 256-byte aligned bump allocator over a device buffer.
+struct Bump {
+  char* base;
+  size_t off = 0, cap;
+  bool dry;  // sizing pass: only count
+  Bump(void* b, size_t c, bool d) : base((char*)b), cap(c), dry(d) {}
+  void* take(size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    void* p = dry ? nullptr : base + off;
+    off += bytes;
+    return p;
+  }
+};
+
+// Per-system device buffers.
+struct SysBuf {
+  const ov_ctx* ctx;
+  int V, nblk, blk0, spb;
+  double2 *basis64, *r64ms, *src64b, *u64, *x64, *r64;
+  void *basisR, *rR, *srcR2, *uR, *xR, *pR, *rcgR;
+  double *part_a, *part_b, *part_c;
+  double *h_rho, *h_alpha, *h_zeta;
+  unsigned* h_active;
+  int* h_ctl;
+  long long* stat;
+  double* dstat;
+  double *coef_term, *coef_c, *coef_d, *cg_s;
+  int *act_cg, *act_ru;
+};
+
+int sites_per_block(const ov_ctx* c, int V) {
+  int spt = c->spt;
+  if (spt <= 0) {
+    const int blocks1 = (V + c->block - 1) / c->block;
+    spt = std::max(1, (blocks1 + 2047) / 2048);
+  }
+  return c->block * spt;
+}
+
+// What a call needs: FP64 ms basis capacity cap64, inner precision buffers.
+struct Plan {
+  int cap64 = 0;   // FP64 basis slots
+  int capR = 0;    // inner basis slots (0 = inner is FP64 and shares)
+  bool mixed = false;
+  bool solve = false;
+};
+
+template <class R>
+size_t cplx_bytes() { return sizeof(c2<R>); }
+
+// Carve one system's buffers (dry run computes the size).
+void carve(Bump& bp, SysBuf& s, const Plan& pl) {
+  const size_t v64 = (size_t)4 * s.V * sizeof(double2);
+  const size_t v32 = (size_t)4 * s.V * sizeof(float2);
+  const int capmax = std::max(pl.cap64, pl.capR);
+  s.basis64 = (double2*)bp.take(v64 * pl.cap64);
+  s.r64ms = (double2*)bp.take(v64);
+  s.src64b = (double2*)bp.take(v64);
+  s.u64 = (double2*)bp.take(v64);
+  s.x64 = (double2*)bp.take(v64);
+  s.r64 = (double2*)bp.take(v64);
+  if (pl.solve) {
+    if (pl.mixed) {
+      s.basisR = bp.take(v32 * pl.capR);
+      s.rR = bp.take(v32);
+      s.srcR2 = bp.take(v32);
+      s.uR = bp.take(v32);
+      s.xR = bp.take(v32);
+      s.pR = bp.take(v32);
+      s.rcgR = bp.take(v32);
+    } else {
+      s.basisR = s.basis64;
+      s.rR = s.r64ms;
+      s.srcR2 = s.src64b;
+      s.uR = s.u64;
+      s.xR = bp.take(v64);
+      s.pR = bp.take(v64);
+      s.rcgR = bp.take(v64);
+    }
+  } else {
+    s.basisR = s.rR = s.srcR2 = s.uR = s.xR = s.pR = s.rcgR = nullptr;
+  }
+  s.part_a = (double*)bp.take(sizeof(double) * s.nblk);
+  s.part_b = (double*)bp.take(sizeof(double) * s.nblk);
+  s.part_c = (double*)bp.take(sizeof(double) * s.nblk);
+  s.h_rho = (double*)bp.take(sizeof(double) * (capmax + 1));
+  s.h_alpha = (double*)bp.take(sizeof(double) * (capmax + 1));
+  s.h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
+  s.h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
+  s.h_ctl = (int*)bp.take(sizeof(int) * 4);
+  s.stat = (long long*)bp.take(sizeof(long long) * 4);
+  s.dstat = (double*)bp.take(sizeof(double) * 2);
+  s.coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
+  s.coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
+  s.coef_d = (double*)bp.take(sizeof(double) * capmax);
+  s.cg_s = (double*)bp.take(sizeof(double) * CG_NSLOT);
+  s.act_cg = (int*)bp.take(sizeof(int));
+  s.act_ru = (int*)bp.take(sizeof(int));
+}
+
+enum Table { T_APPLY = 0, T_APPLY2, T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG, T_CG, T_CG_RU, T_NT };
+
+// A batch of systems sharing poles, tolerances and precision.
+struct Engine {
+  std::vector<ov_ctx*> ctxs;        // per system
+  std::vector<int> rhs_of;          // rhs index inside its ctx call
+  std::vector<SysBuf> sb;
+  ov_ctx* lead;
+  hipStream_t st;
+  Plan pl;
+  int nsys = 0, nb_total = 0;
+  SysDev* tables = nullptr;         // device: T_NT * nsys
+  std::vector<SysDev> htab;         // host copy
+  void** ptrs = nullptr;            // device pointer arrays for pack/unpack (2 * nsys)
+  std::vector<void*> hptrs;         // host staging of ptrs (outlives the async copy)
+  MsParams mp64{}, mpR{};
+  int L64 = 0, LR = 0;              // multi-shift launch counts
+
+  size_t layout(void* base, size_t cap, bool dry) {
+    Bump bp(base, cap, dry);
+    int blk = 0;
+    for (int s = 0; s < nsys; ++s) {
+      SysBuf& b = sb[s];
+      b.ctx = ctxs[s];
+      const ov_params& p = ctxs[s]->p;
+      b.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+      b.spb = sites_per_block(ctxs[s], b.V);
+      b.nblk = (b.V + b.spb - 1) / b.spb;
+      b.blk0 = blk;
+      blk += b.nblk;
+      carve(bp, b, pl);
+    }
+    nb_total = blk;
+    tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
+    ptrs = (void**)bp.take(sizeof(void*) * 2 * nsys);
+    return bp.off + 256;
+  }
+};
+
+ov_status ensure_ws(ov_ctx* c, size_t need, void** base) {
+  if (c->user_ws && c->user_ws_bytes >= need) {
+    *base = c->user_ws;
+    return OV_OK;
+  }
+  if (c->own_ws_bytes < need) {
+    if (c->own_ws) (void)hipFree(c->own_ws);
+    c->own_ws = nullptr;
+    c->own_ws_bytes = 0;
+    HIPCHK(c, hipMalloc(&c->own_ws, need));
+    c->own_ws_bytes = need;
+  }
+  *base = c->own_ws;
+  return OV_OK;
+}
+
+ov_status ensure_pinned(ov_ctx* c, int nsys) {
+  if (c->pinned_n >= nsys) return OV_OK;
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
+  c->pinned = nullptr;
+  c->pinned_flags = nullptr;
+  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * CG_NSLOT * nsys));
+  HIPCHK(c, hipHostMalloc((void**)&c->pinned_flags, sizeof(int) * 2 * nsys + 64));
+  c->pinned_n = nsys;
+  return OV_OK;
+}
+
+MsParams make_mp(const ov_ctx* c, double tol, int cap) {
+  MsParams m{};
+  m.np = c->p.n_poles;
+  m.cap = cap;
+  m.tol = tol;
+  m.diag = 4.0 - c->p.M0;
+  for (int k = 0; k < MAXP; ++k) {
+    m.sigma[k] = k < m.np ? c->b[k] : 0.0;
+    m.coef[k] = k < m.np ? c->a[k] : 0.0;
+  }
+  return m;
+}
+
+// Build the engine for `ctxs` (one entry per system) and carve the workspace.
+ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, bool mixed,
+                      double tol64, double tolR) {
+  E.ctxs = ctxs;
+  E.nsys = (int)ctxs.size();
+  E.sb.assign(E.nsys, SysBuf{});
+  E.lead = ctxs[0];
+  E.st = E.lead->stream;
+  E.lead->ev_call_count[0] = E.lead->ev_call_count[1] = 0;
+  E.pl.solve = solve;
+  E.pl.mixed = mixed;
+  // capacities from the loosest spectral bound over the batch
+  int cap64 = 0, capR = 0;
+  for (auto* c : ctxs) {
+    cap64 = std::max(cap64, capacity(c, tol64));
+    if (solve) capR = std::max(capR, capacity(c, tolR));
+  }
+  E.pl.cap64 = solve && !mixed ? std::max(cap64, capR) : cap64;
+  E.pl.capR = solve ? (mixed ? capR : E.pl.cap64) : 0;
+  E.mp64 = make_mp(E.lead, tol64, E.pl.cap64);
+  E.mpR = make_mp(E.lead, tolR, solve ? E.pl.capR : E.pl.cap64);
+  E.L64 = E.pl.cap64;
+  E.LR = solve ? E.pl.capR : E.pl.cap64;
+  const size_t need = E.layout(nullptr, 0, true);
+  void* base = nullptr;
+  TRY(ensure_ws(E.lead, need, &base));
+  E.layout(base, need, false);
+  TRY(ensure_pinned(E.lead, E.nsys));
+  return OV_OK;
+}
+
+SysDev base_dev(const SysBuf& b) {
+  SysDev d{};
+  const ov_params& p = b.ctx->p;
+  d.g = Geo{p.dims[0], p.dims[1], p.dims[2], p.dims[3], b.V, p.bc_t};
+  d.nblk = b.nblk;
+  d.blk0 = b.blk0;
+  d.spb = b.spb;
+  d.part_a = b.part_a;
+  d.part_b = b.part_b;
+  d.part_c = b.part_c;
+  d.h_rho = b.h_rho;
+  d.h_alpha = b.h_alpha;
+  d.h_zeta = b.h_zeta;
+  d.h_active = b.h_active;
+  d.h_ctl = b.h_ctl;
+  d.stat = b.stat;
+  d.dstat = b.dstat;
+  d.coef_term = b.coef_term;
+  d.coef_c = b.coef_c;
+  d.coef_d = b.coef_d;
+  d.cg_s = b.cg_s;
+  d.m_re = p.m_re;
+  d.m_im = p.m_im;
+  d.g_re = p.g_re;
+  d.g_im = p.g_im;
+  return d;
+}
+
+// Host tables are pageable; synchronise after the copy so that htab can be
+// rebuilt safely (tables change a few times per call, never per iteration).
+ov_status upload_tables(Engine& E) {
+  HIPCHK(E.lead, hipMemcpyAsync(E.tables, E.htab.data(), sizeof(SysDev) * E.htab.size(),
+                                hipMemcpyHostToDevice, E.st));
+  HIPCHK(E.lead, hipStreamSynchronize(E.st));
+  return OV_OK;
+}
+
+const SysDev* tab(const Engine& E, int t) { return E.tables + (size_t)t * E.nsys; }
+
+// ----------------------------------------------------------------- launches
+// Event pair around one launch when sampling is on (first sample_max per kernel and call).
+struct Sample {
+  ov_ctx* c;
+  int k;
+  bool on = false;
+  Sample(ov_ctx* c_, int k_, double bytes) : c(c_), k(k_) {
+    if (c->sample_max <= 0 || c->ev_call_count[k] >= c->sample_max) return;
+    const size_t idx = c->ev_use.size();
+    if (2 * idx + 2 > c->ev_pool.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+      c->ev_pool.push_back(a);
+      c->ev_pool.push_back(b);
+    }
+    c->ev_use.push_back({k, bytes});
+    c->ev_call_count[k]++;
+    on = hipEventRecord(c->ev_pool[2 * idx], c->stream) == hipSuccess;
+  }
+  ~Sample() {
+    if (on) (void)hipEventRecord(c->ev_pool[2 * (c->ev_use.size() - 1) + 1], c->stream);
+  }
+};
+
+// Collect the sampled durations after the stream has been synchronised.
+void collect_samples(ov_ctx* c) {
+  for (size_t i = 0; i < c->ev_use.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]) == hipSuccess) {
+      const int k = c->ev_use[i].first;
+      c->ksum_ms[k] += ms;
+      c->ksum_bytes[k] += c->ev_use[i].second;
+      c->kcount[k]++;
+    }
+  }
+  c->ev_use.clear();
+  c->ev_call_count[0] = c->ev_call_count[1] = 0;
+}
+
+template <class R>
+void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
+  const SysDev* T = tab(E, t);
+  double vol = 0.0;  // active sites in this launch (all systems)
+  for (const auto& b : E.sb) vol += b.V;
+  const double bytes = 3.0 * 4.0 * sizeof(c2<R>) * vol;
+  for (int n = 0; n < L; ++n) {
+    {
+      Sample smp(E.lead, 0, bytes);
+      k_ms_t<R><<<E.nb_total, E.lead->block, 0, E.st>>>(T, E.nsys, E.nb_total, n, mp);
+    }
+    {
+      Sample smp(E.lead, 1, bytes);
+      k_ms_r<R><<<E.nb_total, E.lead->block, 0, E.st>>>(T, E.nsys, E.nb_total, n, mp);
+    }
+  }
+  k_ms_coef<<<E.nsys, 64, 0, E.st>>>(T, E.nsys, L, mp);
+}
+
+template <class R>
+void launch_combine(const Engine& E, int t, int mode) {
+  k_ms_combine<R><<<E.nb_total, E.lead->block, 0, E.st>>>(tab(E, t), E.nsys, E.nb_total, mode);
+}
+
+ov_status check_launch(ov_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("kernel launch: ") + hipGetErrorString(e);
+    return OV_ERR_DEVICE;
+  }
+  return OV_OK;
+}
+
+ov_status sync(Engine& E) {
+  TRY(check_launch(E.lead));
+  HIPCHK(E.lead, hipStreamSynchronize(E.st));
+  if (!E.lead->ev_use.empty()) collect_samples(E.lead);
+  return OV_OK;
+}
+
+ov_status read_ctl(Engine& E, std::vector<int>& ctl3, std::vector<long long>& stat0,
+                   std::vector<double>& dstat0) {
+  ctl3.resize(E.nsys);
+  stat0.resize(E.nsys);
+  dstat0.resize(E.nsys);
+  for (int s = 0; s < E.nsys; ++s) {
+    HIPCHK(E.lead, hipMemcpyAsync(&ctl3[s], E.sb[s].h_ctl + 3, sizeof(int),
+                                  hipMemcpyDeviceToHost, E.st));
+    HIPCHK(E.lead, hipMemcpyAsync(&stat0[s], E.sb[s].stat, sizeof(long long),
+                                  hipMemcpyDeviceToHost, E.st));
+    HIPCHK(E.lead, hipMemcpyAsync(&dstat0[s], E.sb[s].dstat, sizeof(double),
+                                  hipMemcpyDeviceToHost, E.st));
+  }
+  HIPCHK(E.lead, hipStreamSynchronize(E.st));
+  return OV_OK;
+}
+
+ov_status reset_stats(Engine& E) {
+  for (int s = 0; s < E.nsys; ++s) {
+    HIPCHK(E.lead, hipMemsetAsync(E.sb[s].h_ctl, 0, sizeof(int) * 4, E.st));
+    HIPCHK(E.lead, hipMemsetAsync(E.sb[s].stat, 0, sizeof(long long) * 4, E.st));
+    HIPCHK(E.lead, hipMemsetAsync(E.sb[s].dstat, 0, sizeof(double) * 2, E.st));
+  }
+  return OV_OK;
+}
+
+// ABI field pointers -> pack into the planar FP64 buffer chosen by `dst_of`.
+ov_status pack64(Engine& E, const std::vector<const void*>& src, std::vector<void*> dst) {
+  TRY(sync(E));  // the staging vector may still be read by an earlier copy
+  std::vector<void*>& h = E.hptrs;
+  h.assign(2 * E.nsys, nullptr);
+  for (int s = 0; s < E.nsys; ++s) {
+    h[s] = (void*)src[s];
+    h[E.nsys + s] = dst[s];
+  }
+  HIPCHK(E.lead, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(),
+                                hipMemcpyHostToDevice, E.st));
+  k_pack<double><<<E.nb_total, E.lead->block, 0, E.st>>>(
+      tab(E, T_APPLY), E.nsys, E.nb_total, (const double2* const*)E.ptrs, E.ptrs + E.nsys, 1.0);
+  return check_launch(E.lead);
+}
+
+ov_status unpack64(Engine& E, const std::vector<void*>& src, const std::vector<void*>& dst) {
+  TRY(sync(E));
+  std::vector<void*>& h = E.hptrs;
+  h.assign(2 * E.nsys, nullptr);
+  for (int s = 0; s < E.nsys; ++s) {
+    h[s] = src[s];
+    h[E.nsys + s] = dst[s];
+  }
+  HIPCHK(E.lead, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(),
+                                hipMemcpyHostToDevice, E.st));
+  k_unpack<double><<<E.nb_total, E.lead->block, 0, E.st>>>(
+      tab(E, T_APPLY), E.nsys, E.nb_total, E.ptrs, (double2* const*)(E.ptrs + E.nsys));
+  return check_launch(E.lead);
+}
+
+// --------------------------------------------------------- apply / sign
+// Inputs were packed into x64 (planar FP64); result goes to r64 (planar FP64).
+ov_status run_apply(Engine& E, int op) {
+  E.htab.assign((size_t)T_NT * E.nsys, SysDev{});
+  for (int s = 0; s < E.nsys; ++s) {
+    SysBuf& b = E.sb[s];
+    SysDev d = base_dev(b);
+    d.phi = (const double2*)nullptr;
+    d.basis = b.basis64;
+    d.r = b.r64ms;
+    SysDev d1 = d, d2 = d;
+    // phase 1: operator on psi = x64
+    d1.e_in = b.x64;
+    d1.src = (op == OV_OP_DOV_DAG || op == OV_OP_M_DAG) ? (const void*)b.src64b
+                                                        : (const void*)b.x64;
+    d1.e_out = (op == OV_OP_MDAGM) ? (void*)b.u64 : (void*)b.r64;
+    d1.e_out2 = (op == OV_OP_MDAGM) ? (void*)b.src64b : nullptr;
+    // phase 2 (MdagM only): M^dag on u64, source g5 u64 = src64b
+    d2.e_in = b.u64;
+    d2.src = b.src64b;
+    d2.e_out = b.r64;
+    E.htab[(size_t)T_APPLY * E.nsys + s] = d1;
+    E.htab[(size_t)T_APPLY2 * E.nsys + s] = d2;
+  }
+  return upload_tables(E);
+}
+
+ov_status set_phi(Engine& E, const std::vector<const void*>& phi) {
+  for (int t = 0; t < T_NT; ++t)
+    for (int s = 0; s < E.nsys; ++s) E.htab[(size_t)t * E.nsys + s].phi = (const double2*)phi[s];
+  return upload_tables(E);
+}
+
+ov_status apply_sequence(Engine& E, int op) {
+  const ov_ctx* c = E.lead;
+  const double diag = 4.0 - c->p.M0;
+  switch (op) {
+    case OV_OP_HW:
+      k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, diag, 0);
+      break;
+    case -1:  // sign
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 0);
+      launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
+      launch_combine<double>(E, T_APPLY, EPI_SIGN);
+      break;
+    case OV_OP_DOV:
+    case OV_OP_M:
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 0);
+      launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
+      launch_combine<double>(E, T_APPLY, op == OV_OP_DOV ? EPI_DOV : EPI_M);
+      break;
+    case OV_OP_DOV_DAG:
+    case OV_OP_M_DAG:
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 1);
+      launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
+      launch_combine<double>(E, T_APPLY, op == OV_OP_DOV_DAG ? EPI_DOVDAG : EPI_MDAG);
+      break;
+    case OV_OP_MDAGM:
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 0);
+      launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
+      launch_combine<double>(E, T_APPLY, EPI_M);  // u64, src64b = g5 u64, part_b
+      launch_ms<double>(E, T_APPLY2, E.mp64, E.L64);
+      launch_combine<double>(E, T_APPLY2, EPI_MDAG);
+      break;
+    default:
+      return OV_ERR_INVALID_ARG;
+  }
+  return check_launch(E.lead);
+}
+
+// ------------------------------------------------------------------ solve
+// Every pointer a kernel dereferences through a table must be set: which
+// kernels run on which table is fixed by solve_engine / true_residual.
+ov_status check_roles(Engine& E, bool fp64_inner) {
+  auto need = [&](int t, int s, const void* p, const char* what) -> bool {
+    if (p) return true;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "internal: table %d system %d lacks %s", t, s, what);
+    E.lead->err = buf;
+    return false;
+  };
+  for (int s = 0; s < E.nsys; ++s) {
+    const SysDev* T[T_NT];
+    for (int t = 0; t < T_NT; ++t) T[t] = &E.htab[(size_t)t * E.nsys + s];
+    bool ok = true;
+    for (int t : {T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG, T_CG, T_CG_RU}) {
+      ok &= need(t, s, T[t]->part_a, "part_a") && need(t, s, T[t]->part_b, "part_b") &&
+            need(t, s, T[t]->part_c, "part_c") && need(t, s, T[t]->cg_s, "cg_s") &&
+            need(t, s, T[t]->h_ctl, "h_ctl") && need(t, s, T[t]->active, "active");
+    }
+    // multi-shift + combine tables
+    for (int t : {T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG})
+      ok &= need(t, s, T[t]->basis, "basis") && need(t, s, T[t]->r, "r") &&
+            need(t, s, T[t]->src, "src") && need(t, s, T[t]->e_in, "e_in") &&
+            need(t, s, T[t]->phi, "phi") && need(t, s, T[t]->h_rho, "h_rho") &&
+            need(t, s, T[t]->coef_d, "coef_d") && need(t, s, T[t]->stat, "stat");
+    ok &= need(T_IN_M, s, T[T_IN_M]->e_out, "e_out") && need(T_IN_M, s, T[T_IN_M]->e_out2, "e_out2");
+    ok &= need(T_TR_M, s, T[T_TR_M]->e_out, "e_out") && need(T_TR_M, s, T[T_TR_M]->e_out2, "e_out2");
+    // EPI_MDAG_CG
+    ok &= need(T_IN_MDAG, s, T[T_IN_MDAG]->cg_x, "cg_x") && need(T_IN_MDAG, s, T[T_IN_MDAG]->cg_p, "cg_p") &&
+          need(T_IN_MDAG, s, T[T_IN_MDAG]->cg_r, "cg_r");
+    // EPI_MDAG_RES (cg_r only for an FP64 inner solver)
+    ok &= need(T_TR_MDAG, s, T[T_TR_MDAG]->cg_b, "cg_b") && need(T_TR_MDAG, s, T[T_TR_MDAG]->cg_r64, "cg_r64");
+    if (fp64_inner) ok &= need(T_TR_MDAG, s, T[T_TR_MDAG]->cg_r, "cg_r");
+    // k_cg_p / k_cg_misc / k_ms_prep on T_CG and T_CG_RU, k_r64_to_r32 on T_CG_RU
+    for (int t : {T_CG, T_CG_RU})
+      ok &= need(t, s, T[t]->cg_x, "cg_x") && need(t, s, T[t]->cg_p, "cg_p") &&
+            need(t, s, T[t]->cg_r, "cg_r") && need(t, s, T[t]->cg_b, "cg_b") &&
+            need(t, s, T[t]->cg_x64, "cg_x64") && need(t, s, T[t]->src, "src");
+    ok &= need(T_CG_RU, s, T[T_CG_RU]->cg_r64, "cg_r64");
+    if (!ok) return OV_ERR_DEVICE;
+  }
+  return OV_OK;
+}
+
+template <class R>
+ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
+                             const std::vector<const void*>& phi) {
+  E.htab.assign((size_t)T_NT * E.nsys, SysDev{});
+  for (int s = 0; s < E.nsys; ++s) {
+    SysBuf& b = E.sb[s];
+    SysDev d = base_dev(b);
+    d.phi = (const double2*)phi[s];
+    d.cg_b = (const double2*)bvec[s];
+    // inner M p
+    SysDev im = d;
+    im.active = b.act_cg;
+    im.basis = b.basisR;
+    im.r = b.rR;
+    im.src = b.pR;
+    im.e_in = b.pR;
+    im.e_out = b.uR;
+    im.e_out2 = b.srcR2;
+    // inner M^dag u with the CG update
+    SysDev imd = d;
+    imd.active = b.act_cg;
+    imd.basis = b.basisR;
+    imd.r = b.rR;
+    imd.src = b.srcR2;
+    imd.e_in = b.uR;
+    imd.cg_x = b.xR;
+    imd.cg_p = b.pR;
+    imd.cg_r = b.rcgR;
+    // FP64 true residual: M x64, then r64 = b - M^dag (M x64)
+    SysDev tm = d;
+    tm.active = b.act_ru;
+    tm.basis = b.basis64;
+    tm.r = b.r64ms;
+    tm.src = b.x64;
+    tm.e_in = b.x64;
+    tm.e_out = b.u64;
+    tm.e_out2 = b.src64b;
+    SysDev tmd = d;
+    tmd.active = b.act_ru;
+    tmd.basis = b.basis64;
+    tmd.r = b.r64ms;
+    tmd.src = b.src64b;
+    tmd.e_in = b.u64;
+    tmd.cg_r64 = b.r64;
+    tmd.cg_r = (sizeof(R) == sizeof(double)) ? b.rcgR : nullptr;  // FP32 copy: k_r64_to_r32
+    // CG vector ops
+    SysDev cg = d;
+    cg.active = b.act_cg;
+    cg.cg_x = b.xR;
+    cg.cg_p = b.pR;
+    cg.cg_r = b.rcgR;
+    cg.cg_x64 = b.x64;
+    cg.src = b.x64;
+    SysDev cgr = cg;
+    cgr.active = b.act_ru;
+    cgr.cg_r64 = b.r64;
+    E.htab[(size_t)T_IN_M * E.nsys + s] = im;
+    E.htab[(size_t)T_IN_MDAG * E.nsys + s] = imd;
+    E.htab[(size_t)T_TR_M * E.nsys + s] = tm;
+    E.htab[(size_t)T_TR_MDAG * E.nsys + s] = tmd;
+    E.htab[(size_t)T_CG * E.nsys + s] = cg;
+    E.htab[(size_t)T_CG_RU * E.nsys + s] = cgr;
+    SysDev ap = d;  // pack/unpack geometry
+    E.htab[(size_t)T_APPLY * E.nsys + s] = ap;
+  }
+  TRY(check_roles(E, sizeof(R) == sizeof(double)));
+  return upload_tables(E);
+}
+
+ov_status set_flags(Engine& E, const std::vector<int>& cg, const std::vector<int>& ru) {
+  int* h = E.lead->pinned_flags;
+  for (int s = 0; s < E.nsys; ++s) {
+    h[2 * s] = cg[s];
+    h[2 * s + 1] = ru[s];
+  }
+  for (int s = 0; s < E.nsys; ++s) {
+    HIPCHK(E.lead, hipMemcpyAsync(E.sb[s].act_cg, &h[2 * s], sizeof(int), hipMemcpyHostToDevice, E.st));
+    HIPCHK(E.lead, hipMemcpyAsync(E.sb[s].act_ru, &h[2 * s + 1], sizeof(int), hipMemcpyHostToDevice, E.st));
+  }
+  // the pinned staging is reused: make sure the copies are done before rewriting it
+  HIPCHK(E.lead, hipStreamSynchronize(E.st));
+  return OV_OK;
+}
+
+ov_status read_scalars(Engine& E) {
+  for (int s = 0; s < E.nsys; ++s)
+    HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned + (size_t)s * CG_NSLOT, E.sb[s].cg_s,
+                                  sizeof(double) * CG_NSLOT, hipMemcpyDeviceToHost, E.st));
+  return sync(E);
+}
+
+// FP64 true residual r64 = b - MdagM x64 (and the inner-precision copy in rcgR)
+// for the systems with act_ru set, with multi-shift tolerance tol.
+template <class R>
+ov_status true_residual(Engine& E, double tol, int scalar_op) {
+  const ov_ctx* c = E.lead;
+  MsParams mp = make_mp(c, tol, E.pl.cap64);
+  const int L = std::min(E.pl.cap64, capacity(c, tol));
+  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_TR_M), E.nsys, E.nb_total, 0);
+  launch_ms<double>(E, T_TR_M, mp, L);
+  launch_combine<double>(E, T_TR_M, EPI_M);
+  launch_ms<double>(E, T_TR_MDAG, mp, L);
+  // EPI_MDAG_RES writes r64 (FP64) and, for an FP64 inner solver, its copy in
+  // cg_r; an FP32 inner solver gets its copy from k_r64_to_r32 afterwards.
+  launch_combine<double>(E, T_TR_MDAG, EPI_MDAG_RES);
+  k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_TR_MDAG), E.nsys, scalar_op);
+  return check_launch(E.lead);
+}
+
+}  // namespace
+
+// The float inner solver needs r (FP32) = r64 after a true residual; a small
+// conversion kernel keeps the FP64 combine generic.
+namespace ov {
+__global__ void __launch_bounds__(1024) k_r64_to_r32(const SysDev* __restrict__ sys, int nsys,
+                                                     int nb_total) {
+  const int L = xcd_logical_block(nb_total);
+  const int s = find_sys(sys, nsys, L);
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 v[4];
+    load_sp<double>((const double2*)S.cg_r64, V, i, v);
+    float2 w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = float2{(float)v[k].x, (float)v[k].y};
+    store_sp<float>((float2*)S.cg_r, V, i, w);
+  }
+}
+}  // namespace ov
+
+namespace {
+
+struct SolveOut {
+  std::vector<int> outer, ru;
+  std::vector<double> res;
+  std::vector<int> conv;
+};
+
+// Reliable-update CG on MdagM x = b.  Inner iterations run in precision R with
+// multi-shift tolerance tol_in; every time the recursive residual has dropped
+// by `delta` relative to the last true residual (or meets the target) the
+// inner solution is folded into the FP64 x64 and the FP64 true residual
+// replaces the recursive one (Sleijpen & van der Vorst; Clark et al. for
+// mixed precision).  Convergence is declared only on the FP64 true residual
+// computed with multi-shift tolerance truth_tol.
+template <class R>
+ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
+                       const std::vector<const void*>& phi, double tol_in, double delta,
+                       SolveOut& out) {
+  ov_ctx* c = E.lead;
+  const ov_params& P = c->p;
+  const int ns = E.nsys;
+  TRY((build_solve_tables<R>(E, bvec, phi)));
+  TRY(reset_stats(E));
+  std::vector<int> fcg(ns, 1), fru(ns, 1);
+  TRY(set_flags(E, fcg, fru));
+  // x64 <- guess was packed by the caller; xR = 0; rcgR = b, |b|^2
+  k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, 2);
+  k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, 1);
+  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 4);  // BB
+  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);  // RR = |b|^2, beta = 0
+  // |x0|^2 -> part_b via prep on x64 (src = x64 in T_CG)
+  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, 0);
+  std::vector<double> x0n(ns);
+  for (int s = 0; s < ns; ++s) {
+    std::vector<double> tmp(E.sb[s].nblk);
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), E.sb[s].part_b, sizeof(double) * tmp.size(),
+                             hipMemcpyDeviceToHost, E.st));
+    TRY(sync(E));
+    double acc = 0;
+    for (double v : tmp) acc += v;
+    x0n[s] = acc;
+  }
+  TRY(read_scalars(E));
+  std::vector<double> bn(ns), rmax(ns);
+  out.outer.assign(ns, 0);
+  out.ru.assign(ns, 0);
+  out.res.assign(ns, 1.0);
+  out.conv.assign(ns, 0);
+  bool any_guess = false;
+  for (int s = 0; s < ns; ++s) {
+    bn[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_BB]);
+    if (bn[s] == 0.0 || !std::isfinite(bn[s])) {
+      if (!std::isfinite(bn[s])) {
+        c->err = "non-finite right-hand side";
+        return OV_ERR_BREAKDOWN;
+      }
+      out.conv[s] = 1;  // b = 0: x = 0
+      fcg[s] = 0;
+    }
+    fru[s] = (x0n[s] > 0.0 && fcg[s]) ? 1 : 0;
+    if (fru[s]) any_guess = true;
+    rmax[s] = bn[s];
+  }
+  if (any_guess) {  // r = b - A x0 for warm starts
+    TRY(set_flags(E, fcg, fru));
+    TRY(true_residual<R>(E, std::max(P.truth_tol, 1e-3 * P.outer_tol), 3));
+    if (sizeof(R) != sizeof(double))
+      k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), ns, E.nb_total);
+    TRY(read_scalars(E));
+    for (int s = 0; s < ns; ++s)
+      if (fru[s]) {
+        rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
+        out.ru[s]++;
+      }
+    // restart the recurrence from the true residual
+    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);
+  }
+  const MsParams mpR = make_mp(c, tol_in, E.pl.capR);
+  const int LR = std::min(E.pl.capR, capacity(c, tol_in));
+  int iter = 0;
+  bool first = true;
+  while (true) {
+    bool any = false;
+    for (int s = 0; s < ns; ++s) any |= (fcg[s] != 0);
+    if (!any) break;
+    std::fill(fru.begin(), fru.end(), 0);
+    TRY(set_flags(E, fcg, fru));
+    // p = r + beta p ; M p ; alpha ; M^dag u with CG update ; beta
+    k_cg_p<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, first ? 0 : 1);
+    first = false;
+    launch_ms<R>(E, T_IN_M, mpR, LR);
+    launch_combine<R>(E, T_IN_M, EPI_M);
+    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
+    launch_ms<R>(E, T_IN_MDAG, mpR, LR);
+    launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
+    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+    TRY(read_scalars(E));
+    ++iter;
+    bool need_ru = false, final_check = false;
+    double best_rec = 1e300;  // the tightest residual among the systems updated now
+    if (ov_log()) {
+      std::fprintf(stderr, "[ov] iter %d:", iter);
+      for (int s = 0; s < ns; ++s)
+        if (fcg[s])
+          std::fprintf(stderr, " s%d rec=%.3e pap=%.3e", s,
+                       std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RR]) / bn[s],
+                       c->pinned[(size_t)s * CG_NSLOT + CG_PAP]);
+      std::fprintf(stderr, "\n");
+    }
+    for (int s = 0; s < ns; ++s) {
+      if (!fcg[s]) continue;
+      out.outer[s]++;
+      const double* cs = c->pinned + (size_t)s * CG_NSLOT;
+      const double rr = cs[CG_RR];
+      if (!std::isfinite(rr) || !std::isfinite(cs[CG_ALPHA]) || cs[CG_PAP] <= 0.0) {
+        c->err = "CG breakdown (non-finite or non-positive scalar)";
+        return OV_ERR_BREAKDOWN;
+      }
+      const double rec = std::sqrt(rr) / bn[s];
+      const bool at_target = rec <= P.outer_tol;
+      const bool dropped = delta > 0.0 && std::sqrt(rr) < delta * rmax[s];
+      if (at_target || dropped || iter >= P.max_outer) {
+        fru[s] = 1;
+        need_ru = true;
+        if (at_target || iter >= P.max_outer) final_check = true;
+        best_rec = std::min(best_rec, rec);
+      }
+    }
+    if (need_ru) {
+      TRY(set_flags(E, fcg, fru));
+      // x64 += xR ; xR = 0
+      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), ns, E.nb_total, 0);
+      // One multi-shift tolerance serves every updated system, so it follows the
+      // smallest residual: its operator error must stay ~1% of that residual.
+      const double ttol = final_check
+                              ? P.truth_tol
+                              : std::max(P.truth_tol, std::min(1e-6, 0.01 * best_rec));
+      TRY(true_residual<R>(E, ttol, 3));
+      if (sizeof(R) != sizeof(double))
+        k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), ns, E.nb_total);
+      TRY(read_scalars(E));
+      for (int s = 0; s < ns; ++s) {
+        if (!fru[s]) continue;
+        out.ru[s]++;
+        const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
+        rmax[s] = rt;
+        out.res[s] = rt / bn[s];
+        if (ov_log())
+          std::fprintf(stderr, "[ov] reliable update s%d at iter %d: true res %.3e (ms tol %.1e)\n",
+                       s, iter, out.res[s], ttol);
+        if (out.res[s] <= P.outer_tol) {
+          if (ttol <= P.truth_tol) {
+            out.conv[s] = 1;
+            fcg[s] = 0;
+          }
+        }
+      }
+      if (iter >= P.max_outer) break;
+    }
+  }
+  return OV_OK;
+}
+
+ov_status validate(const ov_params* p, std::string& err) {
+  for (int d = 0; d < 4; ++d)
+    if (p->dims[d] < 2 || (p->dims[d] & 1)) {
+      err = "every extent must be even and >= 2";
+      return OV_ERR_INVALID_ARG;
+    }
+  const long long V = (long long)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
+  if (V > (1LL << 28)) {
+    err = "lattice too large";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (p->bc_t != 1 && p->bc_t != -1) {
+    err = "bc_t must be +1 or -1";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (p->n_poles < 1 || p->n_poles > MAXP) {
+    err = "n_poles must be in 1..32";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (!(p->lambda_min > 0) || !(p->lambda_max > p->lambda_min)) {
+    err = "need 0 < lambda_min < lambda_max";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (!(p->inner_tol > 0) || !(p->outer_tol > 0) || !(p->truth_tol > 0) ||
+      !(p->mixed_inner_tol > 0) || p->reliable_delta < 0 || p->reliable_delta >= 1) {
+    err = "tolerances must be positive (0 <= reliable_delta < 1)";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (p->max_inner < 4 || p->max_outer < 1) {
+    err = "max_inner >= 4 and max_outer >= 1 required";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (p->precision != OV_FP64 && p->precision != OV_MIXED) {
+    err = "precision must be OV_FP64 or OV_MIXED";
+    return OV_ERR_INVALID_ARG;
+  }
+  return OV_OK;
+}
+
+// free |H_W| spectrum on the lattice: s(p)^2 = sum sin^2 p + (M0' )^2 with
+// the Wilson mass term 4 - M0 - sum cos p (antiperiodic time: p_t = (2n+1) pi/T)
+void free_spectrum(const ov_params* p, double& smin, double& smax) {
+  smin = 1e300;
+  smax = 0;
+  std::vector<double> cx[4], sx[4];
+  for (int d = 0; d < 4; ++d) {
+    const int L = p->dims[d];
+    for (int n = 0; n < L; ++n) {
+      double ph = 2.0 * M_PI * n / L;
+      if (d == 3 && p->bc_t < 0) ph += M_PI / L;
+      cx[d].push_back(std::cos(ph));
+      sx[d].push_back(std::sin(ph) * std::sin(ph));
+    }
+  }
+  for (size_t a = 0; a < cx[0].size(); ++a)
+    for (size_t b = 0; b < cx[1].size(); ++b)
+      for (size_t c = 0; c < cx[2].size(); ++c)
+        for (size_t d = 0; d < cx[3].size(); ++d) {
+          const double w = 4.0 - p->M0 - (cx[0][a] + cx[1][b] + cx[2][c] + cx[3][d]);
+          const double s2 = sx[0][a] + sx[1][b] + sx[2][c] + sx[3][d] + w * w;
+          const double s = std::sqrt(s2);
+          smin = std::min(smin, s);
+          smax = std::max(smax, s);
+        }
+}
+
+void fill_stats(ov_stats* st, int n, Engine* E, const SolveOut* so, double secs, int prec_bytes) {
+  if (!st) return;
+  std::vector<int> ctl;
+  std::vector<long long> st0;
+  std::vector<double> ds;
+  if (E) read_ctl(*E, ctl, st0, ds);
+  for (int s = 0; s < n; ++s) {
+    ov_stats& o = st[s];
+    std::memset(&o, 0, sizeof(o));
+    if (E) {
+      o.inner_iters = st0[s];
+      o.stencil_apps = 2 * st0[s];
+      o.max_shift_res = ds[s];
+      const double V = E->sb[s].V;
+      o.model_bytes = 7.0 * (double)st0[s] * 4.0 * V * prec_bytes;
+    }
+    if (so) {
+      o.outer_iters = so->outer[s];
+      o.reliable_updates = so->ru[s];
+      o.true_rel_res = so->res[s];
+    }
+    o.seconds = secs;
+  }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void ov_params_default(ov_params* p) {
+  std::memset(p, 0, sizeof(*p));
+  p->dims[0] = p->dims[1] = p->dims[2] = p->dims[3] = 4;
+  p->bc_t = -1;
+  p->M0 = 1.0;
+  p->m_re = 0.05;
+  p->g_re = 0.3;
+  p->n_poles = 20;
+  p->lambda_min = 1e-3;
+  p->lambda_max = 8.0;
+  p->inner_tol = 1e-12;
+  p->outer_tol = 1e-10;
+  p->truth_tol = 1e-13;
+  p->mixed_inner_tol = 1e-6;
+  p->reliable_delta = 0.1;
+  p->max_inner = 400;
+  p->max_outer = 2000;
+  p->precision = OV_MIXED;
+}
+
+const char* ov_status_string(ov_status s) {
+  switch (s) {
+    case OV_OK: return "ok";
+    case OV_ERR_INVALID_ARG: return "invalid argument";
+    case OV_ERR_NOT_CONVERGED: return "not converged";
+    case OV_ERR_BREAKDOWN: return "breakdown";
+    case OV_ERR_SPECTRUM: return "spectrum outside the approximation interval";
+    case OV_ERR_WORKSPACE: return "workspace too small";
+    case OV_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* ov_last_error(const ov_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+ov_status ov_zolotarev(int n, double lmin, double lmax, double* a, double* b, double* delta) {
+  if (!a || !b || n < 1 || n > MAXP) return OV_ERR_INVALID_ARG;
+  return zolotarev_coeffs(n, lmin, lmax, a, b, delta) == 0 ? OV_OK : OV_ERR_INVALID_ARG;
+}
+
+ov_status ov_ctx_create(const ov_params* p, void* hip_stream, ov_ctx** out) {
+  if (!out) return OV_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!p) {
+    g_err = "null params";
+    return OV_ERR_INVALID_ARG;
+  }
+  std::string err;
+  ov_status s = validate(p, err);
+  if (s != OV_OK) {
+    g_err = err;
+    return s;
+  }
+  ov_ctx* c = new ov_ctx();
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  if (zolotarev_coeffs(p->n_poles, p->lambda_min, p->lambda_max, c->a, c->b, &c->delta) != 0) {
+    g_err = "Zolotarev coefficients failed";
+    delete c;
+    return OV_ERR_INVALID_ARG;
+  }
+  free_spectrum(p, c->smin, c->smax);
+  if (c->smin < p->lambda_min * (1 - 1e-12) || c->smax > p->lambda_max * (1 + 1e-12)) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "free |H_W| in [%.6g, %.6g] not inside [%.6g, %.6g]", c->smin,
+                  c->smax, p->lambda_min, p->lambda_max);
+    g_err = buf;
+    delete c;
+    return OV_ERR_SPECTRUM;
+  }
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    g_err = "no HIP device";
+    delete c;
+    return OV_ERR_DEVICE;
+  }
+  *out = c;
+  return OV_OK;
+}
+
+ov_status ov_ctx_destroy(ov_ctx* c) {
+  if (!c) return OV_ERR_INVALID_ARG;
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->own_ws) (void)hipFree(c->own_ws);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
+  delete c;
+  return OV_OK;
+}
+
+size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
+  if (!c || nrhs < 1) return 0;
+  Engine E;
+  std::vector<ov_ctx*> v(nrhs, const_cast<ov_ctx*>(c));
+  E.ctxs = v;
+  E.nsys = nrhs;
+  E.sb.assign(nrhs, SysBuf{});
+  E.lead = v[0];
+  const bool mixed = c->p.precision == OV_MIXED;
+  const double tol64 = std::min(c->p.inner_tol, c->p.truth_tol);
+  const double tolR = mixed ? c->p.mixed_inner_tol : c->p.inner_tol;
+  int cap64 = capacity(c, tol64), capR = capacity(c, tolR);
+  E.pl.solve = true;
+  E.pl.mixed = mixed;
+  E.pl.cap64 = mixed ? cap64 : std::max(cap64, capR);
+  E.pl.capR = mixed ? capR : E.pl.cap64;
+  return E.layout(nullptr, 0, true);
+}
+
+ov_status ov_set_workspace(ov_ctx* c, void* ptr, size_t bytes) {
+  if (!c) return OV_ERR_INVALID_ARG;
+  if (ptr && ((uintptr_t)ptr & 255)) {
+    c->err = "workspace must be 256-byte aligned";
+    return OV_ERR_INVALID_ARG;
+  }
+  c->user_ws = ptr;
+  c->user_ws_bytes = ptr ? bytes : 0;
+  return OV_OK;
+}
+
+ov_status ov_get_coeffs(const ov_ctx* c, double* a, double* b, double* delta) {
+  if (!c || !a || !b) return OV_ERR_INVALID_ARG;
+  for (int k = 0; k < c->p.n_poles; ++k) {
+    a[k] = c->a[k];
+    b[k] = c->b[k];
+  }
+  if (delta) *delta = c->delta;
+  return OV_OK;
+}
+
+ov_status ov_set_launch(ov_ctx* c, int block, int spt) {
+  if (!c) return OV_ERR_INVALID_ARG;
+  if (block) {
+    if (block < 64 || block > 1024 || (block & 63)) return OV_ERR_INVALID_ARG;
+    c->block = block;
+  }
+  if (spt < 0 || spt > 64) return OV_ERR_INVALID_ARG;
+  if (spt) c->spt = spt;
+  return OV_OK;
+}
+
+ov_status ov_get_launch(const ov_ctx* c, int* block, int* spt) {
+  if (!c) return OV_ERR_INVALID_ARG;
+  if (block) *block = c->block;
+  if (spt) *spt = c->spt;
+  return OV_OK;
+}
+
+static ov_status apply_impl(ov_ctx* c, int op, void* out, const void* in, const void* phi,
+                            int nrhs, ov_stats* st) {
+  if (!c || !out || !in || nrhs < 1) return OV_ERR_INVALID_ARG;
+  if ((op == OV_OP_M || op == OV_OP_M_DAG || op == OV_OP_MDAGM) && !phi) {
+    c->err = "phi required for M, M^dag, MdagM";
+    return OV_ERR_INVALID_ARG;
+  }
+  const double t0 = now_s();
+  Engine E;
+  std::vector<ov_ctx*> v(nrhs, c);
+  TRY(engine_init(E, v, false, false, c->p.inner_tol, c->p.inner_tol));
+  TRY(reset_stats(E));
+  const int V = E.sb[0].V;
+  std::vector<const void*> src(nrhs), ph(nrhs, phi);
+  std::vector<void*> dst(nrhs), res(nrhs), outs(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    src[r] = (const char*)in + (size_t)r * V * 4 * sizeof(double2);
+    outs[r] = (char*)out + (size_t)r * V * 4 * sizeof(double2);
+    dst[r] = E.sb[r].x64;
+    res[r] = E.sb[r].r64;
+  }
+  TRY(run_apply(E, op));
+  TRY(set_phi(E, ph));
+  TRY(pack64(E, src, dst));
+  if (op == OV_OP_HW) {
+    // plain stencil: e_in = x64, e_out = r64
+    for (int s = 0; s < nrhs; ++s) {
+      E.htab[(size_t)T_APPLY * nrhs + s].e_in = E.sb[s].x64;
+      E.htab[(size_t)T_APPLY * nrhs + s].e_out = E.sb[s].r64;
+    }
+    TRY(upload_tables(E));
+  }
+  TRY(apply_sequence(E, op));
+  TRY(unpack64(E, res, outs));
+  TRY(sync(E));
+  std::vector<int> ctl;
+  std::vector<long long> st0;
+  std::vector<double> ds;
+  TRY(read_ctl(E, ctl, st0, ds));
+  ov_status rc = OV_OK;
+  for (int s = 0; s < nrhs; ++s) {
+    if (ctl[s] & (1 << 1)) rc = OV_ERR_BREAKDOWN;
+    else if ((ctl[s] & (1 << 2)) && rc == OV_OK) rc = OV_ERR_NOT_CONVERGED;
+  }
+  if (rc == OV_ERR_BREAKDOWN) c->err = "multi-shift breakdown (non-finite input?)";
+  if (rc == OV_ERR_NOT_CONVERGED) c->err = "multi-shift did not converge within its basis";
+  fill_stats(st, nrhs, &E, nullptr, now_s() - t0, 16);
+  return rc;
+}
+
+ov_status ov_sign(ov_ctx* c, void* out, const void* in, int nrhs, ov_stats* st) {
+  return apply_impl(c, -1, out, in, nullptr, nrhs, st);
+}
+
+ov_status ov_apply(ov_ctx* c, ov_op op, void* out, const void* in, const void* phi, int nrhs,
+                   ov_stats* st) {
+  if ((int)op < 0 || (int)op > OV_OP_MDAGM) return OV_ERR_INVALID_ARG;
+  return apply_impl(c, (int)op, out, in, phi, nrhs, st);
+}
+
+static bool same_solver(const ov_params& a, const ov_params& b) {
+  return a.n_poles == b.n_poles && a.lambda_min == b.lambda_min && a.lambda_max == b.lambda_max &&
+         a.inner_tol == b.inner_tol && a.outer_tol == b.outer_tol && a.truth_tol == b.truth_tol &&
+         a.mixed_inner_tol == b.mixed_inner_tol && a.reliable_delta == b.reliable_delta &&
+         a.precision == b.precision && a.M0 == b.M0;
+}
+
+static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,
+                               std::vector<void*>& xv, std::vector<const void*>& phv,
+                               ov_stats* st, Engine* keep = nullptr) {
+  ov_ctx* c = sysctx[0];
+  const double t0 = now_s();
+  const bool mixed = c->p.precision == OV_MIXED;
+  const double tolR = mixed ? c->p.mixed_inner_tol : c->p.inner_tol;
+  Engine Eloc;
+  Engine& E = keep ? *keep : Eloc;
+  TRY(engine_init(E, sysctx, true, mixed, std::min(c->p.inner_tol, c->p.truth_tol), tolR));
+  const int ns = E.nsys;
+  // pack the guesses into x64 (needs a geometry table)
+  E.htab.assign((size_t)T_NT * ns, SysDev{});
+  for (int s = 0; s < ns; ++s) E.htab[(size_t)T_APPLY * ns + s] = base_dev(E.sb[s]);
+  TRY(upload_tables(E));
+  std::vector<void*> x64(ns);
+  std::vector<const void*> xin(ns);
+  for (int s = 0; s < ns; ++s) {
+    x64[s] = E.sb[s].x64;
+    xin[s] = xv[s];
+  }
+  TRY(pack64(E, xin, x64));
+  SolveOut so;
+  const double delta = c->p.reliable_delta;
+  ov_status rc = mixed ? solve_engine<float>(E, bv, phv, tolR, delta, so)
+                       : solve_engine<double>(E, bv, phv, tolR, delta, so);
+  if (rc != OV_OK && rc != OV_ERR_NOT_CONVERGED) return rc;
+  std::vector<void*> x64v(ns);
+  for (int s = 0; s < ns; ++s) x64v[s] = E.sb[s].x64;
+  TRY(unpack64(E, x64v, xv));
+  TRY(sync(E));
+  fill_stats(st, ns, &E, &so, now_s() - t0, mixed ? 8 : 16);
+  for (int s = 0; s < ns; ++s)
+    if (!so.conv[s]) {
+      c->err = "outer CG did not reach outer_tol within max_outer";
+      return OV_ERR_NOT_CONVERGED;
+    }
+  return OV_OK;
+}
+
+ov_status ov_solve(ov_ctx* c, void* x, const void* b, const void* phi, int nrhs, ov_stats* st) {
+  if (!c || !x || !b || !phi || nrhs < 1) return OV_ERR_INVALID_ARG;
+  const size_t vb = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3] * 4 *
+                    sizeof(double2);
+  std::vector<ov_ctx*> sc(nrhs, c);
+  std::vector<const void*> bv(nrhs), ph(nrhs, phi);
+  std::vector<void*> xv(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    bv[r] = (const char*)b + r * vb;
+    xv[r] = (char*)x + r * vb;
+  }
+  return solve_systems(sc, bv, xv, ph, st);
+}
+
+ov_status ov_solve_batch(int n, ov_ctx* const* ctx, void* const* x, const void* const* b,
+                         const void* const* phi, const int* nrhs, ov_stats* st) {
+  if (n < 1 || !ctx || !x || !b || !phi || !nrhs) return OV_ERR_INVALID_ARG;
+  std::vector<ov_ctx*> sc;
+  std::vector<const void*> bv, ph;
+  std::vector<void*> xv;
+  for (int i = 0; i < n; ++i) {
+    if (!ctx[i] || !x[i] || !b[i] || !phi[i] || nrhs[i] < 1) return OV_ERR_INVALID_ARG;
+    if (!same_solver(ctx[i]->p, ctx[0]->p)) {
+      ctx[0]->err = "batched contexts must share poles, interval, tolerances and precision";
+      return OV_ERR_INVALID_ARG;
+    }
+    const size_t vb = (size_t)ctx[i]->p.dims[0] * ctx[i]->p.dims[1] * ctx[i]->p.dims[2] *
+                      ctx[i]->p.dims[3] * 4 * sizeof(double2);
+    for (int r = 0; r < nrhs[i]; ++r) {
+      sc.push_back(ctx[i]);
+      bv.push_back((const char*)b[i] + r * vb);
+      xv.push_back((char*)x[i] + r * vb);
+      ph.push_back(phi[i]);
+    }
+  }
+  return solve_systems(sc, bv, xv, ph, st);
+}
+
+ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, const void* phi,
+                   int nrhs, ov_stats* st) {
+  if (!c || !grad_phi || !S_host || !xi || !phi || nrhs < 1) return OV_ERR_INVALID_ARG;
+  const double t0 = now_s();
+  const size_t V = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3];
+  const size_t vb = V * 4 * sizeof(double2);
+  std::vector<ov_ctx*> sc(nrhs, c);
+  std::vector<const void*> bv(nrhs), ph(nrhs, phi);
+  std::vector<void*> xv(nrhs);
+  // X = (MdagM)^-1 xi, cold start, kept in the engine's x64 buffers
+  Engine E;
+  TRY(engine_init(E, sc, true, c->p.precision == OV_MIXED,
+                  std::min(c->p.inner_tol, c->p.truth_tol),
+                  c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol));
+  // zero guess directly in x64
+  for (int r = 0; r < nrhs; ++r) {
+    bv[r] = (const char*)xi + r * vb;
+    HIPCHK(c, hipMemsetAsync(E.sb[r].x64, 0, vb, c->stream));
+  }
+  SolveOut so;
+  const double tolR = c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol;
+  ov_status rc = c->p.precision == OV_MIXED
+                     ? solve_engine<float>(E, bv, ph, tolR, c->p.reliable_delta, so)
+                     : solve_engine<double>(E, bv, ph, tolR, c->p.reliable_delta, so);
+  if (rc != OV_OK) return rc;
+  for (int r = 0; r < nrhs; ++r)
+    if (!so.conv[r]) {
+      c->err = "force solve did not converge";
+      return OV_ERR_NOT_CONVERGED;
+    }
+  // Y = M X (FP64, recomputed: no shifted vector was kept)
+  E.htab.assign((size_t)T_NT * nrhs, SysDev{});
+  for (int s = 0; s < nrhs; ++s) {
+    SysBuf& b = E.sb[s];
+    SysDev d = base_dev(b);
+    d.phi = (const double2*)phi;
+    d.basis = b.basis64;
+    d.r = b.r64ms;
+    d.src = b.x64;
+    d.e_in = b.x64;
+    d.e_out = b.u64;
+    d.cg_b = (const double2*)bv[s];
+    E.htab[(size_t)T_APPLY * nrhs + s] = d;
+  }
+  TRY(upload_tables(E));
+  MsParams mp = make_mp(c, c->p.truth_tol, E.pl.cap64);
+  const int L = std::min(E.pl.cap64, capacity(c, c->p.truth_tol));
+  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total, 0);
+  launch_ms<double>(E, T_APPLY, mp, L);
+  launch_combine<double>(E, T_APPLY, EPI_M);
+  // S_r = Re <xi_r, X_r>
+  k_dot_re<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total);
+  // G summed over right-hand sides in order (one launch over the sites)
+  k_force<<<E.sb[0].nblk, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.sb[0].nblk,
+                                               (double2*)grad_phi);
+  TRY(sync(E));
+  for (int s = 0; s < nrhs; ++s) {
+    std::vector<double> tmp(E.sb[s].nblk);
+    HIPCHK(c, hipMemcpy(tmp.data(), E.sb[s].part_c, sizeof(double) * tmp.size(),
+                        hipMemcpyDeviceToHost));
+    double acc = 0;
+    for (double v : tmp) acc += v;
+    S_host[s] = acc;
+  }
+  fill_stats(st, nrhs, &E, &so, now_s() - t0, c->p.precision == OV_MIXED ? 8 : 16);
+  return OV_OK;
+}
+
+ov_status ov_pack(ov_ctx* c, int prec, void* dst, const void* src, int nrhs) {
+  if (!c || !dst || !src || nrhs < 1 || (prec != 0 && prec != 1)) return OV_ERR_INVALID_ARG;
+  Engine E;
+  std::vector<ov_ctx*> v(nrhs, c);
+  TRY(engine_init(E, v, false, false, c->p.inner_tol, c->p.inner_tol));
+  E.htab.assign((size_t)T_NT * nrhs, SysDev{});
+  for (int s = 0; s < nrhs; ++s) E.htab[(size_t)T_APPLY * nrhs + s] = base_dev(E.sb[s]);
+  TRY(upload_tables(E));
+  const size_t V = E.sb[0].V;
+  std::vector<void*>& h = E.hptrs;
+  h.assign(2 * nrhs, nullptr);
+  for (int r = 0; r < nrhs; ++r) {
+    h[r] = (char*)src + r * V * 4 * sizeof(double2);
+    h[nrhs + r] = (char*)dst + r * V * 4 * (prec ? sizeof(float2) : sizeof(double2));
+  }
+  HIPCHK(c, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, E.st));
+  if (prec)
+    k_pack<float><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total,
+                                                     (const double2* const*)E.ptrs, E.ptrs + nrhs, 1.0);
+  else
+    k_pack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total,
+                                                      (const double2* const*)E.ptrs, E.ptrs + nrhs, 1.0);
+  return sync(E);
+}
+
+ov_status ov_unpack(ov_ctx* c, int prec, void* dst, const void* src, int nrhs) {
+  if (!c || !dst || !src || nrhs < 1 || (prec != 0 && prec != 1)) return OV_ERR_INVALID_ARG;
+  Engine E;
+  std::vector<ov_ctx*> v(nrhs, c);
+  TRY(engine_init(E, v, false, false, c->p.inner_tol, c->p.inner_tol));
+  E.htab.assign((size_t)T_NT * nrhs, SysDev{});
+  for (int s = 0; s < nrhs; ++s) E.htab[(size_t)T_APPLY * nrhs + s] = base_dev(E.sb[s]);
+  TRY(upload_tables(E));
+  const size_t V = E.sb[0].V;
+  std::vector<void*>& h = E.hptrs;
+  h.assign(2 * nrhs, nullptr);
+  for (int r = 0; r < nrhs; ++r) {
+    h[r] = (char*)src + r * V * 4 * (prec ? sizeof(float2) : sizeof(double2));
+    h[nrhs + r] = (char*)dst + r * V * 4 * sizeof(double2);
+  }
+  HIPCHK(c, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, E.st));
+  if (prec)
+    k_unpack<float><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total, E.ptrs,
+                                                       (double2* const*)(E.ptrs + nrhs));
+  else
+    k_unpack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total, E.ptrs,
+                                                        (double2* const*)(E.ptrs + nrhs));
+  return sync(E);
+}
+
+ov_status ov_kernel_sampling(ov_ctx* c, int max_per_call) {
+  if (!c || max_per_call < 0) return OV_ERR_INVALID_ARG;
+  c->sample_max = max_per_call;
+  return OV_OK;
+}
+
+ov_status ov_kernel_times(ov_ctx* c, int k, double* total_ms, long long* count, double* bytes,
+                          int reset) {
+  if (!c || k < 0 || k > 1) return OV_ERR_INVALID_ARG;
+  if (total_ms) *total_ms = c->ksum_ms[k];
+  if (count) *count = c->kcount[k];
+  if (bytes) *bytes = c->ksum_bytes[k];
+  if (reset) {
+    c->ksum_ms[k] = 0;
+    c->ksum_bytes[k] = 0;
+    c->kcount[k] = 0;
+  }
+  return OV_OK;
+}
+
+ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int nrhs, int reps,
+                           float* ms_per_launch) {
+  if (!c || !out || !in || nrhs < 1 || reps < 1 || (prec != 0 && prec != 1))
+    return OV_ERR_INVALID_ARG;
+  Engine E;
+  std::vector<ov_ctx*> v(nrhs, c);
+  // only tables / partials are needed: a tiny plan
+  E.ctxs = v;
+  E.nsys = nrhs;
+  E.sb.assign(nrhs, SysBuf{});
+  E.lead = c;
+  E.st = c->stream;
+  E.pl.cap64 = 1;
+  E.pl.capR = 0;
+  E.pl.solve = false;
+  // carve without the big vectors: use a dedicated small layout
+  {
+    Bump dry(nullptr, 0, true);
+    int blk = 0;
+    for (int s = 0; s < nrhs; ++s) {
+      SysBuf& b = E.sb[s];
+      b.ctx = c;
+      b.V = c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3];
+      b.spb = sites_per_block(c, b.V);
+      b.nblk = (b.V + b.spb - 1) / b.spb;
+      b.blk0 = blk;
+      blk += b.nblk;
+      b.part_c = (double*)dry.take(sizeof(double) * b.nblk);
+    }
+    E.nb_total = blk;
+    dry.take(sizeof(SysDev) * nrhs);
+    void* base = nullptr;
+    TRY(ensure_ws(c, dry.off + 512, &base));
+    Bump bp(base, dry.off + 512, false);
+    for (int s = 0; s < nrhs; ++s) E.sb[s].part_c = (double*)bp.take(sizeof(double) * E.sb[s].nblk);
+    E.tables = (SysDev*)bp.take(sizeof(SysDev) * nrhs);
+  }
+  const size_t V = E.sb[0].V;
+  const size_t es = prec ? sizeof(float2) : sizeof(double2);
+  E.htab.assign(nrhs, SysDev{});
+  for (int s = 0; s < nrhs; ++s) {
+    SysDev d = base_dev(E.sb[s]);
+    d.e_in = (const char*)in + s * V * 4 * es;
+    d.e_out = (char*)out + s * V * 4 * es;
+    E.htab[s] = d;
+  }
+  HIPCHK(c, hipMemcpyAsync(E.tables, E.htab.data(), sizeof(SysDev) * nrhs, hipMemcpyHostToDevice,
+                           E.st));
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  const double diag = 4.0 - c->p.M0;
+  HIPCHK(c, hipEventRecord(e0, E.st));
+  for (int r = 0; r < reps; ++r) {
+    if (prec)
+      k_hw<float><<<E.nb_total, c->block, 0, E.st>>>(E.tables, nrhs, E.nb_total, diag, 0);
+    else
+      k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(E.tables, nrhs, E.nb_total, diag, 0);
+  }
+  HIPCHK(c, hipEventRecord(e1, E.st));
+  TRY(check_launch(c));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ms_per_launch) *ms_per_launch = ms / reps;
+  return OV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+"""Python front end: one lattice + action + solver setting on one HIP stream.
+
+``Lattice`` wraps an ``ov_ctx``.  Fields are torch complex128 CUDA tensors of
+shape ``(nrhs, T, Z, Y, X, 4)`` (or ``(T, Z, Y, X, 4)`` for one field); phi is
+complex128 ``(T, Z, Y, X)``.  torch only provides device memory and the
+stream; every operation is one call into libov.so.
+"""
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    def __init__(self, dims, **params):
+        self.params = L.default_params(dims=dims, **params)
+        self.dims = tuple(dims)
+        X, Y, Z, T = self.dims
+        self.V = X * Y * Z * T
+        self.field_shape = (T, Z, Y, X, 4)
+        self.phi_shape = (T, Z, Y, X)
+        h = C.c_void_p()
+        L.check(L.lib().ov_ctx_create(C.byref(self.params), _stream_ptr(), C.byref(h)))
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ov_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, status):
+        L.check(status, self._h)
+
+    def _fields(self, x):
+        if x.dtype != torch.complex128 or not x.is_cuda:
+            raise TypeError("fields must be complex128 CUDA tensors")
+        x = x.contiguous()
+        if x.shape[-5:] != self.field_shape:
+            raise ValueError(f"field shape {tuple(x.shape)} does not end in {self.field_shape}")
+        nrhs = 1 if x.dim() == 5 else int(torch.tensor(x.shape[:-5]).prod())
+        return x, nrhs
+
+    def _phi(self, phi):
+        if phi is None:
+            return None
+        if phi.dtype != torch.complex128 or not phi.is_cuda or tuple(phi.shape) != self.phi_shape:
+            raise TypeError(f"phi must be complex128 CUDA {self.phi_shape}")
+        return phi.contiguous()
+
+    def use_workspace(self, nrhs):
+        """Allocate a caller-owned (torch) workspace for nrhs right-hand sides."""
+        nbytes = L.lib().ov_workspace_bytes(self._h, nrhs)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(L.lib().ov_set_workspace(self._h, C.c_void_p(aligned), nbytes))
+        return nbytes
+
+    def coeffs(self):
+        import numpy as np
+        n = self.params.n_poles
+        a = np.zeros(n)
+        b = np.zeros(n)
+        d = C.c_double()
+        self._check(L.lib().ov_get_coeffs(self._h, a.ctypes.data_as(C.c_void_p),
+                                          b.ctypes.data_as(C.c_void_p), C.byref(d)))
+        return a, b, d.value
+
+    def kernel_sampling(self, max_per_call):
+        self._check(L.lib().ov_kernel_sampling(self._h, max_per_call))
+
+    def kernel_times(self, kernel, reset=True):
+        """(total_ms, count, bytes) of the sampled multi-shift kernel (0 t pass, 1 r pass)."""
+        ms = C.c_double()
+        cnt = C.c_longlong()
+        by = C.c_double()
+        self._check(L.lib().ov_kernel_times(self._h, kernel, C.byref(ms), C.byref(cnt),
+                                            C.byref(by), 1 if reset else 0))
+        return ms.value, cnt.value, by.value
+
+    def set_launch(self, block=0, sites_per_thread=0):
+        self._check(L.lib().ov_set_launch(self._h, block, sites_per_thread))
+
+    # --------------------------------------------------------- operations
+    def sign(self, x):
+        x, nrhs = self._fields(x)
+        out = torch.empty_like(x)
+        st = (L.OvStats * nrhs)()
+        self._check(L.lib().ov_sign(self._h, _ptr(out), _ptr(x), nrhs, st))
+        return out, [s.as_dict() for s in st]
+
+    def apply(self, op, x, phi=None):
+        x, nrhs = self._fields(x)
+        phi = self._phi(phi)
+        out = torch.empty_like(x)
+        st = (L.OvStats * nrhs)()
+        code = L.OPS[op] if isinstance(op, str) else int(op)
+        self._check(L.lib().ov_apply(self._h, code, _ptr(out), _ptr(x),
+                                     _ptr(phi) if phi is not None else None, nrhs, st))
+        return out, [s.as_dict() for s in st]
+
+    def solve(self, b, phi, x0=None):
+        b, nrhs = self._fields(b)
+        phi = self._phi(phi)
+        x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
+        st = (L.OvStats * nrhs)()
+        status = L.lib().ov_solve(self._h, _ptr(x), _ptr(b), _ptr(phi), nrhs, st)
+        stats = [s.as_dict() for s in st]
+        if status == L.OV_ERR_NOT_CONVERGED:
+            raise L.OvError(status, f"not converged: {stats}")
+        self._check(status)
+        return x, stats
+
+    def force(self, xi, phi):
+        xi, nrhs = self._fields(xi)
+        phi = self._phi(phi)
+        G = torch.empty(self.phi_shape, dtype=torch.complex128, device=xi.device)
+        S = (C.c_double * nrhs)()
+        st = (L.OvStats * nrhs)()
+        self._check(L.lib().ov_force(self._h, _ptr(G), S, _ptr(xi), _ptr(phi), nrhs, st))
+        return [S[i] for i in range(nrhs)], G, [s.as_dict() for s in st]
+
+    def stencil_bench(self, x_planar, prec, reps=10):
+        """out = H_W x on a spin-planar field (complex64/complex128 (nrhs, 4, V))."""
+        nrhs = x_planar.shape[0]
+        out = torch.empty_like(x_planar)
+        ms = C.c_float()
+        self._check(L.lib().ov_stencil_bench(self._h, prec, _ptr(out), _ptr(x_planar), nrhs,
+                                             reps, C.byref(ms)))
+        return out, ms.value
+
+    def pack(self, x, prec):
+        x, nrhs = self._fields(x)
+        dt = torch.complex64 if prec else torch.complex128
+        out = torch.empty((nrhs, 4, self.V), dtype=dt, device=x.device)
+        self._check(L.lib().ov_pack(self._h, prec, _ptr(out), _ptr(x), nrhs))
+        return out
+
+    def unpack(self, xp, prec):
+        nrhs = xp.shape[0]
+        out = torch.empty((nrhs,) + self.field_shape, dtype=torch.complex128, device=xp.device)
+        self._check(L.lib().ov_unpack(self._h, prec, _ptr(out), _ptr(xp.contiguous()), nrhs))
+        return out
+
+
+def solve_batch(lattices, bs, phis):
+    """Solve every (lattice, b, phi) in one batched launch sequence."""
+    n = len(lattices)
+    ctx = (C.c_void_p * n)(*[l._h.value for l in lattices])
+    bl, xl, pl, nr = [], [], [], []
+    xs = []
+    for lat, b, phi in zip(lattices, bs, phis):
+        b, nrhs = lat._fields(b)
+        x = torch.zeros_like(b)
+        xs.append(x)
+        bl.append(b.data_ptr())
+        xl.append(x.data_ptr())
+        pl.append(lat._phi(phi).data_ptr())
+        nr.append(nrhs)
+    tot = sum(nr)
+    st = (L.OvStats * tot)()
+    status = L.lib().ov_solve_batch(n, ctx, (C.c_void_p * n)(*xl), (C.c_void_p * n)(*bl),
+                                    (C.c_void_p * n)(*pl), (C.c_int * n)(*nr), st)
+    if status == L.OV_ERR_NOT_CONVERGED:
+        raise L.OvError(status, f"not converged: {[s.as_dict() for s in st]}")
+    L.check(status, lattices[0]._h)
+    return xs, [s.as_dict() for s in st]

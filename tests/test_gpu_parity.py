@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP64 path):
+  * H_W stencil: relative 1e-14 (same arithmetic, different summation order);
+  * sign / D_ov / M applications with both sides at multi-shift tolerance
+    tau = 1e-12: relative 1e-11 (each side is within ~tau of the exact rational);
+  * solves: the true relative residual of the GPU solution under the oracle's
+    own operator (inner tolerance 1e-13) <= 1e-10, the metric's target;
+  * force: S relative 1e-9, G max error 1e-8 * max|G| (both solve to 1e-10..1e-12).
+FP32 stencil: relative 2e-6 (24-bit mantissa, 9-point sum).
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_1005_3276_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible HIP device")
+    from paper_1005_3276_amd import _lib
+    _lib.lib()  # raises if libov.so is missing: no fallback path exists
+    print(f"[gpu] {torch.cuda.get_device_name(0)}", flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def lattice(dims, **kw):
+    from paper_1005_3276_amd import Lattice
+    return Lattice(dims, **kw)
+
+
+CFG1 = dict(m=0.05, g=0.1, n_poles=16, lambda_min=0.01, lambda_max=8.0)
+CFG2 = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+
+
+# ------------------------------------------------------------- pack / stencil
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 4, 6, 8)])
+def test_pack_roundtrip_bitexact(dims):
+    lat = lattice(dims)
+    x = inputs.gaussian_field(dims, nrhs=2, seed=1)
+    xd = dev(x)
+    p64 = lat.pack(xd, 0)
+    assert np.array_equal(host(lat.unpack(p64, 0)), x)
+    p32 = lat.pack(xd, 1)
+    back = host(lat.unpack(p32, 1))
+    assert np.array_equal(back, x.astype(np.complex64).astype(np.complex128))
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), -1), ((2, 4, 6, 8), -1), ((6, 4, 2, 10), 1),
+                                     ((8, 8, 8, 8), -1), ((16, 8, 8, 16), -1)])
+def test_hw_fp64_vs_oracle(orc, dims, bc):
+    print(f"[hw] dims={dims} bc={bc}", flush=True)
+    x = inputs.gaussian_field(dims, nrhs=1, seed=2)[0]
+    o = orc.Oracle(dims, bc_t=bc)
+    lat = lattice(dims, bc_t=bc)
+    out, _ = lat.apply("hw", dev(x))
+    assert rel(host(out), o.hw(x)) < 1e-14
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 8, 8, 8), (2, 4, 6, 8)])
+def test_hw_fp32_stencil_vs_oracle(orc, dims):
+    x = inputs.gaussian_field(dims, nrhs=3, seed=3)
+    o = orc.Oracle(dims)
+    lat = lattice(dims)
+    xp = lat.pack(dev(x), 1)
+    outp, ms = lat.stencil_bench(xp, 1, reps=2)
+    out = host(lat.unpack(outp, 1))
+    for r in range(3):
+        assert rel(out[r], o.hw(x[r])) < 2e-6
+    xp64 = lat.pack(dev(x), 0)
+    outp64, _ = lat.stencil_bench(xp64, 0, reps=2)
+    out64 = host(lat.unpack(outp64, 0))
+    for r in range(3):
+        assert rel(out64[r], o.hw(x[r])) < 1e-14
+
+
+# -------------------------------------------------------------- sign / apply
+
+@pytest.mark.parametrize("dims,cfg", [((4, 4, 4, 4), CFG1), ((8, 8, 8, 8), CFG2),
+                                      ((2, 4, 6, 8), CFG2)])
+def test_sign_vs_oracle(orc, dims, cfg):
+    print(f"[sign] dims={dims}", flush=True)
+    tol = 1e-12
+    x = inputs.gaussian_field(dims, nrhs=2, seed=4)
+    o = orc.Oracle(dims, inner_tol=tol, **cfg)
+    lat = lattice(dims, inner_tol=tol, **cfg)
+    out, st = lat.sign(dev(x))
+    out = host(out)
+    for r in range(2):
+        ref, ost = o.sign(x[r])
+        assert rel(out[r], ref) < 1e-11
+        assert abs(st[r]["inner_iters"] - ost.iters) <= 2
+        assert st[r]["max_shift_res"] <= tol
+
+
+def test_sign_config1_vs_exact_rational(orc):
+    """Config 1: 4^4, 16 poles on [0.01, 8]; GPU eps vs the oracle and the sign^2 = 1 check."""
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(1))
+    lat = lattice(dims, inner_tol=1e-12, **CFG1)
+    a, b, delta = lat.coeffs()
+    e1, _ = lat.sign(dev(src))
+    e2, _ = lat.sign(e1)
+    assert rel(host(e2), src) < 3 * delta + 1e-11
+
+
+@pytest.mark.parametrize("op", ["dov", "dov_dag", "m", "m_dag", "mdagm"])
+def test_apply_ops_vs_oracle(orc, op):
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(1))
+    o = orc.Oracle(dims, inner_tol=1e-12, **CFG1)
+    lat = lattice(dims, inner_tol=1e-12, **CFG1)
+    out, _ = lat.apply(op, dev(src), dev(phi))
+    out = host(out)
+    code = {"dov": orc.OP_DOV, "dov_dag": orc.OP_DOV_DAG, "m": orc.OP_M, "m_dag": orc.OP_M_DAG,
+            "mdagm": orc.OP_MDAGM}[op]
+    for r in range(2):
+        assert rel(out[r], o.apply(code, src[r], phi)) < 1e-11
+
+
+def test_zero_source_gives_zero():
+    dims = (4, 4, 4, 4)
+    lat = lattice(dims, **CFG1)
+    z = torch.zeros((1,) + lat.field_shape, dtype=torch.complex128, device="cuda")
+    out, st = lat.sign(z)
+    assert torch.count_nonzero(out).item() == 0
+    assert st[0]["inner_iters"] == 0
+
+
+# ------------------------------------------------------------------- solves
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 4, 6, 8)])
+def test_solve_residual_under_oracle(orc, dims, prec):
+    print(f"[solve] dims={dims} prec={prec}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    lat = lattice(dims, precision=prec, outer_tol=1e-10, inner_tol=1e-8, **CFG2)
+    x, st = lat.solve(dev(src), dev(phi))
+    x = host(x)[0]
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    res = o.residual(src[0], x, phi)
+    print(f"[solve] oracle residual {res:.3e} stats {st[0]}", flush=True)
+    assert res <= 1e-10
+    assert st[0]["true_rel_res"] <= 1e-10
+    xo, ost, rc = o.solve(src[0], phi, tol=1e-11)
+    assert rel(x, xo) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_8x4_config2(orc, prec):
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    lat = lattice(dims, precision=prec, outer_tol=1e-10, inner_tol=1e-8, **CFG2)
+    t = time.time()
+    x, st = lat.solve(dev(src), dev(phi))
+    el = time.time() - t
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    res = o.residual(src[0], host(x)[0], phi)
+    print(f"[solve8] {prec} {el:.3f}s oracle residual {res:.3e} {st[0]}", flush=True)
+    assert res <= 1e-10
+
+
+def test_batched_equals_unbatched(orc):
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=3, sigma2=0.5, seed=inputs.config_seed(3))
+    kw = dict(precision="mixed", outer_tol=1e-10, m=0.02, g=0.5, n_poles=20,
+              lambda_min=1e-3, lambda_max=8.0)
+    lat = lattice(dims, **kw)
+    xb, stb = lat.solve(dev(src), dev(phi))
+    xb = host(xb)
+    o = orc.Oracle(dims, inner_tol=1e-13, m=0.02, g=0.5, n_poles=20, lambda_min=1e-3,
+                   lambda_max=8.0)
+    for r in range(3):
+        xs, _ = lat.solve(dev(src[r:r + 1]), dev(phi))
+        assert rel(xb[r], host(xs)[0]) < 1e-8
+        assert o.residual(src[r], xb[r], phi) <= 1e-10
+
+
+def test_uneven_batch(orc):
+    from paper_1005_3276_amd import solve_batch
+    kw = dict(precision="mixed", outer_tol=1e-10, m=0.05, g=0.3, n_poles=24,
+              lambda_min=1e-4, lambda_max=8.0)
+    members = [((4, 4, 4, 4), 2), ((2, 4, 6, 8), 1), ((6, 6, 6, 6), 1)]
+    lats, bs, phis, raw = [], [], [], []
+    for k, (dims, nrhs) in enumerate(members):
+        phi, src = inputs.draw(dims, nrhs=nrhs, sigma2=0.25, seed=inputs.config_seed(5) + k)
+        lats.append(lattice(dims, **kw))
+        bs.append(dev(src))
+        phis.append(dev(phi))
+        raw.append((dims, phi, src))
+    xs, st = solve_batch(lats, bs, phis)
+    for (dims, phi, src), x in zip(raw, xs):
+        o = orc.Oracle(dims, inner_tol=1e-13, m=0.05, g=0.3, n_poles=24, lambda_min=1e-4,
+                       lambda_max=8.0)
+        xh = host(x)
+        for r in range(src.shape[0]):
+            assert o.residual(src[r], xh[r], phi) <= 1e-10
+
+
+# -------------------------------------------------------------------- force
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_force_vs_oracle(orc, prec):
+    dims = (4, 4, 4, 4)
+    phi, xi = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(4))
+    kw = dict(m=0.05, g=0.3, n_poles=16, lambda_min=0.01, lambda_max=8.0)
+    lat = lattice(dims, precision=prec, outer_tol=1e-12, truth_tol=1e-13, **kw)
+    S, G, st = lat.force(dev(xi), dev(phi))
+    G = host(G)
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    Gref = np.zeros_like(G)
+    for r in range(2):
+        So, Go, ost, rc = o.force(phi, xi[r], tol=1e-12)
+        assert abs(S[r] - So) <= 1e-9 * abs(So)
+        Gref += Go
+    assert np.abs(G - Gref).max() <= 1e-8 * np.abs(Gref).max()
+
+
+def test_force_autograd_backward(orc):
+    from paper_1005_3276_amd import OvForce
+    dims = (4, 4, 4, 4)
+    phi, xi = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=77)
+    kw = dict(m=0.05, g=0.3, n_poles=16, lambda_min=0.01, lambda_max=8.0)
+    lat = lattice(dims, precision="fp64", outer_tol=1e-12, **kw)
+    ph = dev(phi).requires_grad_(True)
+    S = OvForce.apply(lat, ph, dev(xi))
+    (2.5 * S).backward()
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    So, Go, _, _ = o.force(phi, xi[0], tol=1e-12)
+    assert abs(S.item() - So) <= 1e-9 * abs(So)
+    g = host(ph.grad)
+    assert np.abs(g - 2.5 * Go).max() <= 1e-8 * np.abs(2.5 * Go).max()
+
+
+def test_force_g0_is_zero():
+    dims = (4, 4, 4, 4)
+    phi, xi = inputs.draw(dims, nrhs=1, seed=5)
+    lat = lattice(dims, m=0.05, g=0.0, n_poles=16, lambda_min=0.01, lambda_max=8.0)
+    S, G, _ = lat.force(dev(xi), dev(phi))
+    assert torch.count_nonzero(G).item() == 0
+
+
+# ------------------------------------------------------------- error paths
+
+def test_nan_input_breakdown():
+    from paper_1005_3276_amd import _lib as L
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=1, seed=6)
+    src[0, 0, 0, 0, 0, 0] = np.nan
+    lat = lattice(dims, **CFG2)
+    with pytest.raises(L.OvError) as e:
+        lat.solve(dev(src), dev(phi))
+    assert e.value.status == L.OV_ERR_BREAKDOWN
+
+
+def test_max_outer_not_converged():
+    from paper_1005_3276_amd import _lib as L
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=1, seed=7)
+    lat = lattice(dims, max_outer=2, **CFG2)
+    with pytest.raises(L.OvError) as e:
+        lat.solve(dev(src), dev(phi))
+    assert e.value.status == L.OV_ERR_NOT_CONVERGED
+
+
+# ---------------------------------------------------------- full-size case
+
+def test_full_size_16x4_mixed(orc):
+    """Config 2 at full size (16^4) in the benchmark's launch configuration: the
+    GPU mixed solve meets the 1e-10 true residual under the oracle's operator."""
+    dims = (16, 16, 16, 16)
+    print("[full] 16^4 mixed solve", flush=True)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    lat = lattice(dims, precision="mixed", outer_tol=1e-10, **CFG2)
+    t = time.time()
+    x, st = lat.solve(dev(src), dev(phi))
+    torch.cuda.synchronize()
+    print(f"[full] GPU {time.time() - t:.2f}s {st[0]}", flush=True)
+    o = orc.Oracle(dims, inner_tol=1e-12, **CFG2)
+    t = time.time()
+    res = o.residual(src[0], host(x)[0], phi)
+    print(f"[full] oracle residual {res:.3e} ({time.time() - t:.1f}s)", flush=True)
+    assert res <= 1e-10

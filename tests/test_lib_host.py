@@ -1,0 +1,75 @@
+"""Host-side checks of libov.so that need no GPU: it loads, exports every
+symbol include/ov.h declares, and its host logic (parameter validation, the
+spectrum check, the Zolotarev generator) agrees with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1005_3276_amd import _lib as L
+    if not os.path.exists(L.SO):
+        pytest.skip("libov.so not built")
+    return L
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    hdr = open(os.path.join(ROOT, "include", "ov.h")).read()
+    declared = set(re.findall(r"\b(ov_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations parsed"
+    lib = L.lib()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(L.SYMBOLS)
+
+
+@pytest.mark.parametrize("n,lmin,lmax", [(16, 0.01, 8.0), (20, 1e-3, 8.0), (24, 1e-4, 8.0),
+                                         (8, 1.0, 7.0), (1, 0.5, 2.0)])
+def test_library_zolotarev_matches_oracle(orc, n, lmin, lmax):
+    L = _lib()
+    a, b, d = L.zolotarev(n, lmin, lmax)
+    a2, b2, d2, _ = orc.zolotarev(n, lmin, lmax)
+    assert np.max(np.abs(a / a2 - 1)) < 1e-12
+    assert np.max(np.abs(b / b2 - 1)) < 1e-12
+    assert abs(d - d2) < 1e-14 + 1e-6 * d2
+
+
+def _create(**kw):
+    L = _lib()
+    p = L.default_params(**kw)
+    h = C.c_void_p()
+    st = L.lib().ov_ctx_create(C.byref(p), None, C.byref(h))
+    if st == L.OV_OK:
+        L.lib().ov_ctx_destroy(h)
+    return st
+
+
+def test_ctx_create_rejects_bad_params():
+    L = _lib()
+    assert _create(dims=(3, 4, 4, 4)) == L.OV_ERR_INVALID_ARG      # odd extent
+    assert _create(dims=(4, 4, 4, 0)) == L.OV_ERR_INVALID_ARG      # empty lattice
+    assert _create(n_poles=0) == L.OV_ERR_INVALID_ARG
+    assert _create(n_poles=33) == L.OV_ERR_INVALID_ARG
+    assert _create(lambda_min=2.0, lambda_max=1.0) == L.OV_ERR_INVALID_ARG
+    assert _create(bc_t=0) == L.OV_ERR_INVALID_ARG
+    assert _create(outer_tol=-1.0) == L.OV_ERR_INVALID_ARG
+    # free |H_W| in [1, 7): an interval that misses it is a spectrum error
+    assert _create(lambda_min=1.5, lambda_max=8.0) == L.OV_ERR_SPECTRUM
+    assert _create(lambda_min=0.01, lambda_max=5.0) == L.OV_ERR_SPECTRUM
+
+
+def test_null_arguments():
+    L = _lib()
+    lib = L.lib()
+    assert lib.ov_ctx_create(None, None, None) == L.OV_ERR_INVALID_ARG
+    assert lib.ov_sign(None, None, None, 1, None) == L.OV_ERR_INVALID_ARG
+    assert lib.ov_solve(None, None, None, None, 1, None) == L.OV_ERR_INVALID_ARG
+    assert lib.ov_force(None, None, None, None, None, 1, None) == L.OV_ERR_INVALID_ARG
+    assert lib.ov_zolotarev(0, 0.1, 1.0, None, None, None) == L.OV_ERR_INVALID_ARG
+    assert lib.ov_status_string(L.OV_ERR_SPECTRUM).decode().startswith("spectrum")
