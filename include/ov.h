@@ -175,10 +175,12 @@ ov_status ov_get_launch(const ov_ctx *ctx, int *block, int *sites_per_thread);
 /* Kernel-duration sampling with HIP events recorded on the context's stream.
  * While max_per_call > 0, the first max_per_call launches of each multi-shift
  * kernel (0 = t pass  t_n = H r_n + beta t_{n-1},  1 = r pass  r_{n+1} = r_n -
- * alpha H t_n) in every sign/apply/solve/force call are bracketed by events.
- * ov_kernel_times returns, per kernel, the summed duration (ms), the number of
- * sampled launches and their summed algorithmic HBM bytes (3 spinor fields per
- * site and launch: two read, one written).  reset != 0 clears the sums. */
+ * alpha H t_n, 2 = the persistent kernel running every iteration of one
+ * multi-shift solve) in every sign/apply/solve/force call are bracketed by
+ * events.  ov_kernel_times returns, per kernel, the summed duration (ms), the
+ * number of sampled launches and their summed algorithmic HBM bytes (3 spinor
+ * fields per site and pass: two read, one written; two passes per iteration).
+ * reset != 0 clears the sums. */
 ov_status ov_kernel_sampling(ov_ctx *ctx, int max_per_call);
 ov_status ov_kernel_times(ov_ctx *ctx, int kernel, double *total_ms, long long *count,
                           double *bytes, int reset);

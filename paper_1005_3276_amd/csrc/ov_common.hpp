@@ -49,10 +49,17 @@ __device__ __forceinline__ void store_sp(c2<R>* __restrict__ f, int V, int i, co
   for (int s = 0; s < 4; ++s) f[(size_t)s * V + i] = v[s];
 }
 
+// The nine spinors the stencil reads at site i, loaded in one batch so that
+// all 36 loads are in flight together (the caller may overlap other work
+// before consuming them).  Time-boundary phases are applied at load time.
 template <class R>
-__device__ __forceinline__ void hw_site(const c2<R>* __restrict__ f, const Geo& g, int i,
-                                        R diag, c2<R> out[4]) {
-  using C = c2<R>;
+struct Nbr {
+  c2<R> c[4], xf[4], xb[4], yf[4], yb[4], zf[4], zb[4], tf[4], tb[4];
+};
+
+template <class R>
+__device__ __forceinline__ void load_nbr(const c2<R>* __restrict__ f, const Geo& g, int i,
+                                         Nbr<R>& nb) {
   const int X = g.X, Y = g.Y, Z = g.Z, T = g.T, V = g.V;
   int r = i;
   const int x = r % X; r /= X;
@@ -60,60 +67,60 @@ __device__ __forceinline__ void hw_site(const c2<R>* __restrict__ f, const Geo& 
   const int z = r % Z;
   const int t = r / Z;
   const int XY = X * Y, XYZ = XY * Z;
+  load_sp<R>(f, V, i, nb.c);
+  load_sp<R>(f, V, (x + 1 < X) ? i + 1 : i + 1 - X, nb.xf);
+  load_sp<R>(f, V, (x > 0) ? i - 1 : i - 1 + X, nb.xb);
+  load_sp<R>(f, V, (y + 1 < Y) ? i + X : i + X - XY, nb.yf);
+  load_sp<R>(f, V, (y > 0) ? i - X : i - X + XY, nb.yb);
+  load_sp<R>(f, V, (z + 1 < Z) ? i + XY : i + XY - XYZ, nb.zf);
+  load_sp<R>(f, V, (z > 0) ? i - XY : i - XY + XYZ, nb.zb);
+  load_sp<R>(f, V, (t + 1 < T) ? i + XYZ : i + XYZ - V, nb.tf);
+  load_sp<R>(f, V, (t > 0) ? i - XYZ : i - XYZ + V, nb.tb);
+}
 
-  C c[4];
-  load_sp<R>(f, V, i, c);
+// H_W at site i from its loaded neighbourhood.
+template <class R>
+__device__ __forceinline__ void hw_compute(const Nbr<R>& nb, const Geo& g, int i, R diag,
+                                           c2<R> out[4]) {
+  using C = c2<R>;
+  const int T = g.T;
+  const int t = i / (g.X * g.Y * g.Z);
   C a[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) a[s] = C{diag * c[s].x, diag * c[s].y};
-
-  C pf[4], pb[4], S[4], D[4];
+  for (int s = 0; s < 4; ++s) a[s] = C{diag * nb.c[s].x, diag * nb.c[s].y};
+  C S[4], D[4];
   const R h = R(0.5);
   // ---- x
-  {
-    const int jf = (x + 1 < X) ? i + 1 : i + 1 - X;
-    const int jb = (x > 0) ? i - 1 : i - 1 + X;
-    load_sp<R>(f, V, jf, pf);
-    load_sp<R>(f, V, jb, pb);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      S[s] = C{pf[s].x + pb[s].x, pf[s].y + pb[s].y};
-      D[s] = C{h * (pf[s].x - pb[s].x), h * (pf[s].y - pb[s].y)};
-    }
-    C g0 = cmul_i(D[3]), g1 = cmul_i(D[2]), g2 = cmul_i(D[1]), g3 = cmul_i(D[0]);
+  for (int s = 0; s < 4; ++s) {
+    S[s] = C{nb.xf[s].x + nb.xb[s].x, nb.xf[s].y + nb.xb[s].y};
+    D[s] = C{h * (nb.xf[s].x - nb.xb[s].x), h * (nb.xf[s].y - nb.xb[s].y)};
+  }
+  {
+    const C g0 = cmul_i(D[3]), g1 = cmul_i(D[2]), g2 = cmul_i(D[1]), g3 = cmul_i(D[0]);
     a[0] = C{a[0].x - h * S[0].x + g0.x, a[0].y - h * S[0].y + g0.y};
     a[1] = C{a[1].x - h * S[1].x + g1.x, a[1].y - h * S[1].y + g1.y};
     a[2] = C{a[2].x - h * S[2].x - g2.x, a[2].y - h * S[2].y - g2.y};
     a[3] = C{a[3].x - h * S[3].x - g3.x, a[3].y - h * S[3].y - g3.y};
   }
   // ---- y
-  {
-    const int jf = (y + 1 < Y) ? i + X : i + X - XY;
-    const int jb = (y > 0) ? i - X : i - X + XY;
-    load_sp<R>(f, V, jf, pf);
-    load_sp<R>(f, V, jb, pb);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      S[s] = C{pf[s].x + pb[s].x, pf[s].y + pb[s].y};
-      D[s] = C{h * (pf[s].x - pb[s].x), h * (pf[s].y - pb[s].y)};
-    }
-    a[0] = C{a[0].x - h * S[0].x + D[3].x, a[0].y - h * S[0].y + D[3].y};
-    a[1] = C{a[1].x - h * S[1].x - D[2].x, a[1].y - h * S[1].y - D[2].y};
-    a[2] = C{a[2].x - h * S[2].x - D[1].x, a[2].y - h * S[2].y - D[1].y};
-    a[3] = C{a[3].x - h * S[3].x + D[0].x, a[3].y - h * S[3].y + D[0].y};
+  for (int s = 0; s < 4; ++s) {
+    S[s] = C{nb.yf[s].x + nb.yb[s].x, nb.yf[s].y + nb.yb[s].y};
+    D[s] = C{h * (nb.yf[s].x - nb.yb[s].x), h * (nb.yf[s].y - nb.yb[s].y)};
   }
+  a[0] = C{a[0].x - h * S[0].x + D[3].x, a[0].y - h * S[0].y + D[3].y};
+  a[1] = C{a[1].x - h * S[1].x - D[2].x, a[1].y - h * S[1].y - D[2].y};
+  a[2] = C{a[2].x - h * S[2].x - D[1].x, a[2].y - h * S[2].y - D[1].y};
+  a[3] = C{a[3].x - h * S[3].x + D[0].x, a[3].y - h * S[3].y + D[0].y};
   // ---- z
-  {
-    const int jf = (z + 1 < Z) ? i + XY : i + XY - XYZ;
-    const int jb = (z > 0) ? i - XY : i - XY + XYZ;
-    load_sp<R>(f, V, jf, pf);
-    load_sp<R>(f, V, jb, pb);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      S[s] = C{pf[s].x + pb[s].x, pf[s].y + pb[s].y};
-      D[s] = C{h * (pf[s].x - pb[s].x), h * (pf[s].y - pb[s].y)};
-    }
-    C g0 = cmul_i(D[2]), g1 = cmul_i(D[3]), g2 = cmul_i(D[0]), g3 = cmul_i(D[1]);
+  for (int s = 0; s < 4; ++s) {
+    S[s] = C{nb.zf[s].x + nb.zb[s].x, nb.zf[s].y + nb.zb[s].y};
+    D[s] = C{h * (nb.zf[s].x - nb.zb[s].x), h * (nb.zf[s].y - nb.zb[s].y)};
+  }
+  {
+    const C g0 = cmul_i(D[2]), g1 = cmul_i(D[3]), g2 = cmul_i(D[0]), g3 = cmul_i(D[1]);
     a[0] = C{a[0].x - h * S[0].x + g0.x, a[0].y - h * S[0].y + g0.y};
     a[1] = C{a[1].x - h * S[1].x - g1.x, a[1].y - h * S[1].y - g1.y};
     a[2] = C{a[2].x - h * S[2].x - g2.x, a[2].y - h * S[2].y - g2.y};
@@ -121,17 +128,12 @@ __device__ __forceinline__ void hw_site(const c2<R>* __restrict__ f, const Geo& 
   }
   // ---- t (boundary phase bc on wrapping hops)
   {
-    const bool wf = (t + 1 == T), wb = (t == 0);
-    const int jf = wf ? i + XYZ - V : i + XYZ;
-    const int jb = wb ? i - XYZ + V : i - XYZ;
-    load_sp<R>(f, V, jf, pf);
-    load_sp<R>(f, V, jb, pb);
-    const R phf = (wf && g.bc < 0) ? R(-1) : R(1);
-    const R phb = (wb && g.bc < 0) ? R(-1) : R(1);
+    const R phf = (t + 1 == T && g.bc < 0) ? R(-1) : R(1);
+    const R phb = (t == 0 && g.bc < 0) ? R(-1) : R(1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const C u = C{phf * pf[s].x, phf * pf[s].y};
-      const C w = C{phb * pb[s].x, phb * pb[s].y};
+      const C u = C{phf * nb.tf[s].x, phf * nb.tf[s].y};
+      const C w = C{phb * nb.tb[s].x, phb * nb.tb[s].y};
       S[s] = C{u.x + w.x, u.y + w.y};
       D[s] = C{h * (u.x - w.x), h * (u.y - w.y)};
     }
@@ -140,10 +142,19 @@ __device__ __forceinline__ void hw_site(const c2<R>* __restrict__ f, const Geo& 
     a[2] = C{a[2].x - h * S[2].x + D[0].x, a[2].y - h * S[2].y + D[0].y};
     a[3] = C{a[3].x - h * S[3].x + D[1].x, a[3].y - h * S[3].y + D[1].y};
   }
+  // g5
   out[0] = C{-a[0].x, -a[0].y};
   out[1] = C{-a[1].x, -a[1].y};
   out[2] = a[2];
   out[3] = a[3];
+}
+
+template <class R>
+__device__ __forceinline__ void hw_site(const c2<R>* __restrict__ f, const Geo& g, int i,
+                                        R diag, c2<R> out[4]) {
+  Nbr<R> nb;
+  load_nbr<R>(f, g, i, nb);
+  hw_compute<R>(nb, g, i, diag, out);
 }
 
 template <class V> __device__ __forceinline__ double norm2_sp(const V v[4]) {
@@ -162,6 +173,13 @@ template <class V> __device__ __forceinline__ double norm2_sp(const V v[4]) {
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Wave total returned to every lane (butterfly: same bits in every lane).
+__device__ __forceinline__ double wave_sum_all(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 

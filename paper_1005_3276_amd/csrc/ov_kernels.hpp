@@ -93,11 +93,11 @@ __device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys
 // ------------------------------------------------------------------ pack
 // ABI complex128 (V,4) AoS (optionally times g5, times scale) <-> spin-planar R.
 template <class R>
-__global__ void k_pack(const SysDev* __restrict__ sys, int nsys, int nb_total,
+__global__ void k_pack(const SysDev* __restrict__ sys, const int* __restrict__ bmap, int nb_total,
                        const double2* const* __restrict__ src, void* const* __restrict__ dst,
                        double scale) {
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   const int V = S.g.V;
   const int lb = L - S.blk0;
@@ -115,10 +115,10 @@ __global__ void k_pack(const SysDev* __restrict__ sys, int nsys, int nb_total,
 }
 
 template <class R>
-__global__ void k_unpack(const SysDev* __restrict__ sys, int nsys, int nb_total,
+__global__ void k_unpack(const SysDev* __restrict__ sys, const int* __restrict__ bmap, int nb_total,
                          void* const* __restrict__ src, double2* const* __restrict__ dst) {
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   const int V = S.g.V;
   const int lb = L - S.blk0;
@@ -138,11 +138,11 @@ __global__ void k_unpack(const SysDev* __restrict__ sys, int nsys, int nb_total,
 // ---------------------------------------------------------- plain stencil
 // out = H_W in; optional |out|^2 partials.  in/out per system from e_in/e_out.
 template <class R>
-__global__ void __launch_bounds__(1024) k_hw(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_hw(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                              int nb_total, double diag, int want_norm) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   const Geo g = S.g;
   const int lb = L - S.blk0;
@@ -167,89 +167,115 @@ __global__ void __launch_bounds__(1024) k_hw(const SysDev* __restrict__ sys, int
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
 // advances the shift recurrences, decides convergence, then
 //   t_n = H r_n + beta_{n-1} t_{n-1}  -> basis slot n,  partial |t_n|^2.
+// Latency layout: every independent load (control word, partials, scalar
+// history, the nine stencil operands and t_{n-1}) is issued before any of them
+// is consumed, and each wave finishes the reduction and the shift recurrences
+// on its own (identical bits in every wave), so the only barrier is the final
+// block reduction.
 template <class R>
-__global__ void __launch_bounds__(1024) k_ms_t(const SysDev* __restrict__ sys, int nsys,
-                                               int nb_total, int n,
-                                               const MsParams mp_) {
-  __shared__ double lds[17];
-  __shared__ double sh_beta;
-  __shared__ int sh_stop;
-  const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
-  const SysDev& S = sys[s];
-  if (S.active && *S.active == 0) return;
-  if (n > 0 && S.h_ctl[0]) return;  // done in an earlier iteration
-  const int lb = L - S.blk0;
-  const MsParams* mp = &mp_;
+__device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const MsParams* mp,
+                                           double* lds) {
+  const int lane = threadIdx.x & 63;
+  const Geo g = S.g;
   const int np = mp->np;
+  const int nblk = S.nblk;
 
-  const double rho = sum_partials(S.part_b, S.nblk, lds);
-  if (threadIdx.x < 64) {
-    // scalar recurrences, lane k of wave 0 owns shift k (identical in every
-    // workgroup of system s)
-    const int k = threadIdx.x;
-    const double rho0 = (n == 0) ? rho : S.h_rho[0];
-    const double thr = mp->tol * sqrt(rho0);
-    const double srho = sqrt(rho);
-    bool act = false;
-    double zn = 1.0;
-    if (n == 0) {
-      act = (k < np) && (srho > thr);
-    } else if (k < np) {
-      const unsigned int act_prev = S.h_active[n - 1];
-      const double zk1 = S.h_zeta[(size_t)(n - 1) * MAXP + k];  // zeta^{n-1}
-      zn = zk1;
-      if (act_prev & (1u << k)) {
-        const double a1 = S.h_alpha[n - 1];                                  // alpha_{n-1}
-        const double a2 = (n >= 2) ? S.h_alpha[n - 2] : 1.0;                 // alpha_{n-2}
-        const double b2 = (n >= 2) ? S.h_rho[n - 1] / S.h_rho[n - 2] : 0.0;  // beta_{n-2}
-        const double zk2 = (n >= 2) ? S.h_zeta[(size_t)(n - 2) * MAXP + k] : 1.0;
-        const double den = a2 * zk2 * (1.0 + a1 * mp->sigma[k]) + a1 * b2 * (zk2 - zk1);
-        zn = zk1 * zk2 * a2 / den;
-        act = fabs(zn) * srho > thr;
-      }
-    }
-    const unsigned int amask = (unsigned int)__ballot(act);
-    if (lb == 0 && k < np) S.h_zeta[(size_t)n * MAXP + k] = zn;
-    if (k == 0) {
-      int status = 0;
-      if (n > 0 && (!(rho >= 0.0) || !isfinite(rho))) status = 1;  // breakdown
-      int stop = (amask == 0) || status != 0;
-      if (!stop && n >= mp->cap) { stop = 1; status = 2; }  // basis exhausted
-      sh_beta = (n > 0) ? rho / S.h_rho[n - 1] : 0.0;
-      sh_stop = stop;
-      if (lb == 0) {
-        S.h_rho[n] = rho;
-        S.h_active[n] = amask;
-        if (stop) {
-          S.h_ctl[1] = n;
-          S.h_ctl[2] = status;
-        }
-        S.h_ctl[0] = stop;
-      }
+  const int act_sys = S.active ? *S.active : 1;
+  const int done = (n > 0) ? S.h_ctl[0] : 0;
+  // partials of rho_n (this lane's share, summed in a fixed order)
+  double pr = 0.0;
+  for (int j = lane; j < nblk; j += 64) pr += S.part_b[j];
+  // scalar history for lane k = shift k
+  const int k = lane;
+  double zk1 = 1.0, zk2 = 1.0, a1 = 0.0, a2 = 1.0, rho_m1 = 1.0, rho_m2 = 1.0, rho0 = 0.0;
+  unsigned int act_prev = 0xffffffffu;
+  if (n > 0) {
+    act_prev = S.h_active[n - 1];
+    rho_m1 = S.h_rho[n - 1];
+    a1 = S.h_alpha[n - 1];
+    rho0 = S.h_rho[0];
+    if (k < np) zk1 = S.h_zeta[(size_t)(n - 1) * MAXP + k];
+    if (n >= 2) {
+      a2 = S.h_alpha[n - 2];
+      rho_m2 = S.h_rho[n - 2];
+      if (k < np) zk2 = S.h_zeta[(size_t)(n - 2) * MAXP + k];
     }
   }
-  __syncthreads();
-  if (sh_stop) return;
-  const double beta = sh_beta;
-
-  const Geo g = S.g;
+  // stencil operands
   const size_t slot = (size_t)4 * g.V;
   const c2<R>* rin = (const c2<R>*)(n == 0 ? S.src : S.r);
   c2<R>* tn = (c2<R>*)S.basis + (size_t)n * slot;
   const c2<R>* tp = (const c2<R>*)S.basis + (size_t)(n > 0 ? n - 1 : 0) * slot;
-  const R rbeta = (R)beta;
   const int i0 = lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
+  int i = i0 + threadIdx.x;
+  const bool have = i < i1;
+  Nbr<R> nb;
+  c2<R> q[4];
+  if (have) {
+    load_nbr<R>(rin, g, i, nb);
+    if (n > 0) load_sp<R>(tp, g.V, i, q);
+  }
+  if (!act_sys || done) return;
+
+  // rho_n and the shift recurrences, per wave
+  const double rho = wave_sum_all(pr);
+  const double srho = sqrt(rho);
+  if (n == 0) rho0 = rho;
+  const double thr = mp->tol * sqrt(rho0);
+  bool act = false;
+  double zn = 1.0;
+  if (n == 0) {
+    act = (k < np) && (srho > thr);
+  } else if (k < np) {
+    zn = zk1;
+    if (act_prev & (1u << k)) {
+      const double b2 = (n >= 2) ? rho_m1 / rho_m2 : 0.0;  // beta_{n-2}
+      const double den = a2 * zk2 * (1.0 + a1 * mp->sigma[k]) + a1 * b2 * (zk2 - zk1);
+      zn = zk1 * zk2 * a2 / den;
+      act = fabs(zn) * srho > thr;
+    }
+  }
+  const unsigned int amask = (unsigned int)__ballot(act);
+  int status = 0;
+  if (n > 0 && (!(rho >= 0.0) || !isfinite(rho))) status = 1;  // breakdown
+  int stop = (amask == 0) || status != 0;
+  if (!stop && n >= mp->cap) { stop = 1; status = 2; }            // basis exhausted
+  if (lb == 0 && threadIdx.x < 64) {
+    if (k < np) S.h_zeta[(size_t)n * MAXP + k] = zn;
+    if (k == 0) {
+      S.h_rho[n] = rho;
+      S.h_active[n] = amask;
+      if (stop) {
+        S.h_ctl[1] = n;
+        S.h_ctl[2] = status;
+      }
+      // one word: 0 while iterating, n + 1 once finished at iteration n
+      __hip_atomic_store(&S.h_ctl[0], stop ? n + 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (stop) return;
+  const R beta = (R)((n > 0) ? rho / rho_m1 : 0.0);
+
   double acc = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+  if (have) {
+    c2<R> o[4];
+    hw_compute<R>(nb, g, i, (R)mp->diag, o);
+    if (n > 0) {
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) o[k2] = c2<R>{o[k2].x + beta * q[k2].x, o[k2].y + beta * q[k2].y};
+    }
+    store_sp<R>(tn, g.V, i, o);
+    acc = norm2_sp(o);
+  }
+  // remaining sites of this block (sites per thread > 1)
+  for (i += blockDim.x; i < i1; i += blockDim.x) {
     c2<R> o[4];
     hw_site<R>(rin, g, i, (R)mp->diag, o);
     if (n > 0) {
-      c2<R> q[4];
       load_sp<R>(tp, g.V, i, q);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) o[k] = c2<R>{o[k].x + rbeta * q[k].x, o[k].y + rbeta * q[k].y};
+      for (int k2 = 0; k2 < 4; ++k2) o[k2] = c2<R>{o[k2].x + beta * q[k2].x, o[k2].y + beta * q[k2].y};
     }
     store_sp<R>(tn, g.V, i, o);
     acc += norm2_sp(o);
@@ -258,50 +284,56 @@ __global__ void __launch_bounds__(1024) k_ms_t(const SysDev* __restrict__ sys, i
   if (threadIdx.x == 0) S.part_a[lb] = tot;
 }
 
-// ------------------------------------------------------- multi-shift: r pass
-//   alpha_n = rho_n / |t_n|^2;  r_{n+1} = r_n - alpha_n H t_n;  partial |r_{n+1}|^2.
 template <class R>
-__global__ void __launch_bounds__(1024) k_ms_r(const SysDev* __restrict__ sys, int nsys,
-                                               int nb_total, int n,
-                                               const MsParams mp_) {
-  __shared__ double lds[17];
-  __shared__ double sh_alpha;
-  __shared__ int sh_stop;
-  const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
-  const SysDev& S = sys[s];
-  if (S.active && *S.active == 0) return;
-  if (S.h_ctl[0]) return;
-  const MsParams* mp = &mp_;
-  const int lb = L - S.blk0;
-  const double gam = sum_partials(S.part_a, S.nblk, lds);
-  if (threadIdx.x == 0) {
-    const double alpha = S.h_rho[n] / gam;
-    int stop = !(gam > 0.0) || !isfinite(alpha);
-    sh_alpha = alpha;
-    sh_stop = stop;
-    if (lb == 0) {
-      S.h_alpha[n] = alpha;
-      if (stop) {
-        S.h_ctl[1] = n;
-        S.h_ctl[2] = 1;
-        S.h_ctl[0] = 1;
-      }
-    }
-  }
-  __syncthreads();
-  if (sh_stop) return;
-  const R alpha = (R)sh_alpha;
+__device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const MsParams* mp,
+                                           double* lds) {
+  const int lane = threadIdx.x & 63;
   const Geo g = S.g;
+  const int nblk = S.nblk;
+  const int act_sys = S.active ? *S.active : 1;
+  const int done = S.h_ctl[0];
+  double pg = 0.0;
+  for (int j = lane; j < nblk; j += 64) pg += S.part_a[j];
+  const double rho = S.h_rho[n];
   const size_t slot = (size_t)4 * g.V;
   const c2<R>* tn = (const c2<R>*)S.basis + (size_t)n * slot;
   const c2<R>* rin = (const c2<R>*)(n == 0 ? S.src : S.r);
   c2<R>* rout = (c2<R>*)S.r;
   const int i0 = lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
+  int i = i0 + threadIdx.x;
+  const bool have = i < i1;
+  Nbr<R> nb;
+  c2<R> r[4];
+  if (have) {
+    load_nbr<R>(tn, g, i, nb);
+    load_sp<R>(rin, g.V, i, r);
+  }
+  if (!act_sys || done) return;
+  const double gam = wave_sum_all(pg);
+  const double alpha_d = rho / gam;
+  const int stop = !(gam > 0.0) || !isfinite(alpha_d);
+  if (lb == 0 && threadIdx.x == 0) {
+    S.h_alpha[n] = alpha_d;
+    if (stop) {
+      S.h_ctl[1] = n;
+      S.h_ctl[2] = 1;
+      __hip_atomic_store(&S.h_ctl[0], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (stop) return;
+  const R alpha = (R)alpha_d;
   double acc = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    c2<R> w[4], r[4];
+  if (have) {
+    c2<R> w[4];
+    hw_compute<R>(nb, g, i, (R)mp->diag, w);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = c2<R>{r[k].x - alpha * w[k].x, r[k].y - alpha * w[k].y};
+    store_sp<R>(rout, g.V, i, r);
+    acc = norm2_sp(r);
+  }
+  for (i += blockDim.x; i < i1; i += blockDim.x) {
+    c2<R> w[4];
     hw_site<R>(tn, g, i, (R)mp->diag, w);
     load_sp<R>(rin, g.V, i, r);
 #pragma unroll
@@ -311,6 +343,136 @@ __global__ void __launch_bounds__(1024) k_ms_r(const SysDev* __restrict__ sys, i
   }
   const double tot = block_sum(acc, lds);
   if (threadIdx.x == 0) S.part_b[lb] = tot;
+}
+
+// Iteration n, t pass: finishes rho_n = |r_n|^2 from the previous kernel's
+// partials, advances the shift recurrences, decides convergence, then
+//   t_n = H r_n + beta_{n-1} t_{n-1}  -> basis slot n,  partial |t_n|^2.
+// Latency layout: every independent load (control word, partials, scalar
+// history, the nine stencil operands and t_{n-1}) is issued before any of them
+// is consumed, and each wave finishes the reduction and the shift recurrences
+// on its own (identical bits in every wave), so the only barrier is the final
+// block reduction.
+template <class R>
+__global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
+                                              const int* __restrict__ bmap, int nb_total, int n,
+                                              const MsParams mp_) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  ms_t_block<R>(S, L - S.blk0, n, &mp_, lds);
+}
+
+// Iteration n, r pass:
+//   alpha_n = rho_n / |t_n|^2;  r_{n+1} = r_n - alpha_n H t_n;  partial |r_{n+1}|^2.
+template <class R>
+__global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
+                                              const int* __restrict__ bmap, int nb_total, int n,
+                                              const MsParams mp_) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  ms_r_block<R>(S, L - S.blk0, n, &mp_, lds);
+}
+
+// ------------------------------------------------ multi-shift: persistent form
+// All iterations of one multi-shift solve in a single cooperative launch: the
+// t and r passes are separated by grid barriers instead of kernel boundaries.
+// Every spin is bounded: a barrier that does not complete within the limit
+// raises `abort` and every workgroup leaves, so the launch always drains.
+struct GridBar {
+  unsigned int count;  // arrivals in the current barrier
+  unsigned int gen;    // barrier generation
+  int abort;           // set by a workgroup whose wait timed out
+  int pad;
+};
+
+constexpr long long kSpinLimit = 1LL << 20;
+
+// Grid barrier.  Each wave first waits for its own stores to complete, the
+// workgroup meets, then one thread per workgroup publishes the workgroup's
+// writes device-wide (agent-scope release: L2 write-back), arrives with a
+// relaxed atomic, polls the generation with relaxed atomic loads (no cache
+// invalidation per poll) and finally acquires once (agent-scope invalidate).
+__device__ __forceinline__ bool grid_sync(GridBar* gb, unsigned int nblocks) {
+  __shared__ int sh_ok;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned int g0 = __hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned int arrived =
+        __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(&gb->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit ||
+            __hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+      }
+      if (!ok) __hip_atomic_store(&gb->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sh_ok = ok;
+  }
+  __syncthreads();
+  return sh_ok != 0;
+}
+
+// True when every participating system finished at an iteration <= n.  A
+// system that finishes at n' writes n' + 1 in one word, so a workgroup that
+// runs ahead into iteration n + 1 can never change this answer for iteration n.
+__device__ __forceinline__ bool all_done(const SysDev* __restrict__ sys, int nsys, int n) {
+  for (int s = 0; s < nsys; ++s) {
+    const SysDev& S = sys[s];
+    if (S.active && *S.active == 0) continue;
+    const int d = __hip_atomic_load(&S.h_ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == 0 || d - 1 > n) return false;
+  }
+  return true;
+}
+
+// Launch with exactly `grid` co-resident workgroups (cooperative launch).
+// Workgroup b handles logical blocks j, j + grid, ... with j its XCD-contiguous
+// index.  Every workgroup runs the same barriers and leaves at the same
+// iteration (after L iterations, or once all_done holds after a barrier).
+template <class R>
+__global__ void __launch_bounds__(256) k_ms_persistent(const SysDev* __restrict__ sys, int nsys,
+                                                       const int* __restrict__ bmap, int nb_total,
+                                                       int L, const MsParams mp_, GridBar* gb) {
+  __shared__ double lds[17];
+  const int grid = gridDim.x;
+  const int j0 = xcd_logical_block(grid);
+  for (int n = 0; n < L; ++n) {
+    for (int Lb = j0; Lb < nb_total; Lb += grid) {
+      const SysDev& S = sys[bmap[Lb]];
+      ms_t_block<R>(S, Lb - S.blk0, n, &mp_, lds);
+      __syncthreads();
+    }
+    if (!grid_sync(gb, grid)) return;
+    for (int Lb = j0; Lb < nb_total; Lb += grid) {
+      const SysDev& S = sys[bmap[Lb]];
+      ms_r_block<R>(S, Lb - S.blk0, n, &mp_, lds);
+      __syncthreads();
+    }
+    if (!grid_sync(gb, grid)) return;
+    if (all_done(sys, nsys, n)) return;
+  }
+}
+
+__global__ void k_bar_reset(GridBar* gb) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    gb->count = 0;
+    gb->abort = 0;
+  }
 }
 
 // ------------------------------------------------- multi-shift: coefficients
@@ -399,11 +561,11 @@ enum EpiMode {
 
 // c+ = m + g phi, c- = m* + g* phi*;  Y psi = c- psi_{0,1} (P-) + c+ psi_{2,3} (P+).
 template <class R>
-__global__ void __launch_bounds__(1024) k_ms_combine(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_ms_combine(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                      int nb_total, int mode) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   if (S.active && *S.active == 0) return;
   const int lb = L - S.blk0;
@@ -540,11 +702,11 @@ __global__ void __launch_bounds__(1024) k_ms_combine(const SysDev* __restrict__ 
 // ------------------------------------------------------- multi-shift setup
 // Source partials |src|^2 -> part_b (and src = g5 e_in when g5_src).
 template <class R>
-__global__ void __launch_bounds__(1024) k_ms_prep(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_ms_prep(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                   int nb_total, int g5_src) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   if (S.active && *S.active == 0) return;
   const int lb = L - S.blk0;
@@ -608,16 +770,17 @@ __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
 
 // p = r + beta p (beta from cg_s; use_beta = 0 -> p = r); partial |p|^2 -> part_b.
 template <class R>
-__global__ void __launch_bounds__(1024) k_cg_p(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                int nb_total, int use_beta) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   if (S.active && *S.active == 0) return;
   const int lb = L - S.blk0;
   const int V = S.g.V;
   const double beta = use_beta ? S.cg_s[CG_BETA] : 0.0;
+  use_beta = use_beta && beta != 0.0;  // restart: p = r, the old p is never read
   const int i0 = lb * S.spb;
   const int i1 = min(V, i0 + S.spb);
   double acc = 0.0;
@@ -646,11 +809,11 @@ __global__ void __launch_bounds__(1024) k_cg_p(const SysDev* __restrict__ sys, i
 //   op 1: r = b (FP64 AoS -> planar R), partial |b|^2 -> part_c
 //   op 2: x = 0
 template <class R>
-__global__ void __launch_bounds__(1024) k_cg_misc(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                   int nb_total, int op) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   if (S.active && *S.active == 0) return;
   const int lb = L - S.blk0;
@@ -698,7 +861,7 @@ __global__ void __launch_bounds__(1024) k_cg_misc(const SysDev* __restrict__ sys
 // dS/dphi_x = -g [ Y_x^dag P+ X_x + X_x^dag P- Y_x ]  and  G_x = 2 conj(dS/dphi_x),
 // summed over the nsys right-hand sides (same lattice, same phi) in index order.
 // X = e_in, Y = e_out (FP64 planar) per system; G complex128 [V].
-__global__ void __launch_bounds__(1024) k_force(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_force(const SysDev* __restrict__ sys, int nsys,
                                                 int nb0, double2* __restrict__ G) {
   const int L = xcd_logical_block(nb0);
   const SysDev& S0 = sys[0];
@@ -735,11 +898,11 @@ __global__ void __launch_bounds__(1024) k_force(const SysDev* __restrict__ sys, 
 }
 
 // Re <xi, X> partials (xi AoS complex128 from cg_b, X planar FP64 e_in) -> part_c
-__global__ void __launch_bounds__(1024) k_dot_re(const SysDev* __restrict__ sys, int nsys,
+__global__ void __launch_bounds__(256) k_dot_re(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                  int nb_total) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   const int lb = L - S.blk0;
   const int V = S.g.V;

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -25,7 +26,13 @@ using namespace ov;
 
 struct ov_ctx {
   ov_params p;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // caller's stream: work is ordered after it
+  hipStream_t priv = nullptr;    // private non-blocking stream all work runs on
+  hipEvent_t ev_in = nullptr;    // caller-stream marker the private stream waits for
+  std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
+  bool use_graphs = true;
+  int persistent = 0;            // cooperative persistent multi-shift kernel (0: per-pass kernels)
+  int coop_cap[2] = {0, 0};      // co-resident workgroups of k_ms_persistent<double/float>
   int device = 0;
   std::string err;
   double a[MAXP], b[MAXP], delta = 0;
@@ -43,10 +50,15 @@ struct ov_ctx {
   // kernel-duration sampling (see ov_kernel_sampling)
   int sample_max = 0;
   std::vector<hipEvent_t> ev_pool;             // pairs
-  std::vector<std::pair<int, double>> ev_use;  // (kernel, bytes) per recorded pair
-  int ev_call_count[2] = {0, 0};
-  double ksum_ms[2] = {0, 0}, ksum_bytes[2] = {0, 0};
-  long long kcount[2] = {0, 0};
+  struct EvUse {
+    int kernel;
+    double bytes;          // bytes of the launch, or bytes per iteration when n_dev is set
+    const int* n_dev;      // device iteration count of a persistent launch
+  };
+  std::vector<EvUse> ev_use;
+  int ev_call_count[3] = {0, 0, 0};
+  double ksum_ms[3] = {0, 0, 0}, ksum_bytes[3] = {0, 0, 0};
+  long long kcount[3] = {0, 0, 0};
 };
 
 namespace {
@@ -193,9 +205,6 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
   s.coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
   s.coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
   s.coef_d = (double*)bp.take(sizeof(double) * capmax);
-  s.cg_s = (double*)bp.take(sizeof(double) * CG_NSLOT);
-  s.act_cg = (int*)bp.take(sizeof(int));
-  s.act_ru = (int*)bp.take(sizeof(int));
 }
 
 enum Table { T_APPLY = 0, T_APPLY2, T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG, T_CG, T_CG_RU, T_NT };
@@ -212,12 +221,21 @@ struct Engine {
   SysDev* tables = nullptr;         // device: T_NT * nsys
   std::vector<SysDev> htab;         // host copy
   void** ptrs = nullptr;            // device pointer arrays for pack/unpack (2 * nsys)
+  int* bmap = nullptr;              // device: logical workgroup -> system
+  std::vector<int> hbmap;
   std::vector<void*> hptrs;         // host staging of ptrs (outlives the async copy)
+  GridBar* gbar = nullptr;          // device: grid barrier of the persistent kernel
+  double* cg_all = nullptr;         // device: nsys * CG_NSLOT scalars (one copy to the host)
+  int* act_all = nullptr;           // device: act_cg[nsys] then act_ru[nsys]
+  std::vector<int> last_flags;      // last uploaded flags (upload only on change)
   MsParams mp64{}, mpR{};
   int L64 = 0, LR = 0;              // multi-shift launch counts
 
   size_t layout(void* base, size_t cap, bool dry) {
     Bump bp(base, cap, dry);
+    gbar = (GridBar*)bp.take(sizeof(GridBar));
+    cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys);
+    act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0;
     for (int s = 0; s < nsys; ++s) {
       SysBuf& b = sb[s];
@@ -229,13 +247,25 @@ struct Engine {
       b.blk0 = blk;
       blk += b.nblk;
       carve(bp, b, pl);
+      b.cg_s = dry ? nullptr : cg_all + (size_t)s * CG_NSLOT;
+      b.act_cg = dry ? nullptr : act_all + s;
+      b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
     nb_total = blk;
     tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
     ptrs = (void**)bp.take(sizeof(void*) * 2 * nsys);
+    bmap = (int*)bp.take(sizeof(int) * (size_t)nb_total);
+    hbmap.assign(nb_total, 0);
+    for (int s = 0; s < nsys; ++s)
+      for (int b = 0; b < sb[s].nblk; ++b) hbmap[sb[s].blk0 + b] = s;
     return bp.off + 256;
   }
 };
+
+void clear_graphs(ov_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
 
 ov_status ensure_ws(ov_ctx* c, size_t need, void** base) {
   if (c->user_ws && c->user_ws_bytes >= need) {
@@ -243,6 +273,7 @@ ov_status ensure_ws(ov_ctx* c, size_t need, void** base) {
     return OV_OK;
   }
   if (c->own_ws_bytes < need) {
+    clear_graphs(c);
     if (c->own_ws) (void)hipFree(c->own_ws);
     c->own_ws = nullptr;
     c->own_ws_bytes = 0;
@@ -285,8 +316,10 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   E.nsys = (int)ctxs.size();
   E.sb.assign(E.nsys, SysBuf{});
   E.lead = ctxs[0];
-  E.st = E.lead->stream;
-  E.lead->ev_call_count[0] = E.lead->ev_call_count[1] = 0;
+  E.st = E.lead->priv;
+  E.lead->ev_call_count[0] = E.lead->ev_call_count[1] = E.lead->ev_call_count[2] = 0;
+  HIPCHK(E.lead, hipEventRecord(E.lead->ev_in, E.lead->stream));
+  HIPCHK(E.lead, hipStreamWaitEvent(E.st, E.lead->ev_in, 0));
   E.pl.solve = solve;
   E.pl.mixed = mixed;
   // capacities from the loosest spectral bound over the batch
@@ -305,6 +338,7 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   void* base = nullptr;
   TRY(ensure_ws(E.lead, need, &base));
   E.layout(base, need, false);
+  HIPCHK(E.lead, hipMemsetAsync(E.gbar, 0, sizeof(GridBar), E.st));
   TRY(ensure_pinned(E.lead, E.nsys));
   return OV_OK;
 }
@@ -342,6 +376,8 @@ SysDev base_dev(const SysBuf& b) {
 ov_status upload_tables(Engine& E) {
   HIPCHK(E.lead, hipMemcpyAsync(E.tables, E.htab.data(), sizeof(SysDev) * E.htab.size(),
                                 hipMemcpyHostToDevice, E.st));
+  HIPCHK(E.lead, hipMemcpyAsync(E.bmap, E.hbmap.data(), sizeof(int) * E.hbmap.size(),
+                                hipMemcpyHostToDevice, E.st));
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
   return OV_OK;
 }
@@ -354,7 +390,7 @@ struct Sample {
   ov_ctx* c;
   int k;
   bool on = false;
-  Sample(ov_ctx* c_, int k_, double bytes) : c(c_), k(k_) {
+  Sample(ov_ctx* c_, int k_, double bytes, const int* n_dev = nullptr) : c(c_), k(k_) {
     if (c->sample_max <= 0 || c->ev_call_count[k] >= c->sample_max) return;
     const size_t idx = c->ev_use.size();
     if (2 * idx + 2 > c->ev_pool.size()) {
@@ -363,12 +399,12 @@ struct Sample {
       c->ev_pool.push_back(a);
       c->ev_pool.push_back(b);
     }
-    c->ev_use.push_back({k, bytes});
+    c->ev_use.push_back({k, bytes, n_dev});
     c->ev_call_count[k]++;
-    on = hipEventRecord(c->ev_pool[2 * idx], c->stream) == hipSuccess;
+    on = hipEventRecord(c->ev_pool[2 * idx], c->priv) == hipSuccess;
   }
   ~Sample() {
-    if (on) (void)hipEventRecord(c->ev_pool[2 * (c->ev_use.size() - 1) + 1], c->stream);
+    if (on) (void)hipEventRecord(c->ev_pool[2 * (c->ev_use.size() - 1) + 1], c->priv);
   }
 };
 
@@ -377,30 +413,83 @@ void collect_samples(ov_ctx* c) {
   for (size_t i = 0; i < c->ev_use.size(); ++i) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]) == hipSuccess) {
-      const int k = c->ev_use[i].first;
-      c->ksum_ms[k] += ms;
-      c->ksum_bytes[k] += c->ev_use[i].second;
-      c->kcount[k]++;
+      const auto& u = c->ev_use[i];
+      double bytes = u.bytes;
+      if (u.n_dev) {  // persistent launch: bytes per iteration x iterations run
+        int n = 0;
+        if (hipMemcpy(&n, u.n_dev, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) n = 0;
+        bytes *= n;
+      }
+      c->ksum_ms[u.kernel] += ms;
+      c->ksum_bytes[u.kernel] += bytes;
+      c->kcount[u.kernel]++;
     }
   }
   c->ev_use.clear();
-  c->ev_call_count[0] = c->ev_call_count[1] = 0;
+  c->ev_call_count[0] = c->ev_call_count[1] = c->ev_call_count[2] = 0;
+}
+
+// Co-resident workgroups of k_ms_persistent<R> on this device (0: no cooperative launch).
+template <class R>
+int coop_capacity(ov_ctx* c) {
+  int& cap = c->coop_cap[sizeof(R) == sizeof(float) ? 1 : 0];
+  if (cap == 0) {
+    int coop = 0, cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess ||
+        !coop ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_ms_persistent<R>, c->block,
+                                                     0) != hipSuccess ||
+        per < 1) {
+      cap = -1;
+    } else {
+      cap = per * cus;
+    }
+  }
+  return cap > 0 ? cap : 0;
 }
 
 template <class R>
 void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
   const SysDev* T = tab(E, t);
-  double vol = 0.0;  // active sites in this launch (all systems)
+  double vol = 0.0;  // sites in this launch (all systems)
   for (const auto& b : E.sb) vol += b.V;
-  const double bytes = 3.0 * 4.0 * sizeof(c2<R>) * vol;
+  const double bytes = 3.0 * 4.0 * sizeof(c2<R>) * vol;  // per pass
+  ov_ctx* c = E.lead;
+  const int cap = c->persistent ? coop_capacity<R>(c) : 0;
+  if (cap > 0) {
+    int grid = std::min(E.nb_total, cap);
+    k_bar_reset<<<1, 64, 0, E.st>>>(E.gbar);
+    const SysDev* Tp = T;
+    int nsys = E.nsys;
+    const int* bmap = E.bmap;
+    int nbt = E.nb_total;
+    int Lp = L;
+    MsParams mpc = mp;
+    GridBar* gb = E.gbar;
+    void* args[] = {(void*)&Tp, (void*)&nsys, (void*)&bmap, (void*)&nbt, (void*)&Lp, (void*)&mpc,
+                    (void*)&gb};
+    hipError_t e;
+    {
+      Sample smp(c, 2, 2.0 * bytes, E.sb[0].h_ctl + 1);
+      e = hipLaunchCooperativeKernel((const void*)k_ms_persistent<R>, dim3(grid),
+                                     dim3(c->block), args, 0, E.st);
+    }
+    if (e == hipSuccess) {
+      k_ms_coef<<<E.nsys, 64, 0, E.st>>>(T, E.nsys, L, mp);
+      return;
+    }
+    (void)hipGetLastError();
+    c->persistent = 0;  // cooperative launch refused: per-pass kernels from now on
+  }
   for (int n = 0; n < L; ++n) {
     {
-      Sample smp(E.lead, 0, bytes);
-      k_ms_t<R><<<E.nb_total, E.lead->block, 0, E.st>>>(T, E.nsys, E.nb_total, n, mp);
+      Sample smp(c, 0, bytes);
+      k_ms_t<R><<<E.nb_total, c->block, 0, E.st>>>(T, E.bmap, E.nb_total, n, mp);
     }
     {
-      Sample smp(E.lead, 1, bytes);
-      k_ms_r<R><<<E.nb_total, E.lead->block, 0, E.st>>>(T, E.nsys, E.nb_total, n, mp);
+      Sample smp(c, 1, bytes);
+      k_ms_r<R><<<E.nb_total, c->block, 0, E.st>>>(T, E.bmap, E.nb_total, n, mp);
     }
   }
   k_ms_coef<<<E.nsys, 64, 0, E.st>>>(T, E.nsys, L, mp);
@@ -408,7 +497,7 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
 
 template <class R>
 void launch_combine(const Engine& E, int t, int mode) {
-  k_ms_combine<R><<<E.nb_total, E.lead->block, 0, E.st>>>(tab(E, t), E.nsys, E.nb_total, mode);
+  k_ms_combine<R><<<E.nb_total, E.lead->block, 0, E.st>>>(tab(E, t), E.bmap, E.nb_total, mode);
 }
 
 ov_status check_launch(ov_ctx* c) {
@@ -424,6 +513,14 @@ ov_status sync(Engine& E) {
   TRY(check_launch(E.lead));
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
   if (!E.lead->ev_use.empty()) collect_samples(E.lead);
+  if (E.gbar) {
+    GridBar gb;
+    HIPCHK(E.lead, hipMemcpy(&gb, E.gbar, sizeof(gb), hipMemcpyDeviceToHost));
+    if (gb.abort) {
+      E.lead->err = "persistent multi-shift: a grid barrier timed out";
+      return OV_ERR_DEVICE;
+    }
+  }
   return OV_OK;
 }
 
@@ -465,7 +562,7 @@ ov_status pack64(Engine& E, const std::vector<const void*>& src, std::vector<voi
   HIPCHK(E.lead, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(),
                                 hipMemcpyHostToDevice, E.st));
   k_pack<double><<<E.nb_total, E.lead->block, 0, E.st>>>(
-      tab(E, T_APPLY), E.nsys, E.nb_total, (const double2* const*)E.ptrs, E.ptrs + E.nsys, 1.0);
+      tab(E, T_APPLY), E.bmap, E.nb_total, (const double2* const*)E.ptrs, E.ptrs + E.nsys, 1.0);
   return check_launch(E.lead);
 }
 
@@ -480,7 +577,7 @@ ov_status unpack64(Engine& E, const std::vector<void*>& src, const std::vector<v
   HIPCHK(E.lead, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(),
                                 hipMemcpyHostToDevice, E.st));
   k_unpack<double><<<E.nb_total, E.lead->block, 0, E.st>>>(
-      tab(E, T_APPLY), E.nsys, E.nb_total, E.ptrs, (double2* const*)(E.ptrs + E.nsys));
+      tab(E, T_APPLY), E.bmap, E.nb_total, E.ptrs, (double2* const*)(E.ptrs + E.nsys));
   return check_launch(E.lead);
 }
 
@@ -522,27 +619,27 @@ ov_status apply_sequence(Engine& E, int op) {
   const double diag = 4.0 - c->p.M0;
   switch (op) {
     case OV_OP_HW:
-      k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, diag, 0);
+      k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, diag, 0);
       break;
     case -1:  // sign
-      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 0);
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
       launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
       launch_combine<double>(E, T_APPLY, EPI_SIGN);
       break;
     case OV_OP_DOV:
     case OV_OP_M:
-      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 0);
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
       launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
       launch_combine<double>(E, T_APPLY, op == OV_OP_DOV ? EPI_DOV : EPI_M);
       break;
     case OV_OP_DOV_DAG:
     case OV_OP_M_DAG:
-      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 1);
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 1);
       launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
       launch_combine<double>(E, T_APPLY, op == OV_OP_DOV_DAG ? EPI_DOVDAG : EPI_MDAG);
       break;
     case OV_OP_MDAGM:
-      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.nsys, E.nb_total, 0);
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
       launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
       launch_combine<double>(E, T_APPLY, EPI_M);  // u64, src64b = g5 u64, part_b
       launch_ms<double>(E, T_APPLY2, E.mp64, E.L64);
@@ -669,43 +766,63 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
 }
 
 ov_status set_flags(Engine& E, const std::vector<int>& cg, const std::vector<int>& ru) {
+  std::vector<int> f(2 * E.nsys);
+  for (int s = 0; s < E.nsys; ++s) {
+    f[s] = cg[s];
+    f[E.nsys + s] = ru[s];
+  }
+  if (f == E.last_flags) return OV_OK;
   int* h = E.lead->pinned_flags;
-  for (int s = 0; s < E.nsys; ++s) {
-    h[2 * s] = cg[s];
-    h[2 * s + 1] = ru[s];
-  }
-  for (int s = 0; s < E.nsys; ++s) {
-    HIPCHK(E.lead, hipMemcpyAsync(E.sb[s].act_cg, &h[2 * s], sizeof(int), hipMemcpyHostToDevice, E.st));
-    HIPCHK(E.lead, hipMemcpyAsync(E.sb[s].act_ru, &h[2 * s + 1], sizeof(int), hipMemcpyHostToDevice, E.st));
-  }
-  // the pinned staging is reused: make sure the copies are done before rewriting it
+  // the pinned staging may still feed an earlier copy
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
+  std::memcpy(h, f.data(), sizeof(int) * f.size());
+  HIPCHK(E.lead, hipMemcpyAsync(E.act_all, h, sizeof(int) * f.size(), hipMemcpyHostToDevice, E.st));
+  E.last_flags = f;
   return OV_OK;
 }
 
 ov_status read_scalars(Engine& E) {
-  for (int s = 0; s < E.nsys; ++s)
-    HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned + (size_t)s * CG_NSLOT, E.sb[s].cg_s,
-                                  sizeof(double) * CG_NSLOT, hipMemcpyDeviceToHost, E.st));
+  HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all, sizeof(double) * CG_NSLOT * E.nsys,
+                                hipMemcpyDeviceToHost, E.st));
   return sync(E);
 }
 
-// FP64 true residual r64 = b - MdagM x64 (and the inner-precision copy in rcgR)
-// for the systems with act_ru set, with multi-shift tolerance tol.
-template <class R>
-ov_status true_residual(Engine& E, double tol, int scalar_op) {
-  const ov_ctx* c = E.lead;
-  MsParams mp = make_mp(c, tol, E.pl.cap64);
-  const int L = std::min(E.pl.cap64, capacity(c, tol));
-  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_TR_M), E.nsys, E.nb_total, 0);
-  launch_ms<double>(E, T_TR_M, mp, L);
-  launch_combine<double>(E, T_TR_M, EPI_M);
-  launch_ms<double>(E, T_TR_MDAG, mp, L);
-  // EPI_MDAG_RES writes r64 (FP64) and, for an FP64 inner solver, its copy in
-  // cg_r; an FP32 inner solver gets its copy from k_r64_to_r32 afterwards.
-  launch_combine<double>(E, T_TR_MDAG, EPI_MDAG_RES);
-  k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_TR_MDAG), E.nsys, scalar_op);
-  return check_launch(E.lead);
+// Run `enqueue` (kernel launches only) through a cached hipGraph keyed by
+// everything its launches bake in; direct launches while kernel sampling is on.
+template <class F>
+ov_status run_graph(Engine& E, const std::string& key, F&& enqueue) {
+  ov_ctx* c = E.lead;
+  if (!c->use_graphs || c->sample_max > 0 || c->persistent) {
+    enqueue();
+    return check_launch(c);
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "|%p|%p|%d|%d|%d", (void*)E.tables, (void*)E.bmap, E.nb_total,
+                E.nsys, c->block);
+  const std::string k = key + buf;
+  auto it = c->graphs.find(k);
+  if (it == c->graphs.end()) {
+    if (c->graphs.size() >= 64) clear_graphs(c);
+    HIPCHK(c, hipStreamBeginCapture(E.st, hipStreamCaptureModeThreadLocal));
+    enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(E.st, &g);
+    TRY(check_launch(c));
+    if (ec != hipSuccess) {
+      c->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+      return OV_ERR_DEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      c->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+      return OV_ERR_DEVICE;
+    }
+    it = c->graphs.emplace(k, ge).first;
+  }
+  HIPCHK(c, hipGraphLaunch(it->second, E.st));
+  return OV_OK;
 }
 
 }  // namespace
@@ -713,10 +830,10 @@ ov_status true_residual(Engine& E, double tol, int scalar_op) {
 // The float inner solver needs r (FP32) = r64 after a true residual; a small
 // conversion kernel keeps the FP64 combine generic.
 namespace ov {
-__global__ void __launch_bounds__(1024) k_r64_to_r32(const SysDev* __restrict__ sys, int nsys,
-                                                     int nb_total) {
+__global__ void __launch_bounds__(256) k_r64_to_r32(const SysDev* __restrict__ sys,
+                                                    const int* __restrict__ bmap, int nb_total) {
   const int L = xcd_logical_block(nb_total);
-  const int s = find_sys(sys, nsys, L);
+  const int s = bmap[L];
   const SysDev& S = sys[s];
   if (S.active && *S.active == 0) return;
   const int lb = L - S.blk0;
@@ -735,6 +852,35 @@ __global__ void __launch_bounds__(1024) k_r64_to_r32(const SysDev* __restrict__ 
 }  // namespace ov
 
 namespace {
+
+// Reliable update for the systems with act_ru set: x64 += xR, xR = 0, then the
+// FP64 true residual r64 = b - MdagM x64 (inner-precision copy into rcgR) with
+// multi-shift tolerance tol, and its norm through k_cg_scalar(scalar_op).
+// The tolerance is rounded down to a power of ten so that few graphs exist.
+template <class R>
+ov_status reliable_update(Engine& E, double tol, int scalar_op) {
+  const ov_ctx* c = E.lead;
+  tol = std::pow(10.0, std::floor(std::log10(tol) + 1e-9));
+  const MsParams mp = make_mp(c, tol, E.pl.cap64);
+  int L = 0;
+  for (int s = 0; s < E.nsys; ++s) L = std::max(L, capacity(E.ctxs[s], tol));
+  L = std::min(E.pl.cap64, L);
+  char key[96];
+  std::snprintf(key, sizeof key, "ru|%zu|%.3e|%d|%d", sizeof(R), tol, L, scalar_op);
+  return run_graph(E, key, [&]() {
+    k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total, 0);
+    k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_TR_M), E.bmap, E.nb_total, 0);
+    launch_ms<double>(E, T_TR_M, mp, L);
+    launch_combine<double>(E, T_TR_M, EPI_M);
+    launch_ms<double>(E, T_TR_MDAG, mp, L);
+    // EPI_MDAG_RES writes r64 (FP64) and, for an FP64 inner solver, its copy in
+    // cg_r; an FP32 inner solver gets its copy from k_r64_to_r32.
+    launch_combine<double>(E, T_TR_MDAG, EPI_MDAG_RES);
+    k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_TR_MDAG), E.nsys, scalar_op);
+    if (sizeof(R) != sizeof(double))
+      k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
+  });
+}
 
 struct SolveOut {
   std::vector<int> outer, ru;
@@ -761,12 +907,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   std::vector<int> fcg(ns, 1), fru(ns, 1);
   TRY(set_flags(E, fcg, fru));
   // x64 <- guess was packed by the caller; xR = 0; rcgR = b, |b|^2
-  k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, 2);
-  k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, 1);
+  k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 2);
+  k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 1);
   k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 4);  // BB
   k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);  // RR = |b|^2, beta = 0
   // |x0|^2 -> part_b via prep on x64 (src = x64 in T_CG)
-  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, 0);
+  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 0);
   std::vector<double> x0n(ns);
   for (int s = 0; s < ns; ++s) {
     std::vector<double> tmp(E.sb[s].nblk);
@@ -800,9 +946,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   }
   if (any_guess) {  // r = b - A x0 for warm starts
     TRY(set_flags(E, fcg, fru));
-    TRY(true_residual<R>(E, std::max(P.truth_tol, 1e-3 * P.outer_tol), 3));
-    if (sizeof(R) != sizeof(double))
-      k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), ns, E.nb_total);
+    TRY(reliable_update<R>(E, P.truth_tol, 3));
     TRY(read_scalars(E));
     for (int s = 0; s < ns; ++s)
       if (fru[s]) {
@@ -813,24 +957,29 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);
   }
   const MsParams mpR = make_mp(c, tol_in, E.pl.capR);
-  const int LR = std::min(E.pl.capR, capacity(c, tol_in));
+  int LR = 0;
+  for (int s = 0; s < ns; ++s) LR = std::max(LR, capacity(E.ctxs[s], tol_in));
+  LR = std::min(E.pl.capR, LR);
+  char ikey[96];
+  std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d", sizeof(R), tol_in, LR);
   int iter = 0;
-  bool first = true;
   while (true) {
     bool any = false;
     for (int s = 0; s < ns; ++s) any |= (fcg[s] != 0);
     if (!any) break;
     std::fill(fru.begin(), fru.end(), 0);
     TRY(set_flags(E, fcg, fru));
-    // p = r + beta p ; M p ; alpha ; M^dag u with CG update ; beta
-    k_cg_p<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), ns, E.nb_total, first ? 0 : 1);
-    first = false;
-    launch_ms<R>(E, T_IN_M, mpR, LR);
-    launch_combine<R>(E, T_IN_M, EPI_M);
-    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
-    launch_ms<R>(E, T_IN_MDAG, mpR, LR);
-    launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
-    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+    // p = r + beta p (beta = 0 right after a (re)start) ; M p ; alpha ;
+    // M^dag u with the CG update ; beta -- one captured graph per iteration
+    TRY(run_graph(E, ikey, [&]() {
+      k_cg_p<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 1);
+      launch_ms<R>(E, T_IN_M, mpR, LR);
+      launch_combine<R>(E, T_IN_M, EPI_M);
+      k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
+      launch_ms<R>(E, T_IN_MDAG, mpR, LR);
+      launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
+      k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+    }));
     TRY(read_scalars(E));
     ++iter;
     bool need_ru = false, final_check = false;
@@ -865,16 +1014,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     }
     if (need_ru) {
       TRY(set_flags(E, fcg, fru));
-      // x64 += xR ; xR = 0
-      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), ns, E.nb_total, 0);
       // One multi-shift tolerance serves every updated system, so it follows the
       // smallest residual: its operator error must stay ~1% of that residual.
       const double ttol = final_check
                               ? P.truth_tol
                               : std::max(P.truth_tol, std::min(1e-6, 0.01 * best_rec));
-      TRY(true_residual<R>(E, ttol, 3));
-      if (sizeof(R) != sizeof(double))
-        k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), ns, E.nb_total);
+      TRY(reliable_update<R>(E, ttol, 3));
       TRY(read_scalars(E));
       for (int s = 0; s < ns; ++s) {
         if (!fru[s]) continue;
@@ -886,7 +1031,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
           std::fprintf(stderr, "[ov] reliable update s%d at iter %d: true res %.3e (ms tol %.1e)\n",
                        s, iter, out.res[s], ttol);
         if (out.res[s] <= P.outer_tol) {
-          if (ttol <= P.truth_tol) {
+          if (ttol <= P.truth_tol * 1.0000001) {
             out.conv[s] = 1;
             fcg[s] = 0;
           }
@@ -1069,13 +1214,31 @@ ov_status ov_ctx_create(const ov_params* p, void* hip_stream, ov_ctx** out) {
     delete c;
     return OV_ERR_DEVICE;
   }
+  if (hipStreamCreateWithFlags(&c->priv, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess) {
+    g_err = "stream/event creation failed";
+    if (c->priv) (void)hipStreamDestroy(c->priv);
+    delete c;
+    return OV_ERR_DEVICE;
+  }
+  const char* eg = std::getenv("OV_GRAPHS");
+  c->use_graphs = !(eg && *eg == '0');
+  // The persistent cooperative multi-shift kernel is opt-in: its grid barriers
+  // (one L2 write-back and invalidate per workgroup) cost more than a kernel
+  // boundary at these sizes.
+  const char* ep = std::getenv("OV_PERSISTENT");
+  c->persistent = (ep && *ep == '1') ? 1 : 0;
   *out = c;
   return OV_OK;
 }
 
 ov_status ov_ctx_destroy(ov_ctx* c) {
   if (!c) return OV_ERR_INVALID_ARG;
+  if (c->priv) (void)hipStreamSynchronize(c->priv);
+  clear_graphs(c);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->priv) (void)hipStreamDestroy(c->priv);
   if (c->own_ws) (void)hipFree(c->own_ws);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
@@ -1108,6 +1271,8 @@ ov_status ov_set_workspace(ov_ctx* c, void* ptr, size_t bytes) {
     c->err = "workspace must be 256-byte aligned";
     return OV_ERR_INVALID_ARG;
   }
+  if (c->priv) (void)hipStreamSynchronize(c->priv);
+  clear_graphs(c);
   c->user_ws = ptr;
   c->user_ws_bytes = ptr ? bytes : 0;
   return OV_OK;
@@ -1303,7 +1468,7 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   // zero guess directly in x64
   for (int r = 0; r < nrhs; ++r) {
     bv[r] = (const char*)xi + r * vb;
-    HIPCHK(c, hipMemsetAsync(E.sb[r].x64, 0, vb, c->stream));
+    HIPCHK(c, hipMemsetAsync(E.sb[r].x64, 0, vb, E.st));
   }
   SolveOut so;
   const double tolR = c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol;
@@ -1333,11 +1498,11 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   TRY(upload_tables(E));
   MsParams mp = make_mp(c, c->p.truth_tol, E.pl.cap64);
   const int L = std::min(E.pl.cap64, capacity(c, c->p.truth_tol));
-  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total, 0);
+  k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
   launch_ms<double>(E, T_APPLY, mp, L);
   launch_combine<double>(E, T_APPLY, EPI_M);
   // S_r = Re <xi_r, X_r>
-  k_dot_re<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total);
+  k_dot_re<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total);
   // G summed over right-hand sides in order (one launch over the sites)
   k_force<<<E.sb[0].nblk, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.sb[0].nblk,
                                                (double2*)grad_phi);
@@ -1371,10 +1536,10 @@ ov_status ov_pack(ov_ctx* c, int prec, void* dst, const void* src, int nrhs) {
   }
   HIPCHK(c, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, E.st));
   if (prec)
-    k_pack<float><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total,
+    k_pack<float><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total,
                                                      (const double2* const*)E.ptrs, E.ptrs + nrhs, 1.0);
   else
-    k_pack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total,
+    k_pack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total,
                                                       (const double2* const*)E.ptrs, E.ptrs + nrhs, 1.0);
   return sync(E);
 }
@@ -1396,10 +1561,10 @@ ov_status ov_unpack(ov_ctx* c, int prec, void* dst, const void* src, int nrhs) {
   }
   HIPCHK(c, hipMemcpyAsync(E.ptrs, h.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, E.st));
   if (prec)
-    k_unpack<float><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total, E.ptrs,
+    k_unpack<float><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, E.ptrs,
                                                        (double2* const*)(E.ptrs + nrhs));
   else
-    k_unpack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.nb_total, E.ptrs,
+    k_unpack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, E.ptrs,
                                                         (double2* const*)(E.ptrs + nrhs));
   return sync(E);
 }
@@ -1412,7 +1577,7 @@ ov_status ov_kernel_sampling(ov_ctx* c, int max_per_call) {
 
 ov_status ov_kernel_times(ov_ctx* c, int k, double* total_ms, long long* count, double* bytes,
                           int reset) {
-  if (!c || k < 0 || k > 1) return OV_ERR_INVALID_ARG;
+  if (!c || k < 0 || k > 2) return OV_ERR_INVALID_ARG;
   if (total_ms) *total_ms = c->ksum_ms[k];
   if (count) *count = c->kcount[k];
   if (bytes) *bytes = c->ksum_bytes[k];
@@ -1435,7 +1600,9 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
   E.nsys = nrhs;
   E.sb.assign(nrhs, SysBuf{});
   E.lead = c;
-  E.st = c->stream;
+  E.st = c->priv;
+  HIPCHK(c, hipEventRecord(c->ev_in, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(E.st, c->ev_in, 0));
   E.pl.cap64 = 1;
   E.pl.capR = 0;
   E.pl.solve = false;
@@ -1455,11 +1622,16 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
     }
     E.nb_total = blk;
     dry.take(sizeof(SysDev) * nrhs);
+    dry.take(sizeof(int) * (size_t)blk);
     void* base = nullptr;
-    TRY(ensure_ws(c, dry.off + 512, &base));
-    Bump bp(base, dry.off + 512, false);
+    TRY(ensure_ws(c, dry.off + 1024, &base));
+    Bump bp(base, dry.off + 1024, false);
     for (int s = 0; s < nrhs; ++s) E.sb[s].part_c = (double*)bp.take(sizeof(double) * E.sb[s].nblk);
     E.tables = (SysDev*)bp.take(sizeof(SysDev) * nrhs);
+    E.bmap = (int*)bp.take(sizeof(int) * (size_t)blk);
+    E.hbmap.assign(blk, 0);
+    for (int s = 0; s < nrhs; ++s)
+      for (int b = 0; b < E.sb[s].nblk; ++b) E.hbmap[E.sb[s].blk0 + b] = s;
   }
   const size_t V = E.sb[0].V;
   const size_t es = prec ? sizeof(float2) : sizeof(double2);
@@ -1472,6 +1644,9 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
   }
   HIPCHK(c, hipMemcpyAsync(E.tables, E.htab.data(), sizeof(SysDev) * nrhs, hipMemcpyHostToDevice,
                            E.st));
+  HIPCHK(c, hipMemcpyAsync(E.bmap, E.hbmap.data(), sizeof(int) * E.hbmap.size(),
+                           hipMemcpyHostToDevice, E.st));
+  HIPCHK(c, hipStreamSynchronize(E.st));
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -1479,9 +1654,9 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
   HIPCHK(c, hipEventRecord(e0, E.st));
   for (int r = 0; r < reps; ++r) {
     if (prec)
-      k_hw<float><<<E.nb_total, c->block, 0, E.st>>>(E.tables, nrhs, E.nb_total, diag, 0);
+      k_hw<float><<<E.nb_total, c->block, 0, E.st>>>(E.tables, E.bmap, E.nb_total, diag, 0);
     else
-      k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(E.tables, nrhs, E.nb_total, diag, 0);
+      k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(E.tables, E.bmap, E.nb_total, diag, 0);
   }
   HIPCHK(c, hipEventRecord(e1, E.st));
   TRY(check_launch(c));
