@@ -88,6 +88,10 @@ typedef struct {
   int max_inner;           /* multi-shift iteration cap (<= basis capacity) */
   int max_outer;           /* outer CG iteration cap */
   ov_precision precision;  /* OV_FP64 or OV_MIXED for ov_solve / ov_force */
+  double inner_relax;      /* inexact-Krylov relaxation of the solver's inner sign:
+                              tol_j = inner_relax * ||r_cycle|| / ||r_j||, clamped to
+                              [inner tolerance, inner_tol_max]; 0 keeps it fixed */
+  double inner_tol_max;    /* loosest inner multi-shift tolerance the relaxation uses */
 } ov_params;
 
 typedef struct {

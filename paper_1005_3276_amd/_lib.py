@@ -33,7 +33,8 @@ class OvParams(C.Structure):
                 ("inner_tol", C.c_double), ("outer_tol", C.c_double),
                 ("truth_tol", C.c_double), ("mixed_inner_tol", C.c_double),
                 ("reliable_delta", C.c_double), ("max_inner", C.c_int),
-                ("max_outer", C.c_int), ("precision", C.c_int)]
+                ("max_outer", C.c_int), ("precision", C.c_int),
+                ("inner_relax", C.c_double), ("inner_tol_max", C.c_double)]
 
 
 class OvStats(C.Structure):

@@ -956,12 +956,6 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     // restart the recurrence from the true residual
     k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);
   }
-  const MsParams mpR = make_mp(c, tol_in, E.pl.capR);
-  int LR = 0;
-  for (int s = 0; s < ns; ++s) LR = std::max(LR, capacity(E.ctxs[s], tol_in));
-  LR = std::min(E.pl.capR, LR);
-  char ikey[96];
-  std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d", sizeof(R), tol_in, LR);
   int iter = 0;
   while (true) {
     bool any = false;
@@ -969,6 +963,28 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     if (!any) break;
     std::fill(fru.begin(), fru.end(), 0);
     TRY(set_flags(E, fcg, fru));
+    // Inner multi-shift tolerance of this iteration.  With relaxation the sign
+    // may be as inexact as inner_relax * ||r_cycle|| / ||r_j|| (the error it
+    // adds to the residual gap stays a fixed fraction of the cycle's start,
+    // van den Eshof & Sleijpen's inexact-Krylov bound); the tightest system
+    // sets it, rounded down to a power of ten.
+    double tol_it = tol_in;
+    if (P.inner_relax > 0.0) {
+      double t = P.inner_tol_max;
+      for (int s = 0; s < ns; ++s) {
+        if (!fcg[s]) continue;
+        const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_RR];
+        const double rn = std::sqrt(std::max(rr, 0.0));
+        t = std::min(t, rn > 0.0 ? P.inner_relax * rmax[s] / rn : P.inner_tol_max);
+      }
+      tol_it = std::max(tol_in, std::pow(10.0, std::floor(std::log10(t) + 1e-9)));
+    }
+    const MsParams mpR = make_mp(c, tol_it, E.pl.capR);
+    int LR = 0;
+    for (int s = 0; s < ns; ++s) LR = std::max(LR, capacity(E.ctxs[s], tol_it));
+    LR = std::min(E.pl.capR, LR);
+    char ikey[96];
+    std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d", sizeof(R), tol_it, LR);
     // p = r + beta p (beta = 0 right after a (re)start) ; M p ; alpha ;
     // M^dag u with the CG update ; beta -- one captured graph per iteration
     TRY(run_graph(E, ikey, [&]() {
@@ -1071,6 +1087,10 @@ ov_status validate(const ov_params* p, std::string& err) {
     err = "tolerances must be positive (0 <= reliable_delta < 1)";
     return OV_ERR_INVALID_ARG;
   }
+  if (p->inner_relax < 0 || !(p->inner_tol_max > 0) || p->inner_tol_max >= 1) {
+    err = "need inner_relax >= 0 and 0 < inner_tol_max < 1";
+    return OV_ERR_INVALID_ARG;
+  }
   if (p->max_inner < 4 || p->max_outer < 1) {
     err = "max_inner >= 4 and max_outer >= 1 required";
     return OV_ERR_INVALID_ARG;
@@ -1153,10 +1173,12 @@ void ov_params_default(ov_params* p) {
   p->outer_tol = 1e-10;
   p->truth_tol = 1e-13;
   p->mixed_inner_tol = 1e-6;
-  p->reliable_delta = 0.1;
+  p->reliable_delta = 0.03;
   p->max_inner = 400;
   p->max_outer = 2000;
   p->precision = OV_MIXED;
+  p->inner_relax = 1e-3;
+  p->inner_tol_max = 1e-2;
 }
 
 const char* ov_status_string(ov_status s) {
@@ -1370,7 +1392,8 @@ static bool same_solver(const ov_params& a, const ov_params& b) {
   return a.n_poles == b.n_poles && a.lambda_min == b.lambda_min && a.lambda_max == b.lambda_max &&
          a.inner_tol == b.inner_tol && a.outer_tol == b.outer_tol && a.truth_tol == b.truth_tol &&
          a.mixed_inner_tol == b.mixed_inner_tol && a.reliable_delta == b.reliable_delta &&
-         a.precision == b.precision && a.M0 == b.M0;
+         a.precision == b.precision && a.M0 == b.M0 && a.inner_relax == b.inner_relax &&
+         a.inner_tol_max == b.inner_tol_max;
 }
 
 static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,
