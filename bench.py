@@ -64,6 +64,69 @@ def cpu_baseline(phi, src, outer_iters):
                       f"{per:.2f} s each, scaled by {outer_iters} outer CG iterations"}
 
 
+def other_configs(torch, Lattice, inputs):
+    """Timed runs of the batched (16^3x32, 12 rhs), force (12^4) and uneven-batch
+    workloads; one warm-up and one timed call each."""
+    from paper_1005_3276_amd import solve_batch
+    out = {}
+    # config 3
+    dims = (16, 16, 16, 32)
+    phi, src = inputs.draw(dims, nrhs=12, sigma2=0.5, seed=inputs.config_seed(3))
+    lat = Lattice(dims, precision="mixed", m=0.02, g=0.5, n_poles=20, lambda_min=1e-3,
+                  lambda_max=8.0, outer_tol=1e-10)
+    b, p = torch.from_numpy(src).cuda(), torch.from_numpy(phi).cuda()
+    lat.solve(b, p)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st = lat.solve(b, p)
+    torch.cuda.synchronize()
+    e = time.perf_counter() - t
+    out["config3_batched_16x3x32_12rhs"] = {
+        "seconds": e, "rhs_solves_per_s": 12 / e,
+        "max_true_rel_res": max(s["true_rel_res"] for s in st),
+        "outer_iters": [s["outer_iters"] for s in st]}
+    log(f"config3: {out['config3_batched_16x3x32_12rhs']}")
+    del lat
+    # config 4
+    dims = (12, 12, 12, 12)
+    phi, xi = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(4))
+    lat = Lattice(dims, precision="mixed", m=0.05, g=0.3, n_poles=20, lambda_min=1e-3,
+                  lambda_max=8.0, outer_tol=1e-10)
+    x_, p_ = torch.from_numpy(xi).cuda(), torch.from_numpy(phi).cuda()
+    lat.force(x_, p_)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    S, G, st = lat.force(x_, p_)
+    torch.cuda.synchronize()
+    e = time.perf_counter() - t
+    out["config4_force_12x4"] = {"seconds": e, "forces_per_s": 1 / e, "S": S[0],
+                                 "outer_iters": st[0]["outer_iters"]}
+    log(f"config4: {out['config4_force_12x4']}")
+    del lat
+    # config 5
+    members = [((8, 8, 8, 8), 4), ((12, 12, 12, 12), 4), ((16, 16, 16, 16), 2),
+               ((24, 24, 24, 48), 1)]
+    lats, bs, ps = [], [], []
+    for k, (d, n) in enumerate(members):
+        phi, src = inputs.draw(d, nrhs=n, sigma2=0.25, seed=inputs.config_seed(5) + k)
+        lats.append(Lattice(d, precision="mixed", m=0.05, g=0.3, n_poles=24, lambda_min=1e-4,
+                            lambda_max=8.0, outer_tol=1e-10))
+        bs.append(torch.from_numpy(src).cuda())
+        ps.append(torch.from_numpy(phi).cuda())
+    solve_batch(lats, bs, ps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st = solve_batch(lats, bs, ps)
+    torch.cuda.synchronize()
+    e = time.perf_counter() - t
+    out["config5_uneven_batch"] = {
+        "seconds": e, "rhs_solves_per_s": 11 / e,
+        "max_true_rel_res": max(s["true_rel_res"] for s in st),
+        "outer_iters": [s["outer_iters"] for s in st]}
+    log(f"config5: {out['config5_uneven_batch']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +152,9 @@ def main():
     dsrc = torch.from_numpy(src).cuda()
     lat = Lattice(DIMS, precision="mixed", **CFG)
     lat.use_workspace(1)
+    from paper_1005_3276_amd import tune
+    choice, tune_us = tune.autotune(lat, prec=1, nrhs=1)
+    log(f"autotune: {choice} {tune_us}")
 
     # ---- mixed solves (the metric)
     for _ in range(args.warmup):
@@ -168,6 +234,9 @@ def main():
         extra["stencil"] = sweep
         extra["stencil_best_TB_s"] = max(s["GB_s"] for s in sweep) / 1e3
 
+    if not args.quick:
+        extra.update(other_configs(torch, Lattice, inputs))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(phi, src, fp64_outer)
@@ -195,6 +264,8 @@ def main():
                    "inner_iters": stats[0]["inner_iters"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "autotune": {"block_x_sites_per_thread": list(choice) if choice else None,
+                     "us_per_iteration": tune_us},
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

@@ -176,6 +176,15 @@ ov_status ov_unpack(ov_ctx *ctx, int prec, void *dst, const void *src, int nrhs)
 ov_status ov_set_launch(ov_ctx *ctx, int block, int sites_per_thread);
 ov_status ov_get_launch(const ov_ctx *ctx, int *block, int *sites_per_thread);
 
+/* Autotuner probe: time `iters` multi-shift iterations (t pass + r pass, the
+ * solver's hot loop) in precision prec (0 FP64, 1 FP32) for nrhs systems of
+ * this lattice with `block` threads per workgroup (64..256, multiple of 64) and
+ * `sites_per_thread` (1..16), on a deterministic synthetic source.  Writes the
+ * mean time per iteration in microseconds.  The context's launch setting is
+ * left unchanged; apply the winner with ov_set_launch. */
+ov_status ov_tune_ms(ov_ctx *ctx, int prec, int nrhs, int block, int sites_per_thread, int iters,
+                     float *us_per_iter);
+
 /* Kernel-duration sampling with HIP events recorded on the context's stream.
  * While max_per_call > 0, the first max_per_call launches of each multi-shift
  * kernel (0 = t pass  t_n = H r_n + beta t_{n-1},  1 = r pass  r_{n+1} = r_n -

@@ -21,7 +21,7 @@ OPS = {"hw": OP_HW, "dov": OP_DOV, "dov_dag": OP_DOV_DAG, "m": OP_M, "m_dag": OP
 SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace_bytes",
            "ov_set_workspace", "ov_get_coeffs", "ov_zolotarev", "ov_sign", "ov_apply",
            "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
-           "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_kernel_sampling",
+           "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling",
            "ov_kernel_times", "ov_status_string", "ov_last_error"]
 
 
@@ -84,6 +84,7 @@ def lib():
         L.ov_unpack.argtypes = [P, C.c_int, P, P, C.c_int]
         L.ov_set_launch.argtypes = [P, C.c_int, C.c_int]
         L.ov_get_launch.argtypes = [P, P, P]
+        L.ov_tune_ms.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]
         L.ov_kernel_sampling.argtypes = [P, C.c_int]
         L.ov_kernel_times.argtypes = [P, C.c_int, P, P, P, C.c_int]
         L.ov_status_string.argtypes = [C.c_int]
@@ -93,7 +94,7 @@ def lib():
         for fn in ("ov_ctx_create", "ov_ctx_destroy", "ov_set_workspace", "ov_get_coeffs",
                    "ov_zolotarev", "ov_sign", "ov_apply", "ov_solve", "ov_solve_batch",
                    "ov_force", "ov_stencil_bench", "ov_pack", "ov_unpack", "ov_set_launch",
-                   "ov_get_launch", "ov_kernel_sampling", "ov_kernel_times"):
+                   "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling", "ov_kernel_times"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib

@@ -731,6 +731,30 @@ __global__ void __launch_bounds__(256) k_ms_prep(const SysDev* __restrict__ sys,
   if (threadIdx.x == 0) S.part_b[lb] = tot;
 }
 
+// Deterministic synthetic field for tuning runs: a hash of the site and spin
+// mapped to [-1, 1) in both components, written to src.
+template <class R>
+__global__ void __launch_bounds__(256) k_fill(const SysDev* __restrict__ sys,
+                                              const int* __restrict__ bmap, int nb_total) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  c2<R>* out = (c2<R>*)S.src;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      unsigned int h = (unsigned int)(i * 4 + k) * 2654435761u + 0x9e3779b9u;
+      h ^= h >> 15; h *= 2246822519u; h ^= h >> 13;
+      const unsigned int h2 = h * 3266489917u + 374761393u;
+      out[(size_t)k * V + i] = c2<R>{(R)((double)(h & 0xffffff) / 8388608.0 - 1.0),
+                                     (R)((double)(h2 & 0xffffff) / 8388608.0 - 1.0)};
+    }
+  }
+}
+
 // ------------------------------------------------------------ CG kernels
 // Sum part_c into cg_s[slot]; op 0: store, 1: alpha = rr/pap, 2: beta + rr update.
 __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {

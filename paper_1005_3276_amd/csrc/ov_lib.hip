@@ -1156,6 +1156,48 @@ void fill_stats(ov_stats* st, int n, Engine* E, const SolveOut* so, double secs,
 
 }  // namespace
 
+namespace {
+template <class R>
+ov_status tune_run(ov_ctx* c, int nrhs, int iters, float* us) {
+  Engine E;
+  std::vector<ov_ctx*> v(nrhs, c);
+  const bool fp32 = sizeof(R) == sizeof(float);
+  TRY(engine_init(E, v, true, fp32, 1e-13, 1e-13));
+  E.htab.assign((size_t)T_NT * nrhs, SysDev{});
+  for (int s = 0; s < nrhs; ++s) {
+    SysBuf& b = E.sb[s];
+    SysDev d = base_dev(b);
+    d.basis = fp32 ? b.basisR : (void*)b.basis64;
+    d.r = fp32 ? b.rR : (void*)b.r64ms;
+    d.src = fp32 ? b.pR : (void*)b.x64;
+    E.htab[(size_t)T_APPLY * nrhs + s] = d;
+  }
+  TRY(upload_tables(E));
+  TRY(reset_stats(E));
+  const int cap = fp32 ? E.pl.capR : E.pl.cap64;
+  const int L = std::min(iters, cap);
+  MsParams mp = make_mp(c, 1e-300, cap);  // never converges: every iteration works
+  k_fill<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total);
+  k_ms_prep<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
+  launch_ms<R>(E, T_APPLY, mp, std::min(4, L));  // warm-up
+  k_ms_prep<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, E.st));
+  launch_ms<R>(E, T_APPLY, mp, L);
+  HIPCHK(c, hipEventRecord(e1, E.st));
+  TRY(sync(E));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1000.f * ms / (float)L;
+  return OV_OK;
+}
+
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -1313,10 +1355,10 @@ ov_status ov_get_coeffs(const ov_ctx* c, double* a, double* b, double* delta) {
 ov_status ov_set_launch(ov_ctx* c, int block, int spt) {
   if (!c) return OV_ERR_INVALID_ARG;
   if (block) {
-    if (block < 64 || block > 1024 || (block & 63)) return OV_ERR_INVALID_ARG;
+    if (block < 64 || block > 256 || (block & 63)) return OV_ERR_INVALID_ARG;
     c->block = block;
   }
-  if (spt < 0 || spt > 64) return OV_ERR_INVALID_ARG;
+  if (spt < 0 || spt > 16) return OV_ERR_INVALID_ARG;
   if (spt) c->spt = spt;
   return OV_OK;
 }
@@ -1590,6 +1632,19 @@ ov_status ov_unpack(ov_ctx* c, int prec, void* dst, const void* src, int nrhs) {
     k_unpack<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, E.ptrs,
                                                         (double2* const*)(E.ptrs + nrhs));
   return sync(E);
+}
+
+ov_status ov_tune_ms(ov_ctx* c, int prec, int nrhs, int block, int spt, int iters, float* us) {
+  if (!c || !us || nrhs < 1 || iters < 1 || (prec != 0 && prec != 1) || block < 64 ||
+      block > 256 || (block & 63) || spt < 1 || spt > 16)
+    return OV_ERR_INVALID_ARG;
+  const int ob = c->block, os = c->spt;
+  c->block = block;
+  c->spt = spt;
+  const ov_status st = prec ? tune_run<float>(c, nrhs, iters, us) : tune_run<double>(c, nrhs, iters, us);
+  c->block = ob;
+  c->spt = os;
+  return st;
 }
 
 ov_status ov_kernel_sampling(ov_ctx* c, int max_per_call) {

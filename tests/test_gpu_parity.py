@@ -302,3 +302,105 @@ def test_full_size_16x4_mixed(orc):
     res = o.residual(src[0], host(x)[0], phi)
     print(f"[full] oracle residual {res:.3e} ({time.time() - t:.1f}s)", flush=True)
     assert res <= 1e-10
+
+
+# --------------------------------------------------- full-size configurations
+
+def test_config3_batched_16x3x32(orc):
+    """Config 3: 16^3 x 32, 12 sources x 20 shifts in one batched solve (mixed),
+    phi ~ CN(0, 0.5), g = 0.5, m = 0.02.  Every member meets its residual on the
+    GPU's FP64 check; two sampled members are re-checked under the oracle."""
+    dims = (16, 16, 16, 32)
+    kw = dict(m=0.02, g=0.5, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+    phi, src = inputs.draw(dims, nrhs=12, sigma2=0.5, seed=inputs.config_seed(3))
+    lat = lattice(dims, precision="mixed", outer_tol=1e-10, **kw)
+    t = time.time()
+    x, st = lat.solve(dev(src), dev(phi))
+    torch.cuda.synchronize()
+    print(f"[cfg3] 12 rhs in {time.time() - t:.2f}s, outer {[s['outer_iters'] for s in st]}",
+          flush=True)
+    assert all(s["true_rel_res"] <= 1e-10 for s in st)
+    xh = host(x)
+    o = orc.Oracle(dims, inner_tol=1e-12, **kw)
+    for r in (0, 7):
+        res = o.residual(src[r], xh[r], phi)
+        print(f"[cfg3] rhs {r} oracle residual {res:.3e}", flush=True)
+        assert res <= 1e-10
+
+
+def test_config4_force_12x4(orc):
+    """Config 4: HMC force at 12^4 (g = 0.3, m = 0.05, phi ~ CN(0, 0.25)) against the
+    oracle's gradient, and S against the oracle's action."""
+    dims = (12, 12, 12, 12)
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+    phi, xi = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(4))
+    lat = lattice(dims, precision="mixed", outer_tol=1e-12, truth_tol=1e-13, **kw)
+    t = time.time()
+    S, G, st = lat.force(dev(xi), dev(phi))
+    torch.cuda.synchronize()
+    print(f"[cfg4] force in {time.time() - t:.2f}s {st[0]}", flush=True)
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    t = time.time()
+    So, Go, ost, rc = o.force(phi, xi[0], tol=1e-12)
+    print(f"[cfg4] oracle force in {time.time() - t:.1f}s", flush=True)
+    assert rc == 0
+    assert abs(S[0] - So) <= 1e-9 * abs(So)
+    Gh = host(G)
+    assert np.abs(Gh - Go).max() <= 1e-8 * np.abs(Go).max()
+
+
+def test_config5_uneven_full(orc):
+    """Config 5: 8^4 x 4, 12^4 x 4, 16^4 x 2 and 24^3 x 48 x 1 sources in one
+    batched mixed solve, 24 poles on [1e-4, 8]; each member meets 1e-10 on the
+    GPU's FP64 check; the 24^3 x 48 member and one 8^4 member are re-checked
+    under the oracle."""
+    from paper_1005_3276_amd import solve_batch
+    kw = dict(m=0.05, g=0.3, n_poles=24, lambda_min=1e-4, lambda_max=8.0)
+    members = [((8, 8, 8, 8), 4), ((12, 12, 12, 12), 4), ((16, 16, 16, 16), 2),
+               ((24, 24, 24, 48), 1)]
+    lats, bs, phis, raw = [], [], [], []
+    for k, (dims, nrhs) in enumerate(members):
+        phi, src = inputs.draw(dims, nrhs=nrhs, sigma2=0.25, seed=inputs.config_seed(5) + k)
+        lats.append(lattice(dims, precision="mixed", outer_tol=1e-10, **kw))
+        bs.append(dev(src))
+        phis.append(dev(phi))
+        raw.append((dims, phi, src))
+    t = time.time()
+    xs, st = solve_batch(lats, bs, phis)
+    torch.cuda.synchronize()
+    print(f"[cfg5] 11 systems in {time.time() - t:.2f}s, outer "
+          f"{[s['outer_iters'] for s in st]}", flush=True)
+    assert all(s["true_rel_res"] <= 1e-10 for s in st)
+    for idx, r in ((3, 0), (0, 2)):
+        dims, phi, src = raw[idx]
+        o = orc.Oracle(dims, inner_tol=1e-12, **kw)
+        res = o.residual(src[r], host(xs[idx])[r], phi)
+        print(f"[cfg5] member {dims} rhs {r} oracle residual {res:.3e}", flush=True)
+        assert res <= 1e-10
+
+
+# ---------------------------------------------------------------- autotuner
+
+def test_autotune_choices_agree(tmp_path, monkeypatch):
+    """The tuner times every candidate launch shape, applies the fastest, caches it,
+    and every candidate gives the same sign to rounding."""
+    monkeypatch.setenv("OV_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setenv("OV_TUNE", "1")
+    from paper_1005_3276_amd import tune
+    dims = (8, 8, 8, 8)
+    lat = lattice(dims, inner_tol=1e-12, **CFG2)
+    choice, timings = tune.autotune(lat, prec=1, nrhs=2)
+    print(f"[tune] {choice} {timings}", flush=True)
+    assert choice in tune.CANDIDATES and len(timings) == len(tune.CANDIDATES)
+    assert all(v > 0 for v in timings.values())
+    choice2, _ = tune.autotune(lat, prec=1, nrhs=2)  # from the cache
+    assert choice2 == choice
+    x = inputs.gaussian_field(dims, nrhs=2, seed=12)
+    ref = None
+    for b, s in tune.CANDIDATES:
+        lat.set_launch(b, s)
+        out = host(lat.sign(dev(x))[0])
+        if ref is None:
+            ref = out
+        else:
+            assert rel(out, ref) < 1e-12
