@@ -49,7 +49,8 @@ struct SysDev {
   double* h_zeta;           // [(cap+1) * MAXP]
   unsigned int* h_active;   // [cap+1] shift masks
   int* h_ctl;               // [4]: done, n_done, status, sticky error (host-reset)
-  long long* stat;          // [4]: inner iterations, multi-shift solves, max N, (unused)
+  long long* stat;          // [4]: inner iterations, multi-shift solves, max N, max N of the
+                            //      current outer iteration (cleared by k_cg_p)
   double* dstat;            // [2]: max shift residual of the last multi-shift, (unused)
   double* coef_term;        // [MAXP * cap]
   double* coef_c;           // [cap+1]
@@ -482,10 +483,16 @@ __global__ void k_bar_reset(GridBar* gb) {
 //   y_k = sum_j z^j S_k^j r_j,  S_k^j = alpha_{j,k} + beta_{j,k} S_k^{j+1},  S_k^{N_k} = 0,
 //   acc = sum_j c_j r_j,  c_j = sum_k a_k z^j S_k^j,
 //   eps = H acc = sum_j d_j t_j,  d_j = c_j - beta_j c_{j+1}   (H r_j = t_j - beta_{j-1} t_{j-1}).
-__global__ void k_ms_coef(const SysDev* __restrict__ sys, int nsys, int launched,
-                          const MsParams mp_) {
+constexpr int COEF_LDS_ITERS = 160;  // history rows staged in LDS (larger N reads global)
+
+__global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys, int nsys,
+                                                 int launched, const MsParams mp_) {
   __shared__ int sh_N;
   __shared__ double sh_res[MAXP];
+  __shared__ double l_rho[COEF_LDS_ITERS + 1];
+  __shared__ double l_alpha[COEF_LDS_ITERS + 1];
+  __shared__ unsigned int l_act[COEF_LDS_ITERS + 1];
+  __shared__ double l_zeta[(COEF_LDS_ITERS + 1) * MAXP];
   const int s = blockIdx.x;
   if (s >= nsys) return;
   const SysDev& S = sys[s];
@@ -507,28 +514,47 @@ __global__ void k_ms_coef(const SysDev* __restrict__ sys, int nsys, int launched
     S.stat[0] += N;
     S.stat[1] += 1;
     if (N > S.stat[2]) S.stat[2] = N;
+    if (N > S.stat[3]) S.stat[3] = N;  // max N since the host last cleared it
   }
   __syncthreads();
   const int N = sh_N;
-  const double rho0 = S.h_rho[0];
+  // stage rows 0..N of the history (coalesced) when they fit
+  const bool staged = N <= COEF_LDS_ITERS;
+  const double* rho = S.h_rho;
+  const double* alph = S.h_alpha;
+  const unsigned int* actv = S.h_active;
+  const double* zeta = S.h_zeta;
+  if (staged) {
+    for (int j = threadIdx.x; j <= N; j += blockDim.x) {
+      l_rho[j] = S.h_rho[j];
+      l_alpha[j] = S.h_alpha[j];
+      l_act[j] = S.h_active[j];
+    }
+    for (int q = threadIdx.x; q < (N + 1) * MAXP; q += blockDim.x) l_zeta[q] = S.h_zeta[q];
+    __syncthreads();
+    rho = l_rho;
+    alph = l_alpha;
+    actv = l_act;
+    zeta = l_zeta;
+  }
+  const double rho0 = rho[0];
   for (int k = threadIdx.x; k < MAXP; k += blockDim.x) sh_res[k] = 0.0;
   __syncthreads();
   for (int k = threadIdx.x; k < np; k += blockDim.x) {
     int Nk = N;
     for (int j = 0; j < N; ++j)
-      if (!(S.h_active[j] & (1u << k))) { Nk = j; break; }
+      if (!(actv[j] & (1u << k))) { Nk = j; break; }
     double Sk = 0.0;
     for (int j = Nk - 1; j >= 0; --j) {
-      const double zj = S.h_zeta[(size_t)j * MAXP + k];
-      const double zr = S.h_zeta[(size_t)(j + 1) * MAXP + k] / zj;
-      const double aj = S.h_alpha[j] * zr;
-      const double bj = (S.h_rho[j + 1] / S.h_rho[j]) * zr * zr;
+      const double zj = zeta[(size_t)j * MAXP + k];
+      const double zr = zeta[(size_t)(j + 1) * MAXP + k] / zj;
+      const double aj = alph[j] * zr;
+      const double bj = (rho[j + 1] / rho[j]) * zr * zr;
       Sk = aj + bj * Sk;
       S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zj * Sk;
     }
     for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
-    if (rho0 > 0.0)
-      sh_res[k] = fabs(S.h_zeta[(size_t)Nk * MAXP + k]) * sqrt(S.h_rho[Nk] / rho0);
+    if (rho0 > 0.0) sh_res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
   }
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
@@ -539,7 +565,7 @@ __global__ void k_ms_coef(const SysDev* __restrict__ sys, int nsys, int launched
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     const double cn = (j + 1 < N) ? S.coef_c[j + 1] : 0.0;
-    S.coef_d[j] = S.coef_c[j] - (S.h_rho[j + 1] / S.h_rho[j]) * cn;
+    S.coef_d[j] = S.coef_c[j] - (rho[j + 1] / rho[j]) * cn;
   }
   if (threadIdx.x == 0) {
     double mx = 0.0;
@@ -805,6 +831,7 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
   const int V = S.g.V;
   const double beta = use_beta ? S.cg_s[CG_BETA] : 0.0;
   use_beta = use_beta && beta != 0.0;  // restart: p = r, the old p is never read
+  if (lb == 0 && threadIdx.x == 0) S.stat[3] = 0;
   const int i0 = lb * S.spb;
   const int i1 = min(V, i0 + S.spb);
   double acc = 0.0;

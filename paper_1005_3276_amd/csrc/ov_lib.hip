@@ -30,8 +30,9 @@ struct ov_ctx {
   hipStream_t priv = nullptr;    // private non-blocking stream all work runs on
   hipEvent_t ev_in = nullptr;    // caller-stream marker the private stream waits for
   std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
-  bool use_graphs = true;
+  bool use_graphs = false;
   int persistent = 0;            // cooperative persistent multi-shift kernel (0: per-pass kernels)
+  std::map<long long, int> n_est;  // (precision, tolerance) -> iterations the last multi-shift needed
   int coop_cap[2] = {0, 0};      // co-resident workgroups of k_ms_persistent<double/float>
   int device = 0;
   std::string err;
@@ -200,7 +201,6 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
   s.h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
   s.h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
   s.h_ctl = (int*)bp.take(sizeof(int) * 4);
-  s.stat = (long long*)bp.take(sizeof(long long) * 4);
   s.dstat = (double*)bp.take(sizeof(double) * 2);
   s.coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
   s.coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
@@ -226,6 +226,7 @@ struct Engine {
   std::vector<void*> hptrs;         // host staging of ptrs (outlives the async copy)
   GridBar* gbar = nullptr;          // device: grid barrier of the persistent kernel
   double* cg_all = nullptr;         // device: nsys * CG_NSLOT scalars (one copy to the host)
+  long long* stat_all = nullptr;    // device: nsys * 4 multi-shift counters
   int* act_all = nullptr;           // device: act_cg[nsys] then act_ru[nsys]
   std::vector<int> last_flags;      // last uploaded flags (upload only on change)
   MsParams mp64{}, mpR{};
@@ -235,6 +236,7 @@ struct Engine {
     Bump bp(base, cap, dry);
     gbar = (GridBar*)bp.take(sizeof(GridBar));
     cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys);
+    stat_all = (long long*)bp.take(sizeof(long long) * 4 * nsys);
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0;
     for (int s = 0; s < nsys; ++s) {
@@ -248,6 +250,7 @@ struct Engine {
       blk += b.nblk;
       carve(bp, b, pl);
       b.cg_s = dry ? nullptr : cg_all + (size_t)s * CG_NSLOT;
+      b.stat = dry ? nullptr : stat_all + (size_t)s * 4;
       b.act_cg = dry ? nullptr : act_all + s;
       b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
@@ -290,7 +293,7 @@ ov_status ensure_pinned(ov_ctx* c, int nsys) {
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   c->pinned = nullptr;
   c->pinned_flags = nullptr;
-  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * CG_NSLOT * nsys));
+  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 4) * nsys));
   HIPCHK(c, hipHostMalloc((void**)&c->pinned_flags, sizeof(int) * 2 * nsys + 64));
   c->pinned_n = nsys;
   return OV_OK;
@@ -476,7 +479,7 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
                                      dim3(c->block), args, 0, E.st);
     }
     if (e == hipSuccess) {
-      k_ms_coef<<<E.nsys, 64, 0, E.st>>>(T, E.nsys, L, mp);
+      k_ms_coef<<<E.nsys, 256, 0, E.st>>>(T, E.nsys, L, mp);
       return;
     }
     (void)hipGetLastError();
@@ -492,7 +495,7 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
       k_ms_r<R><<<E.nb_total, c->block, 0, E.st>>>(T, E.bmap, E.nb_total, n, mp);
     }
   }
-  k_ms_coef<<<E.nsys, 64, 0, E.st>>>(T, E.nsys, L, mp);
+  k_ms_coef<<<E.nsys, 256, 0, E.st>>>(T, E.nsys, L, mp);
 }
 
 template <class R>
@@ -784,7 +787,21 @@ ov_status set_flags(Engine& E, const std::vector<int>& cg, const std::vector<int
 ov_status read_scalars(Engine& E) {
   HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all, sizeof(double) * CG_NSLOT * E.nsys,
                                 hipMemcpyDeviceToHost, E.st));
+  HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned + (size_t)CG_NSLOT * E.nsys, E.stat_all,
+                                sizeof(long long) * 4 * E.nsys, hipMemcpyDeviceToHost, E.st));
   return sync(E);
+}
+
+// Largest multi-shift iteration count of the current outer iteration (stat[3]).
+int last_ms_iters(const Engine& E) {
+  const long long* st = (const long long*)(E.lead->pinned + (size_t)CG_NSLOT * E.nsys);
+  long long m = 0;
+  for (int s = 0; s < E.nsys; ++s) m = std::max(m, st[(size_t)s * 4 + 3]);
+  return (int)m;
+}
+
+long long n_est_key(size_t rsize, double tol) {
+  return (long long)rsize * 1000 + (long long)std::lround(-std::log10(tol) * 10.0);
 }
 
 // Run `enqueue` (kernel launches only) through a cached hipGraph keyed by
@@ -983,6 +1000,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     int LR = 0;
     for (int s = 0; s < ns; ++s) LR = std::max(LR, capacity(E.ctxs[s], tol_it));
     LR = std::min(E.pl.capR, LR);
+    // launch what the last multi-shift at this tolerance needed, plus a margin
+    const long long nkey = n_est_key(sizeof(R), tol_it);
+    {
+      auto it = c->n_est.find(nkey);
+      if (it != c->n_est.end()) LR = std::min(LR, it->second + 2);
+    }
     char ikey[96];
     std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d", sizeof(R), tol_it, LR);
     // p = r + beta p (beta = 0 right after a (re)start) ; M p ; alpha ;
@@ -998,6 +1021,17 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     }));
     TRY(read_scalars(E));
     ++iter;
+    {
+      // learn the iteration count; a multi-shift that ran out of launches
+      // (sticky flag) widens the estimate for the next iteration
+      const int nobs = last_ms_iters(E);
+      int& est = c->n_est[nkey];
+      if (nobs >= LR - 1) {
+        est = std::max(est, LR + 6);
+      } else {
+        est = nobs;
+      }
+    }
     bool need_ru = false, final_check = false;
     double best_rec = 1e300;  // the tightest residual among the systems updated now
     if (ov_log()) {
@@ -1286,7 +1320,7 @@ ov_status ov_ctx_create(const ov_params* p, void* hip_stream, ov_ctx** out) {
     return OV_ERR_DEVICE;
   }
   const char* eg = std::getenv("OV_GRAPHS");
-  c->use_graphs = !(eg && *eg == '0');
+  c->use_graphs = (eg && *eg == '1');
   // The persistent cooperative multi-shift kernel is opt-in: its grid barriers
   // (one L2 write-back and invalidate per workgroup) cost more than a kernel
   // boundary at these sizes.
