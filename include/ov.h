@@ -67,7 +67,12 @@ typedef enum {
   OV_OP_DOV_DAG = 2, /* psi + eps(g5 psi) */
   OV_OP_M = 3,       /* D_ov psi + c+ P+ psi + c- P- psi */
   OV_OP_M_DAG = 4,   /* D_ov^dag psi + c+* P+ psi + c-* P- psi */
-  OV_OP_MDAGM = 5    /* M^dag M psi */
+  OV_OP_MDAGM = 5,   /* M^dag M psi */
+  OV_OP_M0INV = 6,   /* M0^-1 psi, M0 = D_ov + m P+ + m* P- the free (phi = 0) fermion
+                        matrix with the same rational sign: the preconditioner of
+                        Sec. 7.3, applied exactly in momentum space (per-axis DFTs;
+                        needs every extent <= 64, X*Y <= 1024, X*Z <= 1024) */
+  OV_OP_M0INV_DAG = 7 /* M0^-dag psi (same limits) */
 } ov_op;
 
 typedef struct {
@@ -92,6 +97,11 @@ typedef struct {
                               tol_j = inner_relax * ||r_cycle|| / ||r_j||, clamped to
                               [inner tolerance, inner_tol_max]; 0 keeps it fixed */
   double inner_tol_max;    /* loosest inner multi-shift tolerance the relaxation uses */
+  int precondition;        /* 1 (default): solve with the free-field preconditioner of
+                              Sec. 7.3, CG on (M M0^-1)^dag (M M0^-1) x~ = M0^-dag b,
+                              x = M0^-1 x~ (lattice limits of OV_OP_M0INV); 0: plain CG
+                              on MdagM.  Convergence is always judged on the FP64 true
+                              residual of the original system. */
 } ov_params;
 
 typedef struct {
@@ -134,7 +144,8 @@ ov_status ov_zolotarev(int n, double lmin, double lmax, double *a, double *b, do
 /* out = eps(in) = H_W sum_k a_k (H_W^2 + b_k)^-1 in, FP64, for nrhs fields. */
 ov_status ov_sign(ov_ctx *ctx, void *out, const void *in, int nrhs, ov_stats *st);
 
-/* out = op(in) for nrhs fields (FP64).  phi is required for OV_OP_M* ops. */
+/* out = op(in) for nrhs fields (FP64).  phi is required for OV_OP_M, OV_OP_M_DAG and
+ * OV_OP_MDAGM and ignored otherwise. */
 ov_status ov_apply(ov_ctx *ctx, ov_op op, void *out, const void *in, const void *phi,
                    int nrhs, ov_stats *st);
 

@@ -65,6 +65,7 @@ def lib():
         L.orc_residual.argtypes = [P, P, P, P]
         L.orc_residual.restype = C.c_double
         L.orc_threads.restype = C.c_int
+        L.orc_m0inv.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int]
         _lib = L
     return _lib
 
@@ -195,6 +196,16 @@ class Oracle:
         rc = lib().orc_force(C.byref(self.p), _ptr(ph), _ptr(xi), tol, maxit, C.byref(S),
                              _ptr(G), C.byref(st))
         return S.value, G.reshape(self.shape[:4]), st, rc
+
+    def m0inv(self, v, dag=False, tol=1e-13, maxit=4000):
+        """M0^-1 v (or M0^-dag v), M0 = M at phi = 0: the free-field
+        preconditioner of Sec. 7.3, from its definition by CG."""
+        v = self._field(v)
+        out = np.empty_like(v)
+        rc = lib().orc_m0inv(C.byref(self.p), 1 if dag else 0, _ptr(v), _ptr(out), tol, maxit)
+        if rc != 0:
+            raise RuntimeError(f"orc_m0inv did not converge ({rc})")
+        return out.reshape(v.shape)
 
     def residual(self, b, x, phi):
         b = self._field(b)

@@ -584,3 +584,26 @@ int orc_force(const orc_params *p, const cplx *phi, const cplx *xi, double tol, 
   free(Y);
   return rc;
 }
+
+/* Free-field preconditioner of Sec. 7.3: M0 is the fermion matrix at phi = 0
+ * (same operator, same rational sign), and the preconditioned problem uses
+ * M0^-1 and M0^-dag.  Taken from their definitions:
+ *   M0^-1 v   = (M0^dag M0)^-1 M0^dag v,
+ *   M0^-dag v = M0 (M0^dag M0)^-1 v,
+ * with the CG of orc_solve on MdagM at phi = 0 (true relative residual <= tol). */
+int orc_m0inv(const orc_params *p, int dag, const cplx *in, cplx *out, double tol, int maxit) {
+  long long V = volume(p), N = 4 * V;
+  cplx *phi0 = vec_new(V), *t = vec_new(N);
+  long long inner = 0;
+  int rc;
+  if (!dag) {
+    orc_apply(p, ORC_OP_M_DAG, phi0, in, t, &inner);
+    rc = orc_solve(p, phi0, t, out, tol, maxit, NULL);
+  } else {
+    rc = orc_solve(p, phi0, in, t, tol, maxit, NULL);
+    orc_apply(p, ORC_OP_M, phi0, t, out, &inner);
+  }
+  free(phi0);
+  free(t);
+  return rc;
+}

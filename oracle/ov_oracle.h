@@ -107,6 +107,11 @@ int orc_force(const orc_params *p, const double complex *phi, const double compl
 double orc_residual(const orc_params *p, const double complex *phi,
                     const double complex *b, const double complex *x);
 
+/* out = M0^-1 in (dag = 0) or M0^-dag in (dag = 1), M0 = M at phi = 0 (the
+ * free-field preconditioner of Sec. 7.3), by CG to relative residual tol. */
+int orc_m0inv(const orc_params *p, int dag, const double complex *in, double complex *out,
+              double tol, int maxit);
+
 int orc_threads(void);
 
 #endif

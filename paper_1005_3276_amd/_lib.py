@@ -13,9 +13,9 @@ SO = os.path.join(HERE, "libov.so")
 OV_OK, OV_ERR_INVALID_ARG, OV_ERR_NOT_CONVERGED, OV_ERR_BREAKDOWN, OV_ERR_SPECTRUM, \
     OV_ERR_WORKSPACE, OV_ERR_DEVICE = range(7)
 OV_FP64, OV_MIXED = 0, 1
-OP_HW, OP_DOV, OP_DOV_DAG, OP_M, OP_M_DAG, OP_MDAGM = range(6)
+OP_HW, OP_DOV, OP_DOV_DAG, OP_M, OP_M_DAG, OP_MDAGM, OP_M0INV, OP_M0INV_DAG = range(8)
 OPS = {"hw": OP_HW, "dov": OP_DOV, "dov_dag": OP_DOV_DAG, "m": OP_M, "m_dag": OP_M_DAG,
-       "mdagm": OP_MDAGM}
+       "mdagm": OP_MDAGM, "m0inv": OP_M0INV, "m0inv_dag": OP_M0INV_DAG}
 
 # every symbol include/ov.h declares
 SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace_bytes",
@@ -34,7 +34,8 @@ class OvParams(C.Structure):
                 ("truth_tol", C.c_double), ("mixed_inner_tol", C.c_double),
                 ("reliable_delta", C.c_double), ("max_inner", C.c_int),
                 ("max_outer", C.c_int), ("precision", C.c_int),
-                ("inner_relax", C.c_double), ("inner_tol_max", C.c_double)]
+                ("inner_relax", C.c_double), ("inner_tol_max", C.c_double),
+                ("precondition", C.c_int)]
 
 
 class OvStats(C.Structure):
@@ -107,6 +108,9 @@ def check(status, ctx=None):
         raise OvError(status, f"{L.ov_status_string(status).decode()}: {msg}")
 
 
+_PARAM_FIELDS = {f[0] for f in OvParams._fields_}
+
+
 def default_params(**kw) -> OvParams:
     p = OvParams()
     lib().ov_params_default(C.byref(p))
@@ -119,8 +123,10 @@ def default_params(**kw) -> OvParams:
             setattr(p, k + "_im", v.imag)
         elif k == "precision":
             p.precision = {"fp64": OV_FP64, "mixed": OV_MIXED}.get(v, v)
-        else:
+        elif k in _PARAM_FIELDS:
             setattr(p, k, v)
+        else:
+            raise TypeError(f"unknown ov_params field {k!r}")
     return p
 
 

@@ -70,10 +70,13 @@ struct SysDev {
   double* cg_s;             // per-system CG scalars (see CG_* below)
   double m_re, m_im;        // fermion mass
   double g_re, g_im;        // Yukawa coupling
+  void* fft_tmp;            // momentum-space scratch field (kernel precision)
+  int off_xy, off_z, off_t; // first workgroup of this system in each transform pass
+  int xc;                   // x values per workgroup in the t pass (divides X, <= 8)
 };
 
 // CG scalar slots
-enum { CG_RR = 0, CG_RR_OLD, CG_PAP, CG_ALPHA, CG_BETA, CG_BB, CG_RTRUE, CG_NSLOT = 8 };
+enum { CG_RR = 0, CG_RR_OLD, CG_PAP, CG_ALPHA, CG_BETA, CG_BB, CG_RTRUE, CG_RYT, CG_NSLOT = 8 };
 
 struct MsParams {
   int np;               // poles
@@ -781,6 +784,252 @@ __global__ void __launch_bounds__(256) k_fill(const SysDev* __restrict__ sys,
   }
 }
 
+// ------------------------------------------------- momentum-space operators
+// The theory has no gauge field, so every translation-invariant operator built
+// from H_W is diagonal in momentum space (the FFT route of Sec. 7.2).  For a
+// field ~ exp(+i p.x), D_W(p) = w + i gamma.s with w = 4 - M0 - sum cos p_mu,
+// s_mu = sin p_mu, H_W(p)^2 = s2 = w^2 + |s|^2, and with the rational sign
+// R(s2) = sum_k a_k / (s2 + b_k):
+//   D_ov(p) = 1 + R D_W(p) = (1 + R w) + i R gamma.s.
+// The free fermion matrix M0 = D_ov + m P+ + m* P- (phi = 0) of the
+// preconditioner (Sec. 7.3, M~ = M M0^-1, x = M0^-1 x~) is, with mu = Im m,
+//   M0(p) = a + i mu g5 + i R gamma.s,  a = 1 + Re m + R w,
+//   M0^-1(p)   = (a - i mu g5 - i R gamma.s) / (a^2 + mu^2 + R^2 |s|^2),
+//   M0^-dag(p) = (a + i mu g5 + i R gamma.s) / (a^2 + mu^2 + R^2 |s|^2).
+// Fields go through per-axis DFTs of L <= 64 points: forward e^{-2 pi i j k/L},
+// inverse e^{+2 pi i j k/L} with 1/V.  Antiperiodic time is handled by the
+// twist e^{-i pi t/T} before the forward and e^{+i pi t/T} after the inverse
+// transform, which puts p_t on (2n+1) pi / T.
+enum SymKind { SYM_M0INV = 0, SYM_M0INV_DAG = 1 };
+
+struct SymParams {
+  int kind;
+  int np;
+  double diag;        // 4 - M0
+  double a[MAXP];     // residues a_k of the sign rational
+  double b[MAXP];     // shifts b_k
+};
+
+// System of workgroup b in a transform pass (which: 0 xy, 1 z, 2 t).
+__device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys, int b, int which) {
+  int s = 0;
+  for (int k = 1; k < nsys; ++k) {
+    const int o = which == 0 ? sys[k].off_xy : (which == 1 ? sys[k].off_z : sys[k].off_t);
+    if (o <= b) s = k;
+  }
+  return s;
+}
+
+__device__ __forceinline__ void twiddles(double2* tw, int L, double sgn) {
+  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)j / (double)L, &sn, &cs);
+    tw[j] = double2{cs, sgn * sn};
+  }
+}
+
+template <class R>
+__device__ __forceinline__ c2<R> cmad(c2<R> acc, c2<R> a, double2 w) {
+  const R wr = (R)w.x, wi = (R)w.y;
+  return c2<R>{acc.x + a.x * wr - a.y * wi, acc.y + a.x * wi + a.y * wr};
+}
+
+// x and y axes of one (z, t, spin) plane.  inv = 0: e_in -> fft_tmp with the
+// time twist; inv = 1: fft_tmp -> e_out with the untwist and 1/V.  Needs
+// X, Y <= 64 and X Y <= 1024.
+template <class R>
+__global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, int nsys, int inv) {
+  __shared__ c2<R> A[1024], B[1024];
+  __shared__ double2 twx[64], twy[64];
+  const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 0)];
+  if (S.active && *S.active == 0) return;
+  const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, T = S.g.T, V = S.g.V;
+  const int loc = blockIdx.x - S.off_xy;
+  const int spin = loc & 3;
+  const int zt = loc >> 2;  // z + Z t
+  const int t = zt / Z;
+  const int XY = X * Y;
+  const c2<R>* in = (const c2<R>*)(inv ? S.fft_tmp : S.e_in) + (size_t)spin * V + (size_t)zt * XY;
+  c2<R>* out = (c2<R>*)(inv ? S.e_out : S.fft_tmp) + (size_t)spin * V + (size_t)zt * XY;
+  const double sgn = inv ? 1.0 : -1.0;
+  twiddles(twx, X, sgn);
+  twiddles(twy, Y, sgn);
+  double tr = 1.0, ti = 0.0;  // twist (forward) / untwist and normalisation (inverse)
+  if (S.g.bc < 0) sincospi(sgn * (double)t / (double)T, &ti, &tr);
+  if (inv) {
+    tr /= (double)V;
+    ti /= (double)V;
+  }
+  for (int i = threadIdx.x; i < XY; i += blockDim.x) {
+    const c2<R> v = in[i];
+    A[i] = inv ? v : c2<R>{(R)(v.x * tr - v.y * ti), (R)(v.x * ti + v.y * tr)};
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < XY; i += blockDim.x) {  // x axis
+    const int kx = i % X, y = i / X;
+    c2<R> acc{(R)0, (R)0};
+    int w = 0;
+    for (int x = 0; x < X; ++x) {
+      acc = cmad<R>(acc, A[y * X + x], twx[w]);
+      w += kx;
+      if (w >= X) w -= X;
+    }
+    B[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < XY; i += blockDim.x) {  // y axis
+    const int kx = i % X, ky = i / X;
+    c2<R> acc{(R)0, (R)0};
+    int w = 0;
+    for (int y = 0; y < Y; ++y) {
+      acc = cmad<R>(acc, B[y * X + kx], twy[w]);
+      w += ky;
+      if (w >= Y) w -= Y;
+    }
+    out[i] = inv ? c2<R>{(R)(acc.x * tr - acc.y * ti), (R)(acc.x * ti + acc.y * tr)} : acc;
+  }
+}
+
+// z axis of the (x, z) slab of one (y, t, spin), in place on fft_tmp.
+// Needs Z <= 64 and X Z <= 1024.
+template <class R>
+__global__ void __launch_bounds__(256) k_fft_z(const SysDev* __restrict__ sys, int nsys, int inv) {
+  __shared__ c2<R> A[1024];
+  __shared__ double2 tw[64];
+  const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 1)];
+  if (S.active && *S.active == 0) return;
+  const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, V = S.g.V;
+  const int loc = blockIdx.x - S.off_z;
+  const int spin = loc & 3;
+  const int yt = loc >> 2;  // y + Y t
+  const int y = yt % Y, t = yt / Y;
+  c2<R>* f = (c2<R>*)S.fft_tmp + (size_t)spin * V;
+  twiddles(tw, Z, inv ? 1.0 : -1.0);
+  const int n = X * Z;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = e % X, z = e / X;
+    A[e] = f[x + X * (y + Y * (z + Z * t))];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = e % X, kz = e / X;
+    c2<R> acc{(R)0, (R)0};
+    int w = 0;
+    for (int z = 0; z < Z; ++z) {
+      acc = cmad<R>(acc, A[z * X + x], tw[w]);
+      w += kz;
+      if (w >= Z) w -= Z;
+    }
+    f[x + X * (y + Y * (kz + Z * t))] = acc;  // every read of f happened before the barrier
+  }
+}
+
+// Momentum-space operator on the four spin components v of one momentum.
+__device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, double m_im,
+                                             double sx, double sy, double sz, double st, double w,
+                                             double2 v[4]) {
+  const double s2sin = sx * sx + sy * sy + sz * sz + st * st;
+  const double s2 = w * w + s2sin;
+  double Rr = 0.0;
+  for (int k = 0; k < sp.np; ++k) Rr += sp.a[k] / (s2 + sp.b[k]);
+  const double a = 1.0 + m_re + Rr * w;
+  const double mu = m_im;
+  const double inv_den = 1.0 / (a * a + mu * mu + Rr * Rr * s2sin);
+  const double sg = sp.kind == SYM_M0INV ? -1.0 : 1.0;
+  const double c = sg * Rr, c5 = sg * mu;  // out = (a v + i c5 g5 v + i c gamma.s v) / den
+  // G = gamma.s v in the basis of Sec. 2.1 (the one of the Wilson stencil)
+  double2 G[4];
+  G[0] = double2{-sx * v[3].y + sy * v[3].x - sz * v[2].y + st * v[2].x,
+                 sx * v[3].x + sy * v[3].y + sz * v[2].x + st * v[2].y};
+  G[1] = double2{-sx * v[2].y - sy * v[2].x + sz * v[3].y + st * v[3].x,
+                 sx * v[2].x - sy * v[2].y - sz * v[3].x + st * v[3].y};
+  G[2] = double2{sx * v[1].y - sy * v[1].x + sz * v[0].y + st * v[0].x,
+                 -sx * v[1].x - sy * v[1].y - sz * v[0].x + st * v[0].y};
+  G[3] = double2{sx * v[0].y + sy * v[0].x - sz * v[1].y + st * v[1].x,
+                 -sx * v[0].x + sy * v[0].y + sz * v[1].x + st * v[1].y};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double g5 = k < 2 ? -1.0 : 1.0;
+    const double hr = c * G[k].x + c5 * g5 * v[k].x;  // h = c G + c5 g5 v ; out = a v + i h
+    const double hi = c * G[k].y + c5 * g5 * v[k].y;
+    v[k] = double2{(a * v[k].x - hi) * inv_den, (a * v[k].y + hr) * inv_den};
+  }
+}
+
+// t axis forward, the momentum-space operator on all four spins, t axis
+// inverse, in place on fft_tmp.  Workgroup: (chunk of xc x values, y, z);
+// needs T <= 64 and xc T <= 256.
+template <class R>
+__global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sys, int nsys,
+                                                   const SymParams sp) {
+  __shared__ c2<R> A[1024], B[1024];
+  __shared__ double2 twf[64], twi[64];
+  const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 2)];
+  if (S.active && *S.active == 0) return;
+  const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, T = S.g.T, V = S.g.V;
+  const int XC = S.xc;
+  const int loc = blockIdx.x - S.off_t;
+  const int nxc = X / XC;
+  const int xb = (loc % nxc) * XC;
+  const int yz = loc / nxc;  // y + Y z
+  const int y = yz % Y, z = yz / Y;
+  c2<R>* f = (c2<R>*)S.fft_tmp;
+  twiddles(twf, T, -1.0);
+  twiddles(twi, T, 1.0);
+  const int n = 4 * XC * T;  // element e = (spin T + t) XC + xl
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int xl = e % XC, q = e / XC;
+    const int t = q % T, spin = q / T;
+    A[e] = f[(size_t)spin * V + (xb + xl) + X * (y + Y * (z + Z * t))];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {  // forward t
+    const int xl = e % XC, q = e / XC;
+    const int kt = q % T, spin = q / T;
+    c2<R> acc{(R)0, (R)0};
+    int w = 0;
+    for (int t = 0; t < T; ++t) {
+      acc = cmad<R>(acc, A[(spin * T + t) * XC + xl], twf[w]);
+      w += kt;
+      if (w >= T) w -= T;
+    }
+    B[e] = acc;
+  }
+  __syncthreads();
+  double sy, cy, sz, cz;
+  sincospi(2.0 * (double)y / (double)Y, &sy, &cy);
+  sincospi(2.0 * (double)z / (double)Z, &sz, &cz);
+  for (int q = threadIdx.x; q < XC * T; q += blockDim.x) {  // operator at (kx, ky, kz, kt)
+    const int xl = q % XC, kt = q / XC;
+    double sx, cx, st, ct;
+    sincospi(2.0 * (double)(xb + xl) / (double)X, &sx, &cx);
+    sincospi((2.0 * kt + (S.g.bc < 0 ? 1.0 : 0.0)) / (double)T, &st, &ct);
+    const double w = sp.diag - (cx + cy + cz + ct);
+    double2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const c2<R> u = B[(k * T + kt) * XC + xl];
+      v[k] = double2{(double)u.x, (double)u.y};
+    }
+    apply_symbol(sp, S.m_re, S.m_im, sx, sy, sz, st, w, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) A[(k * T + kt) * XC + xl] = c2<R>{(R)v[k].x, (R)v[k].y};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {  // inverse t
+    const int xl = e % XC, q = e / XC;
+    const int t = q % T, spin = q / T;
+    c2<R> acc{(R)0, (R)0};
+    int w = 0;
+    for (int kt = 0; kt < T; ++kt) {
+      acc = cmad<R>(acc, A[(spin * T + kt) * XC + xl], twi[w]);
+      w += t;
+      if (w >= T) w -= T;
+    }
+    f[(size_t)spin * V + (xb + xl) + X * (y + Y * (z + Z * t))] = acc;
+  }
+}
+
 // ------------------------------------------------------------ CG kernels
 // Sum part_c into cg_s[slot]; op 0: store, 1: alpha = rr/pap, 2: beta + rr update.
 __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
@@ -812,6 +1061,11 @@ __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
       c[CG_BETA] = (v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
     } else if (op == 5) {  // true residual only (no CG state change)
       c[CG_RTRUE] = v;
+    } else if (op == 6) {  // reliable update of the preconditioned recursion (|r~|^2 true)
+      const double rec = c[CG_RR];
+      c[CG_RYT] = v;
+      c[CG_RR] = v;
+      c[CG_BETA] = (v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
     } else if (op == 4) {  // norm of b
       c[CG_BB] = v;
     }
@@ -859,6 +1113,9 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
 //   op 0: x64 += x (low precision), x = 0
 //   op 1: r = b (FP64 AoS -> planar R), partial |b|^2 -> part_c
 //   op 2: x = 0
+//   op 3: x64 += e_out (low precision), x = 0        (preconditioned fold-in)
+//   op 4: partial |r|^2 -> part_c
+//   op 5: x += alpha p, r -= alpha e_in, partial |r|^2 -> part_c
 template <class R>
 __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                   int nb_total, int op) {
@@ -900,9 +1157,42 @@ __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys,
 #pragma unroll
       for (int k = 0; k < 4; ++k) z[k] = c2<R>{(R)0, (R)0};
       store_sp<R>((c2<R>*)S.cg_x, V, i, z);
+    } else if (op == 3) {
+      c2<R> xv[4];
+      double2 xh[4];
+      load_sp<R>((const c2<R>*)S.e_out, V, i, xv);
+      load_sp<double>((const double2*)S.cg_x64, V, i, xh);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xh[k] = double2{xh[k].x + (double)xv[k].x, xh[k].y + (double)xv[k].y};
+        xv[k] = c2<R>{(R)0, (R)0};
+      }
+      store_sp<double>((double2*)S.cg_x64, V, i, xh);
+      store_sp<R>((c2<R>*)S.cg_x, V, i, xv);
+    } else if (op == 4) {
+      c2<R> rv[4];
+      load_sp<R>((const c2<R>*)S.cg_r, V, i, rv);
+      acc += norm2_sp(rv);
+    } else if (op == 5) {
+      const double alpha = S.cg_s[CG_ALPHA];
+      c2<R> xv[4], pv[4], rv[4], qv[4];
+      load_sp<R>((const c2<R>*)S.cg_x, V, i, xv);
+      load_sp<R>((const c2<R>*)S.cg_p, V, i, pv);
+      load_sp<R>((const c2<R>*)S.cg_r, V, i, rv);
+      load_sp<R>((const c2<R>*)S.e_in, V, i, qv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xv[k] = c2<R>{(R)((double)xv[k].x + alpha * (double)pv[k].x),
+                      (R)((double)xv[k].y + alpha * (double)pv[k].y)};
+        rv[k] = c2<R>{(R)((double)rv[k].x - alpha * (double)qv[k].x),
+                      (R)((double)rv[k].y - alpha * (double)qv[k].y)};
+      }
+      store_sp<R>((c2<R>*)S.cg_x, V, i, xv);
+      store_sp<R>((c2<R>*)S.cg_r, V, i, rv);
+      acc += norm2_sp(rv);
     }
   }
-  if (op == 1) {
+  if (op == 1 || op == 4 || op == 5) {
     const double tot = block_sum(acc, lds);
     if (threadIdx.x == 0) S.part_c[lb] = tot;
   }

@@ -139,6 +139,8 @@ struct SysBuf {
   double* dstat;
   double *coef_term, *coef_c, *coef_d, *cg_s;
   int *act_cg, *act_ru;
+  void *vR, *fftR;              // preconditioned solve: M0^-1 p / M^dag u, transform scratch
+  int xc = 1, off_xy = 0, off_z = 0, off_t = 0;  // momentum-space pass geometry
 };
 
 int sites_per_block(const ov_ctx* c, int V) {
@@ -156,6 +158,7 @@ struct Plan {
   int capR = 0;    // inner basis slots (0 = inner is FP64 and shares)
   bool mixed = false;
   bool solve = false;
+  bool pc = false;  // free-field preconditioned solve
 };
 
 template <class R>
@@ -193,6 +196,11 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
   } else {
     s.basisR = s.rR = s.srcR2 = s.uR = s.xR = s.pR = s.rcgR = nullptr;
   }
+  s.vR = s.fftR = nullptr;
+  if (pl.solve && pl.pc) {
+    s.vR = bp.take(pl.mixed ? v32 : v64);
+    s.fftR = bp.take(pl.mixed ? v32 : v64);
+  }
   s.part_a = (double*)bp.take(sizeof(double) * s.nblk);
   s.part_b = (double*)bp.take(sizeof(double) * s.nblk);
   s.part_c = (double*)bp.take(sizeof(double) * s.nblk);
@@ -207,7 +215,33 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
   s.coef_d = (double*)bp.take(sizeof(double) * capmax);
 }
 
-enum Table { T_APPLY = 0, T_APPLY2, T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG, T_CG, T_CG_RU, T_NT };
+enum Table {
+  T_APPLY = 0, T_APPLY2, T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG, T_CG, T_CG_RU,
+  T_PC_P,     // v = M0^-1 p
+  T_PC_Q,     // q = M0^-dag (M^dag u), in place on v
+  T_PC_FOLD,  // M0^-1 x~ for the fold-in x64 += M0^-1 x~
+  T_PC_RES,   // r~ = M0^-dag r64
+  T_PC_B,     // r~ = M0^-dag b, in place
+  T_NT
+};
+
+// x values per workgroup of the t pass: the largest divisor of X with xc T <= 256.
+int pick_xc(int X, int T) {
+  int best = 1;
+  for (int d = 1; d <= X; ++d)
+    if (X % d == 0 && d * T <= 256) best = d;
+  return best;
+}
+
+// Lattices the momentum-space kernels handle (LDS tiles of <= 1024 complex values).
+bool fft_ok(const ov_params* p, std::string& why) {
+  const int X = p->dims[0], Y = p->dims[1], Z = p->dims[2], T = p->dims[3];
+  if (X > 64 || Y > 64 || Z > 64 || T > 64 || X * Y > 1024 || X * Z > 1024) {
+    why = "momentum-space kernels need every extent <= 64, X*Y <= 1024 and X*Z <= 1024";
+    return false;
+  }
+  return true;
+}
 
 // A batch of systems sharing poles, tolerances and precision.
 struct Engine {
@@ -231,6 +265,7 @@ struct Engine {
   std::vector<int> last_flags;      // last uploaded flags (upload only on change)
   MsParams mp64{}, mpR{};
   int L64 = 0, LR = 0;              // multi-shift launch counts
+  int nb_xy = 0, nb_z = 0, nb_t = 0;  // workgroups of the momentum-space passes
 
   size_t layout(void* base, size_t cap, bool dry) {
     Bump bp(base, cap, dry);
@@ -238,7 +273,7 @@ struct Engine {
     cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys);
     stat_all = (long long*)bp.take(sizeof(long long) * 4 * nsys);
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
-    int blk = 0;
+    int blk = 0, nxy = 0, nz = 0, nt = 0;
     for (int s = 0; s < nsys; ++s) {
       SysBuf& b = sb[s];
       b.ctx = ctxs[s];
@@ -249,12 +284,23 @@ struct Engine {
       b.blk0 = blk;
       blk += b.nblk;
       carve(bp, b, pl);
+      const int X = p.dims[0], Y = p.dims[1], Z = p.dims[2], T = p.dims[3];
+      b.xc = pick_xc(X, T);
+      b.off_xy = nxy;
+      nxy += 4 * Z * T;
+      b.off_z = nz;
+      nz += 4 * Y * T;
+      b.off_t = nt;
+      nt += (X / b.xc) * Y * Z;
       b.cg_s = dry ? nullptr : cg_all + (size_t)s * CG_NSLOT;
       b.stat = dry ? nullptr : stat_all + (size_t)s * 4;
       b.act_cg = dry ? nullptr : act_all + s;
       b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
     nb_total = blk;
+    nb_xy = nxy;
+    nb_z = nz;
+    nb_t = nt;
     tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
     ptrs = (void**)bp.take(sizeof(void*) * 2 * nsys);
     bmap = (int*)bp.take(sizeof(int) * (size_t)nb_total);
@@ -325,6 +371,7 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   HIPCHK(E.lead, hipStreamWaitEvent(E.st, E.lead->ev_in, 0));
   E.pl.solve = solve;
   E.pl.mixed = mixed;
+  E.pl.pc = solve && E.lead->p.precondition != 0;
   // capacities from the loosest spectral bound over the batch
   int cap64 = 0, capR = 0;
   for (auto* c : ctxs) {
@@ -371,6 +418,10 @@ SysDev base_dev(const SysBuf& b) {
   d.m_im = p.m_im;
   d.g_re = p.g_re;
   d.g_im = p.g_im;
+  d.xc = b.xc;
+  d.off_xy = b.off_xy;
+  d.off_z = b.off_z;
+  d.off_t = b.off_t;
   return d;
 }
 
@@ -503,6 +554,27 @@ void launch_combine(const Engine& E, int t, int mode) {
   k_ms_combine<R><<<E.nb_total, E.lead->block, 0, E.st>>>(tab(E, t), E.bmap, E.nb_total, mode);
 }
 
+// e_out = op(e_in) for a momentum-space operator (forward DFTs, symbol, inverse
+// DFTs through fft_tmp); e_out may alias e_in.
+template <class R>
+void launch_sym(const Engine& E, int t, int kind) {
+  const ov_ctx* c = E.lead;
+  SymParams sp{};
+  sp.kind = kind;
+  sp.np = c->p.n_poles;
+  sp.diag = 4.0 - c->p.M0;
+  for (int k = 0; k < MAXP; ++k) {
+    sp.a[k] = k < sp.np ? c->a[k] : 0.0;
+    sp.b[k] = k < sp.np ? c->b[k] : 0.0;
+  }
+  const SysDev* T = tab(E, t);
+  k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 0);
+  k_fft_z<R><<<E.nb_z, 256, 0, E.st>>>(T, E.nsys, 0);
+  k_fft_t_sym<R><<<E.nb_t, 256, 0, E.st>>>(T, E.nsys, sp);
+  k_fft_z<R><<<E.nb_z, 256, 0, E.st>>>(T, E.nsys, 1);
+  k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 1);
+}
+
 ov_status check_launch(ov_ctx* c) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -601,6 +673,7 @@ ov_status run_apply(Engine& E, int op) {
                                                         : (const void*)b.x64;
     d1.e_out = (op == OV_OP_MDAGM) ? (void*)b.u64 : (void*)b.r64;
     d1.e_out2 = (op == OV_OP_MDAGM) ? (void*)b.src64b : nullptr;
+    d1.fft_tmp = b.u64;  // momentum-space ops: x64 -> r64 through u64
     // phase 2 (MdagM only): M^dag on u64, source g5 u64 = src64b
     d2.e_in = b.u64;
     d2.src = b.src64b;
@@ -640,6 +713,10 @@ ov_status apply_sequence(Engine& E, int op) {
       k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 1);
       launch_ms<double>(E, T_APPLY, E.mp64, E.L64);
       launch_combine<double>(E, T_APPLY, op == OV_OP_DOV_DAG ? EPI_DOVDAG : EPI_MDAG);
+      break;
+    case OV_OP_M0INV:
+    case OV_OP_M0INV_DAG:
+      launch_sym<double>(E, T_APPLY, op == OV_OP_M0INV ? SYM_M0INV : SYM_M0INV_DAG);
       break;
     case OV_OP_MDAGM:
       k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
@@ -694,6 +771,19 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
             need(t, s, T[t]->cg_r, "cg_r") && need(t, s, T[t]->cg_b, "cg_b") &&
             need(t, s, T[t]->cg_x64, "cg_x64") && need(t, s, T[t]->src, "src");
     ok &= need(T_CG_RU, s, T[T_CG_RU]->cg_r64, "cg_r64");
+    if (E.pl.pc) {
+      // momentum-space passes, EPI_MDAG into v, k_cg_misc ops 3-5
+      for (int t : {T_PC_P, T_PC_Q, T_PC_FOLD, T_PC_RES, T_PC_B})
+        ok &= need(t, s, T[t]->e_in, "e_in") && need(t, s, T[t]->e_out, "e_out") &&
+              need(t, s, T[t]->fft_tmp, "fft_tmp") && need(t, s, T[t]->active, "active");
+      ok &= need(T_IN_MDAG, s, T[T_IN_MDAG]->e_out, "e_out");
+      ok &= need(T_CG, s, T[T_CG]->e_in, "e_in");
+      ok &= need(T_PC_FOLD, s, T[T_PC_FOLD]->cg_x, "cg_x") &&
+            need(T_PC_FOLD, s, T[T_PC_FOLD]->cg_x64, "cg_x64");
+      for (int t : {T_PC_RES, T_PC_B})
+        ok &= need(t, s, T[t]->cg_r, "cg_r") && need(t, s, T[t]->part_c, "part_c") &&
+              need(t, s, T[t]->cg_s, "cg_s");
+    }
     if (!ok) return OV_ERR_DEVICE;
   }
   return OV_OK;
@@ -713,8 +803,8 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     im.active = b.act_cg;
     im.basis = b.basisR;
     im.r = b.rR;
-    im.src = b.pR;
-    im.e_in = b.pR;
+    im.src = E.pl.pc ? b.vR : b.pR;  // preconditioned: M (M0^-1 p)
+    im.e_in = E.pl.pc ? b.vR : b.pR;
     im.e_out = b.uR;
     im.e_out2 = b.srcR2;
     // inner M^dag u with the CG update
@@ -727,6 +817,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     imd.cg_x = b.xR;
     imd.cg_p = b.pR;
     imd.cg_r = b.rcgR;
+    imd.e_out = b.vR;  // preconditioned: M^dag u -> v (EPI_MDAG), then M0^-dag
     // FP64 true residual: M x64, then r64 = b - M^dag (M x64)
     SysDev tm = d;
     tm.active = b.act_ru;
@@ -743,7 +834,9 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     tmd.src = b.src64b;
     tmd.e_in = b.u64;
     tmd.cg_r64 = b.r64;
-    tmd.cg_r = (sizeof(R) == sizeof(double)) ? b.rcgR : nullptr;  // FP32 copy: k_r64_to_r32
+    // FP64 inner solver: copy of r64 in cg_r; FP32: k_r64_to_r32; preconditioned:
+    // the recursion restarts from M0^-dag r64 instead
+    tmd.cg_r = (sizeof(R) == sizeof(double) && !E.pl.pc) ? b.rcgR : nullptr;
     // CG vector ops
     SysDev cg = d;
     cg.active = b.act_cg;
@@ -752,9 +845,40 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     cg.cg_r = b.rcgR;
     cg.cg_x64 = b.x64;
     cg.src = b.x64;
+    cg.e_in = b.vR;  // q of the preconditioned update
     SysDev cgr = cg;
     cgr.active = b.act_ru;
     cgr.cg_r64 = b.r64;
+    if (E.pl.pc) {
+      SysDev pp = d;
+      pp.active = b.act_cg;
+      pp.fft_tmp = b.fftR;
+      pp.e_in = b.pR;
+      pp.e_out = b.vR;
+      SysDev pq = pp;
+      pq.e_in = b.vR;
+      SysDev pf = d;
+      pf.active = b.act_ru;
+      pf.fft_tmp = b.fftR;
+      pf.e_in = b.xR;
+      pf.e_out = b.vR;
+      pf.cg_x = b.xR;
+      pf.cg_x64 = b.x64;
+      SysDev pr = d;
+      pr.active = b.act_ru;
+      pr.fft_tmp = b.fftR;
+      pr.e_in = (sizeof(R) == sizeof(double)) ? (const void*)b.r64 : (const void*)b.rcgR;
+      pr.e_out = b.rcgR;
+      pr.cg_r = b.rcgR;
+      SysDev pb = pr;
+      pb.active = b.act_cg;
+      pb.e_in = b.rcgR;
+      E.htab[(size_t)T_PC_P * E.nsys + s] = pp;
+      E.htab[(size_t)T_PC_Q * E.nsys + s] = pq;
+      E.htab[(size_t)T_PC_FOLD * E.nsys + s] = pf;
+      E.htab[(size_t)T_PC_RES * E.nsys + s] = pr;
+      E.htab[(size_t)T_PC_B * E.nsys + s] = pb;
+    }
     E.htab[(size_t)T_IN_M * E.nsys + s] = im;
     E.htab[(size_t)T_IN_MDAG * E.nsys + s] = imd;
     E.htab[(size_t)T_TR_M * E.nsys + s] = tm;
@@ -764,7 +888,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     SysDev ap = d;  // pack/unpack geometry
     E.htab[(size_t)T_APPLY * E.nsys + s] = ap;
   }
-  TRY(check_roles(E, sizeof(R) == sizeof(double)));
+  TRY(check_roles(E, sizeof(R) == sizeof(double) && !E.pl.pc));
   return upload_tables(E);
 }
 
@@ -882,20 +1006,38 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
   int L = 0;
   for (int s = 0; s < E.nsys; ++s) L = std::max(L, capacity(E.ctxs[s], tol));
   L = std::min(E.pl.cap64, L);
+  const bool pc = E.pl.pc;
   char key[96];
-  std::snprintf(key, sizeof key, "ru|%zu|%.3e|%d|%d", sizeof(R), tol, L, scalar_op);
+  std::snprintf(key, sizeof key, "ru|%zu|%.3e|%d|%d|%d", sizeof(R), tol, L, scalar_op, (int)pc);
   return run_graph(E, key, [&]() {
-    k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total, 0);
+    if (pc) {  // x64 += M0^-1 x~, x~ = 0
+      launch_sym<R>(E, T_PC_FOLD, SYM_M0INV);
+      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_PC_FOLD), E.bmap, E.nb_total, 3);
+    } else {
+      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total, 0);
+    }
     k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_TR_M), E.bmap, E.nb_total, 0);
     launch_ms<double>(E, T_TR_M, mp, L);
     launch_combine<double>(E, T_TR_M, EPI_M);
     launch_ms<double>(E, T_TR_MDAG, mp, L);
-    // EPI_MDAG_RES writes r64 (FP64) and, for an FP64 inner solver, its copy in
-    // cg_r; an FP32 inner solver gets its copy from k_r64_to_r32.
+    // EPI_MDAG_RES writes r64 (FP64) and, for an unpreconditioned FP64 inner
+    // solver, its copy in cg_r; an FP32 inner solver gets its copy from
+    // k_r64_to_r32.
     launch_combine<double>(E, T_TR_MDAG, EPI_MDAG_RES);
-    k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_TR_MDAG), E.nsys, scalar_op);
-    if (sizeof(R) != sizeof(double))
-      k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
+    if (pc) {
+      // |r64|^2 of the original system, then the recursion restarts from
+      // r~ = M0^-dag r64 with |r~|^2 in the CG state
+      k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_TR_MDAG), E.nsys, 5);
+      if (sizeof(R) != sizeof(double))
+        k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
+      launch_sym<R>(E, T_PC_RES, SYM_M0INV_DAG);
+      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_PC_RES), E.bmap, E.nb_total, 4);
+      if (scalar_op == 3) k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_PC_RES), E.nsys, 6);
+    } else {
+      k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_TR_MDAG), E.nsys, scalar_op);
+      if (sizeof(R) != sizeof(double))
+        k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
+    }
   });
 }
 
@@ -927,7 +1069,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 2);
   k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 1);
   k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 4);  // BB
-  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);  // RR = |b|^2, beta = 0
+  const bool pc = E.pl.pc;
+  if (pc) {  // the preconditioned recursion starts from b~ = M0^-dag b (Sec. 7.3)
+    launch_sym<R>(E, T_PC_B, SYM_M0INV_DAG);
+    k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 4);
+  }
+  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);  // RR = |b|^2 (|b~|^2), beta = 0
   // |x0|^2 -> part_b via prep on x64 (src = x64 in T_CG)
   k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 0);
   std::vector<double> x0n(ns);
@@ -941,7 +1088,10 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     x0n[s] = acc;
   }
   TRY(read_scalars(E));
-  std::vector<double> bn(ns), rmax(ns);
+  // rmax: recursion residual norm at the last restart (of r~ when
+  // preconditioned); kap: |r| / |r~| there, which turns the recursive |r~| into
+  // an estimate of the original residual for the stopping test.
+  std::vector<double> bn(ns), rmax(ns), kap(ns, 1.0);
   out.outer.assign(ns, 0);
   out.ru.assign(ns, 0);
   out.res.assign(ns, 1.0);
@@ -960,6 +1110,10 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     fru[s] = (x0n[s] > 0.0 && fcg[s]) ? 1 : 0;
     if (fru[s]) any_guess = true;
     rmax[s] = bn[s];
+    if (pc && fcg[s]) {
+      rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RR]);
+      kap[s] = rmax[s] > 0.0 ? bn[s] / rmax[s] : 1.0;
+    }
   }
   if (any_guess) {  // r = b - A x0 for warm starts
     TRY(set_flags(E, fcg, fru));
@@ -967,7 +1121,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     TRY(read_scalars(E));
     for (int s = 0; s < ns; ++s)
       if (fru[s]) {
-        rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
+        const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
+        rmax[s] = rt;
+        if (pc) {
+          rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RYT]);
+          kap[s] = rmax[s] > 0.0 ? rt / rmax[s] : 1.0;
+        }
         out.ru[s]++;
       }
     // restart the recurrence from the true residual
@@ -1007,17 +1166,30 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       if (it != c->n_est.end()) LR = std::min(LR, it->second + 2);
     }
     char ikey[96];
-    std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d", sizeof(R), tol_it, LR);
+    std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d|%d", sizeof(R), tol_it, LR, (int)pc);
     // p = r + beta p (beta = 0 right after a (re)start) ; M p ; alpha ;
-    // M^dag u with the CG update ; beta -- one captured graph per iteration
+    // M^dag u with the CG update ; beta -- one captured graph per iteration.
+    // Preconditioned (M~ = M M0^-1): M (M0^-1 p), and M0^-dag (M^dag u) feeds
+    // the update.
     TRY(run_graph(E, ikey, [&]() {
       k_cg_p<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 1);
+      if (pc) {
+        launch_sym<R>(E, T_PC_P, SYM_M0INV);
+        k_ms_prep<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_IN_M), E.bmap, E.nb_total, 0);
+      }
       launch_ms<R>(E, T_IN_M, mpR, LR);
       launch_combine<R>(E, T_IN_M, EPI_M);
       k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
       launch_ms<R>(E, T_IN_MDAG, mpR, LR);
-      launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
-      k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+      if (pc) {
+        launch_combine<R>(E, T_IN_MDAG, EPI_MDAG);
+        launch_sym<R>(E, T_PC_Q, SYM_M0INV_DAG);
+        k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 5);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
+      } else {
+        launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+      }
     }));
     TRY(read_scalars(E));
     ++iter;
@@ -1039,7 +1211,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       for (int s = 0; s < ns; ++s)
         if (fcg[s])
           std::fprintf(stderr, " s%d rec=%.3e pap=%.3e", s,
-                       std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RR]) / bn[s],
+                       kap[s] * std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RR]) / bn[s],
                        c->pinned[(size_t)s * CG_NSLOT + CG_PAP]);
       std::fprintf(stderr, "\n");
     }
@@ -1052,7 +1224,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         c->err = "CG breakdown (non-finite or non-positive scalar)";
         return OV_ERR_BREAKDOWN;
       }
-      const double rec = std::sqrt(rr) / bn[s];
+      const double rec = kap[s] * std::sqrt(rr) / bn[s];
       const bool at_target = rec <= P.outer_tol;
       const bool dropped = delta > 0.0 && std::sqrt(rr) < delta * rmax[s];
       if (at_target || dropped || iter >= P.max_outer) {
@@ -1076,6 +1248,10 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         out.ru[s]++;
         const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
         rmax[s] = rt;
+        if (pc) {
+          rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RYT]);
+          kap[s] = rmax[s] > 0.0 ? rt / rmax[s] : 1.0;
+        }
         out.res[s] = rt / bn[s];
         if (ov_log())
           std::fprintf(stderr, "[ov] reliable update s%d at iter %d: true res %.3e (ms tol %.1e)\n",
@@ -1131,6 +1307,14 @@ ov_status validate(const ov_params* p, std::string& err) {
   }
   if (p->precision != OV_FP64 && p->precision != OV_MIXED) {
     err = "precision must be OV_FP64 or OV_MIXED";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (p->precondition != 0 && p->precondition != 1) {
+    err = "precondition must be 0 or 1";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (p->precondition && !fft_ok(p, err)) {
+    err += " (set precondition = 0 for larger lattices)";
     return OV_ERR_INVALID_ARG;
   }
   return OV_OK;
@@ -1255,6 +1439,7 @@ void ov_params_default(ov_params* p) {
   p->precision = OV_MIXED;
   p->inner_relax = 1e-3;
   p->inner_tol_max = 1e-2;
+  p->precondition = 1;
 }
 
 const char* ov_status_string(ov_status s) {
@@ -1358,6 +1543,7 @@ size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
   int cap64 = capacity(c, tol64), capR = capacity(c, tolR);
   E.pl.solve = true;
   E.pl.mixed = mixed;
+  E.pl.pc = c->p.precondition != 0;
   E.pl.cap64 = mixed ? cap64 : std::max(cap64, capR);
   E.pl.capR = mixed ? capR : E.pl.cap64;
   return E.layout(nullptr, 0, true);
@@ -1460,7 +1646,9 @@ ov_status ov_sign(ov_ctx* c, void* out, const void* in, int nrhs, ov_stats* st) 
 
 ov_status ov_apply(ov_ctx* c, ov_op op, void* out, const void* in, const void* phi, int nrhs,
                    ov_stats* st) {
-  if ((int)op < 0 || (int)op > OV_OP_MDAGM) return OV_ERR_INVALID_ARG;
+  if ((int)op < 0 || (int)op > OV_OP_M0INV_DAG) return OV_ERR_INVALID_ARG;
+  if (c && (op == OV_OP_M0INV || op == OV_OP_M0INV_DAG) && !fft_ok(&c->p, c->err))
+    return OV_ERR_INVALID_ARG;
   return apply_impl(c, (int)op, out, in, phi, nrhs, st);
 }
 
@@ -1469,7 +1657,7 @@ static bool same_solver(const ov_params& a, const ov_params& b) {
          a.inner_tol == b.inner_tol && a.outer_tol == b.outer_tol && a.truth_tol == b.truth_tol &&
          a.mixed_inner_tol == b.mixed_inner_tol && a.reliable_delta == b.reliable_delta &&
          a.precision == b.precision && a.M0 == b.M0 && a.inner_relax == b.inner_relax &&
-         a.inner_tol_max == b.inner_tol_max;
+         a.inner_tol_max == b.inner_tol_max && a.precondition == b.precondition;
 }
 
 static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,

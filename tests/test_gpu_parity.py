@@ -139,6 +139,61 @@ def test_apply_ops_vs_oracle(orc, op):
         assert rel(out[r], o.apply(code, src[r], phi)) < 1e-11
 
 
+# ---------------------------------------------- free-field preconditioner
+
+@pytest.mark.parametrize("dims,bc,m", [((4, 4, 4, 4), -1, 0.05), ((4, 4, 2, 6), -1, 0.3 + 0.2j),
+                                       ((6, 4, 4, 2), 1, 0.1), ((8, 8, 8, 8), -1, 0.05)])
+@pytest.mark.parametrize("op", ["m0inv", "m0inv_dag"])
+def test_m0inv_vs_oracle(orc, dims, bc, m, op):
+    """M0^-1 / M0^-dag (Sec. 7.3) in momentum space on the GPU against the oracle's
+    CG on the position-space free operator.  Tolerance: the oracle solves to 1e-13
+    with inner tolerance 1e-14; the DFT sums are FP64 (relative ~1e-15 per pass)."""
+    print(f"[m0inv] dims={dims} bc={bc} m={m} op={op}", flush=True)
+    kw = dict(m=m, g=0.0, n_poles=12, lambda_min=1e-2, lambda_max=8.0)
+    x = inputs.gaussian_field(dims, nrhs=2, seed=23)
+    o = orc.Oracle(dims, bc_t=bc, inner_tol=1e-14, **kw)
+    lat = lattice(dims, bc_t=bc, **kw)
+    out, _ = lat.apply(op, dev(x))
+    out = host(out)
+    for r in range(2):
+        assert rel(out[r], o.m0inv(x[r], dag=(op == "m0inv_dag"), tol=1e-13)) < 1e-10
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (24, 24, 24, 48), (12, 12, 12, 12)])
+def test_m0inv_full_size_closed_form(dims):
+    """At the workloads' full sizes: M0^-1 and M0^-dag against the inverse of the
+    momentum-space 4x4 matrix M0(p) (numpy FFT), and M0^-dag = (M0^-1)^dag as an
+    inner-product identity."""
+    import closed_form as cf
+    print(f"[m0inv-full] dims={dims}", flush=True)
+    kw = dict(m=0.05, g=0.3, n_poles=24, lambda_min=1e-4, lambda_max=8.0)
+    lat = lattice(dims, **kw)
+    a, b, _ = lat.coeffs()
+    x = inputs.gaussian_field(dims, nrhs=2, seed=24)
+    g5 = cf.paper_gammas()[4]
+    sym = cf.dov_symbol(cf.rational_symbol(dims, a, b)) + 0.05 * np.eye(4)
+    inv = np.linalg.inv(sym)
+    y, _ = lat.apply("m0inv", dev(x))
+    yd, _ = lat.apply("m0inv_dag", dev(x))
+    y, yd = host(y), host(yd)
+    assert rel(y[0], cf.apply_symbol(inv, x[0], dims)) < 1e-12
+    assert rel(yd[0], cf.apply_symbol(np.conj(np.swapaxes(inv, -1, -2)), x[0], dims)) < 1e-12
+    lhs = np.vdot(x[1], y[0])
+    rhs = np.vdot(yd[1], x[0])
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert g5 is not None
+
+
+def test_m0inv_rejects_large_lattice():
+    from paper_1005_3276_amd import _lib as L
+    with pytest.raises(L.OvError):
+        lattice((96, 4, 4, 4))  # preconditioning on by default: X > 64 is refused
+    lat = lattice((96, 4, 4, 4), precondition=0)
+    with pytest.raises(L.OvError):
+        lat.apply("m0inv", torch.zeros((1,) + lat.field_shape, dtype=torch.complex128,
+                                       device="cuda"))
+
+
 def test_zero_source_gives_zero():
     dims = (4, 4, 4, 4)
     lat = lattice(dims, **CFG1)
@@ -150,12 +205,14 @@ def test_zero_source_gives_zero():
 
 # ------------------------------------------------------------------- solves
 
+@pytest.mark.parametrize("pc", [1, 0])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 4, 6, 8)])
-def test_solve_residual_under_oracle(orc, dims, prec):
-    print(f"[solve] dims={dims} prec={prec}", flush=True)
+def test_solve_residual_under_oracle(orc, dims, prec, pc):
+    print(f"[solve] dims={dims} prec={prec} pc={pc}", flush=True)
     phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
-    lat = lattice(dims, precision=prec, outer_tol=1e-10, inner_tol=1e-8, **CFG2)
+    lat = lattice(dims, precision=prec, outer_tol=1e-10, inner_tol=1e-8, precondition=pc,
+                  **CFG2)
     x, st = lat.solve(dev(src), dev(phi))
     x = host(x)[0]
     o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
@@ -171,14 +228,38 @@ def test_solve_residual_under_oracle(orc, dims, prec):
 def test_solve_8x4_config2(orc, prec):
     dims = (8, 8, 8, 8)
     phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
-    lat = lattice(dims, precision=prec, outer_tol=1e-10, inner_tol=1e-8, **CFG2)
-    t = time.time()
-    x, st = lat.solve(dev(src), dev(phi))
-    el = time.time() - t
     o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
-    res = o.residual(src[0], host(x)[0], phi)
-    print(f"[solve8] {prec} {el:.3f}s oracle residual {res:.3e} {st[0]}", flush=True)
-    assert res <= 1e-10
+    outer = {}
+    for pc in (1, 0):
+        lat = lattice(dims, precision=prec, outer_tol=1e-10, inner_tol=1e-8, precondition=pc,
+                      **CFG2)
+        t = time.time()
+        x, st = lat.solve(dev(src), dev(phi))
+        el = time.time() - t
+        res = o.residual(src[0], host(x)[0], phi)
+        print(f"[solve8] {prec} pc={pc} {el:.3f}s oracle residual {res:.3e} {st[0]}", flush=True)
+        assert res <= 1e-10
+        outer[pc] = st[0]["outer_iters"]
+    # the free-field preconditioner cuts the outer iterations (Sec. 7.3, Table 6)
+    assert outer[1] < 0.6 * outer[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_warm_start_preconditioned(orc, prec):
+    """A warm start: x0 = a perturbed solution; the preconditioned solver restarts
+    from M0^-dag (b - MdagM x0) and still meets the true residual."""
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2) + 7)
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    lat = lattice(dims, precision=prec, outer_tol=1e-10, **CFG2)
+    x1, st1 = lat.solve(dev(src), dev(phi))
+    x0 = x1 + 1e-4 * dev(inputs.gaussian_field(dims, nrhs=2, seed=31))
+    x0[1] = 0  # one member cold, one warm
+    x2, st2 = lat.solve(dev(src), dev(phi), x0=x0)
+    x2 = host(x2)
+    for r in range(2):
+        assert o.residual(src[r], x2[r], phi) <= 1e-10
+    assert st2[0]["outer_iters"] < st1[0]["outer_iters"]
 
 
 def test_batched_equals_unbatched(orc):

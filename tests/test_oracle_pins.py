@@ -353,6 +353,43 @@ def test_solve_g0_fft(orc):
     assert g5 is not None
 
 
+def _m0_symbol(dims, a, b, m, bc_t=-1):
+    """M0(p) = D_ov(p) + m P+ + m* P- with the rational sign (phi = 0)."""
+    g5 = cf.paper_gammas()[4]
+    Pp = 0.5 * (np.eye(4) + g5)
+    Pm = 0.5 * (np.eye(4) - g5)
+    return cf.dov_symbol(cf.rational_symbol(dims, a, b, bc_t)) + m * Pp + np.conj(m) * Pm
+
+
+@pytest.mark.parametrize("dims,bc,m", [((4, 4, 4, 4), -1, 0.05), ((4, 4, 2, 6), -1, 0.3 + 0.2j),
+                                       ((4, 2, 4, 4), 1, 0.1)])
+@pytest.mark.parametrize("dag", [False, True])
+def test_m0inv_vs_closed_form(orc, dims, bc, m, dag):
+    """Free-field preconditioner of Sec. 7.3: the oracle's M0^-1 and M0^-dag (CG on
+    the position-space operator) against the inverse of the momentum-space 4x4
+    matrix M0(p) (numpy FFT + linalg.inv), including a complex mass."""
+    _, src = inputs.draw(dims, seed=21)
+    o = orc.Oracle(dims, bc_t=bc, m=m, g=0.0, n_poles=12, lambda_min=1e-2, lambda_max=8.0,
+                   inner_tol=1e-14)
+    out = o.m0inv(src[0], dag=dag, tol=1e-13)
+    sym = np.linalg.inv(_m0_symbol(dims, o.a, o.b, m, bc))
+    if dag:
+        sym = np.conj(np.swapaxes(sym, -1, -2))
+    ref = cf.apply_symbol(sym, src[0], dims, bc)
+    assert rel(out, ref) < 1e-10
+
+
+def test_m0inv_free_preconditioning_identity(orc):
+    """With phi = 0 the preconditioned matrix M M0^-1 is the identity (Sec. 7.3)."""
+    dims = (4, 4, 4, 4)
+    _, src = inputs.draw(dims, seed=22)
+    o = orc.Oracle(dims, m=0.05, g=0.3, n_poles=16, lambda_min=1e-2, lambda_max=8.0,
+                   inner_tol=1e-14)
+    y = o.m0inv(src[0], tol=1e-13)
+    back = o.apply(orc.OP_M, y, np.zeros(dims[::-1], complex))
+    assert rel(back, src[0]) < 1e-11
+
+
 # ------------------------------------------------------------------- force
 
 def _S_dense(Dov, phi, xi, m, g):
