@@ -15,6 +15,8 @@ _SO = os.path.join(HERE, "libovoracle.so")
 MAX_POLES = 64
 
 OP_HW, OP_DOV, OP_DOV_DAG, OP_M, OP_M_DAG, OP_MDAGM = range(6)
+# forms of the Dirac operator inside M (ov_oracle.h, ORC_DIRAC_*)
+DIRAC_OVERLAP_MS, DIRAC_OVERLAP_RAT, DIRAC_OVERLAP_EXACT, DIRAC_DSLASH = range(4)
 
 
 class Params(C.Structure):
@@ -25,7 +27,7 @@ class Params(C.Structure):
                 ("lambda_max", C.c_double), ("inner_tol", C.c_double),
                 ("max_inner", C.c_int),
                 ("a", C.c_double * MAX_POLES), ("b", C.c_double * MAX_POLES),
-                ("delta", C.c_double), ("d0", C.c_double)]
+                ("delta", C.c_double), ("d0", C.c_double), ("dirac", C.c_int)]
 
 
 class MsStats(C.Structure):
@@ -82,7 +84,8 @@ class Oracle:
     """One lattice + action + sign-approximation setting."""
 
     def __init__(self, dims, bc_t=-1, M0=1.0, m=0.05, g=0.1, n_poles=16,
-                 lambda_min=0.01, lambda_max=8.0, inner_tol=1e-13, max_inner=5000):
+                 lambda_min=0.01, lambda_max=8.0, inner_tol=1e-13, max_inner=5000,
+                 dirac=DIRAC_OVERLAP_MS):
         p = Params()
         X, Y, Z, T = dims
         p.dims[:] = [X, Y, Z, T]
@@ -94,6 +97,7 @@ class Oracle:
         p.n_poles = n_poles
         p.lambda_min, p.lambda_max = lambda_min, lambda_max
         p.inner_tol, p.max_inner = inner_tol, max_inner
+        p.dirac = dirac
         rc = lib().orc_init(C.byref(p))
         if rc != 0:
             raise ValueError(f"orc_init failed ({rc})")

@@ -399,6 +399,10 @@ int orc_init(orc_params *p) {
   for (int d = 0; d < 4; ++d)
     if (p->dims[d] < 2) return 1;
   if (p->bc_t != 1 && p->bc_t != -1) return 1;
+  if (p->dirac < ORC_DIRAC_OVERLAP_MS || p->dirac > ORC_DIRAC_DSLASH) return 1;
+  /* Dslash needs 1 - D/2 invertible at every lattice momentum: no momentum with
+   * every p_mu in {0, pi}, which antiperiodic time with T even guarantees */
+  if (p->dirac == ORC_DIRAC_DSLASH && (p->bc_t != -1 || (p->dims[3] & 1))) return 1;
   if (p->n_poles < 1 || p->n_poles > ORC_MAX_POLES) return 1;
   if (p->inner_tol <= 0 || p->max_inner < 1) return 1;
   return orc_zolotarev(p->n_poles, p->lambda_min, p->lambda_max, p->a, p->b, &p->delta,
@@ -413,6 +417,163 @@ int orc_sign(const orc_params *p, const cplx *in, cplx *out, orc_ms_stats *st) {
   orc_hw(p, acc, out);
   free(acc);
   return rc;
+}
+
+/* ------------------------------------------------ momentum-space operators
+ * Sec. 7.2: without a gauge field the Dirac operator is diagonal in momentum
+ * space.  For a field ~ exp(+i p.x) the Wilson operator of orc_dw is the 4x4
+ * matrix D_W(p) = (4 - M0 - sum_mu cos p_mu) + i sum_mu gamma_mu sin p_mu, and
+ * H_W(p) = g5 D_W(p) with H_W(p)^2 = s2(p) 1.  Momenta: p_mu = 2 pi k / L_mu,
+ * and (2 k + 1) pi / T in time for antiperiodic fermions (Sec. 3.1). */
+static double momentum(const orc_params *p, int mu, int k) {
+  const double shift = (mu == 3 && p->bc_t < 0) ? 1.0 : 0.0;
+  return M_PI * (2.0 * k + shift) / p->dims[mu];
+}
+
+static void mat4_mul(cplx a[4][4], cplx b[4][4], cplx out[4][4]) {
+  cplx t[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      cplx v = 0;
+      for (int k = 0; k < 4; ++k) v += a[i][k] * b[k][j];
+      t[i][j] = v;
+    }
+  memcpy(out, t, sizeof(t));
+}
+
+/* inverse by Gauss-Jordan elimination with partial pivoting; 1 if singular */
+static int mat4_inv(cplx a[4][4], cplx out[4][4]) {
+  cplx m[4][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) m[i][j] = j < 4 ? a[i][j] : (j - 4 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (cabs(m[r][c]) > cabs(m[piv][c])) piv = r;
+    if (cabs(m[piv][c]) < 1e-300) return 1;
+    if (piv != c)
+      for (int j = 0; j < 8; ++j) { cplx t = m[c][j]; m[c][j] = m[piv][j]; m[piv][j] = t; }
+    cplx d = m[c][c];
+    for (int j = 0; j < 8; ++j) m[c][j] /= d;
+    for (int r = 0; r < 4; ++r)
+      if (r != c) {
+        cplx f = m[r][c];
+        for (int j = 0; j < 8; ++j) m[r][j] -= f * m[c][j];
+      }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) out[i][j] = m[i][j + 4];
+  return 0;
+}
+
+/* D(p) of form p->dirac (or its adjoint): D_ov = 1 + g5 eps(p), eps = H_W(p) R
+ * with R = sum_k a_k / (s2 + b_k) (rational) or 1 / sqrt(s2) (exact), and
+ * Dslash = (1 - D_ov / 2)^-1 D_ov (Sec. 2.2). */
+static int dirac_symbol(const orc_params *p, const double pm[4], int dag, cplx D[4][4]) {
+  cplx gm[5][4][4];
+  for (int mu = 0; mu < 5; ++mu) build_gamma(mu, gm[mu]);
+  double w = 4.0 - p->M0, s2 = 0.0;
+  for (int mu = 0; mu < 4; ++mu) w -= cos(pm[mu]);
+  cplx DW[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      DW[i][j] = (i == j) ? w : 0.0;
+      for (int mu = 0; mu < 4; ++mu) DW[i][j] += _Complex_I * sin(pm[mu]) * gm[mu][i][j];
+    }
+  s2 = w * w;
+  for (int mu = 0; mu < 4; ++mu) s2 += sin(pm[mu]) * sin(pm[mu]);
+  double R = 0.0;
+  if (p->dirac == ORC_DIRAC_OVERLAP_RAT)
+    for (int k = 0; k < p->n_poles; ++k) R += p->a[k] / (s2 + p->b[k]);
+  else
+    R = 1.0 / sqrt(s2);
+  cplx H[4][4], eps[4][4], g5eps[4][4];
+  mat4_mul(gm[4], DW, H);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) eps[i][j] = H[i][j] * R;
+  mat4_mul(gm[4], eps, g5eps);
+  cplx Dov[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Dov[i][j] = (i == j ? 1.0 : 0.0) + g5eps[i][j];
+  cplx out[4][4];
+  if (p->dirac == ORC_DIRAC_DSLASH) {
+    cplx A[4][4], Ai[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) A[i][j] = (i == j ? 1.0 : 0.0) - 0.5 * Dov[i][j];
+    if (mat4_inv(A, Ai)) return 1;
+    mat4_mul(Ai, Dov, out);
+  } else {
+    memcpy(out, Dov, sizeof(out));
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) D[i][j] = dag ? conj(out[j][i]) : out[i][j];
+  return 0;
+}
+
+/* out = D in (dag: D^dag in) through the plain 4-D discrete Fourier transform
+ *   in~(p) = sum_x exp(-i p.x) in(x),   out(x) = 1/V sum_p exp(+i p.x) D(p) in~(p). */
+static int momentum_apply(const orc_params *p, int dag, const cplx *in, cplx *out) {
+  const int L[4] = {p->dims[0], p->dims[1], p->dims[2], p->dims[3]};
+  const long long V = volume(p);
+  cplx *ph[4];  /* ph[mu][k * L + x] = exp(-i p_mu(k) x) */
+  for (int mu = 0; mu < 4; ++mu) {
+    ph[mu] = vec_new((long long)L[mu] * L[mu]);
+    for (int k = 0; k < L[mu]; ++k)
+      for (int x = 0; x < L[mu]; ++x) ph[mu][k * L[mu] + x] = cexp(-_Complex_I * momentum(p, mu, k) * x);
+  }
+  cplx *hat = vec_new(4 * V);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(|| : bad)
+  for (long long kk = 0; kk < V; ++kk) {
+    long long r = kk;
+    const int kx = r % L[0]; r /= L[0];
+    const int ky = r % L[1]; r /= L[1];
+    const int kz = r % L[2];
+    const int kt = (int)(r / L[2]);
+    cplx acc[4] = {0, 0, 0, 0};
+    for (long long i = 0; i < V; ++i) {
+      long long q = i;
+      const int x = q % L[0]; q /= L[0];
+      const int y = q % L[1]; q /= L[1];
+      const int z = q % L[2];
+      const int t = (int)(q / L[2]);
+      const cplx e = ph[0][kx * L[0] + x] * ph[1][ky * L[1] + y] * ph[2][kz * L[2] + z] *
+                     ph[3][kt * L[3] + t];
+      for (int s = 0; s < 4; ++s) acc[s] += e * in[4 * i + s];
+    }
+    const double pm[4] = {momentum(p, 0, kx), momentum(p, 1, ky), momentum(p, 2, kz),
+                          momentum(p, 3, kt)};
+    cplx D[4][4];
+    if (dirac_symbol(p, pm, dag, D)) bad = 1;
+    for (int s = 0; s < 4; ++s) {
+      cplx v = 0;
+      for (int t = 0; t < 4; ++t) v += D[s][t] * acc[t];
+      hat[4 * kk + s] = v;
+    }
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long i = 0; i < V; ++i) {
+    long long q = i;
+    const int x = q % L[0]; q /= L[0];
+    const int y = q % L[1]; q /= L[1];
+    const int z = q % L[2];
+    const int t = (int)(q / L[2]);
+    cplx acc[4] = {0, 0, 0, 0};
+    for (long long kk = 0; kk < V; ++kk) {
+      long long r = kk;
+      const int kx = r % L[0]; r /= L[0];
+      const int ky = r % L[1]; r /= L[1];
+      const int kz = r % L[2];
+      const int kt = (int)(r / L[2]);
+      const cplx e = conj(ph[0][kx * L[0] + x] * ph[1][ky * L[1] + y] * ph[2][kz * L[2] + z] *
+                          ph[3][kt * L[3] + t]);
+      for (int s = 0; s < 4; ++s) acc[s] += e * hat[4 * kk + s];
+    }
+    for (int s = 0; s < 4; ++s) out[4 * i + s] = acc[s] / (double)V;
+  }
+  for (int mu = 0; mu < 4; ++mu) free(ph[mu]);
+  free(hat);
+  return bad;
 }
 
 /* Yukawa term added to out: c+ P+ in + c- P- in (dag = 0) or its adjoint (dag = 1). */
@@ -447,6 +608,18 @@ static int apply_one(const orc_params *p, int op, const cplx *phi, const cplx *i
   orc_ms_stats st = {0, 1, 0.0};
   int rc = 0;
   cplx *tmp = vec_new(N), *eps = vec_new(N);
+  if (p->dirac != ORC_DIRAC_OVERLAP_MS && op != ORC_OP_HW) {
+    if (op != ORC_OP_DOV && op != ORC_OP_M && op != ORC_OP_DOV_DAG && op != ORC_OP_M_DAG) {
+      rc = 1;
+    } else {
+      const int dag = (op == ORC_OP_DOV_DAG || op == ORC_OP_M_DAG);
+      rc = momentum_apply(p, dag, in, out);
+      if (op == ORC_OP_M || op == ORC_OP_M_DAG) add_yukawa(p, phi, in, out, dag);
+    }
+    free(tmp);
+    free(eps);
+    return rc;
+  }
   switch (op) {
     case ORC_OP_HW:
       orc_hw(p, in, out);

@@ -46,7 +46,21 @@ typedef struct {
   double b[ORC_MAX_POLES];
   double delta;         /* max |x R(x^2) - 1| on the interval */
   double d0;            /* minimax normalisation */
+  int dirac;            /* form of the Dirac operator D inside M (see ORC_DIRAC_*) */
 } orc_params;
+
+/* Forms of D (set before orc_init; 0 is the default):
+ *   ORC_DIRAC_OVERLAP_MS     D_ov with the rational sign by multi-shift CG on H_W^2
+ *   ORC_DIRAC_OVERLAP_RAT    D_ov with the same rational sign, per momentum
+ *   ORC_DIRAC_OVERLAP_EXACT  D_ov with the exact sign H_W / |H_W|, per momentum
+ *   ORC_DIRAC_DSLASH         Dslash = (1 - D_ov/2)^-1 D_ov with the exact sign
+ *                            (the paper's kernel, Sec. 2.2 and eq. fmat of Sec. 7.1);
+ *                            needs antiperiodic time with T even (Sec. 3.1)
+ * The per-momentum forms follow Sec. 7.2: with no gauge field D is diagonal in
+ * momentum space, so the field is Fourier transformed, multiplied by the 4x4
+ * matrix D(p) and transformed back. */
+enum { ORC_DIRAC_OVERLAP_MS = 0, ORC_DIRAC_OVERLAP_RAT = 1, ORC_DIRAC_OVERLAP_EXACT = 2,
+       ORC_DIRAC_DSLASH = 3 };
 
 typedef struct {
   int iters;            /* Krylov iterations */
@@ -91,7 +105,9 @@ int orc_multishift(const orc_params *p, int n_shift, const double *sig, const do
 int orc_sign(const orc_params *p, const double complex *in, double complex *out,
              orc_ms_stats *st);
 
-/* out = op(in); phi is complex128 [V] (may be NULL for HW/DOV/DOV_DAG). */
+/* out = op(in); phi is complex128 [V] (may be NULL for HW/DOV/DOV_DAG).  DOV and
+ * DOV_DAG apply the operator D of form p->dirac (and its adjoint); M and M_DAG
+ * add the Yukawa term to it. */
 int orc_apply(const orc_params *p, int op, const double complex *phi,
               const double complex *in, double complex *out, long long *inner_iters);
 

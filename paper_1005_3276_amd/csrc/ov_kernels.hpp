@@ -167,6 +167,81 @@ __global__ void __launch_bounds__(256) k_hw(const SysDev* __restrict__ sys, cons
   }
 }
 
+// out = H_W in with the block's own sites staged in LDS: a block of spb
+// consecutive sites covers whole x rows (and, at 16^4 with 256 sites, a whole
+// xy plane), so its x and y neighbours are read from LDS and only the centre
+// and the z and t neighbours come through the vector cache (5 of 9 spinor
+// loads).  Neighbours outside the block fall back to global loads.
+// Dynamic LDS: 4 * spb complex values.
+template <class R>
+__device__ __forceinline__ void nb_lds(const c2<R>* __restrict__ f, const c2<R>* sh, int V, int spb,
+                                       int i0, int i1, int j, c2<R> v[4]) {
+  if (j >= i0 && j < i1) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = sh[s * spb + (j - i0)];
+  } else {
+    load_sp<R>(f, V, j, v);
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void load_nbr_staged(const c2<R>* __restrict__ f, const Geo& g, int i,
+                                                const c2<R>* sh, int spb, int i0, int i1,
+                                                Nbr<R>& nb) {
+  const int X = g.X, Y = g.Y, Z = g.Z, T = g.T, V = g.V;
+  int r = i;
+  const int x = r % X; r /= X;
+  const int y = r % Y; r /= Y;
+  const int z = r % Z;
+  const int t = r / Z;
+  const int XY = X * Y, XYZ = XY * Z;
+  load_sp<R>(f, V, (z + 1 < Z) ? i + XY : i + XY - XYZ, nb.zf);
+  load_sp<R>(f, V, (z > 0) ? i - XY : i - XY + XYZ, nb.zb);
+  load_sp<R>(f, V, (t + 1 < T) ? i + XYZ : i + XYZ - V, nb.tf);
+  load_sp<R>(f, V, (t > 0) ? i - XYZ : i - XYZ + V, nb.tb);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) nb.c[s] = sh[s * spb + (i - i0)];
+  nb_lds<R>(f, sh, V, spb, i0, i1, (x + 1 < X) ? i + 1 : i + 1 - X, nb.xf);
+  nb_lds<R>(f, sh, V, spb, i0, i1, (x > 0) ? i - 1 : i - 1 + X, nb.xb);
+  nb_lds<R>(f, sh, V, spb, i0, i1, (y + 1 < Y) ? i + X : i + X - XY, nb.yf);
+  nb_lds<R>(f, sh, V, spb, i0, i1, (y > 0) ? i - X : i - X + XY, nb.yb);
+}
+
+// Stage the block's sites [i0, i1) of f into sh (planar, 4 * spb values).
+template <class R>
+__device__ __forceinline__ void stage_block(const c2<R>* __restrict__ f, int V, int spb, int i0,
+                                            int i1, c2<R>* sh) {
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) sh[s * spb + (i - i0)] = f[(size_t)s * V + i];
+  }
+  __syncthreads();
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_hw_lds(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+                                                 int nb_total, double diag) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  c2<R>* sh = (c2<R>*)dyn_lds;
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const Geo g = S.g;
+  const int lb = L - S.blk0;
+  const c2<R>* in = (const c2<R>*)S.e_in;
+  c2<R>* out = (c2<R>*)S.e_out;
+  const int spb = S.spb;
+  const int i0 = lb * spb;
+  const int i1 = min(g.V, i0 + spb);
+  stage_block<R>(in, g.V, spb, i0, i1, sh);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    Nbr<R> nb;
+    load_nbr_staged<R>(in, g, i, sh, spb, i0, i1, nb);
+    c2<R> o[4];
+    hw_compute<R>(nb, g, i, (R)diag, o);
+    store_sp<R>(out, g.V, i, o);
+  }
+}
+
 // ------------------------------------------------------- multi-shift: t pass
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
 // advances the shift recurrences, decides convergence, then

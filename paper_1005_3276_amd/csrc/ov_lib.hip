@@ -1951,12 +1951,23 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   const double diag = 4.0 - c->p.M0;
+  // LDS-staged stencil unless disabled (OV_HW_LDS=0) or the block does not fit
+  const int spb = E.sb[0].spb;
+  const size_t lds_bytes = (size_t)4 * spb * (prec ? sizeof(float2) : sizeof(double2));
+  const char* ev = std::getenv("OV_HW_LDS");
+  const bool use_lds = !(ev && *ev == '0') && lds_bytes <= 64 * 1024;
   HIPCHK(c, hipEventRecord(e0, E.st));
   for (int r = 0; r < reps; ++r) {
-    if (prec)
+    if (use_lds) {
+      if (prec)
+        k_hw_lds<float><<<E.nb_total, c->block, lds_bytes, E.st>>>(E.tables, E.bmap, E.nb_total, diag);
+      else
+        k_hw_lds<double><<<E.nb_total, c->block, lds_bytes, E.st>>>(E.tables, E.bmap, E.nb_total, diag);
+    } else if (prec) {
       k_hw<float><<<E.nb_total, c->block, 0, E.st>>>(E.tables, E.bmap, E.nb_total, diag, 0);
-    else
+    } else {
       k_hw<double><<<E.nb_total, c->block, 0, E.st>>>(E.tables, E.bmap, E.nb_total, diag, 0);
+    }
   }
   HIPCHK(c, hipEventRecord(e1, E.st));
   TRY(check_launch(c));

@@ -353,26 +353,35 @@ def test_solve_g0_fft(orc):
     assert g5 is not None
 
 
-def _m0_symbol(dims, a, b, m, bc_t=-1):
-    """M0(p) = D_ov(p) + m P+ + m* P- with the rational sign (phi = 0)."""
+def _m0_symbol(dims, a, b, m, bc_t=-1, dirac=0):
+    """M0(p) = D(p) + m P+ + m* P- (phi = 0); D = D_ov with the rational sign
+    (dirac 0, 1), the exact sign (2) or Dslash = (1 - D_ov/2)^-1 D_ov (3)."""
     g5 = cf.paper_gammas()[4]
     Pp = 0.5 * (np.eye(4) + g5)
     Pm = 0.5 * (np.eye(4) - g5)
-    return cf.dov_symbol(cf.rational_symbol(dims, a, b, bc_t)) + m * Pp + np.conj(m) * Pm
+    if dirac <= 1:
+        D = cf.dov_symbol(cf.rational_symbol(dims, a, b, bc_t))
+    else:
+        D = cf.dov_symbol(cf.exact_sign_symbol(dims, bc_t))
+        if dirac == 3:
+            D = np.linalg.solve(np.eye(4) - 0.5 * D, D)
+    return D + m * Pp + np.conj(m) * Pm
 
 
-@pytest.mark.parametrize("dims,bc,m", [((4, 4, 4, 4), -1, 0.05), ((4, 4, 2, 6), -1, 0.3 + 0.2j),
-                                       ((4, 2, 4, 4), 1, 0.1)])
+@pytest.mark.parametrize("dims,bc,m,dirac", [((4, 4, 4, 4), -1, 0.05, 0),
+                                             ((4, 4, 2, 6), -1, 0.3 + 0.2j, 0),
+                                             ((4, 2, 4, 4), 1, 0.1, 0), ((4, 2, 4, 4), 1, 0.1, 2),
+                                             ((4, 4, 2, 6), -1, 0.3 + 0.2j, 3)])
 @pytest.mark.parametrize("dag", [False, True])
-def test_m0inv_vs_closed_form(orc, dims, bc, m, dag):
+def test_m0inv_vs_closed_form(orc, dims, bc, m, dirac, dag):
     """Free-field preconditioner of Sec. 7.3: the oracle's M0^-1 and M0^-dag (CG on
     the position-space operator) against the inverse of the momentum-space 4x4
     matrix M0(p) (numpy FFT + linalg.inv), including a complex mass."""
     _, src = inputs.draw(dims, seed=21)
     o = orc.Oracle(dims, bc_t=bc, m=m, g=0.0, n_poles=12, lambda_min=1e-2, lambda_max=8.0,
-                   inner_tol=1e-14)
+                   inner_tol=1e-14, dirac=dirac)
     out = o.m0inv(src[0], dag=dag, tol=1e-13)
-    sym = np.linalg.inv(_m0_symbol(dims, o.a, o.b, m, bc))
+    sym = np.linalg.inv(_m0_symbol(dims, o.a, o.b, m, bc, dirac))
     if dag:
         sym = np.conj(np.swapaxes(sym, -1, -2))
     ref = cf.apply_symbol(sym, src[0], dims, bc)
@@ -388,6 +397,91 @@ def test_m0inv_free_preconditioning_identity(orc):
     y = o.m0inv(src[0], tol=1e-13)
     back = o.apply(orc.OP_M, y, np.zeros(dims[::-1], complex))
     assert rel(back, src[0]) < 1e-11
+
+
+# ------------------------------------- momentum-space Dirac operators (Sec. 7.2)
+
+def _dense_of(apply, n):
+    out = np.zeros((n, n), complex)
+    e = np.zeros(n, complex)
+    for j in range(n):
+        e[:] = 0
+        e[j] = 1
+        out[:, j] = apply(e).reshape(-1)
+    return out
+
+
+def test_dirac_exact_vs_dense_eig(orc, dense44):
+    """Exact-sign D_ov by the oracle's plain 4-D DFT equals 1 + g5 sign(H_W) with
+    sign(H_W) = U sgn(Lambda) U^dag from the dense eigendecomposition of H_W (whose
+    matrix is pinned to the oracle's stencil above); its adjoint too."""
+    dims, H, lam, U = dense44
+    g5 = np.kron(np.eye(np.prod(dims)), cf.paper_gammas()[4])
+    D_eig = np.eye(H.shape[0]) + g5 @ (U * np.sign(lam)) @ U.conj().T
+    o = orc.Oracle(dims, dirac=orc.DIRAC_OVERLAP_EXACT)
+    v = inputs.gaussian_field(dims, nrhs=2, seed=41)
+    for r in range(2):
+        x = v[r].reshape(-1)
+        assert rel(o.apply(orc.OP_DOV, v[r]).reshape(-1), D_eig @ x) < 1e-12
+        assert rel(o.apply(orc.OP_DOV_DAG, v[r]).reshape(-1), D_eig.conj().T @ x) < 1e-12
+
+
+def test_dirac_rational_per_momentum_matches_multishift(orc):
+    """The rational sign evaluated per momentum equals the multi-shift CG result to
+    the inner tolerance: two different evaluations of the same operator."""
+    dims = (4, 4, 2, 6)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=42)
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0, inner_tol=1e-14)
+    o_ms = orc.Oracle(dims, **kw)
+    o_ft = orc.Oracle(dims, dirac=orc.DIRAC_OVERLAP_RAT, **kw)
+    for op in (orc.OP_DOV, orc.OP_DOV_DAG, orc.OP_M, orc.OP_M_DAG):
+        a = o_ms.apply(op, src[0], phi)
+        b = o_ft.apply(op, src[0], phi)
+        assert rel(b, a) < 1e-12
+
+
+def test_dslash_vs_dense(orc):
+    """Dslash = (1 - D/2)^-1 D (Sec. 2.2) with the exact D from the dense
+    eigendecomposition at 2^3 x 4 (antiperiodic, T even): the oracle's per-momentum
+    form, anti-hermiticity and {Dslash, g5} = 0 (Sec. 3.1)."""
+    dims = (2, 2, 2, 4)
+    n = 4 * int(np.prod(dims))
+    o0 = orc.Oracle(dims)
+    H = _dense_of(o0.hw, n)
+    H = 0.5 * (H + H.conj().T)
+    lam, U = np.linalg.eigh(H)
+    g5 = np.kron(np.eye(n // 4), cf.paper_gammas()[4])
+    D = np.eye(n) + g5 @ (U * np.sign(lam)) @ U.conj().T
+    Ds_ref = np.linalg.solve(np.eye(n) - 0.5 * D, D)
+    o = orc.Oracle(dims, dirac=orc.DIRAC_DSLASH)
+    Ds = _dense_of(lambda e: o.apply(orc.OP_DOV, e), n)
+    Dsd = _dense_of(lambda e: o.apply(orc.OP_DOV_DAG, e), n)
+    assert np.abs(Ds - Ds_ref).max() < 1e-12 * np.abs(Ds_ref).max()
+    assert np.abs(Dsd - Ds.conj().T).max() < 1e-13
+    assert np.abs(Ds + Ds.conj().T).max() < 1e-12 * np.abs(Ds).max()
+    assert np.abs(Ds @ g5 + g5 @ Ds).max() < 1e-12 * np.abs(Ds).max()
+
+
+def test_dslash_rejects_periodic_time(orc):
+    with pytest.raises(ValueError):
+        orc.Oracle((2, 2, 2, 4), bc_t=1, dirac=orc.DIRAC_DSLASH)
+
+
+@pytest.mark.parametrize("dirac", [2, 3])
+def test_solve_momentum_forms_vs_dense_lu(orc, dirac):
+    """CG on MdagM with M = D + Y for the exact-sign D_ov and for Dslash (the
+    paper's fermion matrix), against a dense LU solve at 2^2 x 4 x 4."""
+    dims = (2, 2, 4, 4)
+    n = 4 * int(np.prod(dims))
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=43)
+    o = orc.Oracle(dims, m=0.05, g=0.3, dirac=dirac)
+    M = _dense_of(lambda e: o.apply(orc.OP_M, e, phi), n)
+    Md = _dense_of(lambda e: o.apply(orc.OP_M_DAG, e, phi), n)
+    assert np.abs(Md - M.conj().T).max() < 1e-13 * np.abs(M).max()
+    x, st, rc = o.solve(src[0], phi, tol=1e-12)
+    assert rc == 0
+    ref = np.linalg.solve(M.conj().T @ M, src[0].reshape(-1))
+    assert rel(x.reshape(-1), ref) < 1e-9
 
 
 # ------------------------------------------------------------------- force
