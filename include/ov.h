@@ -61,15 +61,28 @@ typedef enum {
 
 typedef enum { OV_FP64 = 0, OV_MIXED = 1 } ov_precision;
 
+/* Form of the Dirac operator D inside M = D + (m + g phi) P+ + (m* + g* phi*) P-. */
+typedef enum {
+  OV_DIRAC_OVERLAP_MS = 0,    /* D_ov = 1 + g5 eps(H_W), eps the Zolotarev rational by
+                                 multi-shift CG on H_W^2 (default) */
+  OV_DIRAC_OVERLAP_RAT = 1,   /* the same rational sign evaluated per momentum: with no
+                                 gauge field D is diagonal in momentum space (Sec. 7.2) */
+  OV_DIRAC_OVERLAP_EXACT = 2, /* D_ov with the exact sign H_W / |H_W|, per momentum */
+  OV_DIRAC_DSLASH = 3         /* the paper's kernel Dslash = (1 - D_ov/2)^-1 D_ov with the
+                                 exact sign (Sec. 2.2, fermion matrix of Sec. 7.1);
+                                 needs bc_t = -1 */
+} ov_dirac;
+
 typedef enum {
   OV_OP_HW = 0,      /* H_W = g5 D_W(-M0) */
-  OV_OP_DOV = 1,     /* psi + g5 eps(psi) */
-  OV_OP_DOV_DAG = 2, /* psi + eps(g5 psi) */
-  OV_OP_M = 3,       /* D_ov psi + c+ P+ psi + c- P- psi */
-  OV_OP_M_DAG = 4,   /* D_ov^dag psi + c+* P+ psi + c-* P- psi */
+  OV_OP_DOV = 1,     /* D psi; D_ov psi = psi + g5 eps(psi) for OV_DIRAC_OVERLAP_MS */
+  OV_OP_DOV_DAG = 2, /* D^dag psi; D_ov^dag psi = psi + eps(g5 psi) */
+  OV_OP_M = 3,       /* D psi + c+ P+ psi + c- P- psi */
+  OV_OP_M_DAG = 4,   /* D^dag psi + c+* P+ psi + c-* P- psi */
   OV_OP_MDAGM = 5,   /* M^dag M psi */
-  OV_OP_M0INV = 6,   /* M0^-1 psi, M0 = D_ov + m P+ + m* P- the free (phi = 0) fermion
-                        matrix with the same rational sign: the preconditioner of
+  OV_OP_M0INV = 6,   /* M0^-1 psi, M0 = D + m P+ + m* P- the free (phi = 0) fermion
+                        matrix with the same D (the multi-shift form uses its rational
+                        sign per momentum): the preconditioner of
                         Sec. 7.3, applied exactly in momentum space (per-axis DFTs;
                         needs every extent <= 64, X*Y <= 1024, X*Z <= 1024) */
   OV_OP_M0INV_DAG = 7 /* M0^-dag psi (same limits) */
@@ -102,6 +115,9 @@ typedef struct {
                               x = M0^-1 x~ (lattice limits of OV_OP_M0INV); 0: plain CG
                               on MdagM.  Convergence is always judged on the FP64 true
                               residual of the original system. */
+  int dirac;               /* ov_dirac: form of D in M (default OV_DIRAC_OVERLAP_MS); the
+                              momentum-space forms have the limits of OV_OP_M0INV and
+                              need no inner solve (inner tolerances are unused) */
 } ov_params;
 
 typedef struct {

@@ -14,6 +14,9 @@ OV_OK, OV_ERR_INVALID_ARG, OV_ERR_NOT_CONVERGED, OV_ERR_BREAKDOWN, OV_ERR_SPECTR
     OV_ERR_WORKSPACE, OV_ERR_DEVICE = range(7)
 OV_FP64, OV_MIXED = 0, 1
 OP_HW, OP_DOV, OP_DOV_DAG, OP_M, OP_M_DAG, OP_MDAGM, OP_M0INV, OP_M0INV_DAG = range(8)
+DIRAC_OVERLAP_MS, DIRAC_OVERLAP_RAT, DIRAC_OVERLAP_EXACT, DIRAC_DSLASH = range(4)
+DIRACS = {"overlap": DIRAC_OVERLAP_MS, "overlap_rat": DIRAC_OVERLAP_RAT,
+          "overlap_exact": DIRAC_OVERLAP_EXACT, "dslash": DIRAC_DSLASH}
 OPS = {"hw": OP_HW, "dov": OP_DOV, "dov_dag": OP_DOV_DAG, "m": OP_M, "m_dag": OP_M_DAG,
        "mdagm": OP_MDAGM, "m0inv": OP_M0INV, "m0inv_dag": OP_M0INV_DAG}
 
@@ -35,7 +38,7 @@ class OvParams(C.Structure):
                 ("reliable_delta", C.c_double), ("max_inner", C.c_int),
                 ("max_outer", C.c_int), ("precision", C.c_int),
                 ("inner_relax", C.c_double), ("inner_tol_max", C.c_double),
-                ("precondition", C.c_int)]
+                ("precondition", C.c_int), ("dirac", C.c_int)]
 
 
 class OvStats(C.Structure):
@@ -123,6 +126,8 @@ def default_params(**kw) -> OvParams:
             setattr(p, k + "_im", v.imag)
         elif k == "precision":
             p.precision = {"fp64": OV_FP64, "mixed": OV_MIXED}.get(v, v)
+        elif k == "dirac":
+            p.dirac = DIRACS.get(v, v)
         elif k in _PARAM_FIELDS:
             setattr(p, k, v)
         else:

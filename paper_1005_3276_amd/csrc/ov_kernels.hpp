@@ -863,22 +863,27 @@ __global__ void __launch_bounds__(256) k_fill(const SysDev* __restrict__ sys,
 // The theory has no gauge field, so every translation-invariant operator built
 // from H_W is diagonal in momentum space (the FFT route of Sec. 7.2).  For a
 // field ~ exp(+i p.x), D_W(p) = w + i gamma.s with w = 4 - M0 - sum cos p_mu,
-// s_mu = sin p_mu, H_W(p)^2 = s2 = w^2 + |s|^2, and with the rational sign
-// R(s2) = sum_k a_k / (s2 + b_k):
-//   D_ov(p) = 1 + R D_W(p) = (1 + R w) + i R gamma.s.
-// The free fermion matrix M0 = D_ov + m P+ + m* P- (phi = 0) of the
-// preconditioner (Sec. 7.3, M~ = M M0^-1, x = M0^-1 x~) is, with mu = Im m,
-//   M0(p) = a + i mu g5 + i R gamma.s,  a = 1 + Re m + R w,
-//   M0^-1(p)   = (a - i mu g5 - i R gamma.s) / (a^2 + mu^2 + R^2 |s|^2),
-//   M0^-dag(p) = (a + i mu g5 + i R gamma.s) / (a^2 + mu^2 + R^2 |s|^2).
+// s_mu = sin p_mu, H_W(p)^2 = s2 = w^2 + |s|^2.  Every Dirac operator form is
+//   D(p) = a0 + i c gamma.s :
+//   overlap, rational sign R = sum_k a_k / (s2 + b_k):  a0 = 1 + R w, c = R;
+//   overlap, exact sign R = 1 / sqrt(s2):                a0 = 1 + R w, c = R;
+//   Dslash = (1 - D_ov/2)^-1 D_ov (exact sign, Sec. 2.2): a0 = 0,
+//     c = 2 / (sqrt(s2) - w) = 2 (sqrt(s2) + w) / |s|^2  (finite when no momentum
+//     has every component in {0, pi}: antiperiodic time, T even).
+// The free fermion matrix of the preconditioner (Sec. 7.3),
+//   M0 = D + m P+ + m* P- = a + i mu g5 + i c gamma.s,  a = a0 + Re m, mu = Im m,
+// has M0^-1 = (a - i mu g5 - i c gamma.s) / (a^2 + mu^2 + c^2 |s|^2), and M0^-dag
+// the same with + signs.
 // Fields go through per-axis DFTs of L <= 64 points: forward e^{-2 pi i j k/L},
 // inverse e^{+2 pi i j k/L} with 1/V.  Antiperiodic time is handled by the
 // twist e^{-i pi t/T} before the forward and e^{+i pi t/T} after the inverse
 // transform, which puts p_t on (2n+1) pi / T.
-enum SymKind { SYM_M0INV = 0, SYM_M0INV_DAG = 1 };
+enum SymKind { SYM_D = 0, SYM_D_DAG = 1, SYM_M0INV = 2, SYM_M0INV_DAG = 3 };
+enum DiracForm { DIRAC_RATIONAL = 0, DIRAC_EXACT = 1, DIRAC_DSLASH = 2 };
 
 struct SymParams {
   int kind;
+  int form;           // DiracForm
   int np;
   double diag;        // 4 - M0
   double a[MAXP];     // residues a_k of the sign rational
@@ -1005,13 +1010,32 @@ __device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, d
                                              double2 v[4]) {
   const double s2sin = sx * sx + sy * sy + sz * sz + st * st;
   const double s2 = w * w + s2sin;
-  double Rr = 0.0;
-  for (int k = 0; k < sp.np; ++k) Rr += sp.a[k] / (s2 + sp.b[k]);
-  const double a = 1.0 + m_re + Rr * w;
-  const double mu = m_im;
-  const double inv_den = 1.0 / (a * a + mu * mu + Rr * Rr * s2sin);
-  const double sg = sp.kind == SYM_M0INV ? -1.0 : 1.0;
-  const double c = sg * Rr, c5 = sg * mu;  // out = (a v + i c5 g5 v + i c gamma.s v) / den
+  double a0, c;
+  if (sp.form == DIRAC_DSLASH) {
+    const double sq = sqrt(s2);
+    a0 = 0.0;
+    c = (w > 0.0) ? 2.0 * (sq + w) / s2sin : 2.0 / (sq - w);
+  } else {
+    double Rr = 0.0;
+    if (sp.form == DIRAC_EXACT) {
+      Rr = 1.0 / sqrt(s2);
+    } else {
+      for (int k = 0; k < sp.np; ++k) Rr += sp.a[k] / (s2 + sp.b[k]);
+    }
+    a0 = 1.0 + Rr * w;
+    c = Rr;
+  }
+  // out = (A v + i (cg gamma.s v + c5 g5 v)) * scale
+  double A = a0, cg = c, c5 = 0.0, scale = 1.0;
+  if (sp.kind == SYM_D_DAG) {
+    cg = -c;
+  } else if (sp.kind == SYM_M0INV || sp.kind == SYM_M0INV_DAG) {
+    A = a0 + m_re;
+    const double sg = sp.kind == SYM_M0INV ? -1.0 : 1.0;
+    cg = sg * c;
+    c5 = sg * m_im;
+    scale = 1.0 / (A * A + m_im * m_im + c * c * s2sin);
+  }
   // G = gamma.s v in the basis of Sec. 2.1 (the one of the Wilson stencil)
   double2 G[4];
   G[0] = double2{-sx * v[3].y + sy * v[3].x - sz * v[2].y + st * v[2].x,
@@ -1025,9 +1049,9 @@ __device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, d
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double g5 = k < 2 ? -1.0 : 1.0;
-    const double hr = c * G[k].x + c5 * g5 * v[k].x;  // h = c G + c5 g5 v ; out = a v + i h
-    const double hi = c * G[k].y + c5 * g5 * v[k].y;
-    v[k] = double2{(a * v[k].x - hi) * inv_den, (a * v[k].y + hr) * inv_den};
+    const double hr = cg * G[k].x + c5 * g5 * v[k].x;
+    const double hi = cg * G[k].y + c5 * g5 * v[k].y;
+    v[k] = double2{(A * v[k].x - hi) * scale, (A * v[k].y + hr) * scale};
   }
 }
 
@@ -1102,6 +1126,76 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
       if (w >= T) w -= T;
     }
     f[(size_t)spin * V + (xb + xl) + X * (y + Y * (z + Z * t))] = acc;
+  }
+}
+
+// Yukawa epilogue of a momentum-space D (psi = e_in, D psi already in e_out):
+//   mode 0:  e_out = D psi + Y psi,           partial |e_out|^2 -> part_c, part_b
+//   mode 1:  e_out = D^dag psi + Y^dag psi
+//   mode 2:  r64 = b - (D^dag psi + Y^dag psi)  (+ copy in cg_r when set),
+//            partial |r64|^2 -> part_c   (FP64 only)
+// c+ = m + g phi, c- = m* + g* phi*;  Y psi = c- P- psi + c+ P+ psi (spins 0,1 / 2,3).
+template <class R>
+__global__ void __launch_bounds__(256) k_yuk(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+                                              int nb_total, int mode) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> p[4], w[4];
+    load_sp<R>((const c2<R>*)S.e_in, V, i, p);
+    load_sp<R>((const c2<R>*)S.e_out, V, i, w);
+    const double2 ph = S.phi[i];
+    double cpr = S.m_re + S.g_re * ph.x - S.g_im * ph.y;
+    double cpi = S.m_im + S.g_re * ph.y + S.g_im * ph.x;
+    const double cmr = cpr;
+    double cmi = -cpi;
+    if (mode != 0) {  // adjoint: conjugate coefficients
+      cpi = -cpi;
+      cmi = -cmi;
+    }
+    double2 o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double cr = (k < 2) ? cmr : cpr, ci = (k < 2) ? cmi : cpi;
+      const double pr = (double)p[k].x, pi = (double)p[k].y;
+      o[k] = double2{(double)w[k].x + cr * pr - ci * pi, (double)w[k].y + cr * pi + ci * pr};
+    }
+    if (mode == 2) {
+      double2 rr[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double2 bv = S.cg_b[(size_t)i * 4 + k];
+        rr[k] = double2{bv.x - o[k].x, bv.y - o[k].y};
+      }
+      store_sp<double>((double2*)S.cg_r64, V, i, rr);
+      if (S.cg_r) {
+        c2<R> lo[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lo[k] = c2<R>{(R)rr[k].x, (R)rr[k].y};
+        store_sp<R>((c2<R>*)S.cg_r, V, i, lo);
+      }
+      acc += norm2_sp(rr);
+      continue;
+    }
+    c2<R> ov[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ov[k] = c2<R>{(R)o[k].x, (R)o[k].y};
+    store_sp<R>((c2<R>*)S.e_out, V, i, ov);
+    if (mode == 0) acc += norm2_sp(ov);
+  }
+  if (mode != 1) {
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+      S.part_c[lb] = tot;
+      if (mode == 0 && S.part_b) S.part_b[lb] = tot;
+    }
   }
 }
 

@@ -194,6 +194,97 @@ def test_m0inv_rejects_large_lattice():
                                        device="cuda"))
 
 
+# ------------------------------------- momentum-space Dirac operators (Sec. 7.2)
+
+@pytest.mark.parametrize("dirac", [1, 2, 3])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 2, 8)])
+def test_dirac_forms_apply_vs_oracle(orc, dirac, dims):
+    """D, D^dag, M, M^dag, MdagM for the per-momentum forms (rational, exact sign,
+    Dslash) against the oracle's plain 4-D DFT.  Both sides are FP64 with no inner
+    tolerance: relative 1e-13."""
+    print(f"[dirac-apply] dirac={dirac} dims={dims}", flush=True)
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=51)
+    o = orc.Oracle(dims, dirac=dirac, **kw)
+    lat = lattice(dims, dirac=dirac, **kw)
+    codes = {"dov": orc.OP_DOV, "dov_dag": orc.OP_DOV_DAG, "m": orc.OP_M, "m_dag": orc.OP_M_DAG,
+             "mdagm": orc.OP_MDAGM}
+    for op, code in codes.items():
+        out, _ = lat.apply(op, dev(src), dev(phi))
+        out = host(out)
+        for r in range(2):
+            assert rel(out[r], o.apply(code, src[r], phi)) < 1e-13, op
+
+
+@pytest.mark.parametrize("pc", [1, 0])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("dirac", [2, 3])
+def test_dirac_forms_solve_vs_oracle(orc, dirac, prec, pc):
+    """CG on MdagM with a momentum-space D at 8^4 (config-2 couplings): the true
+    residual under the oracle's operator of the same form meets 1e-10."""
+    dims = (8, 8, 8, 8)
+    print(f"[dirac-solve] dirac={dirac} prec={prec} pc={pc}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2))
+    lat = lattice(dims, dirac=dirac, precision=prec, precondition=pc, outer_tol=1e-10, **CFG2)
+    x, st = lat.solve(dev(src), dev(phi))
+    x = host(x)
+    o = orc.Oracle(dims, dirac=dirac, **CFG2)
+    for r in range(2):
+        res = o.residual(src[r], x[r], phi)
+        print(f"[dirac-solve] rhs {r}: oracle residual {res:.3e} {st[r]}", flush=True)
+        assert res <= 1e-10
+        assert st[r]["inner_iters"] == 0
+
+
+def test_dslash_force_vs_oracle(orc):
+    """HMC force with the paper's fermion matrix (Dslash) against the oracle."""
+    dims = (4, 4, 4, 4)
+    phi, xi = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(4))
+    kw = dict(m=0.05, g=0.3, n_poles=16, lambda_min=0.01, lambda_max=8.0, dirac=3)
+    lat = lattice(dims, precision="mixed", outer_tol=1e-12, **kw)
+    S, G, st = lat.force(dev(xi), dev(phi))
+    G = host(G)
+    o = orc.Oracle(dims, **kw)
+    Gref = np.zeros_like(G)
+    for r in range(2):
+        So, Go, ost, rc = o.force(phi, xi[r], tol=1e-12)
+        assert abs(S[r] - So) <= 1e-9 * abs(So)
+        Gref += Go
+    assert np.abs(G - Gref).max() <= 1e-8 * np.abs(Gref).max()
+
+
+@pytest.mark.parametrize("dims,m,g,sigma2", [((16, 16, 16, 16), 0.05, 0.3, 0.25),
+                                             ((16, 16, 16, 32), 1.0, 0.2, 0.25)])
+def test_dslash_solve_full_size_closed_form(dims, m, g, sigma2):
+    """Dslash solves at full size (16^4 with config-2 couplings; 16^3 x 32 at the
+    m = 1, g = 1/5 of the paper's inversion benchmarks, Table 6): the true residual
+    is recomputed from the closed form (numpy FFT of the 4x4 Dslash(p) plus the
+    site-local Yukawa term)."""
+    import closed_form as cf
+    print(f"[dslash-full] dims={dims}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=sigma2, seed=inputs.config_seed(2))
+    lat = lattice(dims, dirac=3, precision="mixed", outer_tol=1e-10, m=m, g=g)
+    t = time.time()
+    x, st = lat.solve(dev(src), dev(phi))
+    torch.cuda.synchronize()
+    print(f"[dslash-full] GPU {time.time() - t:.3f}s {st[0]}", flush=True)
+    D = cf.dov_symbol(cf.exact_sign_symbol(dims))
+    Ds = np.linalg.solve(np.eye(4) - 0.5 * D, D)
+    Dsd = np.conj(np.swapaxes(Ds, -1, -2))
+    g5 = cf.paper_gammas()[4]
+    Pp = 0.5 * (np.eye(4) + g5)
+    Pm = 0.5 * (np.eye(4) - g5)
+    ph = phi[..., None, None]
+    Y = (m + g * ph) * Pp + np.conj(m + g * ph) * Pm
+    Yd = np.conj(np.swapaxes(Y, -1, -2))
+    xh = host(x)[0]
+    u = cf.apply_symbol(Ds, xh, dims) + np.einsum("...ab,...b->...a", Y, xh)
+    v = cf.apply_symbol(Dsd, u, dims) + np.einsum("...ab,...b->...a", Yd, u)
+    res = np.linalg.norm(src[0] - v) / np.linalg.norm(src[0])
+    print(f"[dslash-full] closed-form residual {res:.3e}", flush=True)
+    assert res <= 1e-10
+
+
 def test_zero_source_gives_zero():
     dims = (4, 4, 4, 4)
     lat = lattice(dims, **CFG1)
