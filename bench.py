@@ -4,8 +4,9 @@ true residual, plus the Wilson-stencil bandwidth.
 One step = one solve of M^dag M x = b at 16^4 (m = 0.05, g = 0.3, phi ~ CN(0, 0.25),
 20 Zolotarev poles on [1e-3, 8], outer residual 1e-10) with the mixed-precision
 solver: every step of the hot path (pack, multi-shift sign, D_ov / M / M^dag
-epilogues, outer CG, reliable FP64 updates) runs inside it.  Inputs are seeded
-synthetic fields resident in HBM before the timed region.
+epilogues, free-field preconditioner, outer CG, reliable FP64 updates) runs
+inside it.  Inputs are seeded synthetic fields resident in HBM before the timed
+region.
 
 Prints ONE JSON line.  Only one GPU is supported: --gpus N > 1 exits.
 """
@@ -66,7 +67,8 @@ def stencil_bandwidth(lat, torch, nrhs, prec, reps=20):
 
 def cpu_baseline(phi, src, outer_iters):
     """Oracle FP64 M^dag M applications at 16^4 on the host cores; scaled to one
-    solve with the GPU FP64 solver's outer-iteration count."""
+    solve of the oracle's (unpreconditioned) CG by the outer-iteration count of
+    the unpreconditioned GPU FP64 solve."""
     from oracle import oracle as O
     o = O.Oracle(DIMS, m=CFG["m"], g=CFG["g"], n_poles=CFG["n_poles"],
                  lambda_min=CFG["lambda_min"], lambda_max=CFG["lambda_max"], inner_tol=1e-12)
@@ -147,6 +149,48 @@ def other_configs(torch, Lattice, inputs):
         "max_true_rel_res": max(s["true_rel_res"] for s in st),
         "outer_iters": [s["outer_iters"] for s in st]}
     log(f"config5: {out['config5_uneven_batch']}")
+    return out
+
+
+def momentum_forms(torch, Lattice, inputs, dphi, dsrc):
+    """The paper's own operator route (Sec. 7.2-7.3): the Dirac operator applied
+    exactly in momentum space (exact-sign D_ov, and the paper's Dslash), with and
+    without the free-field preconditioner; at 16^4 with the workload's couplings
+    and at 16^3 x 32 with the m = 1, g = 1/5 of the paper's inversion benchmarks."""
+    out = {}
+
+    def timed(lat, b, p):
+        lat.solve(b, p)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = lat.solve(b, p)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st[0]
+
+    cfg = dict(CFG)
+    for dirac in ("overlap_exact", "dslash"):
+        for prec in ("mixed", "fp64"):
+            for pc in (1, 0):
+                lat = Lattice(DIMS, precision=prec, dirac=dirac, precondition=pc, **cfg)
+                e, st = timed(lat, dsrc, dphi)
+                out[f"fft_{dirac}_{prec}_pc{pc}_16x4"] = {
+                    "ms_per_solve": e * 1e3, "solves_per_s": 1 / e,
+                    "outer_iters": st["outer_iters"], "true_rel_res": st["true_rel_res"]}
+                log(f"{dirac} {prec} pc={pc} 16^4: {out[f'fft_{dirac}_{prec}_pc{pc}_16x4']}")
+                del lat
+    dims = (16, 16, 16, 32)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    b, p = torch.from_numpy(src).cuda(), torch.from_numpy(phi).cuda()
+    for prec in ("mixed", "fp64"):
+        for pc in (1, 0):
+            lat = Lattice(dims, precision=prec, dirac="dslash", precondition=pc, m=1.0, g=0.2,
+                          outer_tol=1e-10)
+            e, st = timed(lat, b, p)
+            out[f"fft_dslash_{prec}_pc{pc}_16x3x32_m1_g0.2"] = {
+                "ms_per_solve": e * 1e3, "outer_iters": st["outer_iters"],
+                "true_rel_res": st["true_rel_res"]}
+            log(f"dslash 16^3x32 {prec} pc={pc}: {out[f'fft_dslash_{prec}_pc{pc}_16x3x32_m1_g0.2']}")
+            del lat
     return out
 
 
@@ -233,12 +277,15 @@ def main():
         # P1: plain nested FP64 CG, inner sign at 1e-12, no reliable updates
         # P2: FP64 with reliable updates, inner sign fixed at 1e-8
         # P3: FP64 running the mixed solver's algorithm (relaxed inner sign)
+        # (all preconditioned like the mixed solve; *_unpreconditioned without it)
         for name, kw in (("fp64_p1", dict(inner_tol=1e-12, reliable_delta=0.0, inner_relax=0.0)),
                          ("fp64_p2", dict(inner_tol=1e-8, reliable_delta=0.1, inner_relax=0.0)),
-                         ("fp64_p3", dict(inner_tol=1e-8))):
-            cfg = dict(CFG)
+                         ("fp64_p3", dict(inner_tol=1e-8)),
+                         ("fp64_p3_unpreconditioned", dict(inner_tol=1e-8, precondition=0)),
+                         ("mixed_unpreconditioned", dict(precision="mixed", precondition=0))):
+            cfg = dict(CFG, precision="fp64")
             cfg.update(kw)
-            l64 = Lattice(DIMS, precision="fp64", **cfg)
+            l64 = Lattice(DIMS, **cfg)
             l64.solve(dsrc, dphi)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -249,7 +296,7 @@ def main():
                            "outer_iters": st64[0]["outer_iters"],
                            "inner_iters": st64[0]["inner_iters"],
                            "true_rel_res": st64[0]["true_rel_res"]}
-            if name == "fp64_p1":
+            if name == "fp64_p3_unpreconditioned":
                 fp64_outer = st64[0]["outer_iters"]
             log(f"{name}: {extra[name]}")
             del l64
@@ -266,6 +313,7 @@ def main():
 
     if not args.quick:
         extra.update(other_configs(torch, Lattice, inputs))
+        extra.update(momentum_forms(torch, Lattice, inputs, dphi, dsrc))
 
     cpu = None
     if not args.no_cpu:

@@ -68,6 +68,7 @@ def lib():
         L.orc_residual.restype = C.c_double
         L.orc_threads.restype = C.c_int
         L.orc_m0inv.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int]
+        L.orc_locality.argtypes = [P, C.c_int, P, C.c_int]
         _lib = L
     return _lib
 
@@ -210,6 +211,15 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"orc_m0inv did not converge ({rc})")
         return out.reshape(v.shape)
+
+    def locality(self, spin=0):
+        """f(r), r = 0 .. sum L/2, of the locality probe of Sec. 3.2 for this D."""
+        nr = sum(d // 2 for d in self.dims) + 1
+        f = np.zeros(nr)
+        rc = lib().orc_locality(C.byref(self.p), spin, _ptr(f), nr)
+        if rc != 0:
+            raise RuntimeError(f"orc_locality failed ({rc})")
+        return f
 
     def residual(self, b, x, phi):
         b = self._field(b)

@@ -780,3 +780,36 @@ int orc_m0inv(const orc_params *p, int dag, const cplx *in, cplx *out, double to
   free(t);
   return rc;
 }
+
+/* Locality probe of Sec. 3.2: psi = D eta for a unit point source eta at the
+ * origin in spin component spin (D of form p->dirac; for the paper's probe,
+ * Dslash), and f(r) = max { ||psi(x)|| : ||x||_1 = r } with the taxi-driver
+ * distance ||x||_1 = sum_mu min(x_mu, L_mu - x_mu).  f[0 .. nr-1]; returns 1 if
+ * nr is smaller than the largest distance + 1. */
+int orc_locality(const orc_params *p, int spin, double *f, int nr) {
+  long long V = volume(p), N = 4 * V;
+  int rmax = 0;
+  for (int mu = 0; mu < 4; ++mu) rmax += p->dims[mu] / 2;
+  if (nr < rmax + 1 || spin < 0 || spin > 3) return 1;
+  cplx *eta = vec_new(N), *psi = vec_new(N);
+  eta[spin] = 1.0;
+  long long inner = 0;
+  int rc = orc_apply(p, ORC_OP_DOV, NULL, eta, psi, &inner);
+  for (int r = 0; r < nr; ++r) f[r] = 0.0;
+  for (long long i = 0; i < V; ++i) {
+    long long q = i;
+    int r = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int L = p->dims[mu];
+      const int x = (int)(q % L);
+      q /= L;
+      r += x < L - x ? x : L - x;
+    }
+    double n2 = 0.0;
+    for (int s = 0; s < 4; ++s) n2 += creal(psi[4 * i + s] * conj(psi[4 * i + s]));
+    if (sqrt(n2) > f[r]) f[r] = sqrt(n2);
+  }
+  free(eta);
+  free(psi);
+  return rc;
+}

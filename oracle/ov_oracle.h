@@ -128,6 +128,11 @@ double orc_residual(const orc_params *p, const double complex *phi,
 int orc_m0inv(const orc_params *p, int dag, const double complex *in, double complex *out,
               double tol, int maxit);
 
+/* Locality probe (Sec. 3.2): f(r) = max ||(D eta)(x)|| over ||x||_1 = r for a unit
+ * point source eta at the origin in spin component spin; f has nr >= sum L/2 + 1
+ * entries. */
+int orc_locality(const orc_params *p, int spin, double *f, int nr);
+
 int orc_threads(void);
 
 #endif

@@ -85,6 +85,7 @@ struct MsParams {
   double diag;          // 4 - M0
   double sigma[MAXP];   // shifts b_k
   double coef[MAXP];    // residues a_k
+  int stage;            // 1: stencil input staged in LDS (dynamic, 4 * spb values)
 };
 
 __device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys, int L) {
@@ -253,7 +254,7 @@ __global__ void __launch_bounds__(256) k_hw_lds(const SysDev* __restrict__ sys, 
 // block reduction.
 template <class R>
 __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const MsParams* mp,
-                                           double* lds) {
+                                           double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
   const Geo g = S.g;
   const int np = mp->np;
@@ -291,8 +292,12 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   const bool have = i < i1;
   Nbr<R> nb;
   c2<R> q[4];
+  if (sh) stage_block<R>(rin, g.V, S.spb, i0, i1, sh);
   if (have) {
-    load_nbr<R>(rin, g, i, nb);
+    if (sh)
+      load_nbr_staged<R>(rin, g, i, sh, S.spb, i0, i1, nb);
+    else
+      load_nbr<R>(rin, g, i, nb);
     if (n > 0) load_sp<R>(tp, g.V, i, q);
   }
   if (!act_sys || done) return;
@@ -350,7 +355,13 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   // remaining sites of this block (sites per thread > 1)
   for (i += blockDim.x; i < i1; i += blockDim.x) {
     c2<R> o[4];
-    hw_site<R>(rin, g, i, (R)mp->diag, o);
+    if (sh) {
+      Nbr<R> nb2;
+      load_nbr_staged<R>(rin, g, i, sh, S.spb, i0, i1, nb2);
+      hw_compute<R>(nb2, g, i, (R)mp->diag, o);
+    } else {
+      hw_site<R>(rin, g, i, (R)mp->diag, o);
+    }
     if (n > 0) {
       load_sp<R>(tp, g.V, i, q);
 #pragma unroll
@@ -365,7 +376,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
 
 template <class R>
 __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const MsParams* mp,
-                                           double* lds) {
+                                           double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
   const Geo g = S.g;
   const int nblk = S.nblk;
@@ -384,8 +395,12 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   const bool have = i < i1;
   Nbr<R> nb;
   c2<R> r[4];
+  if (sh) stage_block<R>(tn, g.V, S.spb, i0, i1, sh);
   if (have) {
-    load_nbr<R>(tn, g, i, nb);
+    if (sh)
+      load_nbr_staged<R>(tn, g, i, sh, S.spb, i0, i1, nb);
+    else
+      load_nbr<R>(tn, g, i, nb);
     load_sp<R>(rin, g.V, i, r);
   }
   if (!act_sys || done) return;
@@ -413,7 +428,13 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   }
   for (i += blockDim.x; i < i1; i += blockDim.x) {
     c2<R> w[4];
-    hw_site<R>(tn, g, i, (R)mp->diag, w);
+    if (sh) {
+      Nbr<R> nb2;
+      load_nbr_staged<R>(tn, g, i, sh, S.spb, i0, i1, nb2);
+      hw_compute<R>(nb2, g, i, (R)mp->diag, w);
+    } else {
+      hw_site<R>(tn, g, i, (R)mp->diag, w);
+    }
     load_sp<R>(rin, g.V, i, r);
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[k] = c2<R>{r[k].x - alpha * w[k].x, r[k].y - alpha * w[k].y};
@@ -437,9 +458,10 @@ __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
   __shared__ double lds[17];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  ms_t_block<R>(S, L - S.blk0, n, &mp_, lds);
+  ms_t_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.stage ? (c2<R>*)dyn_lds : nullptr);
 }
 
 // Iteration n, r pass:
@@ -449,9 +471,10 @@ __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
   __shared__ double lds[17];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  ms_r_block<R>(S, L - S.blk0, n, &mp_, lds);
+  ms_r_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.stage ? (c2<R>*)dyn_lds : nullptr);
 }
 
 // ------------------------------------------------ multi-shift: persistent form
@@ -533,13 +556,13 @@ __global__ void __launch_bounds__(256) k_ms_persistent(const SysDev* __restrict_
   for (int n = 0; n < L; ++n) {
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_t_block<R>(S, Lb - S.blk0, n, &mp_, lds);
+      ms_t_block<R>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_r_block<R>(S, Lb - S.blk0, n, &mp_, lds);
+      ms_r_block<R>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;

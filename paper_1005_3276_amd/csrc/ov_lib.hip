@@ -90,6 +90,16 @@ bool ov_log() {
   return v == 1;
 }
 
+// LDS staging of the multi-shift stencil input (OV_MS_LDS=1 enables it).
+bool ms_lds_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("OV_MS_LDS");
+    v = (e && *e == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -544,14 +554,25 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
     (void)hipGetLastError();
     c->persistent = 0;  // cooperative launch refused: per-pass kernels from now on
   }
+  // stage the stencil input of each workgroup in LDS (x/y neighbours) when the
+  // largest block fits and staging is not disabled (OV_MS_LDS=0)
+  MsParams mps = mp;
+  size_t shb = 0;
+  {
+    int spb = 0;
+    for (const auto& b : E.sb) spb = std::max(spb, b.spb);
+    shb = (size_t)4 * spb * sizeof(c2<R>);
+    mps.stage = (ms_lds_enabled() && shb <= 64 * 1024) ? 1 : 0;
+    if (!mps.stage) shb = 0;
+  }
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, 0, bytes);
-      k_ms_t<R><<<E.nb_total, c->block, 0, E.st>>>(T, E.bmap, E.nb_total, n, mp);
+      k_ms_t<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, mps);
     }
     {
       Sample smp(c, 1, bytes);
-      k_ms_r<R><<<E.nb_total, c->block, 0, E.st>>>(T, E.bmap, E.nb_total, n, mp);
+      k_ms_r<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, mps);
     }
   }
   k_ms_coef<<<E.nsys, 256, 0, E.st>>>(T, E.nsys, L, mp);

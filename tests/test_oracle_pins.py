@@ -484,6 +484,47 @@ def test_solve_momentum_forms_vs_dense_lu(orc, dirac):
     assert rel(x.reshape(-1), ref) < 1e-9
 
 
+# --------------------------------------------------- locality probe (Sec. 3.2)
+
+def _locality_closed_form(dims, dirac, spin=0):
+    X, Y, Z, T = dims
+    D = cf.dov_symbol(cf.exact_sign_symbol(dims))
+    if dirac == 3:
+        D = np.linalg.solve(np.eye(4) - 0.5 * D, D)
+    eta = np.zeros((T, Z, Y, X, 4), complex)
+    eta[0, 0, 0, 0, spin] = 1
+    nrm = np.linalg.norm(cf.apply_symbol(D, eta, dims), axis=-1)
+    t, z, y, x = np.meshgrid(*[np.minimum(np.arange(L), L - np.arange(L)) for L in (T, Z, Y, X)],
+                             indexing="ij")
+    r = t + z + y + x
+    return np.array([nrm[r == k].max() for k in range(r.max() + 1)])
+
+
+@pytest.mark.parametrize("dirac", [2, 3])
+def test_locality_vs_closed_form(orc, dirac):
+    """f(r) of the oracle (plain DFT + taxi-distance loop) against numpy's FFT of
+    the closed-form symbol, for a source in each spin component."""
+    dims = (8, 8, 8, 8)
+    o = orc.Oracle(dims, dirac=dirac)
+    for spin in range(4):
+        f = o.locality(spin)
+        ref = _locality_closed_form(dims, dirac, spin)
+        assert np.abs(f - ref).max() < 1e-13 * ref.max()
+
+
+def test_locality_paper_properties(orc):
+    """What the paper states about the probe of Dslash (Sec. 3.2, Fig. rfig): f(0) = 0;
+    even r lower than the odd r around them; a long tail compared with the overlap
+    operator (exponentially local)."""
+    dims = (8, 8, 8, 8)
+    f = orc.Oracle(dims, dirac=3).locality(0)
+    g = orc.Oracle(dims, dirac=2).locality(0)
+    assert f[0] < 1e-13 * f[1]
+    for r in range(4, len(f) - 1, 2):
+        assert f[r] < f[r - 1] and f[r] < f[r + 1]
+    assert f[-1] / f[1] > 100 * (g[-1] / g[1])
+
+
 # ------------------------------------------------------------------- force
 
 def _S_dense(Dov, phi, xi, m, g):
