@@ -185,6 +185,14 @@ ov_status ov_solve_batch(int n, ov_ctx *const *ctx, void *const *x, const void *
 ov_status ov_force(ov_ctx *ctx, void *grad_phi, double *S_host, const void *xi,
                    const void *phi, int nrhs, ov_stats *st);
 
+/* Locality probe of Sec. 3.2: psi = D eta for a unit point source eta at the origin
+ * in spin component `spin` (0..3), D the context's Dirac form (the paper probes
+ * OV_DIRAC_DSLASH), and f[r] = max ||psi(x)|| (spinor norm) over the sites at
+ * taxi-driver distance r = sum_mu min(x_mu, L_mu - x_mu), for r = 0 .. nr-1.
+ * f is a host array of nr >= sum_mu L_mu/2 + 1 doubles (entries beyond the largest
+ * distance are set to 0).  st: one stats record (may be NULL). */
+ov_status ov_locality(ov_ctx *ctx, int spin, double *f, int nr, ov_stats *st);
+
 /* Single Wilson-stencil pass out = H_W in on fields already in the library's
  * internal layout, for bandwidth measurement: prec 0 = FP64, 1 = FP32; in/out
  * hold nrhs * 4 * V complex values in spin-planar order (see DESIGN notes in

@@ -25,7 +25,7 @@ SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace
            "ov_set_workspace", "ov_get_coeffs", "ov_zolotarev", "ov_sign", "ov_apply",
            "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
            "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling",
-           "ov_kernel_times", "ov_status_string", "ov_last_error"]
+           "ov_kernel_times", "ov_locality", "ov_status_string", "ov_last_error"]
 
 
 class OvParams(C.Structure):
@@ -91,6 +91,7 @@ def lib():
         L.ov_tune_ms.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]
         L.ov_kernel_sampling.argtypes = [P, C.c_int]
         L.ov_kernel_times.argtypes = [P, C.c_int, P, P, P, C.c_int]
+        L.ov_locality.argtypes = [P, C.c_int, P, C.c_int, P]
         L.ov_status_string.argtypes = [C.c_int]
         L.ov_status_string.restype = C.c_char_p
         L.ov_last_error.argtypes = [P]
@@ -98,7 +99,8 @@ def lib():
         for fn in ("ov_ctx_create", "ov_ctx_destroy", "ov_set_workspace", "ov_get_coeffs",
                    "ov_zolotarev", "ov_sign", "ov_apply", "ov_solve", "ov_solve_batch",
                    "ov_force", "ov_stencil_bench", "ov_pack", "ov_unpack", "ov_set_launch",
-                   "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling", "ov_kernel_times"):
+                   "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling", "ov_kernel_times",
+                   "ov_locality"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib

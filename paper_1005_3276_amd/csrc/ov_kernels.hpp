@@ -1222,6 +1222,49 @@ __global__ void __launch_bounds__(256) k_yuk(const SysDev* __restrict__ sys, con
   }
 }
 
+// ------------------------------------------------ locality probe (Sec. 3.2)
+// norm[i] = ||psi_i|| (psi = e_in, FP64 planar) for the sites of one system.
+__global__ void __launch_bounds__(256) k_site_norm(const SysDev* __restrict__ sys,
+                                                    const int* __restrict__ bmap, int nb_total,
+                                                    double* __restrict__ norm) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 v[4];
+    load_sp<double>((const double2*)S.e_in, V, i, v);
+    norm[i] = sqrt(norm2_sp(v));
+  }
+}
+
+// f[r] = max norm[i] over the sites at taxi-driver distance r from the origin,
+// r = sum_mu min(x_mu, L_mu - x_mu).  One workgroup per r.
+__global__ void __launch_bounds__(256) k_shell_max(const Geo g, const double* __restrict__ norm,
+                                                    double* __restrict__ f) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < g.V; i += blockDim.x) {
+    int q = i;
+    const int x = q % g.X; q /= g.X;
+    const int y = q % g.Y; q /= g.Y;
+    const int z = q % g.Z;
+    const int t = q / g.Z;
+    const int d = min(x, g.X - x) + min(y, g.Y - y) + min(z, g.Z - z) + min(t, g.T - t);
+    if (d == r) m = fmax(m, norm[i]);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f[r] = red[0];
+}
+
 // ------------------------------------------------------------ CG kernels
 // Sum part_c into cg_s[slot]; op 0: store, 1: alpha = rr/pap, 2: beta + rr update.
 __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {

@@ -1951,6 +1951,54 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   return OV_OK;
 }
 
+ov_status ov_locality(ov_ctx* c, int spin, double* f, int nr, ov_stats* st) {
+  if (!c || !f || spin < 0 || spin > 3) return OV_ERR_INVALID_ARG;
+  const int* d = c->p.dims;
+  const int rmax = d[0] / 2 + d[1] / 2 + d[2] / 2 + d[3] / 2;
+  if (nr < rmax + 1) {
+    c->err = "ov_locality: nr must be at least sum_mu L_mu/2 + 1";
+    return OV_ERR_INVALID_ARG;
+  }
+  const double t0 = now_s();
+  Engine E;
+  std::vector<ov_ctx*> v(1, c);
+  TRY(engine_init(E, v, false, false, c->p.inner_tol, c->p.inner_tol));
+  TRY(reset_stats(E));
+  TRY(run_apply(E, OV_OP_DOV));  // e_in = x64, result in r64
+  SysBuf& b = E.sb[0];
+  const size_t V = b.V;
+  // unit point source at the origin: x64 = 0, plane `spin` of site 0 = 1
+  HIPCHK(c, hipMemsetAsync(b.x64, 0, V * 4 * sizeof(double2), E.st));
+  static const double2 one = {1.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(b.x64 + (size_t)spin * V, &one, sizeof(double2),
+                           hipMemcpyHostToDevice, E.st));
+  TRY(apply_sequence(E, OV_OP_DOV));
+  // norms of r64 into u64 (as doubles), then one workgroup per distance into basis64
+  SysDev dn = E.htab[T_APPLY];
+  dn.e_in = b.r64;
+  E.htab[T_APPLY2] = dn;
+  TRY(upload_tables(E));
+  double* norm = (double*)b.u64;
+  double* fd = (double*)b.basis64;
+  k_site_norm<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY2), E.bmap, E.nb_total, norm);
+  k_shell_max<<<rmax + 1, 256, 0, E.st>>>(dn.g, norm, fd);
+  TRY(check_launch(c));
+  std::vector<double> h(rmax + 1);
+  HIPCHK(c, hipMemcpyAsync(h.data(), fd, sizeof(double) * h.size(), hipMemcpyDeviceToHost, E.st));
+  TRY(sync(E));
+  for (int r = 0; r < nr; ++r) f[r] = r <= rmax ? h[r] : 0.0;
+  std::vector<int> ctl;
+  std::vector<long long> st0;
+  std::vector<double> ds;
+  TRY(read_ctl(E, ctl, st0, ds));
+  fill_stats(st, 1, &E, nullptr, now_s() - t0, 16);
+  if (ctl[0] & (1 << 2)) {
+    c->err = "multi-shift did not converge within its basis";
+    return OV_ERR_NOT_CONVERGED;
+  }
+  return OV_OK;
+}
+
 ov_status ov_pack(ov_ctx* c, int prec, void* dst, const void* src, int nrhs) {
   if (!c || !dst || !src || nrhs < 1 || (prec != 0 && prec != 1)) return OV_ERR_INVALID_ARG;
   Engine E;

@@ -98,6 +98,17 @@ class Lattice:
     def set_launch(self, block=0, sites_per_thread=0):
         self._check(L.lib().ov_set_launch(self._h, block, sites_per_thread))
 
+    def locality(self, spin=0):
+        """Locality probe of Sec. 3.2 for this lattice's Dirac form: f(r) for
+        r = 0 .. sum L/2 (numpy array) and the stats dict."""
+        import numpy as np
+        nr = sum(d // 2 for d in self.dims) + 1
+        f = np.zeros(nr)
+        st = L.OvStats()
+        self._check(L.lib().ov_locality(self._h, spin, f.ctypes.data_as(C.c_void_p), nr,
+                                        C.byref(st)))
+        return f, st.as_dict()
+
     # --------------------------------------------------------- operations
     def sign(self, x):
         x, nrhs = self._fields(x)

@@ -285,6 +285,44 @@ def test_dslash_solve_full_size_closed_form(dims, m, g, sigma2):
     assert res <= 1e-10
 
 
+# --------------------------------------------------- locality probe (Sec. 3.2)
+
+@pytest.mark.parametrize("dirac", [0, 2, 3])
+def test_locality_vs_oracle(orc, dirac):
+    """f(r) of the point-source probe against the oracle at 8^4 (multi-shift D_ov at
+    inner tolerance 1e-12; the momentum-space forms exactly)."""
+    dims = (8, 8, 8, 8)
+    kw = dict(n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+    lat = lattice(dims, dirac=dirac, inner_tol=1e-12, **kw)
+    o = orc.Oracle(dims, dirac=dirac, inner_tol=1e-13, **kw)
+    for spin in (0, 3):
+        f, _ = lat.locality(spin)
+        ref = o.locality(spin)
+        assert np.abs(f - ref).max() <= 1e-11 * ref.max()
+
+
+def test_locality_dslash_16x4_closed_form():
+    """The paper's probe: Dslash on 16^4 (Fig. rfig) against numpy's FFT of the
+    closed form, and the properties the paper states."""
+    import closed_form as cf
+    dims = (16, 16, 16, 16)
+    lat = lattice(dims, dirac=3)
+    f, _ = lat.locality(0)
+    D = cf.dov_symbol(cf.exact_sign_symbol(dims))
+    D = np.linalg.solve(np.eye(4) - 0.5 * D, D)
+    eta = np.zeros((16, 16, 16, 16, 4), complex)
+    eta[0, 0, 0, 0, 0] = 1
+    nrm = np.linalg.norm(cf.apply_symbol(D, eta, dims), axis=-1)
+    ax = np.minimum(np.arange(16), 16 - np.arange(16))
+    t, z, y, x = np.meshgrid(ax, ax, ax, ax, indexing="ij")
+    r = t + z + y + x
+    ref = np.array([nrm[r == k].max() for k in range(33)])
+    assert np.abs(f - ref).max() <= 1e-12 * ref.max()
+    assert f[0] < 1e-13 * f[1]
+    for k in range(4, 32, 2):
+        assert f[k] < f[k - 1] and f[k] < f[k + 1]
+
+
 def test_zero_source_gives_zero():
     dims = (4, 4, 4, 4)
     lat = lattice(dims, **CFG1)
