@@ -69,6 +69,9 @@ def lib():
         L.orc_threads.restype = C.c_int
         L.orc_m0inv.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int]
         L.orc_locality.argtypes = [P, C.c_int, P, C.c_int]
+        L.orc_rational.argtypes = [P, P, C.c_double, C.c_int, P, P, P, P, C.c_double, C.c_int]
+        L.orc_rational_force.argtypes = [P, P, C.c_double, C.c_int, P, P, P, C.c_double,
+                                         C.c_int, P, P]
         _lib = L
     return _lib
 
@@ -211,6 +214,32 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"orc_m0inv did not converge ({rc})")
         return out.reshape(v.shape)
+
+    def rational(self, v, phi, a0, alpha, beta, tol=1e-12, maxit=4000):
+        """a0 v + sum_i alpha_i (MdagM + beta_i)^-1 v, one CG per shift (Sec. 7.3)."""
+        v = self._field(v)
+        ph = self._phi(phi)
+        al = np.ascontiguousarray(alpha, np.float64)
+        be = np.ascontiguousarray(beta, np.float64)
+        out = np.empty_like(v)
+        rc = lib().orc_rational(C.byref(self.p), _ptr(ph), a0, len(al), _ptr(al), _ptr(be),
+                                _ptr(v), _ptr(out), tol, maxit)
+        if rc != 0:
+            raise RuntimeError(f"orc_rational did not converge ({rc})")
+        return out.reshape(v.shape)
+
+    def rational_force(self, phi, xi, a0, alpha, beta, tol=1e-12, maxit=4000):
+        xi = self._field(xi)
+        ph = self._phi(phi)
+        al = np.ascontiguousarray(alpha, np.float64)
+        be = np.ascontiguousarray(beta, np.float64)
+        G = np.empty(self.V, np.complex128)
+        S = C.c_double(0.0)
+        rc = lib().orc_rational_force(C.byref(self.p), _ptr(ph), a0, len(al), _ptr(al),
+                                      _ptr(be), _ptr(xi), tol, maxit, C.byref(S), _ptr(G))
+        if rc != 0:
+            raise RuntimeError(f"orc_rational_force did not converge ({rc})")
+        return S.value, G.reshape(self.shape[:4])
 
     def locality(self, spin=0):
         """f(r), r = 0 .. sum L/2, of the locality probe of Sec. 3.2 for this D."""

@@ -673,8 +673,9 @@ double orc_residual(const orc_params *p, const cplx *phi, const cplx *b, const c
 /* CG on MdagM x = b (Sec. 7.3 states the problem), x0 = 0.  The true residual is
  * recomputed every 25 iterations and whenever the recursive one meets tol; the
  * iteration ends only on the true residual, restarting from it if needed. */
-int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, double tol,
-              int maxit, orc_cg_stats *st) {
+/* CG on (MdagM + shift) x = b from x = 0, stopping on the true relative residual. */
+static int cg_mdagm(const orc_params *p, const cplx *phi, double shift, const cplx *b, cplx *x,
+                    double tol, int maxit, orc_cg_stats *st) {
   long long N = 4 * volume(p);
   long long inner = 0;
   memset(x, 0, (size_t)N * sizeof(cplx));
@@ -689,6 +690,7 @@ int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, doub
   double true_res = 1.0;
   while (it < maxit) {
     orc_apply(p, ORC_OP_MDAGM, phi, pv, q, &inner);
+    vec_axpy(N, shift, pv, q);
     double pq = creal(vec_dot(N, pv, q));
     double alpha = rr / pq;
     vec_axpy(N, alpha, pv, x);
@@ -697,6 +699,7 @@ int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, doub
     ++it;
     if (sqrt(rr_new) <= tol * bn || it % 25 == 0) {
       orc_apply(p, ORC_OP_MDAGM, phi, x, rt, &inner);
+      vec_axpy(N, shift, x, rt);
       for (long long i = 0; i < N; ++i) rt[i] = b[i] - rt[i];
       double rtn = vec_norm2(N, rt);
       true_res = sqrt(rtn) / bn;
@@ -712,7 +715,12 @@ int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, doub
     vec_xpay(N, r, beta, pv);
     rr = rr_new;
   }
-  if (!conv) true_res = orc_residual(p, phi, b, x);
+  if (!conv) {
+    orc_apply(p, ORC_OP_MDAGM, phi, x, rt, &inner);
+    vec_axpy(N, shift, x, rt);
+    for (long long i = 0; i < N; ++i) rt[i] = b[i] - rt[i];
+    true_res = sqrt(vec_norm2(N, rt)) / bn;
+  }
   if (st) {
     st->iters = it;
     st->converged = conv;
@@ -723,18 +731,18 @@ int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, doub
   return conv ? 0 : 2;
 }
 
+int orc_solve(const orc_params *p, const cplx *phi, const cplx *b, cplx *x, double tol,
+              int maxit, orc_cg_stats *st) {
+  return cg_mdagm(p, phi, 0.0, b, x, tol, maxit, st);
+}
+
 /* HMC force of S = xi^dag (MdagM)^-1 xi.  With X = (MdagM)^-1 xi and Y = M X,
  * dS = -2 Re[ Y^dag dM X ] and dM = g P+ dphi + g* P- dphi*, so
  *   dS/dphi_x = -g [ Y_x^dag P+ X_x + X_x^dag P- Y_x ],
  *   G_x = dS/dRe phi_x + i dS/dIm phi_x = 2 conj(dS/dphi_x)   (S real). */
-int orc_force(const orc_params *p, const cplx *phi, const cplx *xi, double tol, int maxit,
-              double *S, cplx *G, orc_cg_stats *st) {
-  long long V = volume(p), N = 4 * V;
-  cplx *X = vec_new(N), *Y = vec_new(N);
-  int rc = orc_solve(p, phi, xi, X, tol, maxit, st);
-  long long inner = 0;
-  orc_apply(p, ORC_OP_M, phi, X, Y, &inner);
-  if (st) st->inner_iters += inner;
+/* G_x += w * 2 conj(dS/dphi_x) for dS/dphi_x = -g [ Y_x^dag P+ X_x + X_x^dag P- Y_x ]. */
+static void force_density(const orc_params *p, const cplx *X, const cplx *Y, double w, cplx *G) {
+  long long V = volume(p);
   cplx g5[4][4];
   build_gamma(4, g5);
   cplx g = p->g_re + _Complex_I * p->g_im;
@@ -750,9 +758,68 @@ int orc_force(const orc_params *p, const cplx *phi, const cplx *xi, double tol, 
         t2 += conj(X[4 * x + s]) * pm * Y[4 * x + t];
       }
     cplx dS = -g * (t1 + t2);
-    G[x] = 2.0 * conj(dS);
+    G[x] += w * 2.0 * conj(dS);
   }
+}
+
+/* HMC force of S = xi^dag (MdagM)^-1 xi.  With X = (MdagM)^-1 xi and Y = M X,
+ * dS = -2 Re[ Y^dag dM X ] and dM = g P+ dphi + g* P- dphi*, so
+ *   dS/dphi_x = -g [ Y_x^dag P+ X_x + X_x^dag P- Y_x ],
+ *   G_x = dS/dRe phi_x + i dS/dIm phi_x = 2 conj(dS/dphi_x)   (S real). */
+int orc_force(const orc_params *p, const cplx *phi, const cplx *xi, double tol, int maxit,
+              double *S, cplx *G, orc_cg_stats *st) {
+  long long V = volume(p), N = 4 * V;
+  cplx *X = vec_new(N), *Y = vec_new(N);
+  int rc = orc_solve(p, phi, xi, X, tol, maxit, st);
+  long long inner = 0;
+  orc_apply(p, ORC_OP_M, phi, X, Y, &inner);
+  if (st) st->inner_iters += inner;
+  memset(G, 0, (size_t)V * sizeof(cplx));
+  force_density(p, X, Y, 1.0, G);
   *S = creal(vec_dot(N, xi, X));
+  free(X);
+  free(Y);
+  return rc;
+}
+
+/* Rational functions of MdagM for RHMC (Sec. 7.3, pseudofermion heatbath and
+ * action): out = a0 in + sum_i alpha_i (MdagM + beta_i)^-1 in, each shifted
+ * system solved by its own CG as the paper does. */
+int orc_rational(const orc_params *p, const cplx *phi, double a0, int n, const double *alpha,
+                 const double *beta, const cplx *in, cplx *out, double tol, int maxit) {
+  long long N = 4 * volume(p);
+  cplx *X = vec_new(N);
+  int rc = 0;
+  for (long long i = 0; i < N; ++i) out[i] = a0 * in[i];
+  for (int k = 0; k < n; ++k) {
+    int r = cg_mdagm(p, phi, beta[k], in, X, tol, maxit, NULL);
+    if (r) rc = r;
+    vec_axpy(N, alpha[k], X, out);
+  }
+  free(X);
+  return rc;
+}
+
+/* Force of S = Re xi^dag R(MdagM) xi, R(x) = a0 + sum_i alpha_i / (x + beta_i):
+ * with X_i = (MdagM + beta_i)^-1 xi, Y_i = M X_i, dS = -sum_i alpha_i 2 Re[Y_i^dag dM X_i],
+ * so G = sum_i alpha_i G(X_i, Y_i) with the density of orc_force. */
+int orc_rational_force(const orc_params *p, const cplx *phi, double a0, int n,
+                       const double *alpha, const double *beta, const cplx *xi, double tol,
+                       int maxit, double *S, cplx *G) {
+  long long V = volume(p), N = 4 * V;
+  cplx *X = vec_new(N), *Y = vec_new(N);
+  long long inner = 0;
+  int rc = 0;
+  memset(G, 0, (size_t)V * sizeof(cplx));
+  double s = a0 * vec_norm2(N, xi);
+  for (int k = 0; k < n; ++k) {
+    int r = cg_mdagm(p, phi, beta[k], xi, X, tol, maxit, NULL);
+    if (r) rc = r;
+    orc_apply(p, ORC_OP_M, phi, X, Y, &inner);
+    force_density(p, X, Y, alpha[k], G);
+    s += alpha[k] * creal(vec_dot(N, xi, X));
+  }
+  *S = s;
   free(X);
   free(Y);
   return rc;

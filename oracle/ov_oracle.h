@@ -119,6 +119,18 @@ int orc_solve(const orc_params *p, const double complex *phi, const double compl
 int orc_force(const orc_params *p, const double complex *phi, const double complex *xi,
               double tol, int maxit, double *S, double complex *G, orc_cg_stats *st);
 
+/* RHMC rational layers (Sec. 7.3): out = a0 in + sum_i alpha_i (MdagM + beta_i)^-1 in,
+ * one CG per shifted system (true relative residual <= tol each). */
+int orc_rational(const orc_params *p, const double complex *phi, double a0, int n,
+                 const double *alpha, const double *beta, const double complex *in,
+                 double complex *out, double tol, int maxit);
+
+/* S = Re xi^dag R(MdagM) xi and G_x = dS/dRe phi_x + i dS/dIm phi_x for
+ * R(x) = a0 + sum_i alpha_i / (x + beta_i). */
+int orc_rational_force(const orc_params *p, const double complex *phi, double a0, int n,
+                       const double *alpha, const double *beta, const double complex *xi,
+                       double tol, int maxit, double *S, double complex *G);
+
 /* true relative residual ||b - MdagM x|| / ||b|| */
 double orc_residual(const orc_params *p, const double complex *phi,
                     const double complex *b, const double complex *x);
