@@ -185,6 +185,28 @@ ov_status ov_solve_batch(int n, ov_ctx *const *ctx, void *const *x, const void *
 ov_status ov_force(ov_ctx *ctx, void *grad_phi, double *S_host, const void *xi,
                    const void *phi, int nrhs, ov_stats *st);
 
+/* Rational functions of MdagM for the RHMC layers of Sec. 7.3 (pseudofermion heatbath
+ * (MdagM)^{1/8} R and action (MdagM)^{-1/4}, each as a0 + sum_i alpha_i / (x + beta_i)):
+ *   out_r = a0 in_r + sum_i alpha_i (MdagM + beta_i)^-1 in_r
+ * for nrhs fields (complex128 layout above; phi as for ov_apply).  alpha, beta: host
+ * arrays of n (1..32) doubles, beta_i >= 0.  One multi-shift CG on MdagM in FP64 serves
+ * every shift (the paper solves one CG per shift); shift i stops when its recursive
+ * residual |zeta_i| ||r|| <= outer_tol ||in||.  No preconditioning (M0 does not
+ * commute with the shifts).  The D of the context's form is used; the multi-shift
+ * form evaluates the sign at inner_tol.  st: nrhs stats (outer_iters = iterations). */
+ov_status ov_rational(ov_ctx *ctx, double a0, int n, const double *alpha, const double *beta,
+                      void *out, const void *in, const void *phi, int nrhs, ov_stats *st);
+
+/* Force of S_r = Re xi_r^dag R(MdagM) xi_r with R as in ov_rational:
+ *   grad_phi = sum_r dS_r/dRe phi + i dS_r/dIm phi  (complex128 [V], device)
+ *   S_host[r] = S_r (host, nrhs doubles)
+ * X_i = (MdagM + beta_i)^-1 xi from one multi-shift CG, Y_i = M X_i recomputed per
+ * shift (sign at truth_tol for the multi-shift form), G = sum_i alpha_i G(X_i, Y_i)
+ * with the density of ov_force. */
+ov_status ov_rational_force(ov_ctx *ctx, double a0, int n, const double *alpha,
+                            const double *beta, void *grad_phi, double *S_host, const void *xi,
+                            const void *phi, int nrhs, ov_stats *st);
+
 /* Locality probe of Sec. 3.2: psi = D eta for a unit point source eta at the origin
  * in spin component `spin` (0..3), D the context's Dirac form (the paper probes
  * OV_DIRAC_DSLASH), and f[r] = max ||psi(x)|| (spinor norm) over the sites at

@@ -25,7 +25,8 @@ SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace
            "ov_set_workspace", "ov_get_coeffs", "ov_zolotarev", "ov_sign", "ov_apply",
            "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
            "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling",
-           "ov_kernel_times", "ov_locality", "ov_status_string", "ov_last_error"]
+           "ov_kernel_times", "ov_locality", "ov_rational", "ov_rational_force",
+           "ov_status_string", "ov_last_error"]
 
 
 class OvParams(C.Structure):
@@ -92,6 +93,8 @@ def lib():
         L.ov_kernel_sampling.argtypes = [P, C.c_int]
         L.ov_kernel_times.argtypes = [P, C.c_int, P, P, P, C.c_int]
         L.ov_locality.argtypes = [P, C.c_int, P, C.c_int, P]
+        L.ov_rational.argtypes = [P, C.c_double, C.c_int, P, P, P, P, P, C.c_int, P]
+        L.ov_rational_force.argtypes = [P, C.c_double, C.c_int, P, P, P, P, P, P, C.c_int, P]
         L.ov_status_string.argtypes = [C.c_int]
         L.ov_status_string.restype = C.c_char_p
         L.ov_last_error.argtypes = [P]
@@ -100,7 +103,7 @@ def lib():
                    "ov_zolotarev", "ov_sign", "ov_apply", "ov_solve", "ov_solve_batch",
                    "ov_force", "ov_stencil_bench", "ov_pack", "ov_unpack", "ov_set_launch",
                    "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling", "ov_kernel_times",
-                   "ov_locality"):
+                   "ov_locality", "ov_rational", "ov_rational_force"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib

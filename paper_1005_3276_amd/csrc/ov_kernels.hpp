@@ -70,6 +70,10 @@ struct SysDev {
   double* cg_s;             // per-system CG scalars (see CG_* below)
   double m_re, m_im;        // fermion mass
   double g_re, g_im;        // Yukawa coupling
+  double2* shx;             // multi-shift CG on MdagM: nshift solutions (FP64 planar)
+  double2* shp;             //   and nshift search directions
+  const double* shc;        //   per-shift coefficients (SHC_* layout)
+  int nshift;
   void* fft_tmp;            // momentum-space scratch field (kernel precision)
   int off_xy, off_z, off_t; // first workgroup of this system in each transform pass
   int xc;                   // x values per workgroup in the t pass (divides X, <= 8)
@@ -1263,6 +1267,103 @@ __global__ void __launch_bounds__(256) k_shell_max(const Geo g, const double* __
     __syncthreads();
   }
   if (threadIdx.x == 0) f[r] = red[0];
+}
+
+// ----------------------------------------- multi-shift CG on MdagM (RHMC layers)
+// (MdagM + beta_i) X_i = b for every shift on the Krylov space of the base CG
+// (beta = 0), with Jegerlehner's zeta recurrences (the rational functions of
+// MdagM of Sec. 7.3).  Per system the coefficient block shc holds, per shift i,
+// (a_i, z_i, b_i, act_i) at 4 i: x_i += a_i p_i; p_i = z_i r + b_i p_i while
+// act_i != 0; the residues alpha_i at SHC_RES + i and a0 at SHC_A0.
+enum { SHC_RES = 4 * MAXP, SHC_A0 = 5 * MAXP, SHC_LEN = 5 * MAXP + 1 };
+
+// mode 0: x_i = 0, p_i = r (cg_r, FP64).  mode 1: the update above.
+__global__ void __launch_bounds__(256) k_shift(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+                                                int nb_total, int mode) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const size_t slot = (size_t)4 * V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  const double* cf = S.shc;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 r[4];
+    load_sp<double>((const double2*)S.cg_r, V, i, r);
+    for (int k = 0; k < S.nshift; ++k) {
+      double2* xk = S.shx + (size_t)k * slot;
+      double2* pk = S.shp + (size_t)k * slot;
+      if (mode == 0) {
+        double2 z[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] = double2{0.0, 0.0};
+        store_sp<double>(xk, V, i, z);
+        store_sp<double>(pk, V, i, r);
+        continue;
+      }
+      if (cf[4 * k + 3] == 0.0) continue;
+      const double a = cf[4 * k], zz = cf[4 * k + 1], bb = cf[4 * k + 2];
+      double2 x[4], pv[4];
+      load_sp<double>(xk, V, i, x);
+      load_sp<double>(pk, V, i, pv);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[q] = double2{x[q].x + a * pv[q].x, x[q].y + a * pv[q].y};
+        pv[q] = double2{zz * r[q].x + bb * pv[q].x, zz * r[q].y + bb * pv[q].y};
+      }
+      store_sp<double>(xk, V, i, x);
+      store_sp<double>(pk, V, i, pv);
+    }
+  }
+}
+
+// e_out = a0 b + sum_i alpha_i x_i (b = cg_b, complex128 AoS; e_out FP64 planar).
+__global__ void __launch_bounds__(256) k_rat_combine(const SysDev* __restrict__ sys,
+                                                      const int* __restrict__ bmap, int nb_total) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const size_t slot = (size_t)4 * V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  const double a0 = S.shc[SHC_A0];
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 o[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 bv = S.cg_b[(size_t)i * 4 + q];
+      o[q] = double2{a0 * bv.x, a0 * bv.y};
+    }
+    for (int k = 0; k < S.nshift; ++k) {
+      const double al = S.shc[SHC_RES + k];
+      double2 x[4];
+      load_sp<double>(S.shx + (size_t)k * slot, V, i, x);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = double2{o[q].x + al * x[q].x, o[q].y + al * x[q].y};
+    }
+    store_sp<double>((double2*)S.e_out, V, i, o);
+  }
+}
+
+// e_out *= f (FP64 planar).
+__global__ void __launch_bounds__(256) k_scale(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+                                                int nb_total, double f) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 v[4];
+    load_sp<double>((const double2*)S.e_out, V, i, v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = double2{f * v[q].x, f * v[q].y};
+    store_sp<double>((double2*)S.e_out, V, i, v);
+  }
 }
 
 // ------------------------------------------------------------ CG kernels

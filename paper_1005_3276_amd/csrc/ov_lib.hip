@@ -150,6 +150,9 @@ struct SysBuf {
   double *coef_term, *coef_c, *coef_d, *cg_s;
   int *act_cg, *act_ru;
   void *vR, *fftR;              // preconditioned solve: M0^-1 p / M^dag u, transform scratch
+  double2 *shx = nullptr, *shp = nullptr;  // multi-shift CG on MdagM: solutions, directions
+  double* shc = nullptr;        //   per-shift coefficients
+  int nshift = 0;
   int xc = 1, off_xy = 0, off_z = 0, off_t = 0;  // momentum-space pass geometry
 };
 
@@ -170,6 +173,7 @@ struct Plan {
   bool solve = false;
   bool pc = false;   // free-field preconditioned solve
   bool fft = false;  // momentum-space Dirac operator (no multi-shift)
+  int nshift = 0;    // shifted systems of a multi-shift CG on MdagM (rational layers)
 };
 
 template <class R>
@@ -208,9 +212,17 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.basisR = s.rR = s.srcR2 = s.uR = s.xR = s.pR = s.rcgR = nullptr;
   }
   s.vR = s.fftR = nullptr;
-  if (pl.solve && (pl.pc || pl.fft)) {
+  if (pl.solve && (pl.pc || pl.fft || pl.nshift > 0)) {
     s.vR = bp.take(pl.mixed ? v32 : v64);
     s.fftR = bp.take(pl.mixed ? v32 : v64);
+  }
+  s.shx = s.shp = nullptr;
+  s.shc = nullptr;
+  s.nshift = (pl.solve && pl.nshift > 0) ? pl.nshift : 0;
+  if (pl.solve && pl.nshift > 0) {
+    s.shx = (double2*)bp.take(v64 * pl.nshift);
+    s.shp = (double2*)bp.take(v64 * pl.nshift);
+    s.shc = (double*)bp.take(sizeof(double) * SHC_LEN);
   }
   s.part_a = (double*)bp.take(sizeof(double) * s.nblk);
   s.part_b = (double*)bp.take(sizeof(double) * s.nblk);
@@ -281,6 +293,7 @@ struct Engine {
   MsParams mp64{}, mpR{};
   int L64 = 0, LR = 0;              // multi-shift launch counts
   int nb_xy = 0, nb_z = 0, nb_t = 0;  // workgroups of the momentum-space passes
+  SysDev* ftab = nullptr;           // device: (system, shift) table of the rational force
 
   size_t layout(void* base, size_t cap, bool dry) {
     Bump bp(base, cap, dry);
@@ -317,6 +330,7 @@ struct Engine {
     nb_z = nz;
     nb_t = nt;
     tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
+    ftab = pl.nshift > 0 ? (SysDev*)bp.take(sizeof(SysDev) * nsys * pl.nshift) : nullptr;
     ptrs = (void**)bp.take(sizeof(void*) * 2 * nsys);
     bmap = (int*)bp.take(sizeof(int) * (size_t)nb_total);
     hbmap.assign(nb_total, 0);
@@ -375,7 +389,7 @@ MsParams make_mp(const ov_ctx* c, double tol, int cap) {
 
 // Build the engine for `ctxs` (one entry per system) and carve the workspace.
 ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, bool mixed,
-                      double tol64, double tolR) {
+                      double tol64, double tolR, int nshift = 0) {
   E.ctxs = ctxs;
   E.nsys = (int)ctxs.size();
   E.sb.assign(E.nsys, SysBuf{});
@@ -386,7 +400,9 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   HIPCHK(E.lead, hipStreamWaitEvent(E.st, E.lead->ev_in, 0));
   E.pl.solve = solve;
   E.pl.mixed = mixed;
-  E.pl.pc = solve && E.lead->p.precondition != 0;
+  E.pl.nshift = solve ? nshift : 0;
+  // the shifted systems of the rational layers are not preconditioned
+  E.pl.pc = solve && nshift == 0 && E.lead->p.precondition != 0;
   E.pl.fft = solve && E.lead->p.dirac != OV_DIRAC_OVERLAP_MS;
   // capacities from the loosest spectral bound over the batch (no multi-shift
   // basis for a momentum-space operator)
@@ -436,6 +452,10 @@ SysDev base_dev(const SysBuf& b) {
   d.m_im = p.m_im;
   d.g_re = p.g_re;
   d.g_im = p.g_im;
+  d.shx = b.shx;
+  d.shp = b.shp;
+  d.shc = b.shc;
+  d.nshift = b.nshift;
   d.xc = b.xc;
   d.off_xy = b.off_xy;
   d.off_z = b.off_z;
@@ -1948,6 +1968,265 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
     S_host[s] = acc;
   }
   fill_stats(st, nrhs, &E, &so, now_s() - t0, c->p.precision == OV_MIXED ? 8 : 16);
+  return OV_OK;
+}
+
+// ------------------------------------------------ rational layers (Sec. 7.3)
+// One multi-shift CG on MdagM (FP64) for (MdagM + beta_i) X_i = b, i < n, for
+// every system of E; the base CG has shift 0.  Leaves X_i in shx and
+// r64 = a0 b + sum_i alpha_i X_i.  Shift i stops once |zeta_i| |r| <= outer_tol |b|.
+static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const double* al,
+                               const double* be, const std::vector<const void*>& bv,
+                               const std::vector<const void*>& phv, std::vector<int>& iters) {
+  const int ns = E.nsys;
+  TRY(build_solve_tables<double>(E, bv, phv));
+  TRY(reset_stats(E));
+  // coefficients: residues and a0 once; per-iteration blocks below
+  std::vector<double> blk((size_t)ns * SHC_LEN, 0.0);
+  auto upload = [&]() -> ov_status {
+    TRY(sync(E));  // the staging vector feeds the copies below
+    for (int s = 0; s < ns; ++s)
+      HIPCHK(c, hipMemcpyAsync(E.sb[s].shc, blk.data() + (size_t)s * SHC_LEN,
+                               sizeof(double) * SHC_LEN, hipMemcpyHostToDevice, E.st));
+    return OV_OK;
+  };
+  for (int s = 0; s < ns; ++s) {
+    double* b = blk.data() + (size_t)s * SHC_LEN;
+    for (int k = 0; k < n; ++k) b[SHC_RES + k] = al[k];
+    b[SHC_A0] = a0;
+  }
+  TRY(upload());
+  std::vector<int> fcg(ns, 1), fru(ns, 0);
+  TRY(set_flags(E, fcg, fru));
+  const int nb = E.nb_total, bl = c->block;
+  k_cg_misc<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 2);  // x = 0
+  k_cg_misc<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);  // r = b, |b|^2
+  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 4);
+  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);
+  k_cg_p<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);     // p = r
+  k_shift<<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 0);             // x_i = 0, p_i = r
+  TRY(read_scalars(E));
+  std::vector<double> bn(ns);
+  // per system and shift: zeta_{n-1}, zeta_n; per system alpha_{n-1}, beta_{n-1}
+  std::vector<double> zo((size_t)ns * n, 1.0), zc((size_t)ns * n, 1.0), aold(ns, 1.0),
+      bold(ns, 0.0);
+  std::vector<char> act((size_t)ns * n, 1);
+  iters.assign(ns, 0);
+  for (int s = 0; s < ns; ++s) {
+    bn[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_BB]);
+    if (!std::isfinite(bn[s])) {
+      c->err = "non-finite right-hand side";
+      return OV_ERR_BREAKDOWN;
+    }
+    if (bn[s] == 0.0) {
+      fcg[s] = 0;
+      for (int k = 0; k < n; ++k) act[(size_t)s * n + k] = 0;
+    }
+  }
+  const double tol = c->p.outer_tol;
+  const MsParams mp = make_mp(c, c->p.inner_tol, E.pl.cap64);
+  int L = 0;
+  for (int s = 0; s < ns; ++s) L = std::max(L, capacity(E.ctxs[s], c->p.inner_tol));
+  L = std::min(E.pl.cap64, L);
+  int Lrun = L;
+  for (int it = 0; it < c->p.max_outer; ++it) {
+    bool any = false;
+    for (int s = 0; s < ns; ++s) any |= fcg[s] != 0;
+    if (!any) break;
+    TRY(set_flags(E, fcg, fru));
+    if (E.pl.fft) {
+      launch_sym<double>(E, T_F_M, SYM_D);
+      k_yuk<double><<<nb, bl, 0, E.st>>>(tab(E, T_F_M), E.bmap, nb, 0);
+      k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_F_M), ns, 1);
+      launch_sym<double>(E, T_F_MD, SYM_D_DAG);
+      k_yuk<double><<<nb, bl, 0, E.st>>>(tab(E, T_F_MD), E.bmap, nb, 1);
+    } else {
+      k_ms_prep<double><<<nb, bl, 0, E.st>>>(tab(E, T_IN_M), E.bmap, nb, 0);
+      launch_ms<double>(E, T_IN_M, mp, Lrun);
+      launch_combine<double>(E, T_IN_M, EPI_M);
+      k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
+      launch_ms<double>(E, T_IN_MDAG, mp, Lrun);
+      launch_combine<double>(E, T_IN_MDAG, EPI_MDAG);
+    }
+    k_cg_misc<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);  // r -= alpha w
+    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);                // rho, beta
+    TRY(read_scalars(E));
+    if (!E.pl.fft) {  // launch what the multi-shift needed, plus a margin
+      const int nobs = last_ms_iters(E);
+      Lrun = (nobs >= Lrun - 1) ? L : std::min(L, nobs + 4);
+    }
+    for (int s = 0; s < ns; ++s) {
+      if (!fcg[s]) continue;
+      iters[s]++;
+      const double* cs = c->pinned + (size_t)s * CG_NSLOT;
+      const double a = cs[CG_ALPHA], bt = cs[CG_BETA], rho = cs[CG_RR];
+      if (!std::isfinite(a) || !std::isfinite(rho) || cs[CG_PAP] <= 0.0) {
+        c->err = "multi-shift CG on MdagM: breakdown (non-finite or non-positive scalar)";
+        return OV_ERR_BREAKDOWN;
+      }
+      double* b = blk.data() + (size_t)s * SHC_LEN;
+      bool live = false;
+      for (int k = 0; k < n; ++k) {
+        const size_t j = (size_t)s * n + k;
+        if (!act[j]) {
+          b[4 * k + 3] = 0.0;
+          continue;
+        }
+        const double zn = zc[j] * zo[j] * aold[s] /
+                          (a * bold[s] * (zo[j] - zc[j]) + zo[j] * aold[s] * (1.0 + be[k] * a));
+        const double ratio = zn / zc[j];
+        b[4 * k] = a * ratio;               // alpha_i
+        b[4 * k + 1] = zn;                  // zeta_i of r_{n+1}
+        b[4 * k + 2] = bt * ratio * ratio;  // beta_i
+        b[4 * k + 3] = 1.0;
+        zo[j] = zc[j];
+        zc[j] = zn;
+        if (std::fabs(zn) * std::sqrt(std::max(rho, 0.0)) <= tol * bn[s]) act[j] = 0;
+        live |= act[j] != 0;
+      }
+      aold[s] = a;
+      bold[s] = bt;
+      if (!live) fcg[s] = 0;
+    }
+    TRY(upload());
+    // the last update of a shift that just converged still applies (act flag set above)
+    std::vector<int> fupd(ns, 0);
+    for (int s = 0; s < ns; ++s) fupd[s] = iters[s] > 0 ? 1 : 0;
+    TRY(set_flags(E, fupd, fru));
+    k_shift<<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);
+    TRY(set_flags(E, fcg, fru));
+    k_cg_p<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);  // p = r + beta p
+  }
+  for (int s = 0; s < ns; ++s)
+    if (fcg[s]) {
+      c->err = "multi-shift CG on MdagM did not converge within max_outer";
+      return OV_ERR_NOT_CONVERGED;
+    }
+  // r64 = a0 b + sum_i alpha_i X_i
+  for (int s = 0; s < ns; ++s) E.htab[(size_t)T_APPLY * ns + s].e_out = E.sb[s].r64;
+  TRY(upload_tables(E));
+  k_rat_combine<<<nb, bl, 0, E.st>>>(tab(E, T_APPLY), E.bmap, nb);
+  return check_launch(c);
+}
+
+ov_status ov_rational(ov_ctx* c, double a0, int n, const double* alpha, const double* beta,
+                      void* out, const void* in, const void* phi, int nrhs, ov_stats* st) {
+  if (!c || !alpha || !beta || !out || !in || !phi || nrhs < 1 || n < 1 || n > MAXP)
+    return OV_ERR_INVALID_ARG;
+  for (int k = 0; k < n; ++k)
+    if (!(beta[k] >= 0.0) || !std::isfinite(alpha[k]) || !std::isfinite(beta[k])) {
+      c->err = "ov_rational: need finite alpha_i and beta_i >= 0";
+      return OV_ERR_INVALID_ARG;
+    }
+  const double t0 = now_s();
+  const size_t vb = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3] * 4 *
+                    sizeof(double2);
+  std::vector<ov_ctx*> sc(nrhs, c);
+  std::vector<const void*> bv(nrhs), ph(nrhs, phi);
+  std::vector<void*> ov(nrhs), r64(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    bv[r] = (const char*)in + r * vb;
+    ov[r] = (char*)out + r * vb;
+  }
+  Engine E;
+  TRY(engine_init(E, sc, true, false, c->p.inner_tol, c->p.inner_tol, n));
+  std::vector<int> iters;
+  TRY(rational_core(c, E, a0, n, alpha, beta, bv, ph, iters));
+  for (int r = 0; r < nrhs; ++r) r64[r] = E.sb[r].r64;
+  TRY(unpack64(E, r64, ov));
+  TRY(sync(E));
+  SolveOut so;
+  so.outer = iters;
+  so.ru.assign(nrhs, 0);
+  so.res.assign(nrhs, 0.0);
+  so.conv.assign(nrhs, 1);
+  fill_stats(st, nrhs, &E, &so, now_s() - t0, 16);
+  return OV_OK;
+}
+
+ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
+                            const double* beta, void* grad_phi, double* S_host, const void* xi,
+                            const void* phi, int nrhs, ov_stats* st) {
+  if (!c || !alpha || !beta || !grad_phi || !S_host || !xi || !phi || nrhs < 1 || n < 1 ||
+      n > MAXP)
+    return OV_ERR_INVALID_ARG;
+  for (int k = 0; k < n; ++k)
+    if (!(beta[k] >= 0.0) || !std::isfinite(alpha[k]) || !std::isfinite(beta[k])) {
+      c->err = "ov_rational_force: need finite alpha_i and beta_i >= 0";
+      return OV_ERR_INVALID_ARG;
+    }
+  const double t0 = now_s();
+  const size_t V = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3];
+  const size_t vb = V * 4 * sizeof(double2);
+  std::vector<ov_ctx*> sc(nrhs, c);
+  std::vector<const void*> bv(nrhs), ph(nrhs, phi);
+  for (int r = 0; r < nrhs; ++r) bv[r] = (const char*)xi + r * vb;
+  Engine E;
+  TRY(engine_init(E, sc, true, false, c->p.inner_tol, c->p.inner_tol, n));
+  std::vector<int> iters;
+  TRY(rational_core(c, E, a0, n, alpha, beta, bv, ph, iters));
+  // S_r = Re xi_r^dag (a0 xi_r + sum_i alpha_i X_i) from the combined field in r64
+  for (int s = 0; s < nrhs; ++s) E.htab[(size_t)T_APPLY * nrhs + s].e_in = E.sb[s].r64;
+  TRY(upload_tables(E));
+  k_dot_re<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total);
+  TRY(sync(E));
+  for (int s = 0; s < nrhs; ++s) {
+    std::vector<double> tmp(E.sb[s].nblk);
+    HIPCHK(c, hipMemcpy(tmp.data(), E.sb[s].part_c, sizeof(double) * tmp.size(),
+                        hipMemcpyDeviceToHost));
+    double acc = 0;
+    for (double v : tmp) acc += v;
+    S_host[s] = acc;
+  }
+  // Y_i = alpha_i M X_i into the (no longer needed) search directions, FP64
+  const MsParams mp = make_mp(c, c->p.truth_tol, E.pl.cap64);
+  const int L = std::min(E.pl.cap64, capacity(c, c->p.truth_tol));
+  const size_t slot = V * 4;
+  std::vector<int> on(nrhs, 1), off(nrhs, 0);
+  TRY(set_flags(E, on, off));
+  for (int k = 0; k < n; ++k) {
+    for (int s = 0; s < nrhs; ++s) {
+      SysDev& d = E.htab[(size_t)T_APPLY * nrhs + s];
+      d.e_in = E.sb[s].shx + (size_t)k * slot;
+      d.src = d.e_in;
+      d.e_out = E.sb[s].shp + (size_t)k * slot;
+      d.e_out2 = nullptr;
+      d.fft_tmp = E.sb[s].src64b;
+      d.basis = E.sb[s].basis64;
+      d.r = E.sb[s].r64ms;
+      d.active = nullptr;
+    }
+    TRY(upload_tables(E));
+    if (E.pl.fft) {
+      launch_sym<double>(E, T_APPLY, SYM_D);
+      k_yuk<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
+    } else {
+      k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
+      launch_ms<double>(E, T_APPLY, mp, L);
+      launch_combine<double>(E, T_APPLY, EPI_M);
+    }
+    k_scale<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, alpha[k]);
+  }
+  // G = sum over (system, shift) of the force density of (X_i, alpha_i M X_i)
+  std::vector<SysDev> ft((size_t)nrhs * n);
+  for (int s = 0; s < nrhs; ++s)
+    for (int k = 0; k < n; ++k) {
+      SysDev d = base_dev(E.sb[s]);
+      d.e_in = E.sb[s].shx + (size_t)k * slot;
+      d.e_out = E.sb[s].shp + (size_t)k * slot;
+      ft[(size_t)s * n + k] = d;
+    }
+  HIPCHK(c, hipMemcpyAsync(E.ftab, ft.data(), sizeof(SysDev) * ft.size(), hipMemcpyHostToDevice,
+                           E.st));
+  k_force<<<E.sb[0].nblk, c->block, 0, E.st>>>(E.ftab, nrhs * n, E.sb[0].nblk,
+                                               (double2*)grad_phi);
+  TRY(sync(E));
+  SolveOut so;
+  so.outer = iters;
+  so.ru.assign(nrhs, 0);
+  so.res.assign(nrhs, 0.0);
+  so.conv.assign(nrhs, 1);
+  fill_stats(st, nrhs, &E, &so, now_s() - t0, 16);
   return OV_OK;
 }
 

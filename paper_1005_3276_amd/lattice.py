@@ -98,6 +98,37 @@ class Lattice:
     def set_launch(self, block=0, sites_per_thread=0):
         self._check(L.lib().ov_set_launch(self._h, block, sites_per_thread))
 
+    def rational(self, x, phi, a0, alphas, betas):
+        """a0 x + sum_i alphas_i (MdagM + betas_i)^-1 x (RHMC layers, Sec. 7.3)."""
+        import numpy as np
+        x, nrhs = self._fields(x)
+        phi = self._phi(phi)
+        al = np.ascontiguousarray(alphas, np.float64)
+        be = np.ascontiguousarray(betas, np.float64)
+        out = torch.empty_like(x)
+        st = (L.OvStats * nrhs)()
+        self._check(L.lib().ov_rational(self._h, float(a0), len(al), al.ctypes.data_as(C.c_void_p),
+                                        be.ctypes.data_as(C.c_void_p), _ptr(out), _ptr(x),
+                                        _ptr(phi), nrhs, st))
+        return out, [s.as_dict() for s in st]
+
+    def rational_force(self, xi, phi, a0, alphas, betas):
+        """(S per rhs, G = dS/dRe phi + i dS/dIm phi summed over rhs, stats) for
+        S = Re xi^dag R(MdagM) xi."""
+        import numpy as np
+        xi, nrhs = self._fields(xi)
+        phi = self._phi(phi)
+        al = np.ascontiguousarray(alphas, np.float64)
+        be = np.ascontiguousarray(betas, np.float64)
+        G = torch.empty(self.phi_shape, dtype=torch.complex128, device=xi.device)
+        S = (C.c_double * nrhs)()
+        st = (L.OvStats * nrhs)()
+        self._check(L.lib().ov_rational_force(self._h, float(a0), len(al),
+                                              al.ctypes.data_as(C.c_void_p),
+                                              be.ctypes.data_as(C.c_void_p), _ptr(G), S,
+                                              _ptr(xi), _ptr(phi), nrhs, st))
+        return list(S), G, [s.as_dict() for s in st]
+
     def locality(self, spin=0):
         """Locality probe of Sec. 3.2 for this lattice's Dirac form: f(r) for
         r = 0 .. sum L/2 (numpy array) and the stats dict."""

@@ -18,6 +18,8 @@ least-squares solution towards the minimax one.  For 0 < alpha < 1 the fit is
 done for x^(alpha - 1) without constant and multiplied by x:
 x sum c_i/(x + p_i) = sum c_i - sum c_i p_i/(x + p_i).
 """
+import functools
+
 import numpy as np
 
 
@@ -56,14 +58,22 @@ def _fit(expo, lo, hi, shifts0, const, samples, rounds, lawson):
     return best
 
 
-def power_approx(alpha, lo, hi, n=20, samples=3000, rounds=3, lawson=20):
+def power_approx(alpha, lo, hi, n=20, samples=1500, rounds=2, lawson=20):
     """Coefficients (a0, alphas, betas, max_rel_err) of x^alpha on [lo, hi].
 
     -1 < alpha < 1, alpha != 0; 0 < lo < hi.  max_rel_err is the largest
-    |r(x)/x^alpha - 1| on a log-spaced sample of the interval.
+    |r(x)/x^alpha - 1| on a log-spaced sample of the interval.  Results are
+    cached per argument set.
     """
     if not (-1.0 < alpha < 1.0) or alpha == 0.0 or not (0.0 < lo < hi):
         raise ValueError("need -1 < alpha < 1, alpha != 0 and 0 < lo < hi")
+    a0, al, be, err = _power_approx(float(alpha), float(lo), float(hi), int(n), int(samples),
+                                    int(rounds), int(lawson))
+    return a0, al.copy(), be.copy(), err
+
+
+@functools.lru_cache(maxsize=32)
+def _power_approx(alpha, lo, hi, n, samples, rounds, lawson):
     from . import _lib
 
     _, z_shifts, _ = _lib.zolotarev(n, np.sqrt(lo), np.sqrt(hi))

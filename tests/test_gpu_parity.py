@@ -614,3 +614,71 @@ def test_autotune_choices_agree(tmp_path, monkeypatch):
             ref = out
         else:
             assert rel(out, ref) < 1e-12
+
+
+# ------------------------------------------------- RHMC rational layers (Sec. 7.3)
+
+RAT_LO, RAT_HI = 1e-5, 10.0
+
+
+@pytest.fixture(scope="module")
+def rat_coeffs():
+    from paper_1005_3276_amd import rational
+    return {a: rational.power_approx(a, RAT_LO, RAT_HI, 20) for a in (-0.25, 0.125)}
+
+
+@pytest.mark.parametrize("dirac", [0, 2])
+def test_rational_vs_oracle(orc, rat_coeffs, dirac):
+    """a0 x + sum alpha_i (MdagM + beta_i)^-1 x: one multi-shift CG (GPU) against one
+    CG per shift (oracle), both to 1e-11 in each shifted system, at 4^4."""
+    dims = (4, 4, 4, 4)
+    print(f"[rational] dirac={dirac}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=71)
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0, dirac=dirac)
+    lat = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, **kw)
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    a0, al, be, _ = rat_coeffs[-0.25]
+    out, st = lat.rational(dev(src), dev(phi), a0, al, be)
+    out = host(out)
+    for r in range(2):
+        ref = o.rational(src[r], phi, a0, al, be, tol=1e-11)
+        assert rel(out[r], ref) < 1e-9
+    print(f"[rational] {st[0]}", flush=True)
+
+
+@pytest.mark.parametrize("dirac", [0, 3])
+def test_rational_force_vs_oracle(orc, rat_coeffs, dirac):
+    dims = (4, 4, 4, 4)
+    print(f"[rational-force] dirac={dirac}", flush=True)
+    phi, xi = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=72)
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0, dirac=dirac)
+    lat = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, truth_tol=1e-13, **kw)
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    a0, al, be, _ = rat_coeffs[-0.25]
+    S, G, _ = lat.rational_force(dev(xi), dev(phi), a0, al, be)
+    G = host(G)
+    Gref = np.zeros_like(G)
+    for r in range(2):
+        So, Go = o.rational_force(phi, xi[r], a0, al, be, tol=1e-11)
+        assert abs(S[r] - So) <= 1e-9 * abs(So)
+        Gref += Go
+    assert np.abs(G - Gref).max() <= 1e-8 * np.abs(Gref).max()
+
+
+@pytest.mark.parametrize("dirac", [2, 0])
+def test_heatbath_identity_16x4(rat_coeffs, dirac):
+    """At full size (16^4, config-2 couplings): eta = (MdagM)^{1/8} R and
+    eta^dag (MdagM)^{-1/4} eta = R^dag R (Sec. 7.3), to the approximation error."""
+    dims = (16, 16, 16, 16)
+    print(f"[heatbath] dirac={dirac}", flush=True)
+    phi, R = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    lat = lattice(dims, dirac=dirac, inner_tol=1e-12, outer_tol=1e-11, **CFG2)
+    t = time.time()
+    eta, st1 = lat.rational(dev(R), dev(phi), *rat_coeffs[0.125][:3])
+    w, st2 = lat.rational(eta, dev(phi), *rat_coeffs[-0.25][:3])
+    torch.cuda.synchronize()
+    lhs = torch.vdot(eta.reshape(-1), w.reshape(-1)).real.item()
+    rhs = float(np.vdot(R.reshape(-1), R.reshape(-1)).real)
+    print(f"[heatbath] {time.time() - t:.2f}s {st1[0]['outer_iters']} + {st2[0]['outer_iters']} "
+          f"iterations, rel dev {abs(lhs - rhs) / rhs:.2e}", flush=True)
+    assert abs(lhs - rhs) < 1e-8 * rhs
