@@ -191,6 +191,38 @@ def momentum_forms(torch, Lattice, inputs, dphi, dsrc):
                 "true_rel_res": st["true_rel_res"]}
             log(f"dslash 16^3x32 {prec} pc={pc}: {out[f'fft_dslash_{prec}_pc{pc}_16x3x32_m1_g0.2']}")
             del lat
+    # RHMC rational layers (Sec. 7.3): heatbath (MdagM)^{1/8} R then the action's
+    # (MdagM)^{-1/4}, degree 20 on [1e-5, 10], with the multi-shift D_ov of the workload
+    from paper_1005_3276_amd import rational
+    c18 = rational.power_approx(0.125, 1e-5, 10.0, 20)
+    c14 = rational.power_approx(-0.25, 1e-5, 10.0, 20)
+    for dirac in ("overlap_exact", "overlap"):
+        lat = Lattice(DIMS, dirac=dirac, inner_tol=1e-12, outer_tol=1e-10,
+                      **{k: v for k, v in CFG.items() if k not in ("outer_tol", "inner_tol")})
+        lat.rational(dsrc, dphi, *c18[:3])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        eta, st1 = lat.rational(dsrc, dphi, *c18[:3])
+        w, st2 = lat.rational(eta, dphi, *c14[:3])
+        torch.cuda.synchronize()
+        e = time.perf_counter() - t
+        lhs = torch.vdot(eta.reshape(-1), w.reshape(-1)).real.item()
+        rhs = torch.vdot(dsrc.reshape(-1), dsrc.reshape(-1)).real.item()
+        out[f"rhmc_heatbath_action_{dirac}_16x4"] = {
+            "seconds": e, "iterations": [st1[0]["outer_iters"], st2[0]["outer_iters"]],
+            "identity_rel_dev": abs(lhs - rhs) / rhs,
+            "fit_rel_err": [c18[3], c14[3]]}
+        log(f"rhmc {dirac}: {out[f'rhmc_heatbath_action_{dirac}_16x4']}")
+        del lat
+    # locality probe of Dslash on 16^4 (Sec. 3.2, Fig. rfig)
+    lat = Lattice(DIMS, dirac="dslash")
+    lat.locality(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    f, _ = lat.locality(0)
+    e = time.perf_counter() - t
+    out["locality_dslash_16x4"] = {"seconds": e, "f": [float(v) for v in f]}
+    log(f"locality: {e * 1e3:.2f} ms")
     return out
 
 

@@ -70,6 +70,10 @@ def lib():
         L.orc_m0inv.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int]
         L.orc_locality.argtypes = [P, C.c_int, P, C.c_int]
         L.orc_rational.argtypes = [P, P, C.c_double, C.c_int, P, P, P, P, C.c_double, C.c_int]
+        L.orc_boson.argtypes = [P, P, P, P, P]
+        L.orc_rhmc_trajectory.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_double, C.c_int,
+                                          P, P, C.c_double, C.c_int, P, P, C.c_double,
+                                          C.c_double, C.c_int, P, P]
         L.orc_rational_force.argtypes = [P, P, C.c_double, C.c_int, P, P, P, C.c_double,
                                          C.c_int, P, P]
         _lib = L
@@ -240,6 +244,32 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"orc_rational_force did not converge ({rc})")
         return S.value, G.reshape(self.shape[:4])
+
+    def boson(self, phi):
+        """(S_B, G_B, F) of the bosonic action of eq. acws (Sec. 7.3)."""
+        ph = np.ascontiguousarray(phi, np.complex128).reshape(-1)
+        G = np.empty(self.V, np.complex128)
+        F = np.empty(self.V, np.complex128)
+        S = C.c_double(0.0)
+        lib().orc_boson(C.byref(self.p), _ptr(ph), C.byref(S), _ptr(G), _ptr(F))
+        return S.value, G.reshape(self.shape[:4]), F.reshape(self.shape[:4])
+
+    def rhmc_trajectory(self, phi, pi, R, nsteps, tau, c18, c14, u, tol=1e-12, maxit=4000):
+        """One RHMC trajectory; returns (phi_end_or_start, dH, accepted)."""
+        ph = np.ascontiguousarray(phi, np.complex128).reshape(-1).copy()
+        pi = np.ascontiguousarray(pi, np.complex128).reshape(-1)
+        R = self._field(R)
+        a18, al18, be18 = c18[0], np.ascontiguousarray(c18[1], np.float64), np.ascontiguousarray(c18[2], np.float64)
+        a14, al14, be14 = c14[0], np.ascontiguousarray(c14[1], np.float64), np.ascontiguousarray(c14[2], np.float64)
+        dH = C.c_double(0.0)
+        acc = C.c_int(0)
+        rc = lib().orc_rhmc_trajectory(C.byref(self.p), _ptr(ph), _ptr(pi), _ptr(R), nsteps, tau,
+                                       a18, len(al18), _ptr(al18), _ptr(be18), a14, len(al14),
+                                       _ptr(al14), _ptr(be14), u, tol, maxit, C.byref(dH),
+                                       C.byref(acc))
+        if rc != 0:
+            raise RuntimeError(f"orc_rhmc_trajectory: a solve did not converge ({rc})")
+        return ph.reshape(self.shape[:4]), dH.value, bool(acc.value)
 
     def locality(self, spin=0):
         """f(r), r = 0 .. sum L/2, of the locality probe of Sec. 3.2 for this D."""

@@ -880,3 +880,126 @@ int orc_locality(const orc_params *p, int spin, double *f, int nr) {
   free(psi);
   return rc;
 }
+
+/* ------------------------------------------------ RHMC (Sec. 7.3, eq. acws)
+ * Bosonic part of the action (a = 1), for a periodic complex scalar phi:
+ *   S_B = sum_x [ 2 conj(phi) (D_2 phi) + conj(W') ((1 - D_2/2) W') ],
+ * D_2 the scalar part of the exact-sign overlap operator (D(p) = D_2(p) + gamma
+ * part; D_2(p) = 1 + w(p)/s(p), so D^dag D = 2 D_2), W' = m phi + lam phi^2 with
+ * lam = g/2: the Yukawa coefficient g of M is the paper's 2g (eq. fmat), so that
+ * M's Yukawa term is W''(phi) = m + g phi.
+ *   G = dS/dRe phi + i dS/dIm phi = 2 [ 2 D_2 phi + conj(W''(phi)) (1 - D_2/2) W' ],
+ *   F = -(1 - D_2/2) conj(W')   (the auxiliary field at the stationary point of
+ *                                eq. lata).                                      */
+static void scalar_d2_apply(const orc_params *p, int which, const cplx *in, cplx *out) {
+  /* which 0: D_2, 1: 1 - D_2/2 ; periodic momenta in every direction */
+  const int L[4] = {p->dims[0], p->dims[1], p->dims[2], p->dims[3]};
+  const long long V = volume(p);
+  cplx *hat = vec_new(V);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long kk = 0; kk < V; ++kk) {
+    long long r = kk;
+    int k[4];
+    for (int mu = 0; mu < 4; ++mu) { k[mu] = (int)(r % L[mu]); r /= L[mu]; }
+    cplx acc = 0;
+    for (long long i = 0; i < V; ++i) {
+      long long q = i;
+      double ph = 0.0;
+      for (int mu = 0; mu < 4; ++mu) {
+        const int x = (int)(q % L[mu]);
+        q /= L[mu];
+        ph += 2.0 * M_PI * (double)k[mu] * x / L[mu];
+      }
+      acc += cexp(-_Complex_I * ph) * in[i];
+    }
+    double w = 4.0 - p->M0, s2 = 0.0;
+    for (int mu = 0; mu < 4; ++mu) {
+      const double pm = 2.0 * M_PI * k[mu] / L[mu];
+      w -= cos(pm);
+      s2 += sin(pm) * sin(pm);
+    }
+    s2 += w * w;
+    const double d2 = 1.0 + w / sqrt(s2);
+    hat[kk] = acc * (which == 0 ? d2 : 1.0 - 0.5 * d2);
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long i = 0; i < V; ++i) {
+    long long q = i;
+    int x[4];
+    for (int mu = 0; mu < 4; ++mu) { x[mu] = (int)(q % L[mu]); q /= L[mu]; }
+    cplx acc = 0;
+    for (long long kk = 0; kk < V; ++kk) {
+      long long r = kk;
+      double ph = 0.0;
+      for (int mu = 0; mu < 4; ++mu) {
+        const int k = (int)(r % L[mu]);
+        r /= L[mu];
+        ph += 2.0 * M_PI * (double)k * x[mu] / L[mu];
+      }
+      acc += cexp(_Complex_I * ph) * hat[kk];
+    }
+    out[i] = acc / (double)V;
+  }
+  free(hat);
+}
+
+int orc_boson(const orc_params *p, const cplx *phi, double *S, cplx *G, cplx *F) {
+  const long long V = volume(p);
+  const cplx m = p->m_re + _Complex_I * p->m_im;
+  const cplx g = p->g_re + _Complex_I * p->g_im;
+  const cplx lam = 0.5 * g;
+  cplx *W1 = vec_new(V), *D2phi = vec_new(V), *KW = vec_new(V), *cW = vec_new(V);
+  for (long long x = 0; x < V; ++x) W1[x] = m * phi[x] + lam * phi[x] * phi[x];
+  scalar_d2_apply(p, 0, phi, D2phi);
+  scalar_d2_apply(p, 1, W1, KW);
+  double s = 0.0;
+  for (long long x = 0; x < V; ++x) {
+    s += creal(2.0 * conj(phi[x]) * D2phi[x] + conj(W1[x]) * KW[x]);
+    if (G) G[x] = 2.0 * (2.0 * D2phi[x] + conj(m + g * phi[x]) * KW[x]);
+    cW[x] = conj(W1[x]);
+  }
+  if (S) *S = s;
+  if (F) {
+    scalar_d2_apply(p, 1, cW, F);
+    for (long long x = 0; x < V; ++x) F[x] = -F[x];
+  }
+  free(W1); free(D2phi); free(KW); free(cW);
+  return 0;
+}
+
+/* One RHMC trajectory (Sec. 7.3): pseudofermion heatbath eta = r18(MdagM) R, then
+ * leapfrog molecular dynamics of length tau in nsteps steps for
+ *   H = 1/2 sum |pi_x|^2 + S_B(phi) + S_PF(phi),  S_PF = Re eta^dag r14(MdagM) eta,
+ * (r18 ~ x^{1/8}, r14 ~ x^{-1/4}: a0 + sum alpha_i/(x + beta_i)), with
+ * dphi/dt = pi and dpi/dt = -G; accepted when u < exp(-dH).  phi is updated in
+ * place when accepted.  Momenta pi, the Gaussian R and u are inputs. */
+int orc_rhmc_trajectory(const orc_params *p, cplx *phi, const cplx *pi0, const cplx *R,
+                        int nsteps, double tau, double a18, int n18, const double *al18,
+                        const double *be18, double a14, int n14, const double *al14,
+                        const double *be14, double u, double tol, int maxit, double *dH,
+                        int *accepted) {
+  const long long V = volume(p), N = 4 * V;
+  cplx *eta = vec_new(N), *ph = vec_new(V), *pi = vec_new(V), *G = vec_new(V), *Gf = vec_new(V);
+  int rc = orc_rational(p, phi, a18, n18, al18, be18, R, eta, tol, maxit);
+  memcpy(ph, phi, (size_t)V * sizeof(cplx));
+  memcpy(pi, pi0, (size_t)V * sizeof(cplx));
+  const double eps = tau / nsteps;
+  double Sb, Sf, H0, H1;
+  /* force at the start, and H0 */
+  orc_boson(p, ph, &Sb, G, NULL);
+  rc |= orc_rational_force(p, ph, a14, n14, al14, be14, eta, tol, maxit, &Sf, Gf);
+  H0 = 0.5 * vec_norm2(V, pi) + Sb + Sf;
+  for (int k = 0; k < nsteps; ++k) {
+    for (long long x = 0; x < V; ++x) pi[x] -= 0.5 * eps * (G[x] + Gf[x]);
+    for (long long x = 0; x < V; ++x) ph[x] += eps * pi[x];
+    orc_boson(p, ph, &Sb, G, NULL);
+    rc |= orc_rational_force(p, ph, a14, n14, al14, be14, eta, tol, maxit, &Sf, Gf);
+    for (long long x = 0; x < V; ++x) pi[x] -= 0.5 * eps * (G[x] + Gf[x]);
+  }
+  H1 = 0.5 * vec_norm2(V, pi) + Sb + Sf;
+  *dH = H1 - H0;
+  *accepted = (u < exp(-*dH)) ? 1 : 0;
+  if (*accepted) memcpy(phi, ph, (size_t)V * sizeof(cplx));
+  free(eta); free(ph); free(pi); free(G); free(Gf);
+  return rc;
+}

@@ -145,6 +145,20 @@ int orc_m0inv(const orc_params *p, int dag, const double complex *in, double com
  * entries. */
 int orc_locality(const orc_params *p, int spin, double *f, int nr);
 
+/* Bosonic action of eq. acws for a periodic complex scalar phi [V] (W' = m phi +
+ * (g/2) phi^2, D_2 the scalar part of the exact overlap operator): S (may be NULL),
+ * G = dS/dRe phi + i dS/dIm phi (may be NULL), F = -(1 - D_2/2) conj(W') (may be NULL). */
+int orc_boson(const orc_params *p, const double complex *phi, double *S, double complex *G,
+              double complex *F);
+
+/* One RHMC trajectory (heatbath, leapfrog, Metropolis with the input u); phi [V] is
+ * replaced by the end point when accepted.  dH = H_end - H_start. */
+int orc_rhmc_trajectory(const orc_params *p, double complex *phi, const double complex *pi0,
+                        const double complex *R, int nsteps, double tau, double a18, int n18,
+                        const double *al18, const double *be18, double a14, int n14,
+                        const double *al14, const double *be14, double u, double tol,
+                        int maxit, double *dH, int *accepted);
+
 int orc_threads(void);
 
 #endif

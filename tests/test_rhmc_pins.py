@@ -1,0 +1,125 @@
+"""Pins of the oracle's RHMC pieces (Sec. 7.3, eq. acws, eq. lata) on the CPU.
+
+* The bosonic action S_B, its force and the auxiliary field F against numpy's FFT
+  of the closed-form D_2(p) = 1 + w(p)/s(p) (periodic scalar momenta), and the
+  force against central finite differences.
+* D^dag D = 2 D_2 for the exact overlap operator (the identity of Sec. 2.2 that
+  defines D_2 as the scalar part).
+* Leapfrog: the energy violation dH of a trajectory shrinks as eps^2 (a wrong
+  force term breaks this), and the Metropolis decision follows u < exp(-dH).
+"""
+import numpy as np
+import pytest
+
+import closed_form as cf
+from paper_1005_3276_amd import inputs
+
+
+def _d2_periodic(dims, M0=1.0):
+    X, Y, Z, T = dims
+    ks = [2 * np.pi * np.fft.fftfreq(L) for L in (X, Y, Z, T)]
+    PT, PZ, PY, PX = np.meshgrid(ks[3], ks[2], ks[1], ks[0], indexing="ij")
+    w = 4 - M0 - (np.cos(PX) + np.cos(PY) + np.cos(PZ) + np.cos(PT))
+    s2 = w * w + np.sin(PX) ** 2 + np.sin(PY) ** 2 + np.sin(PZ) ** 2 + np.sin(PT) ** 2
+    return 1 + w / np.sqrt(s2)
+
+
+def _apply_scalar(sym, f):
+    return np.fft.ifftn(sym * np.fft.fftn(f))
+
+
+def _boson_closed_form(dims, phi, m, g):
+    lam = 0.5 * g
+    d2 = _d2_periodic(dims)
+    W1 = m * phi + lam * phi ** 2
+    D2phi = _apply_scalar(d2, phi)
+    KW = _apply_scalar(1 - 0.5 * d2, W1)
+    S = np.sum(2 * np.conj(phi) * D2phi + np.conj(W1) * KW).real
+    G = 2 * (2 * D2phi + np.conj(m + g * phi) * KW)
+    F = -_apply_scalar(1 - 0.5 * d2, np.conj(W1))
+    return S, G, F
+
+
+@pytest.mark.parametrize("dims,m,g", [((4, 4, 2, 6), 0.5, 0.2), ((2, 4, 4, 4), 0.3 + 0.1j, 0.4)])
+def test_boson_vs_closed_form(orc, dims, m, g):
+    phi, _ = inputs.draw(dims, nrhs=1, sigma2=0.5, seed=81)
+    o = orc.Oracle(dims, m=m, g=g)
+    S, G, F = o.boson(phi)
+    S0, G0, F0 = _boson_closed_form(dims, phi, m, g)
+    assert abs(S - S0) < 1e-12 * abs(S0)
+    assert np.abs(G - G0).max() < 1e-12 * np.abs(G0).max()
+    assert np.abs(F - F0).max() < 1e-12 * np.abs(F0).max()
+
+
+def test_boson_force_vs_fd(orc):
+    dims = (2, 2, 4, 4)
+    phi, _ = inputs.draw(dims, nrhs=1, sigma2=0.5, seed=82)
+    o = orc.Oracle(dims, m=0.5, g=0.3)
+    _, G, _ = o.boson(phi)
+    h = 1e-6
+    flat = phi.reshape(-1)
+    for site in (0, 7, 30):
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            pp, pm = flat.copy(), flat.copy()
+            pp[site] += h * unit
+            pm[site] -= h * unit
+            fd = (o.boson(pp.reshape(phi.shape))[0] - o.boson(pm.reshape(phi.shape))[0]) / (2 * h)
+            got = G.reshape(-1)[site]
+            got = got.real if part == "re" else got.imag
+            assert abs(got - fd) < 1e-7 * np.abs(G).max()
+
+
+def test_dagger_d_is_2_d2():
+    """D^dag D = 2 D_2 (Sec. 2.2) with D the exact overlap operator, per momentum."""
+    dims = (4, 4, 2, 6)
+    D = cf.dov_symbol(cf.exact_sign_symbol(dims, bc_t=1))
+    DdD = np.einsum("...ba,...bc->...ac", D.conj(), D)
+    d2 = _d2_periodic(dims)
+    d2 = np.transpose(d2, (0, 1, 2, 3))
+    assert np.abs(DdD - 2 * d2[..., None, None] * np.eye(4)).max() < 1e-13
+
+
+@pytest.fixture(scope="module")
+def traj_setup(orc):
+    from paper_1005_3276_amd import rational
+    dims = (2, 2, 2, 4)
+    m, g = 0.5, 0.4
+    phi, R = inputs.draw(dims, nrhs=1, sigma2=0.2, seed=83)
+    rng = np.random.default_rng(84)
+    pi = (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape)) / np.sqrt(2)
+    o = orc.Oracle(dims, m=m, g=g, dirac=orc.DIRAC_DSLASH)
+    n = 4 * int(np.prod(dims))
+    Md = np.zeros((n, n), complex)
+    e = np.zeros(n, complex)
+    for j in range(n):
+        e[:] = 0
+        e[j] = 1
+        Md[:, j] = o.apply(orc.OP_M, e, phi).reshape(-1)
+    lam = np.linalg.eigvalsh(Md.conj().T @ Md)
+    lo, hi = 0.3 * lam.min(), 3.0 * lam.max()
+    c18 = rational.power_approx(0.125, lo, hi, 12)
+    c14 = rational.power_approx(-0.25, lo, hi, 12)
+    return o, phi, pi, R[0], c18, c14
+
+
+def test_leapfrog_dh_scales_as_eps_squared(traj_setup):
+    o, phi, pi, R, c18, c14 = traj_setup
+    tau = 0.5
+    dh = []
+    for nsteps in (5, 10, 20):
+        _, d, _ = o.rhmc_trajectory(phi, pi, R, nsteps, tau, c18[:3], c14[:3], u=0.0)
+        dh.append(abs(d))
+    assert dh[0] > 1e-8
+    for a, b in zip(dh, dh[1:]):
+        assert 0.15 < b / a < 0.35
+
+
+def test_metropolis_decision(traj_setup):
+    o, phi, pi, R, c18, c14 = traj_setup
+    end, d, acc = o.rhmc_trajectory(phi, pi, R, 5, 0.5, c18[:3], c14[:3], u=0.0)
+    assert acc and not np.allclose(end, phi)
+    end2, d2, acc2 = o.rhmc_trajectory(phi, pi, R, 5, 0.5, c18[:3], c14[:3], u=np.nextafter(1.0, 2.0))
+    assert abs(d2 - d) < 1e-9  # OpenMP sums: rounding-level run-to-run differences
+    assert acc2 == (d < 0)
+    if not acc2:
+        assert np.array_equal(end2, phi)
