@@ -207,6 +207,34 @@ ov_status ov_rational_force(ov_ctx *ctx, double a0, int n, const double *alpha,
                             const double *beta, void *grad_phi, double *S_host, const void *xi,
                             const void *phi, int nrhs, ov_stats *st);
 
+/* Bosonic part of the lattice action (eq. acws, a = 1) for a periodic complex scalar
+ * phi (complex128 [V], device):
+ *   S_B = sum_x [ 2 conj(phi) (D_2 phi) + conj(W') ((1 - D_2/2) W') ],
+ *   W' = m phi + (g/2) phi^2,  D_2(p) = 1 + w(p)/|H_W(p)| the scalar part of the exact
+ *   overlap operator (D^dag D = 2 D_2).  g is the Yukawa coefficient of M, i.e. the
+ *   paper's 2g of eq. fmat, so that M's Yukawa term is W''(phi) = m + g phi.
+ * S_host: host double.  G (device complex128 [V], may be NULL) = dS/dRe phi + i dS/dIm phi
+ * = 2 [2 D_2 phi + conj(m + g phi) (1 - D_2/2) W'].  F (device complex128 [V], may be
+ * NULL) = -(1 - D_2/2) conj(W'), the auxiliary field at the stationary point of eq. lata
+ * (its lattice average is the Ward-identity observable of Sec. 7.4).  Lattice limits of
+ * OV_OP_M0INV. */
+ov_status ov_boson(ov_ctx *ctx, const void *phi, double *S_host, void *G, void *F);
+
+/* One RHMC trajectory (Sec. 7.3): pseudofermion heatbath eta = r18(MdagM) R, leapfrog
+ * molecular dynamics of length tau in nsteps steps for
+ *   H = 1/2 sum_x |pi_x|^2 + S_B(phi) + Re eta^dag r14(MdagM) eta
+ * (dphi/dt = pi, dpi/dt = -G), and the Metropolis decision u < exp(-dH).
+ * r18 ~ x^{1/8} and r14 ~ x^{-1/4} are given as (a0, n, alpha, beta) of ov_rational.
+ * phi: device complex128 [V], replaced by the end point when accepted.  pi0 (complex128
+ * [V]) and R (one field) are the caller's Gaussian draws and u its uniform draw.
+ * Writes dH = H_end - H_start and accepted (0/1).  Allocates its trajectory state
+ * (8 V complex values) with hipMalloc for the duration of the call. */
+ov_status ov_rhmc_trajectory(ov_ctx *ctx, void *phi, const void *pi0, const void *R,
+                             int nsteps, double tau, double a18, int n18, const double *al18,
+                             const double *be18, double a14, int n14, const double *al14,
+                             const double *be14, double u, double *dH, int *accepted,
+                             ov_stats *st);
+
 /* Locality probe of Sec. 3.2: psi = D eta for a unit point source eta at the origin
  * in spin component `spin` (0..3), D the context's Dirac form (the paper probes
  * OV_DIRAC_DSLASH), and f[r] = max ||psi(x)|| (spinor norm) over the sites at

@@ -25,7 +25,8 @@ SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace
            "ov_set_workspace", "ov_get_coeffs", "ov_zolotarev", "ov_sign", "ov_apply",
            "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
            "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling",
-           "ov_kernel_times", "ov_locality", "ov_rational", "ov_rational_force",
+           "ov_kernel_times", "ov_locality", "ov_rational", "ov_rational_force", "ov_boson",
+           "ov_rhmc_trajectory",
            "ov_status_string", "ov_last_error"]
 
 
@@ -95,6 +96,9 @@ def lib():
         L.ov_locality.argtypes = [P, C.c_int, P, C.c_int, P]
         L.ov_rational.argtypes = [P, C.c_double, C.c_int, P, P, P, P, P, C.c_int, P]
         L.ov_rational_force.argtypes = [P, C.c_double, C.c_int, P, P, P, P, P, P, C.c_int, P]
+        L.ov_boson.argtypes = [P, P, P, P, P]
+        L.ov_rhmc_trajectory.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_double, C.c_int,
+                                         P, P, C.c_double, C.c_int, P, P, C.c_double, P, P, P]
         L.ov_status_string.argtypes = [C.c_int]
         L.ov_status_string.restype = C.c_char_p
         L.ov_last_error.argtypes = [P]
@@ -103,7 +107,8 @@ def lib():
                    "ov_zolotarev", "ov_sign", "ov_apply", "ov_solve", "ov_solve_batch",
                    "ov_force", "ov_stencil_bench", "ov_pack", "ov_unpack", "ov_set_launch",
                    "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling", "ov_kernel_times",
-                   "ov_locality", "ov_rational", "ov_rational_force"):
+                   "ov_locality", "ov_rational", "ov_rational_force", "ov_boson",
+                   "ov_rhmc_trajectory"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib

@@ -905,12 +905,13 @@ __global__ void __launch_bounds__(256) k_fill(const SysDev* __restrict__ sys,
 // inverse e^{+2 pi i j k/L} with 1/V.  Antiperiodic time is handled by the
 // twist e^{-i pi t/T} before the forward and e^{+i pi t/T} after the inverse
 // transform, which puts p_t on (2n+1) pi / T.
-enum SymKind { SYM_D = 0, SYM_D_DAG = 1, SYM_M0INV = 2, SYM_M0INV_DAG = 3 };
+enum SymKind { SYM_D = 0, SYM_D_DAG = 1, SYM_M0INV = 2, SYM_M0INV_DAG = 3, SYM_BOSON = 4 };
 enum DiracForm { DIRAC_RATIONAL = 0, DIRAC_EXACT = 1, DIRAC_DSLASH = 2 };
 
 struct SymParams {
   int kind;
   int form;           // DiracForm
+  int periodic;       // 1: periodic time (scalar fields) whatever the fermion boundary
   int np;
   double diag;        // 4 - M0
   double a[MAXP];     // residues a_k of the sign rational
@@ -945,7 +946,8 @@ __device__ __forceinline__ c2<R> cmad(c2<R> acc, c2<R> a, double2 w) {
 // time twist; inv = 1: fft_tmp -> e_out with the untwist and 1/V.  Needs
 // X, Y <= 64 and X Y <= 1024.
 template <class R>
-__global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, int nsys, int inv) {
+__global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, int nsys, int inv,
+                                                int periodic) {
   __shared__ c2<R> A[1024], B[1024];
   __shared__ double2 twx[64], twy[64];
   const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 0)];
@@ -962,7 +964,7 @@ __global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, 
   twiddles(twx, X, sgn);
   twiddles(twy, Y, sgn);
   double tr = 1.0, ti = 0.0;  // twist (forward) / untwist and normalisation (inverse)
-  if (S.g.bc < 0) sincospi(sgn * (double)t / (double)T, &ti, &tr);
+  if (S.g.bc < 0 && !periodic) sincospi(sgn * (double)t / (double)T, &ti, &tr);
   if (inv) {
     tr /= (double)V;
     ti /= (double)V;
@@ -1129,7 +1131,7 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
     const int xl = q % XC, kt = q / XC;
     double sx, cx, st, ct;
     sincospi(2.0 * (double)(xb + xl) / (double)X, &sx, &cx);
-    sincospi((2.0 * kt + (S.g.bc < 0 ? 1.0 : 0.0)) / (double)T, &st, &ct);
+    sincospi((2.0 * kt + ((S.g.bc < 0 && !sp.periodic) ? 1.0 : 0.0)) / (double)T, &st, &ct);
     const double w = sp.diag - (cx + cy + cz + ct);
     double2 v[4];
 #pragma unroll
@@ -1137,7 +1139,18 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
       const c2<R> u = B[(k * T + kt) * XC + xl];
       v[k] = double2{(double)u.x, (double)u.y};
     }
-    apply_symbol(sp, S.m_re, S.m_im, sx, sy, sz, st, w, v);
+    if (sp.kind == SYM_BOSON) {
+      // scalar fields in planes 0-2: D_2 = 1 + w/s (scalar part of the exact overlap
+      // operator), then 1 - D_2/2 twice; plane 3 unused
+      const double d2 = 1.0 + w / sqrt(w * w + sx * sx + sy * sy + sz * sz + st * st);
+      v[0] = double2{d2 * v[0].x, d2 * v[0].y};
+      const double k2 = 1.0 - 0.5 * d2;
+      v[1] = double2{k2 * v[1].x, k2 * v[1].y};
+      v[2] = double2{k2 * v[2].x, k2 * v[2].y};
+      v[3] = double2{0.0, 0.0};
+    } else {
+      apply_symbol(sp, S.m_re, S.m_im, sx, sy, sz, st, w, v);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) A[(k * T + kt) * XC + xl] = c2<R>{(R)v[k].x, (R)v[k].y};
   }
@@ -1363,6 +1376,88 @@ __global__ void __launch_bounds__(256) k_scale(const SysDev* __restrict__ sys, c
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] = double2{f * v[q].x, f * v[q].y};
     store_sp<double>((double2*)S.e_out, V, i, v);
+  }
+}
+
+// ------------------------------------------------- RHMC bosonic action (eq. acws)
+// phi: complex128 [V] (site order).  Pack planes of e_out2 (FP64 planar):
+// 0 = phi, 1 = W' = m phi + (g/2) phi^2, 2 = conj(W'), 3 = 0.
+__global__ void __launch_bounds__(256) k_boson_pack(const SysDev* __restrict__ sys,
+                                                     const int* __restrict__ bmap, int nb_total) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  const double lr = 0.5 * S.g_re, li = 0.5 * S.g_im;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double2 f = S.phi[i];
+    const double f2r = f.x * f.x - f.y * f.y, f2i = 2.0 * f.x * f.y;
+    const double wr = S.m_re * f.x - S.m_im * f.y + lr * f2r - li * f2i;
+    const double wi = S.m_re * f.y + S.m_im * f.x + lr * f2i + li * f2r;
+    double2 v[4] = {f, double2{wr, wi}, double2{wr, -wi}, double2{0.0, 0.0}};
+    store_sp<double>((double2*)S.e_in, V, i, v);
+  }
+}
+
+// From the transformed planes (e_out: D_2 phi, K W', K conj(W'), K = 1 - D_2/2):
+//   S partials  2 Re conj(phi) D_2 phi + Re conj(W') K W'  -> part_c
+//   G = 2 [2 D_2 phi + conj(m + g phi) K W']   (G_out, may be null)
+//   F = -K conj(W')                            (F_out, may be null)
+__global__ void __launch_bounds__(256) k_boson_finish(const SysDev* __restrict__ sys,
+                                                       const int* __restrict__ bmap, int nb_total,
+                                                       double2* __restrict__ G_out,
+                                                       double2* __restrict__ F_out) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 a[4], t[4];
+    load_sp<double>((const double2*)S.e_in, V, i, a);   // phi, W', conj W'
+    load_sp<double>((const double2*)S.e_out, V, i, t);  // D_2 phi, K W', K conj W'
+    const double2 f = a[0], w = a[1];
+    acc += 2.0 * (f.x * t[0].x + f.y * t[0].y) + (w.x * t[1].x + w.y * t[1].y);
+    if (G_out) {
+      // conj(m + g phi)
+      const double cr = S.m_re + S.g_re * f.x - S.g_im * f.y;
+      const double ci = -(S.m_im + S.g_re * f.y + S.g_im * f.x);
+      const double pr = cr * t[1].x - ci * t[1].y, pi = cr * t[1].y + ci * t[1].x;
+      G_out[i] = double2{2.0 * (2.0 * t[0].x + pr), 2.0 * (2.0 * t[0].y + pi)};
+    }
+    if (F_out) F_out[i] = double2{-t[2].x, -t[2].y};
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_c[lb] = tot;
+}
+
+// Molecular-dynamics updates on complex128 [n] arrays: y += a (x1 + x2) (x2 may be
+// null); optional partial |y|^2 per workgroup into part (null: none).
+__global__ void __launch_bounds__(256) k_md_axpy(double2* __restrict__ y, double a,
+                                                  const double2* __restrict__ x1,
+                                                  const double2* __restrict__ x2, int n,
+                                                  double* __restrict__ part) {
+  __shared__ double lds[17];
+  double acc = 0.0;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double2 v = y[i];
+    if (x1) {
+      double2 d = x1[i];
+      if (x2) d = double2{d.x + x2[i].x, d.y + x2[i].y};
+      v = double2{v.x + a * d.x, v.y + a * d.y};
+      y[i] = v;
+    }
+    acc = v.x * v.x + v.y * v.y;
+  }
+  if (part) {
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
   }
 }
 

@@ -619,12 +619,13 @@ void launch_sym(const Engine& E, int t, int kind) {
     sp.a[k] = k < sp.np ? c->a[k] : 0.0;
     sp.b[k] = k < sp.np ? c->b[k] : 0.0;
   }
+  sp.periodic = kind == SYM_BOSON ? 1 : 0;  // scalar fields are periodic in time
   const SysDev* T = tab(E, t);
-  k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 0);
+  k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 0, sp.periodic);
   k_fft_z<R><<<E.nb_z, 256, 0, E.st>>>(T, E.nsys, 0);
   k_fft_t_sym<R><<<E.nb_t, 256, 0, E.st>>>(T, E.nsys, sp);
   k_fft_z<R><<<E.nb_z, 256, 0, E.st>>>(T, E.nsys, 1);
-  k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 1);
+  k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 1, sp.periodic);
 }
 
 ov_status check_launch(ov_ctx* c) {
@@ -2227,6 +2228,116 @@ ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
   so.res.assign(nrhs, 0.0);
   so.conv.assign(nrhs, 1);
   fill_stats(st, nrhs, &E, &so, now_s() - t0, 16);
+  return OV_OK;
+}
+
+// ------------------------------------------------------------ RHMC (Sec. 7.3)
+ov_status ov_boson(ov_ctx* c, const void* phi, double* S_host, void* G, void* F) {
+  if (!c || !phi || !S_host) return OV_ERR_INVALID_ARG;
+  std::string why;
+  if (!fft_ok(&c->p, why)) {
+    c->err = "ov_boson: " + why;
+    return OV_ERR_INVALID_ARG;
+  }
+  Engine E;
+  std::vector<ov_ctx*> v(1, c);
+  TRY(engine_init(E, v, false, false, c->p.inner_tol, c->p.inner_tol));
+  SysBuf& b = E.sb[0];
+  E.htab.assign((size_t)T_NT, SysDev{});
+  SysDev d = base_dev(b);
+  d.phi = (const double2*)phi;
+  d.e_in = b.x64;      // packed planes phi, W', conj W'
+  d.e_out = b.r64;     // transformed planes
+  d.fft_tmp = b.src64b;
+  E.htab[T_APPLY] = d;
+  TRY(upload_tables(E));
+  k_boson_pack<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total);
+  launch_sym<double>(E, T_APPLY, SYM_BOSON);
+  k_boson_finish<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total,
+                                                    (double2*)G, (double2*)F);
+  TRY(sync(E));
+  std::vector<double> tmp(b.nblk);
+  HIPCHK(c, hipMemcpy(tmp.data(), b.part_c, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost));
+  double acc = 0;
+  for (double x : tmp) acc += x;
+  *S_host = acc;
+  return OV_OK;
+}
+
+namespace {
+// sum of |y|^2 over n complex values after y += a (x1 + x2), on the caller's stream
+ov_status md_axpy(ov_ctx* c, double2* y, double a, const double2* x1, const double2* x2, int n,
+                  double* part, double* norm2) {
+  const int nb = (n + 255) / 256;
+  k_md_axpy<<<nb, 256, 0, c->stream>>>(y, a, x1, x2, n, norm2 ? part : nullptr);
+  TRY(check_launch(c));
+  if (norm2) {
+    std::vector<double> h(nb);
+    HIPCHK(c, hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double acc = 0;
+    for (double v : h) acc += v;
+    *norm2 = acc;
+  }
+  return OV_OK;
+}
+}  // namespace
+
+ov_status ov_rhmc_trajectory(ov_ctx* c, void* phi, const void* pi0, const void* R, int nsteps,
+                             double tau, double a18, int n18, const double* al18,
+                             const double* be18, double a14, int n14, const double* al14,
+                             const double* be14, double u, double* dH, int* accepted,
+                             ov_stats* st) {
+  if (!c || !phi || !pi0 || !R || nsteps < 1 || !(tau > 0) || !al18 || !be18 || !al14 ||
+      !be14 || !dH || !accepted)
+    return OV_ERR_INVALID_ARG;
+  const double t0 = now_s();
+  const int V = c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3];
+  const size_t sb = (size_t)V * sizeof(double2);
+  // trajectory state: eta (4V), phi and pi working copies, G_B, G_F, partial sums
+  char* buf = nullptr;
+  const size_t nbytes = 8 * sb + sizeof(double) * ((V + 255) / 256 + 64);
+  HIPCHK(c, hipMalloc((void**)&buf, nbytes));
+  struct Free {
+    char* p;
+    ~Free() { if (p) (void)hipFree(p); }
+  } guard{buf};
+  double2* eta = (double2*)buf;
+  double2* ph = (double2*)(buf + 4 * sb);
+  double2* pi = ph + V;
+  double2* Gb = pi + V;
+  double2* Gf = Gb + V;
+  double* part = (double*)(Gf + V);
+  HIPCHK(c, hipMemcpyAsync(ph, phi, sb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(pi, pi0, sb, hipMemcpyDeviceToDevice, c->stream));
+  // heatbath eta = r18(MdagM) R
+  TRY(ov_rational(c, a18, n18, al18, be18, eta, R, phi, 1, nullptr));
+  const double eps = tau / nsteps;
+  double Sb = 0, Sf = 0, p2 = 0;
+  auto forces = [&]() -> ov_status {
+    TRY(ov_boson(c, ph, &Sb, Gb, nullptr));
+    TRY(ov_rational_force(c, a14, n14, al14, be14, Gf, &Sf, eta, ph, 1, nullptr));
+    return OV_OK;
+  };
+  TRY(forces());
+  TRY(md_axpy(c, pi, 0.0, nullptr, nullptr, V, part, &p2));
+  const double H0 = 0.5 * p2 + Sb + Sf;
+  for (int k = 0; k < nsteps; ++k) {
+    TRY(md_axpy(c, pi, -0.5 * eps, Gb, Gf, V, part, nullptr));
+    TRY(md_axpy(c, ph, eps, pi, nullptr, V, part, nullptr));
+    TRY(forces());
+    TRY(md_axpy(c, pi, -0.5 * eps, Gb, Gf, V, part, k + 1 == nsteps ? &p2 : nullptr));
+  }
+  const double H1 = 0.5 * p2 + Sb + Sf;
+  *dH = H1 - H0;
+  *accepted = (u < std::exp(-*dH)) ? 1 : 0;
+  if (*accepted) HIPCHK(c, hipMemcpyAsync(phi, ph, sb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->outer_iters = nsteps;
+    st->seconds = now_s() - t0;
+  }
   return OV_OK;
 }
 

@@ -129,6 +129,36 @@ class Lattice:
                                               _ptr(xi), _ptr(phi), nrhs, st))
         return list(S), G, [s.as_dict() for s in st]
 
+    def boson(self, phi):
+        """(S_B, G_B, F) of the bosonic action of eq. acws (see ov_boson)."""
+        phi = self._phi(phi)
+        G = torch.empty(self.phi_shape, dtype=torch.complex128, device=phi.device)
+        F = torch.empty_like(G)
+        S = C.c_double()
+        self._check(L.lib().ov_boson(self._h, _ptr(phi), C.byref(S), _ptr(G), _ptr(F)))
+        return S.value, G, F
+
+    def rhmc_trajectory(self, phi, pi, R, nsteps, tau, c18, c14, u):
+        """One RHMC trajectory; phi is updated in place when accepted.
+        c18, c14: (a0, alphas, betas) of x^{1/8} and x^{-1/4}.  Returns (dH, accepted)."""
+        import numpy as np
+        phi = self._phi(phi)
+        pi = self._phi(pi)
+        R, nrhs = self._fields(R)
+        if nrhs != 1:
+            raise ValueError("one pseudofermion field")
+        a18, al18, be18 = float(c18[0]), np.ascontiguousarray(c18[1], np.float64), np.ascontiguousarray(c18[2], np.float64)
+        a14, al14, be14 = float(c14[0]), np.ascontiguousarray(c14[1], np.float64), np.ascontiguousarray(c14[2], np.float64)
+        dH = C.c_double()
+        acc = C.c_int()
+        st = L.OvStats()
+        vp = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(L.lib().ov_rhmc_trajectory(self._h, _ptr(phi), _ptr(pi), _ptr(R), nsteps,
+                                               float(tau), a18, len(al18), vp(al18), vp(be18),
+                                               a14, len(al14), vp(al14), vp(be14), float(u),
+                                               C.byref(dH), C.byref(acc), C.byref(st)))
+        return dH.value, bool(acc.value)
+
     def locality(self, spin=0):
         """Locality probe of Sec. 3.2 for this lattice's Dirac form: f(r) for
         r = 0 .. sum L/2 (numpy array) and the stats dict."""

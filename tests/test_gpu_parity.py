@@ -682,3 +682,77 @@ def test_heatbath_identity_16x4(rat_coeffs, dirac):
     print(f"[heatbath] {time.time() - t:.2f}s {st1[0]['outer_iters']} + {st2[0]['outer_iters']} "
           f"iterations, rel dev {abs(lhs - rhs) / rhs:.2e}", flush=True)
     assert abs(lhs - rhs) < 1e-8 * rhs
+
+
+# ------------------------------------------------------- RHMC (Sec. 7.3, eq. acws)
+
+def test_boson_vs_oracle(orc):
+    dims = (4, 4, 2, 6)
+    phi, _ = inputs.draw(dims, nrhs=1, sigma2=0.5, seed=91)
+    kw = dict(m=0.3 + 0.1j, g=0.4)
+    lat = lattice(dims, **kw)
+    S, G, F = lat.boson(dev(phi))
+    So, Go, Fo = orc.Oracle(dims, **kw).boson(phi)
+    assert abs(S - So) < 1e-13 * abs(So)
+    assert np.abs(host(G) - Go).max() < 1e-13 * np.abs(Go).max()
+    assert np.abs(host(F) - Fo).max() < 1e-13 * np.abs(Fo).max()
+
+
+@pytest.fixture(scope="module")
+def rhmc_setup(orc):
+    """4^4 Dslash (the paper's fermion matrix), m = 0.5, paper's g = 0.1 (M's 0.2);
+    rational coefficients on [0.3 lambda_min, 3 lambda_max] of the dense MdagM."""
+    from paper_1005_3276_amd import rational
+    dims = (4, 4, 4, 4)
+    phi, R = inputs.draw(dims, nrhs=1, sigma2=0.2, seed=92)
+    rng = np.random.default_rng(93)
+    pi = (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape)) / np.sqrt(2)
+    kw = dict(m=0.5, g=0.2, dirac=3)
+    o = orc.Oracle(dims, **kw)
+    n = 4 * int(np.prod(dims))
+    Md = np.zeros((n, n), complex)
+    e = np.zeros(n, complex)
+    for j in range(n):
+        e[:] = 0
+        e[j] = 1
+        Md[:, j] = o.apply(orc.OP_M, e, phi).reshape(-1)
+    lam = np.linalg.eigvalsh(Md.conj().T @ Md)
+    lo, hi = 0.3 * lam.min(), 3.0 * lam.max()
+    c18 = rational.power_approx(0.125, lo, hi, 16)
+    c14 = rational.power_approx(-0.25, lo, hi, 16)
+    return dims, kw, o, phi, pi, R, c18, c14
+
+
+def test_rhmc_trajectory_vs_oracle(rhmc_setup):
+    dims, kw, o, phi, pi, R, c18, c14 = rhmc_setup
+    print("[rhmc] trajectory 4^4", flush=True)
+    lat = lattice(dims, outer_tol=1e-12, **kw)
+    ph = dev(phi)
+    dH, acc = lat.rhmc_trajectory(ph, dev(pi), dev(R), 4, 0.2, c18[:3], c14[:3], u=0.0)
+    end_o, dH_o, acc_o = o.rhmc_trajectory(phi, pi, R[0], 4, 0.2, c18[:3], c14[:3], u=0.0,
+                                           tol=1e-12)
+    print(f"[rhmc] dH gpu {dH:.6e} oracle {dH_o:.6e}", flush=True)
+    assert acc and acc_o
+    assert abs(dH - dH_o) < 1e-7 * max(1.0, abs(dH_o))
+    assert rel(host(ph), end_o) < 1e-10
+
+
+def test_rhmc_dh_scaling_16x4():
+    """At 16^4 (the paper's lattice size class): leapfrog energy violation ~ eps^2."""
+    from paper_1005_3276_amd import rational
+    dims = (16, 16, 16, 16)
+    phi, R = inputs.draw(dims, nrhs=1, sigma2=0.2, seed=94)
+    rng = np.random.default_rng(95)
+    pi = (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape)) / np.sqrt(2)
+    # exact overlap D: |D| <= 2, so MdagM lies in [~m^2/4, (2 + m + g|phi|)^2]
+    lat = lattice(dims, m=0.5, g=0.2, dirac=2, outer_tol=1e-11)
+    c18 = rational.power_approx(0.125, 1e-3, 20.0, 16)
+    c14 = rational.power_approx(-0.25, 1e-3, 20.0, 16)
+    dh = []
+    for nsteps in (4, 8):
+        t = time.time()
+        d, _ = lat.rhmc_trajectory(dev(phi), dev(pi), dev(R), nsteps, 0.2, c18[:3], c14[:3],
+                                   u=0.0)
+        print(f"[rhmc16] nsteps={nsteps} dH={d:.4e} ({time.time() - t:.1f}s)", flush=True)
+        dh.append(abs(d))
+    assert 0.15 < dh[1] / dh[0] < 0.35
