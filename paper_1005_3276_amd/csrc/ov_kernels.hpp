@@ -1483,20 +1483,21 @@ __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
       c[CG_RR_OLD] = c[CG_RR];
       c[CG_RR] = v;
       c[CG_BETA] = v / c[CG_RR_OLD];
-    } else if (op == 3) {  // reliable update: replace the recursive |r|^2 by the true one
+    } else if (op == 3 || op == 7) {  // reliable update: recursive |r|^2 -> true one
       // Keep the search direction unless the true residual exceeds the recursive
-      // one by more than 2x (the recursion drifted): then restart with p = r.
+      // one by more than 2x (the recursion drifted) or a restart is forced (op 7,
+      // a stalled recursion): then restart with p = r.
       const double rec = c[CG_RR];
       c[CG_RTRUE] = v;
       c[CG_RR] = v;
-      c[CG_BETA] = (v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
+      c[CG_BETA] = (op == 7 || v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
     } else if (op == 5) {  // true residual only (no CG state change)
       c[CG_RTRUE] = v;
-    } else if (op == 6) {  // reliable update of the preconditioned recursion (|r~|^2 true)
+    } else if (op == 6 || op == 8) {  // the same for the preconditioned recursion (|r~|^2)
       const double rec = c[CG_RR];
       c[CG_RYT] = v;
       c[CG_RR] = v;
-      c[CG_BETA] = (v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
+      c[CG_BETA] = (op == 8 || v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
     } else if (op == 4) {  // norm of b
       c[CG_BB] = v;
     }

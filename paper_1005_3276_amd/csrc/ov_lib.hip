@@ -1165,7 +1165,8 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
         k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
       launch_sym<R>(E, T_PC_RES, SYM_M0INV_DAG);
       k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_PC_RES), E.bmap, E.nb_total, 4);
-      if (scalar_op == 3) k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_PC_RES), E.nsys, 6);
+      if (scalar_op == 3 || scalar_op == 7)
+        k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_PC_RES), E.nsys, scalar_op == 3 ? 6 : 8);
     } else {
       k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, tres), E.nsys, scalar_op);
       if (sizeof(R) != sizeof(double))
@@ -1225,6 +1226,8 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   // preconditioned); kap: |r| / |r~| there, which turns the recursive |r~| into
   // an estimate of the original residual for the stopping test.
   std::vector<double> bn(ns), rmax(ns), kap(ns, 1.0);
+  std::vector<int> last_ru(ns, 0);  // outer iteration of the last reliable update
+  constexpr int kStall = 250;
   out.outer.assign(ns, 0);
   out.ru.assign(ns, 0);
   out.res.assign(ns, 1.0);
@@ -1351,7 +1354,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         est = nobs;
       }
     }
-    bool need_ru = false, final_check = false;
+    bool need_ru = false, final_check = false, restart = false;
     double best_rec = 1e300;  // the tightest residual among the systems updated now
     if (ov_log()) {
       std::fprintf(stderr, "[ov] iter %d:", iter);
@@ -1374,7 +1377,11 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       const double rec = kap[s] * std::sqrt(rr) / bn[s];
       const bool at_target = rec <= P.outer_tol;
       const bool dropped = delta > 0.0 && std::sqrt(rr) < delta * rmax[s];
-      if (at_target || dropped || iter >= P.max_outer) {
+      // a recursion that has not dropped by delta for kStall iterations has
+      // stalled (lost conjugacy in the inner precision): update and restart
+      const bool stalled = delta > 0.0 && iter - last_ru[s] >= kStall;
+      if (stalled) restart = true;
+      if (at_target || dropped || stalled || iter >= P.max_outer) {
         fru[s] = 1;
         need_ru = true;
         if (at_target || iter >= P.max_outer) final_check = true;
@@ -1388,11 +1395,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       const double ttol = final_check
                               ? P.truth_tol
                               : std::max(P.truth_tol, std::min(1e-6, 0.01 * best_rec));
-      TRY(reliable_update<R>(E, ttol, 3));
+      TRY(reliable_update<R>(E, ttol, restart ? 7 : 3));
       TRY(read_scalars(E));
       for (int s = 0; s < ns; ++s) {
         if (!fru[s]) continue;
         out.ru[s]++;
+        last_ru[s] = iter;
         const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
         rmax[s] = rt;
         if (pc) {
