@@ -65,6 +65,29 @@ def stencil_bandwidth(lat, torch, nrhs, prec, reps=20):
             "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def copy_bandwidth(torch):
+    """Read + write bandwidth of a plain device copy (torch) at the stencil's working
+    set sizes: the streaming bandwidth this part reaches in practice."""
+    out = {}
+    for mib in (100, 800):
+        n = mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[f"{mib}MiB"] = 2.0 * n / (ms * 1e-3) / 1e12
+        del a, b
+    return out
+
+
 def cpu_baseline(phi, src, outer_iters):
     """Oracle FP64 M^dag M applications at 16^4 on the host cores; scaled to one
     solve of the oracle's (unpreconditioned) CG by the outer-iteration count of
@@ -341,8 +364,14 @@ def main():
             for nrhs in (1, 12, 48):
                 sweep.append(stencil_bandwidth(lat, torch, nrhs, prec))
                 log(f"stencil {sweep[-1]}")
+        # beyond the 256 MB Infinity Cache: 16^4 x 192 (FP32) / x 96 (FP64) fields
+        sweep.append(stencil_bandwidth(lat, torch, 192, 1))
+        sweep.append(stencil_bandwidth(lat, torch, 96, 0))
+        log(f"stencil {sweep[-2]}\nstencil {sweep[-1]}")
         extra["stencil"] = sweep
         extra["stencil_best_TB_s"] = max(s["GB_s"] for s in sweep) / 1e3
+        extra["device_copy_TB_s"] = copy_bandwidth(torch)
+        log(f"device copy: {extra['device_copy_TB_s']}")
 
     if not args.quick:
         extra.update(other_configs(torch, Lattice, inputs))

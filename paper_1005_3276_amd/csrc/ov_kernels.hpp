@@ -247,6 +247,83 @@ __global__ void __launch_bounds__(256) k_hw_lds(const SysDev* __restrict__ sys, 
   }
 }
 
+// out = H_W in, z-marching form: a workgroup owns one xy plane (X Y <= 256
+// sites, one per thread) of one time slice and walks ZC consecutive z planes.
+// The z neighbours stay in registers (the plane below, the current one, the
+// plane above), the x and y neighbours come from the current plane staged in
+// LDS, so each output site reads (ZC + 2)/ZC centre spinors plus its two time
+// neighbours from the memory hierarchy instead of nine spinors.  Every system
+// of the table has the same lattice.  Grid: nsys * T * (Z / ZC) workgroups.
+template <class R, int ZC>
+__global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, double diag) {
+  __shared__ c2<R> sh[4 * 256];
+  const Geo g = sys[0].g;
+  const int X = g.X, Y = g.Y, Z = g.Z, T = g.T, V = g.V;
+  const int XY = X * Y, XYZ = XY * Z;
+  const int nzc = Z / ZC;
+  // XCD-contiguous order: the workgroups of neighbouring time slices share an L2,
+  // which then serves the time-neighbour reads
+  const int b = xcd_logical_block(gridDim.x);
+  const int s = b / (T * nzc);
+  const int t = (b / nzc) % T;
+  const int z0 = (b % nzc) * ZC;
+  const SysDev& S = sys[s];
+  const c2<R>* in = (const c2<R>*)S.e_in;
+  c2<R>* out = (c2<R>*)S.e_out;
+  const int j = threadIdx.x;
+  const bool on = j < XY;
+  const int x = on ? j % X : 0, y = on ? j / X : 0;
+  const int tf_off = (t + 1 < T) ? XYZ : XYZ - V;
+  const int tb_off = (t > 0) ? -XYZ : V - XYZ;
+  const int jxf = y * X + ((x + 1 < X) ? x + 1 : 0);
+  const int jxb = y * X + ((x > 0) ? x - 1 : X - 1);
+  const int jyf = ((y + 1 < Y) ? y + 1 : 0) * X + x;
+  const int jyb = ((y > 0) ? y - 1 : Y - 1) * X + x;
+  auto site = [&](int z) { return j + XY * (z + Z * t); };
+  Nbr<R> nb;
+  c2<R> prev[4], cur[4], next[4];
+  if (on) {
+    load_sp<R>(in, V, site(z0 > 0 ? z0 - 1 : Z - 1), prev);
+    load_sp<R>(in, V, site(z0), cur);
+  }
+#pragma unroll
+  for (int zi = 0; zi < ZC; ++zi) {
+    const int z = z0 + zi;
+    const int i = site(z);
+    if (on) {
+      load_sp<R>(in, V, site(z + 1 < Z ? z + 1 : 0), next);
+      load_sp<R>(in, V, i + tf_off, nb.tf);
+      load_sp<R>(in, V, i + tb_off, nb.tb);
+    }
+    __syncthreads();  // the previous plane's LDS reads are done
+    if (on) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh[q * 256 + j] = cur[q];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        nb.c[q] = cur[q];
+        nb.xf[q] = sh[q * 256 + jxf];
+        nb.xb[q] = sh[q * 256 + jxb];
+        nb.yf[q] = sh[q * 256 + jyf];
+        nb.yb[q] = sh[q * 256 + jyb];
+        nb.zf[q] = next[q];
+        nb.zb[q] = prev[q];
+      }
+      c2<R> o[4];
+      hw_compute<R>(nb, g, i, (R)diag, o);
+      store_sp<R>(out, V, i, o);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        prev[q] = cur[q];
+        cur[q] = next[q];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------- multi-shift: t pass
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
 // advances the shift recurrences, decides convergence, then

@@ -2542,14 +2542,27 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   const double diag = 4.0 - c->p.M0;
-  // LDS-staged stencil unless disabled (OV_HW_LDS=0) or the block does not fit
+  // Stencil form: z-marching (xy plane in LDS, z neighbours in registers) where
+  // the plane fits a workgroup, else the LDS-staged block form; OV_HW_LDS=0
+  // selects the plain form, OV_HW_LDS=1 the block form (measurement switches).
   const int spb = E.sb[0].spb;
   const size_t lds_bytes = (size_t)4 * spb * (prec ? sizeof(float2) : sizeof(double2));
   const char* ev = std::getenv("OV_HW_LDS");
-  const bool use_lds = !(ev && *ev == '0') && lds_bytes <= 64 * 1024;
+  const int* dm = c->p.dims;
+  const int zc = (dm[2] % 4 == 0) ? 4 : (dm[2] % 2 == 0 ? 2 : 1);
+  const bool use_zm = !(ev && (*ev == '0' || *ev == '1')) && dm[0] * dm[1] <= 256 && zc >= 2;
+  const bool use_lds = !use_zm && !(ev && *ev == '0') && lds_bytes <= 64 * 1024;
+  const int nzm = nrhs * dm[3] * (dm[2] / zc);
   HIPCHK(c, hipEventRecord(e0, E.st));
   for (int r = 0; r < reps; ++r) {
-    if (use_lds) {
+    if (use_zm) {
+      if (prec)
+        zc == 4 ? k_hw_zm<float, 4><<<nzm, 256, 0, E.st>>>(E.tables, diag)
+                : k_hw_zm<float, 2><<<nzm, 256, 0, E.st>>>(E.tables, diag);
+      else
+        zc == 4 ? k_hw_zm<double, 4><<<nzm, 256, 0, E.st>>>(E.tables, diag)
+                : k_hw_zm<double, 2><<<nzm, 256, 0, E.st>>>(E.tables, diag);
+    } else if (use_lds) {
       if (prec)
         k_hw_lds<float><<<E.nb_total, c->block, lds_bytes, E.st>>>(E.tables, E.bmap, E.nb_total, diag);
       else

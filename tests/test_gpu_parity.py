@@ -95,6 +95,21 @@ def test_hw_fp32_stencil_vs_oracle(orc, dims):
         assert rel(out64[r], o.hw(x[r])) < 1e-14
 
 
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (12, 12, 12, 12), (24, 24, 24, 48)])
+def test_stencil_bench_kernels_full_size(orc, dims):
+    """The stencil benchmark's kernels (z-marching form where the xy plane fits a
+    workgroup, LDS-staged block form otherwise) at the workloads' full sizes."""
+    x = inputs.gaussian_field(dims, nrhs=2, seed=4)
+    o = orc.Oracle(dims)
+    lat = lattice(dims)
+    for prec, tol in ((1, 2e-6), (0, 1e-14)):
+        xp = lat.pack(dev(x), prec)
+        outp, _ = lat.stencil_bench(xp, prec, reps=1)
+        out = host(lat.unpack(outp, prec))
+        for r in range(2):
+            assert rel(out[r], o.hw(x[r])) < tol
+
+
 # -------------------------------------------------------------- sign / apply
 
 @pytest.mark.parametrize("dims,cfg", [((4, 4, 4, 4), CFG1), ((8, 8, 8, 8), CFG2),
