@@ -89,7 +89,7 @@ struct MsParams {
   double diag;          // 4 - M0
   double sigma[MAXP];   // shifts b_k
   double coef[MAXP];    // residues a_k
-  int stage;            // 1: stencil input staged in LDS (dynamic, 4 * spb values)
+  int zm;               // > 0: z-marching passes over zm planes per workgroup (zm_march)
 };
 
 __device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys, int L) {
@@ -324,6 +324,65 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
   }
 }
 
+// H_W of f on the sites of a workgroup that owns zc consecutive z planes of one
+// time slice (X Y == blockDim.x; the block's sites i0 .. i0 + zc X Y - 1), in the
+// z-marching order of k_hw_zm: plane z below and above in registers, the
+// current plane in LDS (sh: 4 X Y values) for the x and y neighbours.  For each
+// site, epi(i, w) receives w = (H_W f)_i and returns a partial sum; the total
+// is returned.  Every thread of the block must call it.
+template <class R, class Epi>
+__device__ __forceinline__ double zm_march(const c2<R>* __restrict__ f, const Geo& g, int i0,
+                                           int zc, R diag, c2<R>* sh, Epi epi) {
+  const int X = g.X, Y = g.Y, Z = g.Z, T = g.T, V = g.V;
+  const int XY = X * Y, XYZ = XY * Z;
+  const int j = threadIdx.x;
+  const int x = j % X, y = j / X;
+  const int p0 = i0 / XY;  // z0 + Z t
+  const int t = p0 / Z, z0 = p0 - Z * t;
+  const int tf_off = (t + 1 < T) ? XYZ : XYZ - V;
+  const int tb_off = (t > 0) ? -XYZ : V - XYZ;
+  const int jxf = y * X + ((x + 1 < X) ? x + 1 : 0);
+  const int jxb = y * X + ((x > 0) ? x - 1 : X - 1);
+  const int jyf = ((y + 1 < Y) ? y + 1 : 0) * X + x;
+  const int jyb = ((y > 0) ? y - 1 : Y - 1) * X + x;
+  const int base = j + XYZ * t;
+  Nbr<R> nb;
+  c2<R> prev[4], cur[4], next[4];
+  load_sp<R>(f, V, base + XY * (z0 > 0 ? z0 - 1 : Z - 1), prev);
+  load_sp<R>(f, V, base + XY * z0, cur);
+  double acc = 0.0;
+  for (int k = 0; k < zc; ++k) {
+    const int z = z0 + k;
+    const int i = base + XY * z;
+    load_sp<R>(f, V, base + XY * (z + 1 < Z ? z + 1 : 0), next);
+    load_sp<R>(f, V, i + tf_off, nb.tf);
+    load_sp<R>(f, V, i + tb_off, nb.tb);
+    __syncthreads();  // reads of the previous plane are done
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[q * XY + j] = cur[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      nb.c[q] = cur[q];
+      nb.xf[q] = sh[q * XY + jxf];
+      nb.xb[q] = sh[q * XY + jxb];
+      nb.yf[q] = sh[q * XY + jyf];
+      nb.yb[q] = sh[q * XY + jyb];
+      nb.zf[q] = next[q];
+      nb.zb[q] = prev[q];
+    }
+    c2<R> w[4];
+    hw_compute<R>(nb, g, i, diag, w);
+    acc += epi(i, w);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      prev[q] = cur[q];
+      cur[q] = next[q];
+    }
+  }
+  return acc;
+}
+
 // ------------------------------------------------------- multi-shift: t pass
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
 // advances the shift recurrences, decides convergence, then
@@ -370,15 +429,12 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   const int i0 = lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
   int i = i0 + threadIdx.x;
-  const bool have = i < i1;
+  const bool zm = mp->zm > 0;
+  const bool have = !zm && i < i1;  // z-marching loads inside its own loop
   Nbr<R> nb;
   c2<R> q[4];
-  if (sh) stage_block<R>(rin, g.V, S.spb, i0, i1, sh);
   if (have) {
-    if (sh)
-      load_nbr_staged<R>(rin, g, i, sh, S.spb, i0, i1, nb);
-    else
-      load_nbr<R>(rin, g, i, nb);
+    load_nbr<R>(rin, g, i, nb);
     if (n > 0) load_sp<R>(tp, g.V, i, q);
   }
   if (!act_sys || done) return;
@@ -423,6 +479,20 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   const R beta = (R)((n > 0) ? rho / rho_m1 : 0.0);
 
   double acc = 0.0;
+  if (zm) {
+    acc = zm_march<R>(rin, g, i0, mp->zm, (R)mp->diag, sh, [&](int ii, c2<R>* o) -> double {
+      if (n > 0) {
+        c2<R> qq[4];
+        load_sp<R>(tp, g.V, ii, qq);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+          o[k2] = c2<R>{o[k2].x + beta * qq[k2].x, o[k2].y + beta * qq[k2].y};
+      }
+      store_sp<R>(tn, g.V, ii, o);
+      return norm2_sp(o);
+    });
+    i = i1;  // every site done
+  }
   if (have) {
     c2<R> o[4];
     hw_compute<R>(nb, g, i, (R)mp->diag, o);
@@ -436,13 +506,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   // remaining sites of this block (sites per thread > 1)
   for (i += blockDim.x; i < i1; i += blockDim.x) {
     c2<R> o[4];
-    if (sh) {
-      Nbr<R> nb2;
-      load_nbr_staged<R>(rin, g, i, sh, S.spb, i0, i1, nb2);
-      hw_compute<R>(nb2, g, i, (R)mp->diag, o);
-    } else {
-      hw_site<R>(rin, g, i, (R)mp->diag, o);
-    }
+    hw_site<R>(rin, g, i, (R)mp->diag, o);
     if (n > 0) {
       load_sp<R>(tp, g.V, i, q);
 #pragma unroll
@@ -473,15 +537,12 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   const int i0 = lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
   int i = i0 + threadIdx.x;
-  const bool have = i < i1;
+  const bool zm = mp->zm > 0;
+  const bool have = !zm && i < i1;
   Nbr<R> nb;
   c2<R> r[4];
-  if (sh) stage_block<R>(tn, g.V, S.spb, i0, i1, sh);
   if (have) {
-    if (sh)
-      load_nbr_staged<R>(tn, g, i, sh, S.spb, i0, i1, nb);
-    else
-      load_nbr<R>(tn, g, i, nb);
+    load_nbr<R>(tn, g, i, nb);
     load_sp<R>(rin, g.V, i, r);
   }
   if (!act_sys || done) return;
@@ -499,6 +560,17 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   if (stop) return;
   const R alpha = (R)alpha_d;
   double acc = 0.0;
+  if (zm) {
+    acc = zm_march<R>(tn, g, i0, mp->zm, (R)mp->diag, sh, [&](int ii, c2<R>* w) -> double {
+      c2<R> rr[4];
+      load_sp<R>(rin, g.V, ii, rr);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rr[k] = c2<R>{rr[k].x - alpha * w[k].x, rr[k].y - alpha * w[k].y};
+      store_sp<R>(rout, g.V, ii, rr);
+      return norm2_sp(rr);
+    });
+    i = i1;
+  }
   if (have) {
     c2<R> w[4];
     hw_compute<R>(nb, g, i, (R)mp->diag, w);
@@ -509,13 +581,7 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   }
   for (i += blockDim.x; i < i1; i += blockDim.x) {
     c2<R> w[4];
-    if (sh) {
-      Nbr<R> nb2;
-      load_nbr_staged<R>(tn, g, i, sh, S.spb, i0, i1, nb2);
-      hw_compute<R>(nb2, g, i, (R)mp->diag, w);
-    } else {
-      hw_site<R>(tn, g, i, (R)mp->diag, w);
-    }
+    hw_site<R>(tn, g, i, (R)mp->diag, w);
     load_sp<R>(rin, g.V, i, r);
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[k] = c2<R>{r[k].x - alpha * w[k].x, r[k].y - alpha * w[k].y};
@@ -542,7 +608,7 @@ __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  ms_t_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.stage ? (c2<R>*)dyn_lds : nullptr);
+  ms_t_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.zm ? (c2<R>*)dyn_lds : nullptr);
 }
 
 // Iteration n, r pass:
@@ -555,7 +621,7 @@ __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  ms_r_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.stage ? (c2<R>*)dyn_lds : nullptr);
+  ms_r_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.zm ? (c2<R>*)dyn_lds : nullptr);
 }
 
 // ------------------------------------------------ multi-shift: persistent form

@@ -90,12 +90,12 @@ bool ov_log() {
   return v == 1;
 }
 
-// LDS staging of the multi-shift stencil input (OV_MS_LDS=1 enables it).
-bool ms_lds_enabled() {
+// z-marching multi-shift passes (OV_MS_ZM=0 switches them off).
+bool ms_zm_enabled() {
   static int v = -1;
   if (v < 0) {
-    const char* e = std::getenv("OV_MS_LDS");
-    v = (e && *e == '1') ? 1 : 0;
+    const char* e = std::getenv("OV_MS_ZM");
+    v = (e && *e == '0') ? 0 : 1;
   }
   return v == 1;
 }
@@ -156,11 +156,17 @@ struct SysBuf {
   int xc = 1, off_xy = 0, off_z = 0, off_t = 0;  // momentum-space pass geometry
 };
 
-int sites_per_block(const ov_ctx* c, int V) {
+// Sites per workgroup.  Automatic choice (spt = 0) from the sites of the whole
+// launch: one site per thread while the launch is small enough for every
+// workgroup to start at once (latency-bound single systems), more when many
+// systems share the launch (bandwidth-bound batches: fewer, longer workgroups
+// and, where the xy plane is one workgroup, z-marching passes).
+int sites_per_block(const ov_ctx* c, int V, long long total_sites) {
   int spt = c->spt;
   if (spt <= 0) {
-    const int blocks1 = (V + c->block - 1) / c->block;
-    spt = std::max(1, (blocks1 + 2047) / 2048);
+    const long long blocks1 = (std::max<long long>(total_sites, V) + c->block - 1) / c->block;
+    spt = blocks1 <= 1024 ? 1 : (blocks1 <= 4096 ? 2 : 4);
+    spt = std::max(spt, (int)(((V + c->block - 1) / c->block + 2047) / 2048));
   }
   return c->block * spt;
 }
@@ -302,12 +308,17 @@ struct Engine {
     stat_all = (long long*)bp.take(sizeof(long long) * 4 * nsys);
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0, nxy = 0, nz = 0, nt = 0;
+    long long total_sites = 0;
+    for (int s = 0; s < nsys; ++s) {
+      const ov_params& p = ctxs[s]->p;
+      total_sites += (long long)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+    }
     for (int s = 0; s < nsys; ++s) {
       SysBuf& b = sb[s];
       b.ctx = ctxs[s];
       const ov_params& p = ctxs[s]->p;
       b.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
-      b.spb = sites_per_block(ctxs[s], b.V);
+      b.spb = sites_per_block(ctxs[s], b.V, total_sites);
       b.nblk = (b.V + b.spb - 1) / b.spb;
       b.blk0 = blk;
       blk += b.nblk;
@@ -574,16 +585,24 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
     (void)hipGetLastError();
     c->persistent = 0;  // cooperative launch refused: per-pass kernels from now on
   }
-  // stage the stencil input of each workgroup in LDS (x/y neighbours) when the
-  // largest block fits and staging is not disabled (OV_MS_LDS=0)
+  // z-marching passes when every system's workgroup owns whole xy planes of one
+  // time slice (X Y == threads per workgroup, sites per thread zc >= 2 dividing Z);
+  // OV_MS_ZM=0 switches them off
   MsParams mps = mp;
   size_t shb = 0;
   {
-    int spb = 0;
-    for (const auto& b : E.sb) spb = std::max(spb, b.spb);
-    shb = (size_t)4 * spb * sizeof(c2<R>);
-    mps.stage = (ms_lds_enabled() && shb <= 64 * 1024) ? 1 : 0;
-    if (!mps.stage) shb = 0;
+    int zc = 0;
+    bool ok = ms_zm_enabled();
+    for (const auto& b : E.sb) {
+      const ov_params& p = b.ctx->p;
+      const int XY = p.dims[0] * p.dims[1];
+      const int k = b.spb / c->block;
+      ok &= XY == c->block && b.spb == k * c->block && k >= 2 && p.dims[2] % k == 0 &&
+            (zc == 0 || zc == k);
+      zc = k;
+    }
+    mps.zm = ok ? zc : 0;
+    shb = ok ? (size_t)4 * c->block * sizeof(c2<R>) : 0;
   }
   for (int n = 0; n < L; ++n) {
     {
@@ -2505,7 +2524,7 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
       SysBuf& b = E.sb[s];
       b.ctx = c;
       b.V = c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3];
-      b.spb = sites_per_block(c, b.V);
+      b.spb = sites_per_block(c, b.V, (long long)b.V * nrhs);
       b.nblk = (b.V + b.spb - 1) / b.spb;
       b.blk0 = blk;
       blk += b.nblk;
@@ -2550,9 +2569,11 @@ ov_status ov_stencil_bench(ov_ctx* c, int prec, void* out, const void* in, int n
   const char* ev = std::getenv("OV_HW_LDS");
   const int* dm = c->p.dims;
   const int zc = (dm[2] % 4 == 0) ? 4 : (dm[2] % 2 == 0 ? 2 : 1);
-  const bool use_zm = !(ev && (*ev == '0' || *ev == '1')) && dm[0] * dm[1] <= 256 && zc >= 2;
-  const bool use_lds = !use_zm && !(ev && *ev == '0') && lds_bytes <= 64 * 1024;
   const int nzm = nrhs * dm[3] * (dm[2] / zc);
+  // z-marching needs enough workgroups (one per xy plane and z chunk) to fill the chip
+  const bool use_zm = !(ev && (*ev == '0' || *ev == '1')) && dm[0] * dm[1] <= 256 && zc >= 2 &&
+                      nzm >= 512;
+  const bool use_lds = !use_zm && !(ev && *ev == '0') && lds_bytes <= 64 * 1024;
   HIPCHK(c, hipEventRecord(e0, E.st));
   for (int r = 0; r < reps; ++r) {
     if (use_zm) {

@@ -110,6 +110,27 @@ def test_stencil_bench_kernels_full_size(orc, dims):
             assert rel(out[r], o.hw(x[r])) < tol
 
 
+@pytest.mark.parametrize("spt", [2, 4])
+def test_zmarch_multishift_passes(orc, spt):
+    """Multi-shift passes in the z-marching form (a workgroup of X Y = 256 threads
+    owning spt z planes of a time slice): sign and a mixed solve against the oracle."""
+    dims = (16, 16, 8, 4)
+    print(f"[zm] spt={spt}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2))
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    lat = lattice(dims, inner_tol=1e-12, outer_tol=1e-10, **CFG2)
+    lat.set_launch(256, spt)
+    out, _ = lat.sign(dev(src))
+    out = host(out)
+    for r in range(2):
+        ref, _ = o.sign(src[r])
+        assert rel(out[r], ref) < 1e-11
+    x, st = lat.solve(dev(src), dev(phi))
+    x = host(x)
+    for r in range(2):
+        assert o.residual(src[r], x[r], phi) <= 1e-10
+
+
 # -------------------------------------------------------------- sign / apply
 
 @pytest.mark.parametrize("dims,cfg", [((4, 4, 4, 4), CFG1), ((8, 8, 8, 8), CFG2),
