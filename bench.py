@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip FP64, stencil and other configs")
     ap.add_argument("--no-sample", action="store_true", help="skip the event-sampled solve")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shape (256 threads, 1 site per thread at 16^4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 512 MiB device copy (reference for traffic counters)")
     args = ap.parse_args()
@@ -279,7 +281,10 @@ def main():
     lat = Lattice(DIMS, precision="mixed", **CFG)
     lat.use_workspace(1)
     from paper_1005_3276_amd import tune
-    choice, tune_us = tune.autotune(lat, prec=1, nrhs=1)
+    if args.no_tune:
+        choice, tune_us = None, None
+    else:
+        choice, tune_us = tune.autotune(lat, prec=1, nrhs=1)
     log(f"autotune: {choice} {tune_us}")
 
     # ---- mixed solves (the metric)

@@ -118,6 +118,10 @@ typedef struct {
   int dirac;               /* ov_dirac: form of D in M (default OV_DIRAC_OVERLAP_MS); the
                               momentum-space forms have the limits of OV_OP_M0INV and
                               need no inner solve (inner tolerances are unused) */
+  double truth_relax;      /* intermediate true residuals (reliable updates before the
+                              final check) use the multi-shift tolerance
+                              max(truth_tol, min(1e-6, truth_relax * recursive residual));
+                              default 0.01 */
 } ov_params;
 
 typedef struct {

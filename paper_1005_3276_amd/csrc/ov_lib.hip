@@ -1413,7 +1413,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       // smallest residual: its operator error must stay ~1% of that residual.
       const double ttol = final_check
                               ? P.truth_tol
-                              : std::max(P.truth_tol, std::min(1e-6, 0.01 * best_rec));
+                              : std::max(P.truth_tol, std::min(1e-6, P.truth_relax * best_rec));
       TRY(reliable_update<R>(E, ttol, restart ? 7 : 3));
       TRY(read_scalars(E));
       for (int s = 0; s < ns; ++s) {
@@ -1482,6 +1482,10 @@ ov_status validate(const ov_params* p, std::string& err) {
   }
   if (p->precision != OV_FP64 && p->precision != OV_MIXED) {
     err = "precision must be OV_FP64 or OV_MIXED";
+    return OV_ERR_INVALID_ARG;
+  }
+  if (!(p->truth_relax > 0) || p->truth_relax > 1) {
+    err = "need 0 < truth_relax <= 1";
     return OV_ERR_INVALID_ARG;
   }
   if (p->precondition != 0 && p->precondition != 1) {
@@ -1621,9 +1625,10 @@ void ov_params_default(ov_params* p) {
   p->max_inner = 400;
   p->max_outer = 2000;
   p->precision = OV_MIXED;
-  p->inner_relax = 1e-3;
+  p->inner_relax = 3e-3;
   p->inner_tol_max = 1e-2;
   p->precondition = 1;
+  p->truth_relax = 0.01;
 }
 
 const char* ov_status_string(ov_status s) {
@@ -1844,7 +1849,7 @@ static bool same_solver(const ov_params& a, const ov_params& b) {
          a.mixed_inner_tol == b.mixed_inner_tol && a.reliable_delta == b.reliable_delta &&
          a.precision == b.precision && a.M0 == b.M0 && a.inner_relax == b.inner_relax &&
          a.inner_tol_max == b.inner_tol_max && a.precondition == b.precondition &&
-         a.dirac == b.dirac;
+         a.dirac == b.dirac && a.truth_relax == b.truth_relax;
 }
 
 static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,
