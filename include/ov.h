@@ -276,16 +276,24 @@ ov_status ov_tune_ms(ov_ctx *ctx, int prec, int nrhs, int block, int sites_per_t
 
 /* Kernel-duration sampling with HIP events recorded on the context's stream.
  * While max_per_call > 0, the first max_per_call launches of each multi-shift
- * kernel (0 = t pass  t_n = H r_n + beta t_{n-1},  1 = r pass  r_{n+1} = r_n -
- * alpha H t_n, 2 = the persistent kernel running every iteration of one
- * multi-shift solve) in every sign/apply/solve/force call are bracketed by
- * events.  ov_kernel_times returns, per kernel, the summed duration (ms), the
- * number of sampled launches and their summed algorithmic HBM bytes (3 spinor
- * fields per site and pass: two read, one written; two passes per iteration).
- * reset != 0 clears the sums. */
+ * kernel (0 = FP32 t pass  t_n = H r_n + beta t_{n-1},  1 = FP32 r pass
+ * r_{n+1} = r_n - alpha H t_n, 2 = the persistent kernel running every iteration
+ * of one multi-shift solve, 3 / 4 = the FP64 t / r passes) in every
+ * sign/apply/solve/force call are bracketed by
+ * events; the sampled per-pass launches (kernels 0 and 1) also record, in every
+ * workgroup, device wall-clock stamps at its start and after its last wave.
+ * ov_kernel_times returns, per kernel, the summed event duration (ms: from the
+ * completion of the preceding work to the kernel's completion, so it includes
+ * the dispatch gap), the number of sampled launches, their summed algorithmic
+ * HBM bytes (3 spinor fields per site and pass: two read, one written; two
+ * passes per iteration), and the summed kernel-only span max(end) - min(start)
+ * over the workgroups (ms; what a kernel trace reports) with its launch count.
+ * Any output pointer may be NULL.  reset != 0 clears the sums.  The stamp buffer
+ * (2 x 8 bytes per workgroup and sampled launch) is allocated with hipMalloc
+ * when sampling first needs it and freed by ov_ctx_destroy. */
 ov_status ov_kernel_sampling(ov_ctx *ctx, int max_per_call);
 ov_status ov_kernel_times(ov_ctx *ctx, int kernel, double *total_ms, long long *count,
-                          double *bytes, int reset);
+                          double *bytes, double *kernel_ms, long long *kernel_count, int reset);
 
 const char *ov_status_string(ov_status s);
 const char *ov_last_error(const ov_ctx *ctx);

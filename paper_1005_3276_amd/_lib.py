@@ -92,7 +92,7 @@ def lib():
         L.ov_get_launch.argtypes = [P, P, P]
         L.ov_tune_ms.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]
         L.ov_kernel_sampling.argtypes = [P, C.c_int]
-        L.ov_kernel_times.argtypes = [P, C.c_int, P, P, P, C.c_int]
+        L.ov_kernel_times.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int]
         L.ov_locality.argtypes = [P, C.c_int, P, C.c_int, P]
         L.ov_rational.argtypes = [P, C.c_double, C.c_int, P, P, P, P, P, C.c_int, P]
         L.ov_rational_force.argtypes = [P, C.c_double, C.c_int, P, P, P, P, P, P, C.c_int, P]

@@ -90,6 +90,7 @@ struct MsParams {
   double sigma[MAXP];   // shifts b_k
   double coef[MAXP];    // residues a_k
   int zm;               // > 0: z-marching passes over zm planes per workgroup (zm_march)
+  unsigned long long* tstamp;  // non-null: per workgroup (start, end) wall-clock stamps
 };
 
 __device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys, int L) {
@@ -592,6 +593,17 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   if (threadIdx.x == 0) S.part_b[lb] = tot;
 }
 
+// Kernel-duration sampling: once every wave of the workgroup is done, thread 0
+// stores the workgroup's start and end wall-clock stamps (vector stores); the
+// host takes max(end) - min(start) over the workgroups of the launch.
+__device__ __forceinline__ void stamp_block(unsigned long long* ts, unsigned long long t0) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ts[2 * blockIdx.x] = t0;
+    ts[2 * blockIdx.x + 1] = wall_clock64();
+  }
+}
+
 // Iteration n, t pass: finishes rho_n = |r_n|^2 from the previous kernel's
 // partials, advances the shift recurrences, decides convergence, then
 //   t_n = H r_n + beta_{n-1} t_{n-1}  -> basis slot n,  partial |t_n|^2.
@@ -606,9 +618,12 @@ __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
                                               const MsParams mp_) {
   __shared__ double lds[17];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
+  unsigned long long t0 = 0;
+  if (mp_.tstamp && threadIdx.x == 0) t0 = wall_clock64();
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
   ms_t_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.zm ? (c2<R>*)dyn_lds : nullptr);
+  if (mp_.tstamp) stamp_block(mp_.tstamp, t0);
 }
 
 // Iteration n, r pass:
@@ -619,9 +634,12 @@ __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
                                               const MsParams mp_) {
   __shared__ double lds[17];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
+  unsigned long long t0 = 0;
+  if (mp_.tstamp && threadIdx.x == 0) t0 = wall_clock64();
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
   ms_r_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.zm ? (c2<R>*)dyn_lds : nullptr);
+  if (mp_.tstamp) stamp_block(mp_.tstamp, t0);
 }
 
 // ------------------------------------------------ multi-shift: persistent form

@@ -55,11 +55,17 @@ struct ov_ctx {
     int kernel;
     double bytes;          // bytes of the launch, or bytes per iteration when n_dev is set
     const int* n_dev;      // device iteration count of a persistent launch
+    int ts_blocks;         // workgroups that stamped region ts_index (0: none)
   };
   std::vector<EvUse> ev_use;
-  int ev_call_count[3] = {0, 0, 0};
-  double ksum_ms[3] = {0, 0, 0}, ksum_bytes[3] = {0, 0, 0};
-  long long kcount[3] = {0, 0, 0};
+  // kernels: 0 / 1 FP32 t / r pass, 2 persistent, 3 / 4 FP64 t / r pass
+  int ev_call_count[5] = {0, 0, 0, 0, 0};
+  double ksum_ms[5] = {0, 0, 0, 0, 0}, ksum_bytes[5] = {0, 0, 0, 0, 0};
+  double ksum_kernel_ms[5] = {0, 0, 0, 0, 0};  // device-stamped kernel spans
+  long long kcount[5] = {0, 0, 0, 0, 0}, kcount_kernel[5] = {0, 0, 0, 0, 0};
+  unsigned long long* ts_dev = nullptr;  // stamp regions, ts_region u64 each
+  size_t ts_regions = 0, ts_region = 0;
+  double wall_khz = 0;                   // wall-clock rate of the stamps
 };
 
 namespace {
@@ -406,7 +412,7 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   E.sb.assign(E.nsys, SysBuf{});
   E.lead = ctxs[0];
   E.st = E.lead->priv;
-  E.lead->ev_call_count[0] = E.lead->ev_call_count[1] = E.lead->ev_call_count[2] = 0;
+  for (int& k : E.lead->ev_call_count) k = 0;
   HIPCHK(E.lead, hipEventRecord(E.lead->ev_in, E.lead->stream));
   HIPCHK(E.lead, hipStreamWaitEvent(E.st, E.lead->ev_in, 0));
   E.pl.solve = solve;
@@ -502,7 +508,7 @@ struct Sample {
       c->ev_pool.push_back(a);
       c->ev_pool.push_back(b);
     }
-    c->ev_use.push_back({k, bytes, n_dev});
+    c->ev_use.push_back({k, bytes, n_dev, 0});
     c->ev_call_count[k]++;
     on = hipEventRecord(c->ev_pool[2 * idx], c->priv) == hipSuccess;
   }
@@ -527,9 +533,25 @@ void collect_samples(ov_ctx* c) {
       c->ksum_bytes[u.kernel] += bytes;
       c->kcount[u.kernel]++;
     }
+    const auto& u = c->ev_use[i];
+    if (u.ts_blocks > 0 && c->ts_dev && c->wall_khz > 0 && i < c->ts_regions) {
+      std::vector<unsigned long long> h(2 * (size_t)u.ts_blocks);
+      if (hipMemcpy(h.data(), c->ts_dev + i * c->ts_region, sizeof(unsigned long long) * h.size(),
+                    hipMemcpyDeviceToHost) == hipSuccess) {
+        unsigned long long lo = ~0ull, hi = 0;
+        for (int b = 0; b < u.ts_blocks; ++b) {
+          lo = std::min(lo, h[2 * b]);
+          hi = std::max(hi, h[2 * b + 1]);
+        }
+        if (hi > lo) {
+          c->ksum_kernel_ms[u.kernel] += (double)(hi - lo) / c->wall_khz;
+          c->kcount_kernel[u.kernel]++;
+        }
+      }
+    }
   }
   c->ev_use.clear();
-  c->ev_call_count[0] = c->ev_call_count[1] = c->ev_call_count[2] = 0;
+  for (int& k : c->ev_call_count) k = 0;
 }
 
 // Co-resident workgroups of k_ms_persistent<R> on this device (0: no cooperative launch).
@@ -604,14 +626,43 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
     mps.zm = ok ? zc : 0;
     shb = ok ? (size_t)4 * c->block * sizeof(c2<R>) : 0;
   }
+  if (c->sample_max > 0) {  // stamp regions for the sampled launches of this call
+    const size_t region = 2 * (size_t)E.nb_total;
+    const size_t regions = 4 * (size_t)c->sample_max + 2;
+    if (c->ts_region < region || c->ts_regions < regions) {
+      if (c->ts_dev) (void)hipFree(c->ts_dev);  // synchronises the device
+      c->ts_dev = nullptr;
+      c->ts_region = std::max(region, c->ts_region);
+      c->ts_regions = std::max(regions, c->ts_regions);
+      if (hipMalloc((void**)&c->ts_dev, sizeof(unsigned long long) * c->ts_region * c->ts_regions) !=
+          hipSuccess) {
+        c->ts_dev = nullptr;
+        c->ts_region = c->ts_regions = 0;
+      }
+    }
+    if (c->wall_khz <= 0) {
+      int khz = 0;
+      if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess)
+        c->wall_khz = khz;
+    }
+  }
+  auto stamped = [&](Sample& smp) -> MsParams {
+    MsParams m = mps;
+    const size_t idx = c->ev_use.size() - 1;
+    if (smp.on && c->ts_dev && idx < c->ts_regions) {
+      m.tstamp = c->ts_dev + idx * c->ts_region;
+      c->ev_use[idx].ts_blocks = E.nb_total;
+    }
+    return m;
+  };
   for (int n = 0; n < L; ++n) {
     {
-      Sample smp(c, 0, bytes);
-      k_ms_t<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, mps);
+      Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);
+      k_ms_t<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, stamped(smp));
     }
     {
-      Sample smp(c, 1, bytes);
-      k_ms_r<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, mps);
+      Sample smp(c, sizeof(R) == sizeof(double) ? 4 : 1, bytes);
+      k_ms_r<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, stamped(smp));
     }
   }
   k_ms_coef<<<E.nsys, 256, 0, E.st>>>(T, E.nsys, L, mp);
@@ -1712,6 +1763,7 @@ ov_status ov_ctx_destroy(ov_ctx* c) {
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->priv) (void)hipStreamDestroy(c->priv);
   if (c->own_ws) (void)hipFree(c->own_ws);
+  if (c->ts_dev) (void)hipFree(c->ts_dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   delete c;
@@ -2491,15 +2543,19 @@ ov_status ov_kernel_sampling(ov_ctx* c, int max_per_call) {
 }
 
 ov_status ov_kernel_times(ov_ctx* c, int k, double* total_ms, long long* count, double* bytes,
-                          int reset) {
-  if (!c || k < 0 || k > 2) return OV_ERR_INVALID_ARG;
+                          double* kernel_ms, long long* kernel_count, int reset) {
+  if (!c || k < 0 || k > 4) return OV_ERR_INVALID_ARG;
   if (total_ms) *total_ms = c->ksum_ms[k];
   if (count) *count = c->kcount[k];
   if (bytes) *bytes = c->ksum_bytes[k];
+  if (kernel_ms) *kernel_ms = c->ksum_kernel_ms[k];
+  if (kernel_count) *kernel_count = c->kcount_kernel[k];
   if (reset) {
     c->ksum_ms[k] = 0;
     c->ksum_bytes[k] = 0;
     c->kcount[k] = 0;
+    c->ksum_kernel_ms[k] = 0;
+    c->kcount_kernel[k] = 0;
   }
   return OV_OK;
 }

@@ -87,13 +87,23 @@ class Lattice:
         self._check(L.lib().ov_kernel_sampling(self._h, max_per_call))
 
     def kernel_times(self, kernel, reset=True):
-        """(total_ms, count, bytes) of the sampled multi-shift kernel (0 t pass, 1 r pass)."""
-        ms = C.c_double()
-        cnt = C.c_longlong()
-        by = C.c_double()
+        """(event_ms, count, bytes) of the sampled multi-shift kernel (0 t pass, 1 r pass,
+        2 persistent); see kernel_spans for the device-stamped kernel-only spans."""
+        return self._kernel_times(kernel, reset)[:3]
+
+    def kernel_spans(self, kernel, reset=True):
+        """(kernel_ms, count, event_ms, event_count, bytes): device-stamped spans and
+        the event durations of the same sampled launches."""
+        ms, cnt, by, kms, kcnt = self._kernel_times(kernel, reset)
+        return kms, kcnt, ms, cnt, by
+
+    def _kernel_times(self, kernel, reset):
+        ms, by, kms = C.c_double(), C.c_double(), C.c_double()
+        cnt, kcnt = C.c_longlong(), C.c_longlong()
         self._check(L.lib().ov_kernel_times(self._h, kernel, C.byref(ms), C.byref(cnt),
-                                            C.byref(by), 1 if reset else 0))
-        return ms.value, cnt.value, by.value
+                                            C.byref(by), C.byref(kms), C.byref(kcnt),
+                                            1 if reset else 0))
+        return ms.value, cnt.value, by.value, kms.value, kcnt.value
 
     def set_launch(self, block=0, sites_per_thread=0):
         self._check(L.lib().ov_set_launch(self._h, block, sites_per_thread))
