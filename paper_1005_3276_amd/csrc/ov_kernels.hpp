@@ -281,20 +281,26 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
   const int jyf = ((y + 1 < Y) ? y + 1 : 0) * X + x;
   const int jyb = ((y > 0) ? y - 1 : Y - 1) * X + x;
   auto site = [&](int z) { return j + XY * (z + Z * t); };
-  Nbr<R> nb;
-  c2<R> prev[4], cur[4], next[4];
+  auto zwrap = [&](int z) { return z < 0 ? z + Z : (z >= Z ? z - Z : z); };
+  // software pipeline: the plane above and the time neighbours of the next plane
+  // are loaded one step ahead
+  c2<R> prev[4], cur[4], next[4], tf[4], tb[4];
   if (on) {
-    load_sp<R>(in, V, site(z0 > 0 ? z0 - 1 : Z - 1), prev);
+    load_sp<R>(in, V, site(zwrap(z0 - 1)), prev);
     load_sp<R>(in, V, site(z0), cur);
+    load_sp<R>(in, V, site(zwrap(z0 + 1)), next);
+    load_sp<R>(in, V, site(z0) + tf_off, tf);
+    load_sp<R>(in, V, site(z0) + tb_off, tb);
   }
 #pragma unroll
   for (int zi = 0; zi < ZC; ++zi) {
     const int z = z0 + zi;
     const int i = site(z);
-    if (on) {
-      load_sp<R>(in, V, site(z + 1 < Z ? z + 1 : 0), next);
-      load_sp<R>(in, V, i + tf_off, nb.tf);
-      load_sp<R>(in, V, i + tb_off, nb.tb);
+    c2<R> next2[4], tf2[4], tb2[4];
+    if (on && zi + 1 < ZC) {
+      load_sp<R>(in, V, site(zwrap(z + 2)), next2);
+      load_sp<R>(in, V, site(z + 1) + tf_off, tf2);
+      load_sp<R>(in, V, site(z + 1) + tb_off, tb2);
     }
     __syncthreads();  // the previous plane's LDS reads are done
     if (on) {
@@ -303,6 +309,7 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
     }
     __syncthreads();
     if (on) {
+      Nbr<R> nb;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         nb.c[q] = cur[q];
@@ -312,6 +319,8 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
         nb.yb[q] = sh[q * 256 + jyb];
         nb.zf[q] = next[q];
         nb.zb[q] = prev[q];
+        nb.tf[q] = tf[q];
+        nb.tb[q] = tb[q];
       }
       c2<R> o[4];
       hw_compute<R>(nb, g, i, (R)diag, o);
@@ -320,6 +329,9 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
       for (int q = 0; q < 4; ++q) {
         prev[q] = cur[q];
         cur[q] = next[q];
+        next[q] = next2[q];
+        tf[q] = tf2[q];
+        tb[q] = tb2[q];
       }
     }
   }
