@@ -106,8 +106,16 @@ def cpu_baseline(phi, src, outer_iters):
             break
     el = time.perf_counter() - t
     per = el / napp
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": 1.0 / (per * outer_iters), "unit": "solves/s", "cores": O.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": model,
             "sample": f"{napp} MdagM applications (FP64 oracle, multi-shift tol 1e-12) at 16^4, "
                       f"{per:.2f} s each, scaled by {outer_iters} outer CG iterations"}
 
