@@ -143,6 +143,21 @@ def other_configs(torch, Lattice, inputs):
         "outer_iters": [s["outer_iters"] for s in st]}
     log(f"config3: {out['config3_batched_16x3x32_12rhs']}")
     del lat
+    # the same batch with the FP64 solver (the mixed solver's algorithm in FP64)
+    lat = Lattice(dims, precision="fp64", m=0.02, g=0.5, n_poles=20, lambda_min=1e-3,
+                  lambda_max=8.0, outer_tol=1e-10, inner_tol=1e-8)
+    lat.solve(b, p)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st = lat.solve(b, p)
+    torch.cuda.synchronize()
+    e64 = time.perf_counter() - t
+    out["config3_batched_16x3x32_12rhs_fp64"] = {
+        "seconds": e64, "rhs_solves_per_s": 12 / e64,
+        "max_true_rel_res": max(s["true_rel_res"] for s in st),
+        "mixed_speedup": e64 / e}
+    log(f"config3 fp64: {out['config3_batched_16x3x32_12rhs_fp64']}")
+    del lat
     # config 4
     dims = (12, 12, 12, 12)
     phi, xi = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(4))
