@@ -40,7 +40,8 @@ class OvParams(C.Structure):
                 ("reliable_delta", C.c_double), ("max_inner", C.c_int),
                 ("max_outer", C.c_int), ("precision", C.c_int),
                 ("inner_relax", C.c_double), ("inner_tol_max", C.c_double),
-                ("precondition", C.c_int), ("dirac", C.c_int), ("truth_relax", C.c_double)]
+                ("precondition", C.c_int), ("dirac", C.c_int), ("truth_relax", C.c_double),
+                ("inner_form", C.c_int)]
 
 
 class OvStats(C.Structure):

@@ -1552,6 +1552,143 @@ __global__ void __launch_bounds__(256) k_scale(const SysDev* __restrict__ sys, c
   }
 }
 
+// ----------------------------- inner MdagM in Ginsparg-Wilson form (Sec. 2.2)
+// With D = 1 + g5 eps and eps^2 = 1, D^dag D = D + D^dag (the Ginsparg-Wilson
+// relation at a = 1), so with the site-local Y = c- P- + c+ P+
+//   MdagM v = (1 + |1 + c|^2) v + (1 + c*) g5 eps(v) + eps(g5 (1 + Y) v)
+// per spin component (c = c- on spins 0,1 and c+ on spins 2,3).  The two signs
+// are independent, so one two-source multi-shift solve replaces the two
+// dependent ones of M then M^dag.  For the rational eps the result differs from
+// MdagM by (1 - eps^2) v, i.e. by the approximation error: the inner solver
+// uses it, the FP64 true residuals use M then M^dag.
+//
+// prep (entries A = ta[s], B = tb[s]; v = A.e_in): B.src = g5 (1 + Y) v, the
+// source partials |v|^2 -> A.part_b and |B.src|^2 -> B.part_b (rho_0 of both
+// multi-shift solves), and B's per-outer-iteration counter stat[3] cleared.
+template <class R>
+__global__ void __launch_bounds__(256) k_gw_prep(const SysDev* __restrict__ ta,
+                                                  const SysDev* __restrict__ tb,
+                                                  const int* __restrict__ bmap, int nb_total) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = bmap[L];
+  const SysDev& A = ta[s];
+  const SysDev& B = tb[s];
+  if (A.active && *A.active == 0) return;
+  const int lb = L - A.blk0;
+  const int V = A.g.V;
+  const int i0 = lb * A.spb;
+  const int i1 = min(V, i0 + A.spb);
+  if (lb == 0 && threadIdx.x == 0) B.stat[3] = 0;
+  double av = 0.0, as = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> v[4];
+    load_sp<R>((const c2<R>*)A.e_in, V, i, v);
+    const double2 ph = A.phi[i];
+    const double cpr = A.m_re + A.g_re * ph.x - A.g_im * ph.y;
+    const double cpi = A.m_im + A.g_re * ph.y + A.g_im * ph.x;
+    c2<R> o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double cr = cpr, ci = (k < 2) ? -cpi : cpi;  // c- = conj(c+)
+      const double vr = (double)v[k].x, vi = (double)v[k].y;
+      const double g5 = k < 2 ? -1.0 : 1.0;
+      o[k] = c2<R>{(R)(g5 * (vr + cr * vr - ci * vi)), (R)(g5 * (vi + cr * vi + ci * vr))};
+    }
+    store_sp<R>((c2<R>*)B.src, V, i, o);
+    av += norm2_sp(v);
+    as += norm2_sp(o);
+  }
+  const double tv = block_sum(av, lds);
+  const double ts = block_sum(as, lds);
+  if (threadIdx.x == 0) {
+    A.part_b[lb] = tv;
+    B.part_b[lb] = ts;
+  }
+}
+
+// e = sum_{j < N} d_j t_j at site i (FP64 accumulation, two slots per step).
+template <class R>
+__device__ __forceinline__ void basis_sum(const c2<R>* __restrict__ basis,
+                                          const double* __restrict__ d, int N, size_t slot, int V,
+                                          int i, double2 e[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k] = double2{0.0, 0.0};
+  int j = 0;
+  for (; j + 1 < N; j += 2) {
+    const double d0 = d[j], d1 = d[j + 1];
+    const c2<R>* b0 = basis + (size_t)j * slot;
+    c2<R> v0[4], v1[4];
+    load_sp<R>(b0, V, i, v0);
+    load_sp<R>(b0 + slot, V, i, v1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      e[k].x += d0 * (double)v0[k].x + d1 * (double)v1[k].x;
+      e[k].y += d0 * (double)v0[k].y + d1 * (double)v1[k].y;
+    }
+  }
+  if (j < N) {
+    const double d0 = d[j];
+    c2<R> v0[4];
+    load_sp<R>(basis + (size_t)j * slot, V, i, v0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      e[k].x += d0 * (double)v0[k].x;
+      e[k].y += d0 * (double)v0[k].y;
+    }
+  }
+}
+
+// combine: e1 = sum_j dA_j tA_j (entry A: eps(v)), e23 = sum_j dB_j tB_j (entry
+// B: eps(g5 (1 + Y) v)), w = (1 + |1 + c|^2) v + (1 + c*) g5 e1 + e23 -> A.e_out;
+// partial Re <v, w> -> A.part_c.  v = A.e_in.
+template <class R>
+__global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ ta,
+                                                     const SysDev* __restrict__ tb,
+                                                     const int* __restrict__ bmap, int nb_total) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = bmap[L];
+  const SysDev& A = ta[s];
+  const SysDev& B = tb[s];
+  if (A.active && *A.active == 0) return;
+  const int lb = L - A.blk0;
+  const int V = A.g.V;
+  const size_t slot = (size_t)4 * V;
+  const int NA = A.h_ctl[1], NB = B.h_ctl[1];
+  const int i0 = lb * A.spb;
+  const int i1 = min(V, i0 + A.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 e1[4], e2[4];
+    basis_sum<R>((const c2<R>*)A.basis, A.coef_d, NA, slot, V, i, e1);
+    basis_sum<R>((const c2<R>*)B.basis, B.coef_d, NB, slot, V, i, e2);
+    c2<R> v[4];
+    load_sp<R>((const c2<R>*)A.e_in, V, i, v);
+    const double2 ph = A.phi[i];
+    const double cpr = A.m_re + A.g_re * ph.x - A.g_im * ph.y;
+    const double cpi = A.m_im + A.g_re * ph.y + A.g_im * ph.x;
+    c2<R> w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double cr = cpr, ci = (k < 2) ? -cpi : cpi;
+      const double g5 = k < 2 ? -1.0 : 1.0;
+      const double a = 1.0 + (1.0 + cr) * (1.0 + cr) + ci * ci;  // 1 + |1 + c|^2
+      // (1 + c*) g5 e1
+      const double br = 1.0 + cr, bi = -ci;
+      const double fr = g5 * (br * e1[k].x - bi * e1[k].y);
+      const double fi = g5 * (br * e1[k].y + bi * e1[k].x);
+      const double vr = (double)v[k].x, vi = (double)v[k].y;
+      const double wr = a * vr + fr + e2[k].x, wi = a * vi + fi + e2[k].y;
+      w[k] = c2<R>{(R)wr, (R)wi};
+      acc += vr * wr + vi * wi;
+    }
+    store_sp<R>((c2<R>*)A.e_out, V, i, w);
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) A.part_c[lb] = tot;
+}
+
 // ------------------------------------------------- RHMC bosonic action (eq. acws)
 // phi: complex128 [V] (site order).  Pack planes of e_out2 (FP64 planar):
 // 0 = phi, 1 = W' = m phi + (g/2) phi^2, 2 = conj(W'), 3 = 0.

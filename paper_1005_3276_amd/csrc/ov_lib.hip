@@ -156,6 +156,15 @@ struct SysBuf {
   double *coef_term, *coef_c, *coef_d, *cg_s;
   int *act_cg, *act_ru;
   void *vR, *fftR;              // preconditioned solve: M0^-1 p / M^dag u, transform scratch
+  // second multi-shift entry of the inner operator in Ginsparg-Wilson form (ms_b*)
+  void *ms_b_basis = nullptr, *ms_b_r = nullptr, *ms_b_src = nullptr;
+  double *ms_b_part_a = nullptr, *ms_b_part_b = nullptr, *ms_b_part_c = nullptr;
+  double *ms_b_h_rho = nullptr, *ms_b_h_alpha = nullptr, *ms_b_h_zeta = nullptr;
+  unsigned* ms_b_h_active = nullptr;
+  int* ms_b_h_ctl = nullptr;
+  double* ms_b_dstat = nullptr;
+  double *ms_b_coef_term = nullptr, *ms_b_coef_c = nullptr, *ms_b_coef_d = nullptr;
+  long long* ms_b_stat = nullptr;
   double2 *shx = nullptr, *shp = nullptr;  // multi-shift CG on MdagM: solutions, directions
   double* shc = nullptr;        //   per-shift coefficients
   int nshift = 0;
@@ -186,6 +195,7 @@ struct Plan {
   bool pc = false;   // free-field preconditioned solve
   bool fft = false;  // momentum-space Dirac operator (no multi-shift)
   int nshift = 0;    // shifted systems of a multi-shift CG on MdagM (rational layers)
+  bool gw = false;   // inner MdagM in Ginsparg-Wilson form: one two-source multi-shift
 };
 
 template <class R>
@@ -224,7 +234,7 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.basisR = s.rR = s.srcR2 = s.uR = s.xR = s.pR = s.rcgR = nullptr;
   }
   s.vR = s.fftR = nullptr;
-  if (pl.solve && (pl.pc || pl.fft || pl.nshift > 0)) {
+  if (pl.solve && (pl.pc || pl.fft || pl.nshift > 0 || pl.gw)) {
     s.vR = bp.take(pl.mixed ? v32 : v64);
     s.fftR = bp.take(pl.mixed ? v32 : v64);
   }
@@ -248,6 +258,24 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
   s.coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
   s.coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
   s.coef_d = (double*)bp.take(sizeof(double) * capmax);
+  if (pl.solve && pl.gw) {
+    const size_t vR = pl.mixed ? v32 : v64;
+    s.ms_b_basis = bp.take(vR * pl.capR);
+    s.ms_b_r = bp.take(vR);
+    s.ms_b_src = bp.take(vR);
+    s.ms_b_part_a = (double*)bp.take(sizeof(double) * s.nblk);
+    s.ms_b_part_b = (double*)bp.take(sizeof(double) * s.nblk);
+    s.ms_b_part_c = (double*)bp.take(sizeof(double) * s.nblk);
+    s.ms_b_h_rho = (double*)bp.take(sizeof(double) * (capmax + 1));
+    s.ms_b_h_alpha = (double*)bp.take(sizeof(double) * (capmax + 1));
+    s.ms_b_h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
+    s.ms_b_h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
+    s.ms_b_h_ctl = (int*)bp.take(sizeof(int) * 4);
+    s.ms_b_dstat = (double*)bp.take(sizeof(double) * 2);
+    s.ms_b_coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
+    s.ms_b_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
+    s.ms_b_coef_d = (double*)bp.take(sizeof(double) * capmax);
+  }
 }
 
 enum Table {
@@ -306,12 +334,16 @@ struct Engine {
   int L64 = 0, LR = 0;              // multi-shift launch counts
   int nb_xy = 0, nb_z = 0, nb_t = 0;  // workgroups of the momentum-space passes
   SysDev* ftab = nullptr;           // device: (system, shift) table of the rational force
+  SysDev* gwtab = nullptr;          // device: 2 nsys multi-shift entries of the GW inner operator
+  int* gwbmap = nullptr;            // device: 2 nb_total workgroups -> entry
+  std::vector<int> hgwbmap;
+  std::vector<SysDev> hgwtab;       // host copy of gwtab
 
   size_t layout(void* base, size_t cap, bool dry) {
     Bump bp(base, cap, dry);
     gbar = (GridBar*)bp.take(sizeof(GridBar));
     cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys);
-    stat_all = (long long*)bp.take(sizeof(long long) * 4 * nsys);
+    stat_all = (long long*)bp.take(sizeof(long long) * 8 * nsys);  // entries A then B
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0, nxy = 0, nz = 0, nt = 0;
     long long total_sites = 0;
@@ -339,6 +371,7 @@ struct Engine {
       nt += (X / b.xc) * Y * Z;
       b.cg_s = dry ? nullptr : cg_all + (size_t)s * CG_NSLOT;
       b.stat = dry ? nullptr : stat_all + (size_t)s * 4;
+      b.ms_b_stat = (dry || !pl.gw) ? nullptr : stat_all + (size_t)(nsys + s) * 4;
       b.act_cg = dry ? nullptr : act_all + s;
       b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
@@ -348,6 +381,17 @@ struct Engine {
     nb_t = nt;
     tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
     ftab = pl.nshift > 0 ? (SysDev*)bp.take(sizeof(SysDev) * nsys * pl.nshift) : nullptr;
+    gwtab = pl.gw ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
+    gwbmap = pl.gw ? (int*)bp.take(sizeof(int) * 2 * (size_t)nb_total) : nullptr;
+    hgwbmap.clear();
+    if (pl.gw) {
+      hgwbmap.assign(2 * (size_t)nb_total, 0);
+      for (int s = 0; s < nsys; ++s)
+        for (int b = 0; b < sb[s].nblk; ++b) {
+          hgwbmap[sb[s].blk0 + b] = s;
+          hgwbmap[nb_total + sb[s].blk0 + b] = nsys + s;
+        }
+    }
     ptrs = (void**)bp.take(sizeof(void*) * 2 * nsys);
     bmap = (int*)bp.take(sizeof(int) * (size_t)nb_total);
     hbmap.assign(nb_total, 0);
@@ -385,7 +429,7 @@ ov_status ensure_pinned(ov_ctx* c, int nsys) {
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   c->pinned = nullptr;
   c->pinned_flags = nullptr;
-  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 4) * nsys));
+  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 8) * nsys));
   HIPCHK(c, hipHostMalloc((void**)&c->pinned_flags, sizeof(int) * 2 * nsys + 64));
   c->pinned_n = nsys;
   return OV_OK;
@@ -421,6 +465,7 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   // the shifted systems of the rational layers are not preconditioned
   E.pl.pc = solve && nshift == 0 && E.lead->p.precondition != 0;
   E.pl.fft = solve && E.lead->p.dirac != OV_DIRAC_OVERLAP_MS;
+  E.pl.gw = solve && !E.pl.fft && nshift == 0 && E.lead->p.inner_form == 1;
   // capacities from the loosest spectral bound over the batch (no multi-shift
   // basis for a momentum-space operator)
   int cap64 = 0, capR = 0;
@@ -487,6 +532,12 @@ ov_status upload_tables(Engine& E) {
                                 hipMemcpyHostToDevice, E.st));
   HIPCHK(E.lead, hipMemcpyAsync(E.bmap, E.hbmap.data(), sizeof(int) * E.hbmap.size(),
                                 hipMemcpyHostToDevice, E.st));
+  if (E.pl.gw && E.hgwtab.size() == 2 * (size_t)E.nsys) {
+    HIPCHK(E.lead, hipMemcpyAsync(E.gwtab, E.hgwtab.data(), sizeof(SysDev) * E.hgwtab.size(),
+                                  hipMemcpyHostToDevice, E.st));
+    HIPCHK(E.lead, hipMemcpyAsync(E.gwbmap, E.hgwbmap.data(), sizeof(int) * E.hgwbmap.size(),
+                                  hipMemcpyHostToDevice, E.st));
+  }
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
   return OV_OK;
 }
@@ -575,13 +626,16 @@ int coop_capacity(ov_ctx* c) {
 }
 
 template <class R>
-void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
-  const SysDev* T = tab(E, t);
-  double vol = 0.0;  // sites in this launch (all systems)
-  for (const auto& b : E.sb) vol += b.V;
+// Multi-shift solves of `nent` table entries (nent / E.nsys entries per system,
+// laid out system-major per copy) over nbt workgroups mapped by bmap.
+void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_, int nent,
+                   const MsParams& mp, int L) {
+  const int copies = nent / E.nsys;
+  double vol = 0.0;  // sites in this launch (all entries)
+  for (const auto& b : E.sb) vol += (double)b.V * copies;
   const double bytes = 3.0 * 4.0 * sizeof(c2<R>) * vol;  // per pass
   ov_ctx* c = E.lead;
-  const int cap = c->persistent ? coop_capacity<R>(c) : 0;
+  const int cap = (c->persistent && copies == 1) ? coop_capacity<R>(c) : 0;
   if (cap > 0) {
     int grid = std::min(E.nb_total, cap);
     k_bar_reset<<<1, 64, 0, E.st>>>(E.gbar);
@@ -627,7 +681,7 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
     shb = ok ? (size_t)4 * c->block * sizeof(c2<R>) : 0;
   }
   if (c->sample_max > 0) {  // stamp regions for the sampled launches of this call
-    const size_t region = 2 * (size_t)E.nb_total;
+    const size_t region = 2 * (size_t)nbt_;
     const size_t regions = 4 * (size_t)c->sample_max + 2;
     if (c->ts_region < region || c->ts_regions < regions) {
       if (c->ts_dev) (void)hipFree(c->ts_dev);  // synchronises the device
@@ -651,21 +705,26 @@ void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
     const size_t idx = c->ev_use.size() - 1;
     if (smp.on && c->ts_dev && idx < c->ts_regions) {
       m.tstamp = c->ts_dev + idx * c->ts_region;
-      c->ev_use[idx].ts_blocks = E.nb_total;
+      c->ev_use[idx].ts_blocks = nbt_;
     }
     return m;
   };
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);
-      k_ms_t<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, stamped(smp));
+      k_ms_t<R><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 4 : 1, bytes);
-      k_ms_r<R><<<E.nb_total, c->block, shb, E.st>>>(T, E.bmap, E.nb_total, n, stamped(smp));
+      k_ms_r<R><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
   }
-  k_ms_coef<<<E.nsys, 256, 0, E.st>>>(T, E.nsys, L, mp);
+  k_ms_coef<<<nent, 256, 0, E.st>>>(T, nent, L, mp);
+}
+
+template <class R>
+void launch_ms(const Engine& E, int t, const MsParams& mp, int L) {
+  launch_ms_tab<R>(E, tab(E, t), E.bmap, E.nb_total, E.nsys, mp, L);
 }
 
 template <class R>
@@ -727,6 +786,8 @@ ov_status read_ctl(Engine& E, std::vector<int>& ctl3, std::vector<long long>& st
   ctl3.resize(E.nsys);
   stat0.resize(E.nsys);
   dstat0.resize(E.nsys);
+  std::vector<long long> statb(E.nsys, 0);
+  std::vector<int> ctlb(E.nsys, 0);
   for (int s = 0; s < E.nsys; ++s) {
     HIPCHK(E.lead, hipMemcpyAsync(&ctl3[s], E.sb[s].h_ctl + 3, sizeof(int),
                                   hipMemcpyDeviceToHost, E.st));
@@ -734,8 +795,18 @@ ov_status read_ctl(Engine& E, std::vector<int>& ctl3, std::vector<long long>& st
                                   hipMemcpyDeviceToHost, E.st));
     HIPCHK(E.lead, hipMemcpyAsync(&dstat0[s], E.sb[s].dstat, sizeof(double),
                                   hipMemcpyDeviceToHost, E.st));
+    if (E.sb[s].ms_b_stat) {  // second multi-shift entry of the GW inner operator
+      HIPCHK(E.lead, hipMemcpyAsync(&statb[s], E.sb[s].ms_b_stat, sizeof(long long),
+                                    hipMemcpyDeviceToHost, E.st));
+      HIPCHK(E.lead, hipMemcpyAsync(&ctlb[s], E.sb[s].ms_b_h_ctl + 3, sizeof(int),
+                                    hipMemcpyDeviceToHost, E.st));
+    }
   }
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
+  for (int s = 0; s < E.nsys; ++s) {
+    stat0[s] += statb[s];
+    ctl3[s] |= ctlb[s];
+  }
   return OV_OK;
 }
 
@@ -744,6 +815,11 @@ ov_status reset_stats(Engine& E) {
     HIPCHK(E.lead, hipMemsetAsync(E.sb[s].h_ctl, 0, sizeof(int) * 4, E.st));
     HIPCHK(E.lead, hipMemsetAsync(E.sb[s].stat, 0, sizeof(long long) * 4, E.st));
     HIPCHK(E.lead, hipMemsetAsync(E.sb[s].dstat, 0, sizeof(double) * 2, E.st));
+    if (E.sb[s].ms_b_stat) {
+      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_h_ctl, 0, sizeof(int) * 4, E.st));
+      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_stat, 0, sizeof(long long) * 4, E.st));
+      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_dstat, 0, sizeof(double) * 2, E.st));
+    }
   }
   return OV_OK;
 }
@@ -954,6 +1030,25 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
         ok &= need(t, s, T[t]->cg_r, "cg_r") && need(t, s, T[t]->part_c, "part_c") &&
               need(t, s, T[t]->cg_s, "cg_s");
     }
+    if (E.pl.gw) {
+      // k_gw_prep / multi-shift / k_gw_combine over both entries, k_cg_scalar on A
+      for (int e = 0; e < 2; ++e) {
+        const SysDev* G = &E.hgwtab[(size_t)e * E.nsys + s];
+        const int t = 100 + e;
+        ok &= need(t, s, G->basis, "basis") && need(t, s, G->r, "r") && need(t, s, G->src, "src") &&
+              need(t, s, G->part_a, "part_a") && need(t, s, G->part_b, "part_b") &&
+              need(t, s, G->part_c, "part_c") && need(t, s, G->h_rho, "h_rho") &&
+              need(t, s, G->h_alpha, "h_alpha") && need(t, s, G->h_zeta, "h_zeta") &&
+              need(t, s, G->h_active, "h_active") && need(t, s, G->h_ctl, "h_ctl") &&
+              need(t, s, G->coef_term, "coef_term") && need(t, s, G->coef_c, "coef_c") &&
+              need(t, s, G->coef_d, "coef_d") && need(t, s, G->stat, "stat") &&
+              need(t, s, G->dstat, "dstat") && need(t, s, G->active, "active") &&
+              need(t, s, G->phi, "phi");
+      }
+      const SysDev* A = &E.hgwtab[s];
+      ok &= need(100, s, A->e_in, "e_in") && need(100, s, A->e_out, "e_out") &&
+            need(100, s, A->cg_s, "cg_s") && need(T_CG, s, T[T_CG]->e_in, "e_in");
+    }
     if (!ok) return OV_ERR_DEVICE;
   }
   return OV_OK;
@@ -963,6 +1058,7 @@ template <class R>
 ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
                              const std::vector<const void*>& phi) {
   E.htab.assign((size_t)T_NT * E.nsys, SysDev{});
+  E.hgwtab.assign(E.pl.gw ? 2 * (size_t)E.nsys : 0, SysDev{});
   for (int s = 0; s < E.nsys; ++s) {
     SysBuf& b = E.sb[s];
     SysDev d = base_dev(b);
@@ -1073,6 +1169,34 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
       E.htab[(size_t)T_F_TM * E.nsys + s] = ftm;
       E.htab[(size_t)T_F_TMD * E.nsys + s] = ftmd;
     }
+    if (E.pl.gw) {
+      // entry A: eps(v) on the system's inner buffers, MdagM v -> vR; entry B:
+      // eps(g5 (1 + Y) v) on the twin buffers, workgroups after all of A's
+      SysDev ga = im;
+      ga.e_out = b.vR;
+      SysDev gb = d;
+      gb.active = b.act_cg;
+      gb.blk0 = b.blk0 + E.nb_total;
+      gb.basis = b.ms_b_basis;
+      gb.r = b.ms_b_r;
+      gb.src = b.ms_b_src;
+      gb.part_a = b.ms_b_part_a;
+      gb.part_b = b.ms_b_part_b;
+      gb.part_c = b.ms_b_part_c;
+      gb.h_rho = b.ms_b_h_rho;
+      gb.h_alpha = b.ms_b_h_alpha;
+      gb.h_zeta = b.ms_b_h_zeta;
+      gb.h_active = b.ms_b_h_active;
+      gb.h_ctl = b.ms_b_h_ctl;
+      gb.stat = b.ms_b_stat;
+      gb.dstat = b.ms_b_dstat;
+      gb.coef_term = b.ms_b_coef_term;
+      gb.coef_c = b.ms_b_coef_c;
+      gb.coef_d = b.ms_b_coef_d;
+      gb.cg_s = nullptr;
+      E.hgwtab[s] = ga;
+      E.hgwtab[E.nsys + s] = gb;
+    }
     E.htab[(size_t)T_IN_M * E.nsys + s] = im;
     E.htab[(size_t)T_IN_MDAG * E.nsys + s] = imd;
     E.htab[(size_t)T_TR_M * E.nsys + s] = tm;
@@ -1106,7 +1230,7 @@ ov_status read_scalars(Engine& E) {
   HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all, sizeof(double) * CG_NSLOT * E.nsys,
                                 hipMemcpyDeviceToHost, E.st));
   HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned + (size_t)CG_NSLOT * E.nsys, E.stat_all,
-                                sizeof(long long) * 4 * E.nsys, hipMemcpyDeviceToHost, E.st));
+                                sizeof(long long) * 8 * E.nsys, hipMemcpyDeviceToHost, E.st));
   return sync(E);
 }
 
@@ -1114,7 +1238,7 @@ ov_status read_scalars(Engine& E) {
 int last_ms_iters(const Engine& E) {
   const long long* st = (const long long*)(E.lead->pinned + (size_t)CG_NSLOT * E.nsys);
   long long m = 0;
-  for (int s = 0; s < E.nsys; ++s) m = std::max(m, st[(size_t)s * 4 + 3]);
+  for (int s = 0; s < 2 * E.nsys; ++s) m = std::max(m, st[(size_t)s * 4 + 3]);  // A and B
   return (int)m;
 }
 
@@ -1372,8 +1496,8 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       if (it != c->n_est.end()) LR = std::min(LR, it->second + 2);
     }
     char ikey[96];
-    std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d|%d|%d", sizeof(R), tol_it, LR, (int)pc,
-                  (int)E.pl.fft);
+    std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d|%d|%d|%d", sizeof(R), tol_it, LR, (int)pc,
+                  (int)E.pl.fft, (int)E.pl.gw);
     // p = r + beta p (beta = 0 right after a (re)start) ; M p ; alpha ;
     // M^dag u with the CG update ; beta -- one captured graph per iteration.
     // Preconditioned (M~ = M M0^-1): M (M0^-1 p), and M0^-dag (M^dag u) feeds
@@ -1388,6 +1512,18 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_F_M), ns, 1);
         launch_sym<R>(E, T_F_MD, SYM_D_DAG);
         k_yuk<R><<<nb, bl, 0, E.st>>>(tab(E, T_F_MD), E.bmap, nb, 1);
+        if (pc) launch_sym<R>(E, T_PC_Q, SYM_M0INV_DAG);
+        k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
+        return;
+      }
+      if (E.pl.gw) {  // w = MdagM v in Ginsparg-Wilson form: both signs in one multi-shift
+        const int nb = E.nb_total, bl = c->block;
+        if (pc) launch_sym<R>(E, T_PC_P, SYM_M0INV);
+        k_gw_prep<R><<<nb, bl, 0, E.st>>>(E.gwtab, E.gwtab + ns, E.bmap, nb);
+        launch_ms_tab<R>(E, E.gwtab, E.gwbmap, 2 * nb, 2 * ns, mpR, LR);
+        k_gw_combine<R><<<nb, bl, 0, E.st>>>(E.gwtab, E.gwtab + ns, E.bmap, nb);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(E.gwtab, ns, 1);  // alpha = rr / Re<v, w>
         if (pc) launch_sym<R>(E, T_PC_Q, SYM_M0INV_DAG);
         k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);
         k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
@@ -1539,6 +1675,10 @@ ov_status validate(const ov_params* p, std::string& err) {
     err = "need 0 < truth_relax <= 1";
     return OV_ERR_INVALID_ARG;
   }
+  if (p->inner_form != 0 && p->inner_form != 1) {
+    err = "inner_form must be 0 or 1";
+    return OV_ERR_INVALID_ARG;
+  }
   if (p->precondition != 0 && p->precondition != 1) {
     err = "precondition must be 0 or 1";
     return OV_ERR_INVALID_ARG;
@@ -1680,6 +1820,7 @@ void ov_params_default(ov_params* p) {
   p->inner_tol_max = 1e-2;
   p->precondition = 1;
   p->truth_relax = 0.01;
+  p->inner_form = 1;
 }
 
 const char* ov_status_string(ov_status s) {
@@ -1786,6 +1927,7 @@ size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
   E.pl.mixed = mixed;
   E.pl.pc = c->p.precondition != 0;
   E.pl.fft = c->p.dirac != OV_DIRAC_OVERLAP_MS;
+  E.pl.gw = !E.pl.fft && c->p.inner_form == 1;
   E.pl.cap64 = mixed ? cap64 : std::max(cap64, capR);
   E.pl.capR = mixed ? capR : E.pl.cap64;
   if (E.pl.fft) E.pl.cap64 = E.pl.capR = 0;
@@ -1901,7 +2043,7 @@ static bool same_solver(const ov_params& a, const ov_params& b) {
          a.mixed_inner_tol == b.mixed_inner_tol && a.reliable_delta == b.reliable_delta &&
          a.precision == b.precision && a.M0 == b.M0 && a.inner_relax == b.inner_relax &&
          a.inner_tol_max == b.inner_tol_max && a.precondition == b.precondition &&
-         a.dirac == b.dirac && a.truth_relax == b.truth_relax;
+         a.dirac == b.dirac && a.truth_relax == b.truth_relax && a.inner_form == b.inner_form;
 }
 
 static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,
