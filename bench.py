@@ -40,16 +40,20 @@ def kernel_source_hash():
     return hashlib.sha256((common + kern[a:b]).encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter runs, if the kernels are unchanged."""
-    path = os.path.join(ROOT, "profiles", "k_ms_fp32_16x4_traffic.json")
+def measured_traffic(family, bytes_per_launch):
+    """HBM bytes per launch of a pass family from the committed counter runs, if the
+    kernels and the launch composition (algorithmic bytes per launch) are unchanged."""
+    path = os.path.join(ROOT, "profiles", "k_ms_passes_16x4_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    f = rec.get("families", {}).get(family)
+    if not f or abs(f.get("algorithmic_bytes_per_launch", -1) - bytes_per_launch) > 0.5:
+        return None
+    return f.get("hbm_bytes_per_launch")
 
 
 def stencil_bandwidth(lat, torch, nrhs, prec, reps=20):
@@ -323,44 +327,54 @@ def main():
     value = args.steps / el
     log(f"mixed: {el / args.steps * 1e3:.2f} ms/solve  {stats[0]}")
 
-    # ---- dominant kernel: live HIP-event sampling on the library's stream
+    # ---- dominant kernel: live HIP-event sampling on the library's stream.  Every
+    # multi-shift pass launch of one solve is sampled (the cap applies per host
+    # synchronisation, i.e. per outer iteration / reliable update), so the per-family
+    # sums below cover the whole solve and decide which pass family dominates.
     if args.no_sample:
         lat.kernel_sampling(0)
     else:
-        lat.kernel_sampling(64)
-    for k in (0, 1, 2):
+        lat.kernel_sampling(512)
+    for k in range(5):
         lat.kernel_spans(k, reset=True)
     lat.solve(dsrc, dphi)
     lat.kernel_sampling(0)
-    spans = [lat.kernel_spans(k) for k in (0, 1, 2)]
-    kt = [(sp[2], sp[3], sp[4]) for sp in spans]
-    if kt[2][1] > 0:  # persistent multi-shift kernel: one launch per multi-shift solve
-        ms_sum, cnt, bytes_sum = kt[2]
-        kname = "k_ms_persistent<float> (every iteration of one multi-shift solve)"
-        detail = {}
-    else:
-        ms_sum = kt[0][0] + kt[1][0]
-        cnt = kt[0][1] + kt[1][1]
-        bytes_sum = kt[0][2] + kt[1][2]
-        kname = "k_ms_t<float> + k_ms_r<float> (multi-shift Wilson passes)"
-        detail = {"t_pass_us": kt[0][0] / max(kt[0][1], 1) * 1e3,
-                  "r_pass_us": kt[1][0] / max(kt[1][1], 1) * 1e3}
-    avg_us = ms_sum / max(cnt, 1) * 1e3
-    per_launch = bytes_sum / max(cnt, 1)
-    achieved = bytes_sum / (ms_sum * 1e-3) / 1e9 if ms_sum > 0 else 0.0
-    traffic = measured_traffic() if kt[2][1] == 0 else None
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
-                "avg_launch_us": avg_us, "bytes_per_launch": per_launch, "samples": cnt}
-    roofline.update(detail)
-    # the same sampled launches, kernel-only: max(end) - min(start) of device wall-clock
-    # stamps taken by every workgroup (what a kernel trace reports; the event duration
-    # above also holds the dispatch gap before each launch)
-    kms = spans[0][0] + spans[1][0]
-    kcnt = spans[0][1] + spans[1][1]
-    if kcnt > 0:
-        roofline["kernel_only_us"] = kms / kcnt * 1e3
-        roofline["achieved_kernel_only"] = per_launch / (kms / kcnt * 1e-3) / 1e9
+    spans = [lat.kernel_spans(k) for k in range(5)]  # (kernel_ms, kcnt, event_ms, cnt, bytes)
+    families = {
+        "fp64_truth": ((3, 4), "k_ms_t<double> + k_ms_r<double> (FP64 multi-shift passes of "
+                               "the true residuals)"),
+        "fp32_inner": ((0, 1), "k_ms_t<float> + k_ms_r<float> (FP32 multi-shift passes of "
+                               "the inner CG, two sources per launch)"),
+    }
+
+    def family_roofline(name):
+        ids, kname = families[name]
+        ms_sum = sum(spans[k][2] for k in ids)
+        cnt = sum(spans[k][3] for k in ids)
+        bytes_sum = sum(spans[k][4] for k in ids)
+        per_launch = bytes_sum / max(cnt, 1)
+        achieved = bytes_sum / (ms_sum * 1e-3) / 1e9 if ms_sum > 0 else 0.0
+        r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, per_launch),
+             "kernel": kname, "avg_launch_us": ms_sum / max(cnt, 1) * 1e3,
+             "bytes_per_launch": per_launch, "launches_per_solve": cnt,
+             "event_ms_per_solve": ms_sum,
+             "t_pass_us": spans[ids[0]][2] / max(spans[ids[0]][3], 1) * 1e3,
+             "r_pass_us": spans[ids[1]][2] / max(spans[ids[1]][3], 1) * 1e3}
+        # the same launches, kernel-only: max(end) - min(start) of device wall-clock
+        # stamps taken by every workgroup (what a kernel trace reports; the event
+        # duration above also holds the dispatch gap before each launch)
+        kms = sum(spans[k][0] for k in ids)
+        kcnt = sum(spans[k][1] for k in ids)
+        if kcnt > 0:
+            r["kernel_only_us"] = kms / kcnt * 1e3
+            r["achieved_kernel_only"] = per_launch / (kms / kcnt * 1e-3) / 1e9
+        return r
+
+    fam = {n: family_roofline(n) for n in families}
+    dom = max(fam, key=lambda n: fam[n]["event_ms_per_solve"])
+    roofline = fam[dom]
+    roofline_secondary = fam[[n for n in fam if n != dom][0]]
     log(f"roofline: {roofline}")
 
     extra = {}
@@ -440,6 +454,7 @@ def main():
                    "outer_iters": stats[0]["outer_iters"],
                    "inner_iters": stats[0]["inner_iters"]},
         "roofline": roofline,
+        "roofline_secondary": roofline_secondary,
         "cpu_baseline": cpu,
         "autotune": {"block_x_sites_per_thread": list(choice) if choice else None,
                      "us_per_iteration": tune_us},
