@@ -1814,6 +1814,12 @@ __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
   }
 }
 
+// stat[3] = 0 for the nsys entries (the per-update maximum of multi-shift iterations).
+__global__ void k_stat3_clear(const SysDev* __restrict__ sys, int nsys) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x)
+    if (sys[s].stat) sys[s].stat[3] = 0;
+}
+
 // p = r + beta p (beta from cg_s; use_beta = 0 -> p = r); partial |p|^2 -> part_b.
 template <class R>
 __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, const int* __restrict__ bmap,

@@ -1234,6 +1234,15 @@ ov_status read_scalars(Engine& E) {
   return sync(E);
 }
 
+// Largest iteration count of the FP64 multi-shift solves of the last reliable
+// update (stat[3] of the systems' own entries, cleared at the update's start).
+int last_truth_iters(const Engine& E) {
+  const long long* st = (const long long*)(E.lead->pinned + (size_t)CG_NSLOT * E.nsys);
+  long long m = 0;
+  for (int s = 0; s < E.nsys; ++s) m = std::max(m, st[(size_t)s * 4 + 3]);
+  return (int)m;
+}
+
 // Largest multi-shift iteration count of the current outer iteration (stat[3]).
 int last_ms_iters(const Engine& E) {
   const long long* st = (const long long*)(E.lead->pinned + (size_t)CG_NSLOT * E.nsys);
@@ -1317,18 +1326,16 @@ namespace {
 // multi-shift tolerance tol, and its norm through k_cg_scalar(scalar_op).
 // The tolerance is rounded down to a power of ten so that few graphs exist.
 template <class R>
-ov_status reliable_update(Engine& E, double tol, int scalar_op) {
+ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
   const ov_ctx* c = E.lead;
-  tol = std::pow(10.0, std::floor(std::log10(tol) + 1e-9));
   const MsParams mp = make_mp(c, tol, E.pl.cap64);
-  int L = 0;
-  for (int s = 0; s < E.nsys; ++s) L = std::max(L, capacity(E.ctxs[s], tol));
-  L = std::min(E.pl.cap64, L);
   const bool pc = E.pl.pc;
   char key[96];
   std::snprintf(key, sizeof key, "ru|%zu|%.3e|%d|%d|%d|%d", sizeof(R), tol, L, scalar_op, (int)pc,
                 (int)E.pl.fft);
   return run_graph(E, key, [&]() {
+    if (!E.pl.fft)  // per-update maximum of the FP64 multi-shift iteration counts
+      k_stat3_clear<<<1, 64, 0, E.st>>>(tab(E, T_TR_M), E.nsys);
     if (pc) {  // x64 += M0^-1 x~, x~ = 0
       launch_sym<R>(E, T_PC_FOLD, SYM_M0INV);
       k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_PC_FOLD), E.bmap, E.nb_total, 3);
@@ -1367,6 +1374,44 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
         k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
     }
   });
+}
+
+// Reliable update (above) followed by the scalar read-back.  The FP64 multi-shift
+// solves launch as many iterations as the last update at this tolerance needed plus
+// a margin; when an update may have been cut short by that (its largest iteration
+// count reached the launched count) it is repeated with the full Chebyshev bound.
+// The repeat is exact: the fold-in adds the (now zero) inner solution again and the
+// residual, its norm and the CG state update are recomputed from x64 alone.
+template <class R>
+ov_status reliable_update(Engine& E, double tol, int scalar_op) {
+  ov_ctx* c = E.lead;
+  tol = std::pow(10.0, std::floor(std::log10(tol) + 1e-9));
+  int Lfull = 0;
+  for (int s = 0; s < E.nsys; ++s) Lfull = std::max(Lfull, capacity(E.ctxs[s], tol));
+  Lfull = std::min(E.pl.cap64, Lfull);
+  if (E.pl.fft) {
+    TRY(reliable_update_L<R>(E, tol, scalar_op, Lfull));
+    return read_scalars(E);
+  }
+  const long long key = n_est_key(1000 + sizeof(R), tol);  // FP64 truth solves of this solver
+  int L = Lfull;
+  {
+    auto it = c->n_est.find(key);
+    if (it != c->n_est.end()) L = std::min(Lfull, it->second + std::max(4, it->second / 8));
+  }
+  TRY(reliable_update_L<R>(E, tol, scalar_op, L));
+  TRY(read_scalars(E));
+  int nobs = last_truth_iters(E);
+  if (L < Lfull && nobs >= L - 1) {
+    if (ov_log())
+      std::fprintf(stderr, "[ov] truth multi-shift at tol %.0e cut at %d of %d: repeated\n", tol, L,
+                   Lfull);
+    TRY(reliable_update_L<R>(E, tol, scalar_op, Lfull));
+    TRY(read_scalars(E));
+    nobs = last_truth_iters(E);
+  }
+  c->n_est[key] = nobs;
+  return OV_OK;
 }
 
 struct SolveOut {
@@ -1448,7 +1493,6 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   if (any_guess) {  // r = b - A x0 for warm starts
     TRY(set_flags(E, fcg, fru));
     TRY(reliable_update<R>(E, P.truth_tol, 3));
-    TRY(read_scalars(E));
     for (int s = 0; s < ns; ++s)
       if (fru[s]) {
         const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
@@ -1602,7 +1646,6 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
                               ? P.truth_tol
                               : std::max(P.truth_tol, std::min(1e-6, P.truth_relax * best_rec));
       TRY(reliable_update<R>(E, ttol, restart ? 7 : 3));
-      TRY(read_scalars(E));
       for (int s = 0; s < ns; ++s) {
         if (!fru[s]) continue;
         out.ru[s]++;
