@@ -1638,6 +1638,21 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         best_rec = std::min(best_rec, rec);
       }
     }
+    if (need_ru && ns > 1 && delta > 0.0) {
+      // Batched systems drop by delta at different iterations; each update launches the
+      // FP64 multi-shift passes over the whole batch however few systems take part.  A
+      // system that is more than halfway there (in log scale) joins now, which keeps the
+      // updates of a batch together and cuts the number of update launch sequences.
+      const double half = std::sqrt(delta);
+      for (int s = 0; s < ns; ++s) {
+        if (!fcg[s] || fru[s]) continue;
+        const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_RR];
+        if (std::sqrt(rr) < half * rmax[s]) {
+          fru[s] = 1;
+          best_rec = std::min(best_rec, kap[s] * std::sqrt(rr) / bn[s]);
+        }
+      }
+    }
     if (need_ru) {
       TRY(set_flags(E, fcg, fru));
       // One multi-shift tolerance serves every updated system, so it follows the
