@@ -55,6 +55,8 @@ struct SysDev {
   double* coef_term;        // [MAXP * cap]
   double* coef_c;           // [cap+1]
   double* coef_d;           // [cap]
+  double* coef_d2;          // [cap] non-null: also the coefficients of H r(A)^2 psi (k_ms_coef)
+  double* coef_sq;          // [(2 MAXP + 1) cap] scratch of those coefficients
   // epilogue / CG
   const double2* phi;       // [V] background scalar
   const void* e_in;         // operator input psi (spin-planar, kernel precision)
@@ -849,6 +851,61 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
     double mx = 0.0;
     for (int k = 0; k < np; ++k) mx = fmax(mx, sh_res[k]);
     S.dstat[0] = mx;
+  }
+  if (!S.coef_d2 || N == 0) return;
+  // Second function of the same Krylov space (entries with coef_d2 set):
+  //   w = H r(A)^2 psi = sum_j d2_j t_j,   so that eps^2 psi = A r(A)^2 psi = H w.
+  // The CG scalars give the Lanczos tridiagonal of A on v_j = (-1)^j r_j / |r_j|:
+  //   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_j,j+1 = sqrt(beta_j)/alpha_j,
+  // and r(A)^2 psi ~ |psi| V r(T)^2 e_1 with r(T)^2 e_1 = sum_l a_l (T + b_l)^-1 g,
+  // g = sum_k a_k (T + b_k)^-1 e_1: 2 np tridiagonal solves (T + b is positive definite,
+  // elimination without pivoting is stable), one thread per shift.  Coefficients on r_j:
+  // c2_j = |psi| (-1)^j h_j / |r_j|; on t_j: d2_j = c2_j - beta_j c2_{j+1}.
+  double* U = S.coef_sq;                       // [MAXP][cap]: solutions per shift
+  double* CP = S.coef_sq + (size_t)MAXP * cap;  // [MAXP][cap]: elimination multipliers
+  double* G = S.coef_sq + (size_t)2 * MAXP * cap;  // [cap]
+  auto tdiag = [&](int j) {
+    return 1.0 / alph[j] + (j > 0 ? (rho[j] / rho[j - 1]) / alph[j - 1] : 0.0);
+  };
+  auto toff = [&](int j) { return sqrt(rho[j + 1] / rho[j]) / alph[j]; };
+  auto solve = [&](int k, bool from_g) {
+    double* u = U + (size_t)k * cap;
+    double* cp = CP + (size_t)k * cap;
+    const double bk = mp->sigma[k];
+    double cprev = 0.0, dprev = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const double ol = j > 0 ? toff(j - 1) : 0.0;
+      const double m = tdiag(j) + bk - ol * cprev;
+      const double cj = j + 1 < N ? toff(j) / m : 0.0;
+      const double rhs = from_g ? G[j] : (j == 0 ? 1.0 : 0.0);
+      const double dj = (rhs - ol * dprev) / m;
+      cp[j] = cj;
+      u[j] = dj;
+      cprev = cj;
+      dprev = dj;
+    }
+    for (int j = N - 2; j >= 0; --j) u[j] -= cp[j] * u[j + 1];
+  };
+  if (threadIdx.x < np) solve(threadIdx.x, false);
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    double g = 0.0;
+    for (int k = 0; k < np; ++k) g += mp->coef[k] * U[(size_t)k * cap + j];
+    G[j] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x < np) solve(threadIdx.x, true);
+  __syncthreads();
+  const double sr0 = sqrt(rho[0]);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    double h = 0.0;
+    for (int k = 0; k < np; ++k) h += mp->coef[k] * U[(size_t)k * cap + j];
+    G[j] = sr0 * ((j & 1) ? -h : h) / sqrt(rho[j]);  // c2_j
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const double cn = (j + 1 < N) ? G[j + 1] : 0.0;
+    S.coef_d2[j] = G[j] - (rho[j + 1] / rho[j]) * cn;
   }
 }
 
@@ -1687,6 +1744,102 @@ __global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ t
   }
   const double tot = block_sum(acc, lds);
   if (threadIdx.x == 0) A.part_c[lb] = tot;
+}
+
+// ------------------------ FP64 true residual in Ginsparg-Wilson form (Sec. 2.2)
+// For any Hermitian eps, D = 1 + g5 eps gives D^dag D = 1 + g5 eps + eps g5 + eps^2, so
+//   MdagM x = |1 + c|^2 x + (1 + c*) g5 eps(x) + eps(g5 (1 + Y) x) + eps^2 x
+// exactly (rational eps included).  One multi-shift with the two sources x (entry A)
+// and g5 (1 + Y) x (entry B) provides eps(x), eps(g5 (1 + Y) x) and, from the Krylov
+// space of x, w = H r(A)^2 x (coef_d2), with eps^2 x = H w: the true residual needs one
+// multi-shift depth instead of two (M, then M^dag).
+// combine: P = |1 + c|^2 x + (1 + c*) g5 e1 + e23 -> A.e_out, w -> A.e_out2; x = A.e_in.
+__global__ void __launch_bounds__(256) k_truth_combine(const SysDev* __restrict__ ta,
+                                                       const SysDev* __restrict__ tb,
+                                                       const int* __restrict__ bmap, int nb_total) {
+  const int L = xcd_logical_block(nb_total);
+  const int s = bmap[L];
+  const SysDev& A = ta[s];
+  const SysDev& B = tb[s];
+  if (A.active && *A.active == 0) return;
+  const int lb = L - A.blk0;
+  const int V = A.g.V;
+  const size_t slot = (size_t)4 * V;
+  const int NA = A.h_ctl[1], NB = B.h_ctl[1];
+  const int i0 = lb * A.spb;
+  const int i1 = min(V, i0 + A.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 e1[4], w[4], e2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e1[k] = w[k] = double2{0.0, 0.0};
+    for (int j = 0; j < NA; ++j) {
+      const double d = A.coef_d[j], d2 = A.coef_d2[j];
+      double2 t[4];
+      load_sp<double>((const double2*)A.basis + (size_t)j * slot, V, i, t);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        e1[k] = double2{e1[k].x + d * t[k].x, e1[k].y + d * t[k].y};
+        w[k] = double2{w[k].x + d2 * t[k].x, w[k].y + d2 * t[k].y};
+      }
+    }
+    basis_sum<double>((const double2*)B.basis, B.coef_d, NB, slot, V, i, e2);
+    double2 x[4];
+    load_sp<double>((const double2*)A.e_in, V, i, x);
+    const double2 ph = A.phi[i];
+    const double cpr = A.m_re + A.g_re * ph.x - A.g_im * ph.y;
+    const double cpi = A.m_im + A.g_re * ph.y + A.g_im * ph.x;
+    double2 P[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double cr = cpr, ci = (k < 2) ? -cpi : cpi;
+      const double g5 = k < 2 ? -1.0 : 1.0;
+      const double a = (1.0 + cr) * (1.0 + cr) + ci * ci;  // |1 + c|^2
+      const double br = 1.0 + cr, bi = -ci;                // 1 + c*
+      const double fr = g5 * (br * e1[k].x - bi * e1[k].y);
+      const double fi = g5 * (br * e1[k].y + bi * e1[k].x);
+      P[k] = double2{a * x[k].x + fr + e2[k].x, a * x[k].y + fi + e2[k].y};
+    }
+    store_sp<double>((double2*)A.e_out, V, i, P);
+    store_sp<double>((double2*)A.e_out2, V, i, w);
+  }
+}
+
+// finish: r64 = b - P - H w (H w = eps^2 x), low-precision copy in cg_r when set,
+// partial |r64|^2 -> part_c.  P = e_out, w = e_out2, b = cg_b (AoS), r64 = cg_r64.
+template <class R>
+__global__ void __launch_bounds__(256) k_truth_finish(const SysDev* __restrict__ sys,
+                                                      const int* __restrict__ bmap, int nb_total,
+                                                      double diag) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const Geo g = S.g;
+  const int V = g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double2 hw[4], P[4], rr[4];
+    hw_site<double>((const double2*)S.e_out2, g, i, diag, hw);
+    load_sp<double>((const double2*)S.e_out, V, i, P);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 bv = S.cg_b[(size_t)i * 4 + k];
+      rr[k] = double2{bv.x - P[k].x - hw[k].x, bv.y - P[k].y - hw[k].y};
+    }
+    store_sp<double>((double2*)S.cg_r64, V, i, rr);
+    if (S.cg_r) {
+      c2<R> lo[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) lo[k] = c2<R>{(R)rr[k].x, (R)rr[k].y};
+      store_sp<R>((c2<R>*)S.cg_r, V, i, lo);
+    }
+    acc += norm2_sp(rr);
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_c[lb] = tot;
 }
 
 // ------------------------------------------------- RHMC bosonic action (eq. acws)

@@ -165,6 +165,17 @@ struct SysBuf {
   double* ms_b_dstat = nullptr;
   double *ms_b_coef_term = nullptr, *ms_b_coef_c = nullptr, *ms_b_coef_d = nullptr;
   long long* ms_b_stat = nullptr;
+  // FP64 true residual in Ginsparg-Wilson form: entry B twins (tb_*) and entry A's
+  // coefficients of H r(A)^2 x with their scratch
+  double2 *tb_basis = nullptr, *tb_r = nullptr, *tb_src = nullptr;
+  double *tb_part_a = nullptr, *tb_part_b = nullptr, *tb_part_c = nullptr;
+  double *tb_h_rho = nullptr, *tb_h_alpha = nullptr, *tb_h_zeta = nullptr;
+  unsigned* tb_h_active = nullptr;
+  int* tb_h_ctl = nullptr;
+  double* tb_dstat = nullptr;
+  double *tb_coef_term = nullptr, *tb_coef_c = nullptr, *tb_coef_d = nullptr;
+  long long* tb_stat = nullptr;
+  double *coef_d2 = nullptr, *coef_sq = nullptr;
   double2 *shx = nullptr, *shp = nullptr;  // multi-shift CG on MdagM: solutions, directions
   double* shc = nullptr;        //   per-shift coefficients
   int nshift = 0;
@@ -275,6 +286,23 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.ms_b_coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
     s.ms_b_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.ms_b_coef_d = (double*)bp.take(sizeof(double) * capmax);
+    s.tb_basis = (double2*)bp.take(v64 * pl.cap64);
+    s.tb_r = (double2*)bp.take(v64);
+    s.tb_src = (double2*)bp.take(v64);
+    s.tb_part_a = (double*)bp.take(sizeof(double) * s.nblk);
+    s.tb_part_b = (double*)bp.take(sizeof(double) * s.nblk);
+    s.tb_part_c = (double*)bp.take(sizeof(double) * s.nblk);
+    s.tb_h_rho = (double*)bp.take(sizeof(double) * (capmax + 1));
+    s.tb_h_alpha = (double*)bp.take(sizeof(double) * (capmax + 1));
+    s.tb_h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
+    s.tb_h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
+    s.tb_h_ctl = (int*)bp.take(sizeof(int) * 4);
+    s.tb_dstat = (double*)bp.take(sizeof(double) * 2);
+    s.tb_coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
+    s.tb_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
+    s.tb_coef_d = (double*)bp.take(sizeof(double) * capmax);
+    s.coef_d2 = (double*)bp.take(sizeof(double) * capmax);
+    s.coef_sq = (double*)bp.take(sizeof(double) * (2 * MAXP + 1) * capmax);
   }
 }
 
@@ -338,12 +366,15 @@ struct Engine {
   int* gwbmap = nullptr;            // device: 2 nb_total workgroups -> entry
   std::vector<int> hgwbmap;
   std::vector<SysDev> hgwtab;       // host copy of gwtab
+  SysDev* trgwtab = nullptr;        // device: 2 nsys entries of the FP64 true residual (same map)
+  std::vector<SysDev> htrgw;        // host copy
 
   size_t layout(void* base, size_t cap, bool dry) {
     Bump bp(base, cap, dry);
     gbar = (GridBar*)bp.take(sizeof(GridBar));
     cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys);
-    stat_all = (long long*)bp.take(sizeof(long long) * 8 * nsys);  // entries A then B
+    // counters of entries A, B (inner) and B (true residual)
+    stat_all = (long long*)bp.take(sizeof(long long) * 12 * nsys);
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0, nxy = 0, nz = 0, nt = 0;
     long long total_sites = 0;
@@ -372,6 +403,7 @@ struct Engine {
       b.cg_s = dry ? nullptr : cg_all + (size_t)s * CG_NSLOT;
       b.stat = dry ? nullptr : stat_all + (size_t)s * 4;
       b.ms_b_stat = (dry || !pl.gw) ? nullptr : stat_all + (size_t)(nsys + s) * 4;
+      b.tb_stat = (dry || !pl.gw) ? nullptr : stat_all + (size_t)(2 * nsys + s) * 4;
       b.act_cg = dry ? nullptr : act_all + s;
       b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
@@ -383,6 +415,7 @@ struct Engine {
     ftab = pl.nshift > 0 ? (SysDev*)bp.take(sizeof(SysDev) * nsys * pl.nshift) : nullptr;
     gwtab = pl.gw ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
     gwbmap = pl.gw ? (int*)bp.take(sizeof(int) * 2 * (size_t)nb_total) : nullptr;
+    trgwtab = pl.gw ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
     hgwbmap.clear();
     if (pl.gw) {
       hgwbmap.assign(2 * (size_t)nb_total, 0);
@@ -429,7 +462,7 @@ ov_status ensure_pinned(ov_ctx* c, int nsys) {
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   c->pinned = nullptr;
   c->pinned_flags = nullptr;
-  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 8) * nsys));
+  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 12) * nsys));
   HIPCHK(c, hipHostMalloc((void**)&c->pinned_flags, sizeof(int) * 2 * nsys + 64));
   c->pinned_n = nsys;
   return OV_OK;
@@ -534,6 +567,8 @@ ov_status upload_tables(Engine& E) {
                                 hipMemcpyHostToDevice, E.st));
   if (E.pl.gw && E.hgwtab.size() == 2 * (size_t)E.nsys) {
     HIPCHK(E.lead, hipMemcpyAsync(E.gwtab, E.hgwtab.data(), sizeof(SysDev) * E.hgwtab.size(),
+                                  hipMemcpyHostToDevice, E.st));
+    HIPCHK(E.lead, hipMemcpyAsync(E.trgwtab, E.htrgw.data(), sizeof(SysDev) * E.htrgw.size(),
                                   hipMemcpyHostToDevice, E.st));
     HIPCHK(E.lead, hipMemcpyAsync(E.gwbmap, E.hgwbmap.data(), sizeof(int) * E.hgwbmap.size(),
                                   hipMemcpyHostToDevice, E.st));
@@ -786,7 +821,7 @@ ov_status read_ctl(Engine& E, std::vector<int>& ctl3, std::vector<long long>& st
   ctl3.resize(E.nsys);
   stat0.resize(E.nsys);
   dstat0.resize(E.nsys);
-  std::vector<long long> statb(E.nsys, 0);
+  std::vector<long long> statb(E.nsys, 0), statt(E.nsys, 0);
   std::vector<int> ctlb(E.nsys, 0);
   for (int s = 0; s < E.nsys; ++s) {
     HIPCHK(E.lead, hipMemcpyAsync(&ctl3[s], E.sb[s].h_ctl + 3, sizeof(int),
@@ -801,10 +836,13 @@ ov_status read_ctl(Engine& E, std::vector<int>& ctl3, std::vector<long long>& st
       HIPCHK(E.lead, hipMemcpyAsync(&ctlb[s], E.sb[s].ms_b_h_ctl + 3, sizeof(int),
                                     hipMemcpyDeviceToHost, E.st));
     }
+    if (E.sb[s].tb_stat)  // entry B of the true residuals (iteration counts only)
+      HIPCHK(E.lead, hipMemcpyAsync(&statt[s], E.sb[s].tb_stat, sizeof(long long),
+                                    hipMemcpyDeviceToHost, E.st));
   }
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
   for (int s = 0; s < E.nsys; ++s) {
-    stat0[s] += statb[s];
+    stat0[s] += statb[s] + statt[s];
     ctl3[s] |= ctlb[s];
   }
   return OV_OK;
@@ -819,6 +857,11 @@ ov_status reset_stats(Engine& E) {
       HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_h_ctl, 0, sizeof(int) * 4, E.st));
       HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_stat, 0, sizeof(long long) * 4, E.st));
       HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_dstat, 0, sizeof(double) * 2, E.st));
+    }
+    if (E.sb[s].tb_stat) {
+      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].tb_h_ctl, 0, sizeof(int) * 4, E.st));
+      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].tb_stat, 0, sizeof(long long) * 4, E.st));
+      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].tb_dstat, 0, sizeof(double) * 2, E.st));
     }
   }
   return OV_OK;
@@ -1048,6 +1091,25 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
       const SysDev* A = &E.hgwtab[s];
       ok &= need(100, s, A->e_in, "e_in") && need(100, s, A->e_out, "e_out") &&
             need(100, s, A->cg_s, "cg_s") && need(T_CG, s, T[T_CG]->e_in, "e_in");
+      // the FP64 true residual's two entries, its combine and finish
+      for (int e = 0; e < 2; ++e) {
+        const SysDev* G = &E.htrgw[(size_t)e * E.nsys + s];
+        const int t = 110 + e;
+        ok &= need(t, s, G->basis, "basis") && need(t, s, G->r, "r") && need(t, s, G->src, "src") &&
+              need(t, s, G->part_a, "part_a") && need(t, s, G->part_b, "part_b") &&
+              need(t, s, G->part_c, "part_c") && need(t, s, G->h_rho, "h_rho") &&
+              need(t, s, G->h_alpha, "h_alpha") && need(t, s, G->h_zeta, "h_zeta") &&
+              need(t, s, G->h_active, "h_active") && need(t, s, G->h_ctl, "h_ctl") &&
+              need(t, s, G->coef_term, "coef_term") && need(t, s, G->coef_c, "coef_c") &&
+              need(t, s, G->coef_d, "coef_d") && need(t, s, G->stat, "stat") &&
+              need(t, s, G->dstat, "dstat") && need(t, s, G->active, "active") &&
+              need(t, s, G->phi, "phi");
+      }
+      const SysDev* TA = &E.htrgw[s];
+      ok &= need(110, s, TA->e_in, "e_in") && need(110, s, TA->e_out, "e_out") &&
+            need(110, s, TA->e_out2, "e_out2") && need(110, s, TA->coef_d2, "coef_d2") &&
+            need(110, s, TA->coef_sq, "coef_sq") && need(110, s, TA->cg_b, "cg_b") &&
+            need(110, s, TA->cg_r64, "cg_r64");
     }
     if (!ok) return OV_ERR_DEVICE;
   }
@@ -1059,6 +1121,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
                              const std::vector<const void*>& phi) {
   E.htab.assign((size_t)T_NT * E.nsys, SysDev{});
   E.hgwtab.assign(E.pl.gw ? 2 * (size_t)E.nsys : 0, SysDev{});
+  E.htrgw.assign(E.pl.gw ? 2 * (size_t)E.nsys : 0, SysDev{});
   for (int s = 0; s < E.nsys; ++s) {
     SysBuf& b = E.sb[s];
     SysDev d = base_dev(b);
@@ -1196,6 +1259,36 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
       gb.cg_s = nullptr;
       E.hgwtab[s] = ga;
       E.hgwtab[E.nsys + s] = gb;
+      // FP64 true residual: entry A on x64 (also the finish: r64 = b - P - H w),
+      // entry B on g5 (1 + Y) x64 with the FP64 twins
+      SysDev ta = tm;
+      ta.coef_d2 = b.coef_d2;
+      ta.coef_sq = b.coef_sq;
+      ta.cg_b = (const double2*)bvec[s];
+      ta.cg_r64 = b.r64;
+      ta.cg_r = tmd.cg_r;
+      SysDev tbb = d;
+      tbb.active = b.act_ru;
+      tbb.blk0 = b.blk0 + E.nb_total;
+      tbb.basis = b.tb_basis;
+      tbb.r = b.tb_r;
+      tbb.src = b.tb_src;
+      tbb.part_a = b.tb_part_a;
+      tbb.part_b = b.tb_part_b;
+      tbb.part_c = b.tb_part_c;
+      tbb.h_rho = b.tb_h_rho;
+      tbb.h_alpha = b.tb_h_alpha;
+      tbb.h_zeta = b.tb_h_zeta;
+      tbb.h_active = b.tb_h_active;
+      tbb.h_ctl = b.tb_h_ctl;
+      tbb.stat = b.tb_stat;
+      tbb.dstat = b.tb_dstat;
+      tbb.coef_term = b.tb_coef_term;
+      tbb.coef_c = b.tb_coef_c;
+      tbb.coef_d = b.tb_coef_d;
+      tbb.cg_s = nullptr;
+      E.htrgw[s] = ta;
+      E.htrgw[E.nsys + s] = tbb;
     }
     E.htab[(size_t)T_IN_M * E.nsys + s] = im;
     E.htab[(size_t)T_IN_MDAG * E.nsys + s] = imd;
@@ -1230,7 +1323,7 @@ ov_status read_scalars(Engine& E) {
   HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all, sizeof(double) * CG_NSLOT * E.nsys,
                                 hipMemcpyDeviceToHost, E.st));
   HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned + (size_t)CG_NSLOT * E.nsys, E.stat_all,
-                                sizeof(long long) * 8 * E.nsys, hipMemcpyDeviceToHost, E.st));
+                                sizeof(long long) * 12 * E.nsys, hipMemcpyDeviceToHost, E.st));
   return sync(E);
 }
 
@@ -1239,7 +1332,10 @@ ov_status read_scalars(Engine& E) {
 int last_truth_iters(const Engine& E) {
   const long long* st = (const long long*)(E.lead->pinned + (size_t)CG_NSLOT * E.nsys);
   long long m = 0;
-  for (int s = 0; s < E.nsys; ++s) m = std::max(m, st[(size_t)s * 4 + 3]);
+  for (int s = 0; s < E.nsys; ++s) {
+    m = std::max(m, st[(size_t)s * 4 + 3]);
+    if (E.pl.gw) m = std::max(m, st[(size_t)(2 * E.nsys + s) * 4 + 3]);  // its entry B
+  }
   return (int)m;
 }
 
@@ -1325,10 +1421,19 @@ namespace {
 // FP64 true residual r64 = b - MdagM x64 (inner-precision copy into rcgR) with
 // multi-shift tolerance tol, and its norm through k_cg_scalar(scalar_op).
 // The tolerance is rounded down to a power of ten so that few graphs exist.
+// Multi-shift tolerance of a true residual at tolerance tol: the Ginsparg-Wilson form
+// takes eps^2 x from the Krylov space of x, about ten times less accurate than the
+// shifted solutions themselves, so the final check (tol = truth_tol) runs ten times
+// tighter; intermediate updates tolerate that much by construction (truth_relax).
+double truth_ms_tol(const Engine& E, double tol) {
+  const bool final_check = tol <= E.lead->p.truth_tol * 1.0000001;
+  return (E.pl.gw && !E.pl.fft && final_check) ? 0.1 * tol : tol;
+}
+
 template <class R>
 ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
   const ov_ctx* c = E.lead;
-  const MsParams mp = make_mp(c, tol, E.pl.cap64);
+  const MsParams mp = make_mp(c, truth_ms_tol(E, tol), E.pl.cap64);
   const bool pc = E.pl.pc;
   char key[96];
   std::snprintf(key, sizeof key, "ru|%zu|%.3e|%d|%d|%d|%d", sizeof(R), tol, L, scalar_op, (int)pc,
@@ -1351,6 +1456,13 @@ ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
       k_yuk<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_F_TM), E.bmap, E.nb_total, 0);
       launch_sym<double>(E, T_F_TMD, SYM_D_DAG);
       k_yuk<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_F_TMD), E.bmap, E.nb_total, 2);
+    } else if (E.pl.gw) {  // one two-source multi-shift (see k_truth_combine)
+      const int nb = E.nb_total, ns = E.nsys;
+      k_stat3_clear<<<1, 64, 0, E.st>>>(E.trgwtab, 2 * ns);
+      k_gw_prep<double><<<nb, c->block, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
+      launch_ms_tab<double>(E, E.trgwtab, E.gwbmap, 2 * nb, 2 * ns, mp, L);
+      k_truth_combine<<<nb, c->block, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
+      k_truth_finish<R><<<nb, c->block, 0, E.st>>>(E.trgwtab, E.bmap, nb, 4.0 - c->p.M0);
     } else {
       k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_TR_M), E.bmap, E.nb_total, 0);
       launch_ms<double>(E, T_TR_M, mp, L);
@@ -1387,7 +1499,8 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
   ov_ctx* c = E.lead;
   tol = std::pow(10.0, std::floor(std::log10(tol) + 1e-9));
   int Lfull = 0;
-  for (int s = 0; s < E.nsys; ++s) Lfull = std::max(Lfull, capacity(E.ctxs[s], tol));
+  for (int s = 0; s < E.nsys; ++s)
+    Lfull = std::max(Lfull, capacity(E.ctxs[s], truth_ms_tol(E, tol)));
   Lfull = std::min(E.pl.cap64, Lfull);
   if (E.pl.fft) {
     TRY(reliable_update_L<R>(E, tol, scalar_op, Lfull));
