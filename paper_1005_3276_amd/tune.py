@@ -39,12 +39,33 @@ def probe(lattice, prec, nrhs, block, spt, iters=24):
     return us.value
 
 
-def autotune(lattice, prec=1, nrhs=1, iters=24, candidates=CANDIDATES):
-    """Pick (block, sites_per_thread) for this lattice; returns (choice, timings)."""
+def _time_workload(workload, reps=2):
+    import time
+    import torch
+    workload()  # warm (graphs, iteration estimates)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t = time.perf_counter()
+        workload()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best * 1e6
+
+
+def autotune(lattice, prec=1, nrhs=1, iters=24, candidates=CANDIDATES, workload=None, tag=""):
+    """Pick (block, sites_per_thread) for this lattice; returns (choice, timings in us).
+
+    Without ``workload`` each candidate is timed on ``iters`` multi-shift iterations
+    (``ov_tune_ms``); with it (a callable running the real work on this lattice, e.g.
+    one solve) on that work itself, and ``tag`` names it in the cache key.
+    """
     mode = os.environ.get("OV_TUNE", "1")
     if mode == "0":
         return None, {}
     key = f"{_arch()}|{'x'.join(map(str, lattice.dims))}|{'fp32' if prec else 'fp64'}|{nrhs}"
+    if workload is not None:
+        key += f"|{tag or 'workload'}"
     path = _cache_path()
     cache = {}
     if os.path.exists(path):
@@ -59,8 +80,12 @@ def autotune(lattice, prec=1, nrhs=1, iters=24, candidates=CANDIDATES):
         return (b, s), cache[key].get("us", {})
     timings = {}
     for b, s in candidates:
-        probe(lattice, prec, nrhs, b, s, iters=4)  # warm the code path
-        timings[f"{b}x{s}"] = probe(lattice, prec, nrhs, b, s, iters=iters)
+        if workload is not None:
+            lattice.set_launch(b, s)
+            timings[f"{b}x{s}"] = _time_workload(workload)
+        else:
+            probe(lattice, prec, nrhs, b, s, iters=4)  # warm the code path
+            timings[f"{b}x{s}"] = probe(lattice, prec, nrhs, b, s, iters=iters)
     best = min(timings, key=timings.get)
     b, s = (int(v) for v in best.split("x"))
     lattice.set_launch(b, s)

@@ -684,6 +684,27 @@ def test_autotune_choices_agree(tmp_path, monkeypatch):
             assert rel(out, ref) < 1e-12
 
 
+def test_autotune_on_solve(tmp_path, monkeypatch):
+    """Tuning on the real work (one mixed solve per candidate) picks a candidate,
+    caches it under its own key, and the chosen shape still meets the 1e-10 residual."""
+    monkeypatch.setenv("OV_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setenv("OV_TUNE", "1")
+    from paper_1005_3276_amd import tune
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    b, p = dev(src), dev(phi)
+    lat = lattice(dims, precision="mixed", outer_tol=1e-10, **CFG2)
+    choice, timings = tune.autotune(lat, prec=1, nrhs=1, workload=lambda: lat.solve(b, p),
+                                    tag="solve")
+    print(f"[tune-solve] {choice} {timings}", flush=True)
+    assert choice in tune.CANDIDATES and len(timings) == len(tune.CANDIDATES)
+    assert all(v > 0 for v in timings.values())
+    choice2, _ = tune.autotune(lat, prec=1, nrhs=1, workload=lambda: lat.solve(b, p), tag="solve")
+    assert choice2 == choice
+    _, st = lat.solve(b, p)
+    assert st[0]["true_rel_res"] <= 1e-10
+
+
 # ------------------------------------------------- RHMC rational layers (Sec. 7.3)
 
 RAT_LO, RAT_HI = 1e-5, 10.0
