@@ -344,7 +344,7 @@ def main():
     spans = [lat.kernel_spans(k) for k in range(5)]  # (kernel_ms, kcnt, event_ms, cnt, bytes)
     families = {
         "fp64_truth": ((3, 4), "k_ms_t<double> + k_ms_r<double> (FP64 multi-shift passes of "
-                               "the true residuals)"),
+                               "the true residuals, two sources per launch)"),
         "fp32_inner": ((0, 1), "k_ms_t<float> + k_ms_r<float> (FP32 multi-shift passes of "
                                "the inner CG, two sources per launch)"),
     }

@@ -56,7 +56,7 @@ struct SysDev {
   double* coef_c;           // [cap+1]
   double* coef_d;           // [cap]
   double* coef_d2;          // [cap] non-null: also the coefficients of H r(A)^2 psi (k_ms_coef)
-  double* coef_sq;          // [(2 MAXP + 1) cap] scratch of those coefficients
+  double* coef_sq;          // [(2 MAXP + 2) cap] scratch of those coefficients
   // epilogue / CG
   const double2* phi;       // [V] background scalar
   const void* e_in;         // operator input psi (spin-planar, kernel precision)
@@ -773,6 +773,10 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
   __shared__ double l_alpha[COEF_LDS_ITERS + 1];
   __shared__ unsigned int l_act[COEF_LDS_ITERS + 1];
   __shared__ double l_zeta[(COEF_LDS_ITERS + 1) * MAXP];
+  // second-function coefficients (entries with coef_d2): tridiagonal solves per shift
+  __shared__ double l_u[MAXP][COEF_LDS_ITERS + 1];
+  __shared__ double l_cp[MAXP][COEF_LDS_ITERS + 1];
+  __shared__ double l_g[COEF_LDS_ITERS + 1], l_td[COEF_LDS_ITERS + 1], l_to[COEF_LDS_ITERS + 1];
   const int s = blockIdx.x;
   if (s >= nsys) return;
   const SysDev& S = sys[s];
@@ -861,36 +865,46 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
   // g = sum_k a_k (T + b_k)^-1 e_1: 2 np tridiagonal solves (T + b is positive definite,
   // elimination without pivoting is stable), one thread per shift.  Coefficients on r_j:
   // c2_j = |psi| (-1)^j h_j / |r_j|; on t_j: d2_j = c2_j - beta_j c2_{j+1}.
-  double* U = S.coef_sq;                       // [MAXP][cap]: solutions per shift
-  double* CP = S.coef_sq + (size_t)MAXP * cap;  // [MAXP][cap]: elimination multipliers
-  double* G = S.coef_sq + (size_t)2 * MAXP * cap;  // [cap]
-  auto tdiag = [&](int j) {
-    return 1.0 / alph[j] + (j > 0 ? (rho[j] / rho[j - 1]) / alph[j - 1] : 0.0);
-  };
-  auto toff = [&](int j) { return sqrt(rho[j + 1] / rho[j]) / alph[j]; };
+  // Work arrays in LDS while the history is staged there (N <= COEF_LDS_ITERS), else
+  // in the entry's global scratch coef_sq; T's entries are computed once.
+  const int ld = staged ? COEF_LDS_ITERS + 1 : cap;
+  double* U = staged ? &l_u[0][0] : S.coef_sq;                                // [MAXP][ld]
+  double* CP = staged ? &l_cp[0][0] : S.coef_sq + (size_t)MAXP * cap;          // [MAXP][ld]
+  double* G = staged ? l_g : S.coef_sq + (size_t)2 * MAXP * cap;              // [ld]
+  double* TD = staged ? l_td : S.coef_sq + (size_t)2 * MAXP * cap + cap;      // [ld]
+  double* TO = staged ? l_to : S.coef_term;  // the shifts' terms are consumed by now
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    TD[j] = 1.0 / alph[j] + (j > 0 ? (rho[j] / rho[j - 1]) / alph[j - 1] : 0.0);
+    TO[j] = sqrt(rho[j + 1] / rho[j]) / alph[j];
+  }
+  __syncthreads();
   auto solve = [&](int k, bool from_g) {
-    double* u = U + (size_t)k * cap;
-    double* cp = CP + (size_t)k * cap;
+    double* u = U + (size_t)k * ld;
+    double* cp = CP + (size_t)k * ld;
     const double bk = mp->sigma[k];
     double cprev = 0.0, dprev = 0.0;
     for (int j = 0; j < N; ++j) {
-      const double ol = j > 0 ? toff(j - 1) : 0.0;
-      const double m = tdiag(j) + bk - ol * cprev;
-      const double cj = j + 1 < N ? toff(j) / m : 0.0;
+      const double ol = j > 0 ? TO[j - 1] : 0.0;
+      const double inv = 1.0 / (TD[j] + bk - ol * cprev);
+      const double cj = j + 1 < N ? TO[j] * inv : 0.0;
       const double rhs = from_g ? G[j] : (j == 0 ? 1.0 : 0.0);
-      const double dj = (rhs - ol * dprev) / m;
+      const double dj = (rhs - ol * dprev) * inv;
       cp[j] = cj;
       u[j] = dj;
       cprev = cj;
       dprev = dj;
     }
-    for (int j = N - 2; j >= 0; --j) u[j] -= cp[j] * u[j + 1];
+    double un = dprev;
+    for (int j = N - 2; j >= 0; --j) {
+      un = u[j] - cp[j] * un;
+      u[j] = un;
+    }
   };
   if (threadIdx.x < np) solve(threadIdx.x, false);
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     double g = 0.0;
-    for (int k = 0; k < np; ++k) g += mp->coef[k] * U[(size_t)k * cap + j];
+    for (int k = 0; k < np; ++k) g += mp->coef[k] * U[(size_t)k * ld + j];
     G[j] = g;
   }
   __syncthreads();
@@ -899,7 +913,7 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
   const double sr0 = sqrt(rho[0]);
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     double h = 0.0;
-    for (int k = 0; k < np; ++k) h += mp->coef[k] * U[(size_t)k * cap + j];
+    for (int k = 0; k < np; ++k) h += mp->coef[k] * U[(size_t)k * ld + j];
     G[j] = sr0 * ((j & 1) ? -h : h) / sqrt(rho[j]);  // c2_j
   }
   __syncthreads();

@@ -307,7 +307,7 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.tb_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.tb_coef_d = (double*)bp.take(sizeof(double) * capmax);
     s.coef_d2 = (double*)bp.take(sizeof(double) * capmax);
-    s.coef_sq = (double*)bp.take(sizeof(double) * (2 * MAXP + 1) * capmax);
+    s.coef_sq = (double*)bp.take(sizeof(double) * (2 * MAXP + 2) * capmax);
   }
 }
 
