@@ -122,15 +122,19 @@ typedef struct {
                               final check) use the multi-shift tolerance
                               max(truth_tol, min(1e-6, truth_relax * recursive residual));
                               default 0.01 */
-  int inner_form;          /* MdagM of the CG iterations for OV_DIRAC_OVERLAP_MS:
-                              1 (default): the Ginsparg-Wilson form (Sec. 2.2: with
-                              eps^2 = 1, D^dag D = D + D^dag), which applies
+  int inner_form;          /* MdagM in the solvers for OV_DIRAC_OVERLAP_MS:
+                              1 (default): Ginsparg-Wilson form (Sec. 2.2).  The CG
+                              iterations take eps^2 = 1 (D^dag D = D + D^dag) and apply
                               (1 + |1 + c|^2) v + (1 + c*) g5 eps(v) + eps(g5 (1 + Y) v)
-                              with c the site's c- / c+ of Y, i.e. one multi-shift solve
-                              with two independent sources instead of two dependent
-                              ones.  It differs from MdagM only through 1 - eps^2 (the
-                              rational approximation error); the FP64 true residuals
-                              always apply M, then M^dag.  0: M, then M^dag. */
+                              with c the site's c- / c+ of Y: one multi-shift solve with
+                              two independent sources instead of two dependent ones,
+                              differing from MdagM only through 1 - eps^2 (the rational
+                              approximation error).  The FP64 true residuals apply the
+                              exact identity MdagM x = |1 + c|^2 x + (1 + c*) g5 eps(x)
+                              + eps(g5 (1 + Y) x) + eps^2 x, eps^2 x taken from the
+                              Krylov space of x of the same two-source multi-shift (the
+                              final check at truth_tol / 10).  0: M, then M^dag, for
+                              both. */
 } ov_params;
 
 typedef struct {
