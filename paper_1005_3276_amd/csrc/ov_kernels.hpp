@@ -257,6 +257,18 @@ __global__ void __launch_bounds__(256) k_hw_lds(const SysDev* __restrict__ sys, 
 // LDS, so each output site reads (ZC + 2)/ZC centre spinors plus its two time
 // neighbours from the memory hierarchy instead of nine spinors.  Every system
 // of the table has the same lattice.  Grid: nsys * T * (Z / ZC) workgroups.
+// Streaming store of a site's spinor: marked non-temporal so that the output lines do
+// not push the input planes, which neighbouring workgroups still read, out of L2.
+template <class R>
+__device__ __forceinline__ void store_sp_nt(c2<R>* __restrict__ f, int V, int i, const c2<R> v[4]) {
+  using E = R __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const E e = {v[s].x, v[s].y};
+    __builtin_nontemporal_store(e, (E*)(f + (size_t)s * V + i));
+  }
+}
+
 template <class R, int ZC>
 __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, double diag) {
   __shared__ c2<R> sh[4 * 256];
@@ -326,7 +338,7 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
       }
       c2<R> o[4];
       hw_compute<R>(nb, g, i, (R)diag, o);
-      store_sp<R>(out, V, i, o);
+      store_sp_nt<R>(out, V, i, o);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         prev[q] = cur[q];
@@ -503,7 +515,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
         for (int k2 = 0; k2 < 4; ++k2)
           o[k2] = c2<R>{o[k2].x + beta * qq[k2].x, o[k2].y + beta * qq[k2].y};
       }
-      store_sp<R>(tn, g.V, ii, o);
+      store_sp_nt<R>(tn, g.V, ii, o);
       return norm2_sp(o);
     });
     i = i1;  // every site done
@@ -515,7 +527,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
 #pragma unroll
       for (int k2 = 0; k2 < 4; ++k2) o[k2] = c2<R>{o[k2].x + beta * q[k2].x, o[k2].y + beta * q[k2].y};
     }
-    store_sp<R>(tn, g.V, i, o);
+    store_sp_nt<R>(tn, g.V, i, o);
     acc = norm2_sp(o);
   }
   // remaining sites of this block (sites per thread > 1)
@@ -527,7 +539,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
 #pragma unroll
       for (int k2 = 0; k2 < 4; ++k2) o[k2] = c2<R>{o[k2].x + beta * q[k2].x, o[k2].y + beta * q[k2].y};
     }
-    store_sp<R>(tn, g.V, i, o);
+    store_sp_nt<R>(tn, g.V, i, o);
     acc += norm2_sp(o);
   }
   const double tot = block_sum(acc, lds);
@@ -581,7 +593,7 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
       load_sp<R>(rin, g.V, ii, rr);
 #pragma unroll
       for (int k = 0; k < 4; ++k) rr[k] = c2<R>{rr[k].x - alpha * w[k].x, rr[k].y - alpha * w[k].y};
-      store_sp<R>(rout, g.V, ii, rr);
+      store_sp_nt<R>(rout, g.V, ii, rr);
       return norm2_sp(rr);
     });
     i = i1;
@@ -591,7 +603,7 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
     hw_compute<R>(nb, g, i, (R)mp->diag, w);
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[k] = c2<R>{r[k].x - alpha * w[k].x, r[k].y - alpha * w[k].y};
-    store_sp<R>(rout, g.V, i, r);
+    store_sp_nt<R>(rout, g.V, i, r);
     acc = norm2_sp(r);
   }
   for (i += blockDim.x; i < i1; i += blockDim.x) {
@@ -600,7 +612,7 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
     load_sp<R>(rin, g.V, i, r);
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[k] = c2<R>{r[k].x - alpha * w[k].x, r[k].y - alpha * w[k].y};
-    store_sp<R>(rout, g.V, i, r);
+    store_sp_nt<R>(rout, g.V, i, r);
     acc += norm2_sp(r);
   }
   const double tot = block_sum(acc, lds);
