@@ -69,6 +69,30 @@ def stencil_bandwidth(lat, torch, nrhs, prec, reps=20):
             "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def stencil_sweep(lat, torch):
+    """H_W alone at 16^4: 1, 12, 48 right-hand sides in FP32 and FP64, then beyond the
+    256 MB Infinity Cache (192 FP32 / 96 FP64 fields)."""
+    sweep = []
+    for prec in (1, 0):
+        for nrhs in (1, 12, 48):
+            sweep.append(stencil_bandwidth(lat, torch, nrhs, prec))
+            log(f"stencil {sweep[-1]}")
+    for nrhs, prec in ((192, 1), (96, 0)):
+        sweep.append(stencil_bandwidth(lat, torch, nrhs, prec))
+        log(f"stencil {sweep[-1]}")
+    return sweep
+
+
+def calibrate_copy(torch):
+    """One 512 MiB device copy: the reference dispatch for the traffic counters."""
+    nbytes = 512 << 20
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def copy_bandwidth(torch):
     """Read + write bandwidth of a plain device copy (torch) at the stencil's working
     set sizes: the streaming bandwidth this part reaches in practice."""
@@ -289,6 +313,8 @@ def main():
                     help="keep the default launch shape (256 threads, 1 site per thread at 16^4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 512 MiB device copy (reference for traffic counters)")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only the 16^4 stencil sweep (one JSON line of its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the batched and "
@@ -302,6 +328,17 @@ def main():
     from paper_1005_3276_amd import Lattice, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.stencil_only:
+        lat = Lattice(DIMS, **CFG)
+        stencil_bandwidth(lat, torch, 48, 1, reps=20)  # clocks up
+        sweep = stencil_sweep(lat, torch)
+        out = {"metric": "stencil_only", "stencil": sweep,
+               "stencil_best_TB_s": max(s["GB_s"] for s in sweep) / 1e3}
+        if args.calibrate_copy:
+            calibrate_copy(torch)
+            out["calibration_copy_bytes"] = 512 << 20
+        print(json.dumps(out), flush=True)
+        return
     phi, src = inputs.draw(DIMS, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
     dphi = torch.from_numpy(phi).cuda()
     dsrc = torch.from_numpy(src).cuda()
@@ -412,15 +449,7 @@ def main():
         best64 = max(extra[k]["solves_per_s"] for k in ("fp64_p1", "fp64_p2", "fp64_p3"))
         extra["mixed_speedup_vs_best_fp64"] = value / best64
         # ---- stencil bandwidth at 16^4
-        sweep = []
-        for prec in (1, 0):
-            for nrhs in (1, 12, 48):
-                sweep.append(stencil_bandwidth(lat, torch, nrhs, prec))
-                log(f"stencil {sweep[-1]}")
-        # beyond the 256 MB Infinity Cache: 16^4 x 192 (FP32) / x 96 (FP64) fields
-        sweep.append(stencil_bandwidth(lat, torch, 192, 1))
-        sweep.append(stencil_bandwidth(lat, torch, 96, 0))
-        log(f"stencil {sweep[-2]}\nstencil {sweep[-1]}")
+        sweep = stencil_sweep(lat, torch)
         extra["stencil"] = sweep
         extra["stencil_best_TB_s"] = max(s["GB_s"] for s in sweep) / 1e3
         extra["device_copy_TB_s"] = copy_bandwidth(torch)
@@ -463,13 +492,8 @@ def main():
     }
     out.update(extra)
     if args.calibrate_copy:
-        nbytes = 512 << 20
-        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = nbytes
+        calibrate_copy(torch)
+        out["calibration_copy_bytes"] = 512 << 20
     print(json.dumps(out), flush=True)
 
 
