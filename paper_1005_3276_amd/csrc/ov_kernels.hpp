@@ -1830,12 +1830,14 @@ __global__ void __launch_bounds__(256) k_truth_combine(const SysDev* __restrict_
   }
 }
 
-// finish: r64 = b - P - H w (H w = eps^2 x), low-precision copy in cg_r when set,
-// partial |r64|^2 -> part_c.  P = e_out, w = e_out2, b = cg_b (AoS), r64 = cg_r64.
+// finish, P = e_out, w = e_out2 (H w = eps^2 x):
+//   mode 0 (true residual): r64 = b - P - H w -> cg_r64 (b = cg_b, AoS), low-precision
+//          copy in cg_r when set, partial |r64|^2 -> part_c;
+//   mode 1 (product): W = P + H w = MdagM x -> cg_r64, partial Re <x, W> -> part_c, x = e_in.
 template <class R>
 __global__ void __launch_bounds__(256) k_truth_finish(const SysDev* __restrict__ sys,
                                                       const int* __restrict__ bmap, int nb_total,
-                                                      double diag) {
+                                                      double diag, int mode) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
@@ -1850,6 +1852,17 @@ __global__ void __launch_bounds__(256) k_truth_finish(const SysDev* __restrict__
     double2 hw[4], P[4], rr[4];
     hw_site<double>((const double2*)S.e_out2, g, i, diag, hw);
     load_sp<double>((const double2*)S.e_out, V, i, P);
+    if (mode == 1) {
+      double2 x[4];
+      load_sp<double>((const double2*)S.e_in, V, i, x);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        rr[k] = double2{P[k].x + hw[k].x, P[k].y + hw[k].y};
+        acc += x[k].x * rr[k].x + x[k].y * rr[k].y;
+      }
+      store_sp<double>((double2*)S.cg_r64, V, i, rr);
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const double2 bv = S.cg_b[(size_t)i * 4 + k];

@@ -212,6 +212,7 @@ struct Plan {
   bool fft = false;  // momentum-space Dirac operator (no multi-shift)
   int nshift = 0;    // shifted systems of a multi-shift CG on MdagM (rational layers)
   bool gw = false;   // inner MdagM in Ginsparg-Wilson form: one two-source multi-shift
+  bool gwx = false;  // exact Ginsparg-Wilson MdagM (true residuals, rational layers): tb_* twins
 };
 
 template <class R>
@@ -291,6 +292,8 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.ms_b_coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
     s.ms_b_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.ms_b_coef_d = (double*)bp.take(sizeof(double) * capmax);
+  }
+  if (pl.solve && pl.gwx) {
     s.tb_basis = (double2*)bp.take(v64 * pl.cap64);
     s.tb_r = (double2*)bp.take(v64);
     s.tb_src = (double2*)bp.take(v64);
@@ -408,7 +411,7 @@ struct Engine {
       b.cg_s = dry ? nullptr : cg_all + (size_t)s * CG_NSLOT;
       b.stat = dry ? nullptr : stat_all + (size_t)s * 4;
       b.ms_b_stat = (dry || !pl.gw) ? nullptr : stat_all + (size_t)(nsys + s) * 4;
-      b.tb_stat = (dry || !pl.gw) ? nullptr : stat_all + (size_t)(2 * nsys + s) * 4;
+      b.tb_stat = (dry || !pl.gwx) ? nullptr : stat_all + (size_t)(2 * nsys + s) * 4;
       b.act_cg = dry ? nullptr : act_all + s;
       b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
@@ -419,10 +422,10 @@ struct Engine {
     tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
     ftab = pl.nshift > 0 ? (SysDev*)bp.take(sizeof(SysDev) * nsys * pl.nshift) : nullptr;
     gwtab = pl.gw ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
-    gwbmap = pl.gw ? (int*)bp.take(sizeof(int) * 2 * (size_t)nb_total) : nullptr;
-    trgwtab = pl.gw ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
+    gwbmap = (pl.gw || pl.gwx) ? (int*)bp.take(sizeof(int) * 2 * (size_t)nb_total) : nullptr;
+    trgwtab = pl.gwx ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
     hgwbmap.clear();
-    if (pl.gw) {
+    if (pl.gw || pl.gwx) {
       hgwbmap.assign(2 * (size_t)nb_total, 0);
       for (int s = 0; s < nsys; ++s)
         for (int b = 0; b < sb[s].nblk; ++b) {
@@ -504,6 +507,7 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   E.pl.pc = solve && nshift == 0 && E.lead->p.precondition != 0;
   E.pl.fft = solve && E.lead->p.dirac != OV_DIRAC_OVERLAP_MS;
   E.pl.gw = solve && !E.pl.fft && nshift == 0 && E.lead->p.inner_form == 1;
+  E.pl.gwx = solve && !E.pl.fft && E.lead->p.inner_form == 1;
   // capacities from the loosest spectral bound over the batch (no multi-shift
   // basis for a momentum-space operator)
   int cap64 = 0, capR = 0;
@@ -570,11 +574,13 @@ ov_status upload_tables(Engine& E) {
                                 hipMemcpyHostToDevice, E.st));
   HIPCHK(E.lead, hipMemcpyAsync(E.bmap, E.hbmap.data(), sizeof(int) * E.hbmap.size(),
                                 hipMemcpyHostToDevice, E.st));
-  if (E.pl.gw && E.hgwtab.size() == 2 * (size_t)E.nsys) {
+  if (E.pl.gw && E.hgwtab.size() == 2 * (size_t)E.nsys)
     HIPCHK(E.lead, hipMemcpyAsync(E.gwtab, E.hgwtab.data(), sizeof(SysDev) * E.hgwtab.size(),
                                   hipMemcpyHostToDevice, E.st));
+  if (E.pl.gwx && E.htrgw.size() == 2 * (size_t)E.nsys)
     HIPCHK(E.lead, hipMemcpyAsync(E.trgwtab, E.htrgw.data(), sizeof(SysDev) * E.htrgw.size(),
                                   hipMemcpyHostToDevice, E.st));
+  if ((E.pl.gw || E.pl.gwx) && E.hgwbmap.size() == 2 * (size_t)E.nb_total) {
     HIPCHK(E.lead, hipMemcpyAsync(E.gwbmap, E.hgwbmap.data(), sizeof(int) * E.hgwbmap.size(),
                                   hipMemcpyHostToDevice, E.st));
   }
@@ -1096,7 +1102,9 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
       const SysDev* A = &E.hgwtab[s];
       ok &= need(100, s, A->e_in, "e_in") && need(100, s, A->e_out, "e_out") &&
             need(100, s, A->cg_s, "cg_s") && need(T_CG, s, T[T_CG]->e_in, "e_in");
-      // the FP64 true residual's two entries, its combine and finish
+    }
+    if (E.pl.gwx) {
+      // the exact form's two entries, its combine and finish
       for (int e = 0; e < 2; ++e) {
         const SysDev* G = &E.htrgw[(size_t)e * E.nsys + s];
         const int t = 110 + e;
@@ -1126,7 +1134,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
                              const std::vector<const void*>& phi) {
   E.htab.assign((size_t)T_NT * E.nsys, SysDev{});
   E.hgwtab.assign(E.pl.gw ? 2 * (size_t)E.nsys : 0, SysDev{});
-  E.htrgw.assign(E.pl.gw ? 2 * (size_t)E.nsys : 0, SysDev{});
+  E.htrgw.assign(E.pl.gwx ? 2 * (size_t)E.nsys : 0, SysDev{});
   for (int s = 0; s < E.nsys; ++s) {
     SysBuf& b = E.sb[s];
     SysDev d = base_dev(b);
@@ -1264,14 +1272,24 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
       gb.cg_s = nullptr;
       E.hgwtab[s] = ga;
       E.hgwtab[E.nsys + s] = gb;
-      // FP64 true residual: entry A on x64 (also the finish: r64 = b - P - H w),
-      // entry B on g5 (1 + Y) x64 with the FP64 twins
+    }
+    if (E.pl.gwx) {
+      // exact MdagM: entry A on x64 (also the finish: r64 = b - P - H w), entry B on
+      // g5 (1 + Y) x64 with the FP64 twins.  The rational layers' CG applies it to p
+      // instead (W = MdagM p -> vR, Re <p, W>).
       SysDev ta = tm;
       ta.coef_d2 = b.coef_d2;
       ta.coef_sq = b.coef_sq;
       ta.cg_b = (const double2*)bvec[s];
       ta.cg_r64 = b.r64;
       ta.cg_r = tmd.cg_r;
+      if (E.pl.nshift > 0) {
+        ta.active = b.act_cg;
+        ta.src = b.pR;
+        ta.e_in = b.pR;
+        ta.cg_r64 = b.vR;
+        ta.cg_r = nullptr;
+      }
       SysDev tbb = d;
       tbb.active = b.act_ru;
       tbb.blk0 = b.blk0 + E.nb_total;
@@ -1292,6 +1310,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
       tbb.coef_c = b.tb_coef_c;
       tbb.coef_d = b.tb_coef_d;
       tbb.cg_s = nullptr;
+      if (E.pl.nshift > 0) tbb.active = b.act_cg;
       E.htrgw[s] = ta;
       E.htrgw[E.nsys + s] = tbb;
     }
@@ -1339,7 +1358,7 @@ int last_truth_iters(const Engine& E) {
   long long m = 0;
   for (int s = 0; s < E.nsys; ++s) {
     m = std::max(m, st[(size_t)s * 4 + 3]);
-    if (E.pl.gw) m = std::max(m, st[(size_t)(2 * E.nsys + s) * 4 + 3]);  // its entry B
+    if (E.pl.gwx) m = std::max(m, st[(size_t)(2 * E.nsys + s) * 4 + 3]);  // its entry B
   }
   return (int)m;
 }
@@ -1432,7 +1451,7 @@ namespace {
 // tighter; intermediate updates tolerate that much by construction (truth_relax).
 double truth_ms_tol(const Engine& E, double tol) {
   const bool final_check = tol <= E.lead->p.truth_tol * 1.0000001;
-  return (E.pl.gw && !E.pl.fft && final_check) ? 0.1 * tol : tol;
+  return (E.pl.gwx && final_check) ? 0.1 * tol : tol;
 }
 
 template <class R>
@@ -1461,13 +1480,13 @@ ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
       k_yuk<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_F_TM), E.bmap, E.nb_total, 0);
       launch_sym<double>(E, T_F_TMD, SYM_D_DAG);
       k_yuk<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_F_TMD), E.bmap, E.nb_total, 2);
-    } else if (E.pl.gw) {  // one two-source multi-shift (see k_truth_combine)
+    } else if (E.pl.gwx) {  // one two-source multi-shift (see k_truth_combine)
       const int nb = E.nb_total, ns = E.nsys;
       k_stat3_clear<<<1, 64, 0, E.st>>>(E.trgwtab, 2 * ns);
       k_gw_prep<double><<<nb, c->block, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
       launch_ms_tab<double>(E, E.trgwtab, E.gwbmap, 2 * nb, 2 * ns, mp, L);
       k_truth_combine<<<nb, c->block, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
-      k_truth_finish<R><<<nb, c->block, 0, E.st>>>(E.trgwtab, E.bmap, nb, 4.0 - c->p.M0);
+      k_truth_finish<R><<<nb, c->block, 0, E.st>>>(E.trgwtab, E.bmap, nb, 4.0 - c->p.M0, 0);
     } else {
       k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_TR_M), E.bmap, E.nb_total, 0);
       launch_ms<double>(E, T_TR_M, mp, L);
@@ -2104,6 +2123,7 @@ size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
   E.pl.pc = c->p.precondition != 0;
   E.pl.fft = c->p.dirac != OV_DIRAC_OVERLAP_MS;
   E.pl.gw = !E.pl.fft && c->p.inner_form == 1;
+  E.pl.gwx = E.pl.gw;
   E.pl.cap64 = mixed ? cap64 : std::max(cap64, capR);
   E.pl.capR = mixed ? capR : E.pl.cap64;
   if (E.pl.fft) E.pl.cap64 = E.pl.capR = 0;
@@ -2428,8 +2448,13 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
   }
   const double tol = c->p.outer_tol;
   const MsParams mp = make_mp(c, c->p.inner_tol, E.pl.cap64);
+  // the exact Ginsparg-Wilson product takes eps^2 p from the Krylov space of p, about
+  // ten times less accurate than the shifted solutions: its multi-shift runs ten times
+  // tighter
+  const double tol_ms = E.pl.gwx ? 0.1 * c->p.inner_tol : c->p.inner_tol;
+  const MsParams mpx = make_mp(c, tol_ms, E.pl.cap64);
   int L = 0;
-  for (int s = 0; s < ns; ++s) L = std::max(L, capacity(E.ctxs[s], c->p.inner_tol));
+  for (int s = 0; s < ns; ++s) L = std::max(L, capacity(E.ctxs[s], tol_ms));
   L = std::min(E.pl.cap64, L);
   int Lrun = L;
   for (int it = 0; it < c->p.max_outer; ++it) {
@@ -2443,6 +2468,15 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
       k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_F_M), ns, 1);
       launch_sym<double>(E, T_F_MD, SYM_D_DAG);
       k_yuk<double><<<nb, bl, 0, E.st>>>(tab(E, T_F_MD), E.bmap, nb, 1);
+    } else if (E.pl.gwx) {
+      // w = MdagM p exactly in Ginsparg-Wilson form: one two-source multi-shift
+      // (eps^2 p from the Krylov space of p) -> vR, alpha = rho / Re <p, w>
+      k_stat3_clear<<<1, 64, 0, E.st>>>(E.trgwtab, 2 * ns);
+      k_gw_prep<double><<<nb, bl, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
+      launch_ms_tab<double>(E, E.trgwtab, E.gwbmap, 2 * nb, 2 * ns, mpx, Lrun);
+      k_truth_combine<<<nb, bl, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
+      k_truth_finish<double><<<nb, bl, 0, E.st>>>(E.trgwtab, E.bmap, nb, 4.0 - c->p.M0, 1);
+      k_cg_scalar<<<ns, 256, 0, E.st>>>(E.trgwtab, ns, 1);
     } else {
       k_ms_prep<double><<<nb, bl, 0, E.st>>>(tab(E, T_IN_M), E.bmap, nb, 0);
       launch_ms<double>(E, T_IN_M, mp, Lrun);
@@ -2455,7 +2489,7 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
     k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);                // rho, beta
     TRY(read_scalars(E));
     if (!E.pl.fft) {  // launch what the multi-shift needed, plus a margin
-      const int nobs = last_ms_iters(E);
+      const int nobs = E.pl.gwx ? last_truth_iters(E) : last_ms_iters(E);
       Lrun = (nobs >= Lrun - 1) ? L : std::min(L, nobs + 4);
     }
     for (int s = 0; s < ns; ++s) {

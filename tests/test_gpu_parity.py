@@ -716,15 +716,17 @@ def rat_coeffs():
     return {a: rational.power_approx(a, RAT_LO, RAT_HI, 20) for a in (-0.25, 0.125)}
 
 
-@pytest.mark.parametrize("dirac", [0, 2])
-def test_rational_vs_oracle(orc, rat_coeffs, dirac):
+@pytest.mark.parametrize("dirac,form", [(0, 1), (0, 0), (2, 1)])
+def test_rational_vs_oracle(orc, rat_coeffs, dirac, form):
     """a0 x + sum alpha_i (MdagM + beta_i)^-1 x: one multi-shift CG (GPU) against one
-    CG per shift (oracle), both to 1e-11 in each shifted system, at 4^4."""
+    CG per shift (oracle), both to 1e-11 in each shifted system, at 4^4; with the
+    multi-shift operator through the exact Ginsparg-Wilson product (inner_form 1) and
+    through M, then M^dag (0)."""
     dims = (4, 4, 4, 4)
-    print(f"[rational] dirac={dirac}", flush=True)
+    print(f"[rational] dirac={dirac} inner_form={form}", flush=True)
     phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=71)
     kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0, dirac=dirac)
-    lat = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, **kw)
+    lat = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, inner_form=form, **kw)
     o = orc.Oracle(dims, inner_tol=1e-13, **kw)
     a0, al, be, _ = rat_coeffs[-0.25]
     out, st = lat.rational(dev(src), dev(phi), a0, al, be)
