@@ -135,6 +135,12 @@ typedef struct {
                               Krylov space of x of the same two-source multi-shift (the
                               final check at truth_tol / 10).  0: M, then M^dag, for
                               both. */
+  int pc_mass;             /* mass of the preconditioner M0 of a preconditioned solve:
+                              1 (default): the root mean square over the lattice of the
+                              site-local coefficient c = m + g phi (in the direction of
+                              m; real when m = 0), the free-field operator closest to M
+                              on average; 0: the action's mass m, the phi = 0 operator
+                              of Sec. 7.3.  OV_OP_M0INV(_DAG) of ov_apply always use m. */
 } ov_params;
 
 typedef struct {

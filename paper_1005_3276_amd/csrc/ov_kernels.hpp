@@ -71,6 +71,7 @@ struct SysDev {
   void* cg_x64;             // FP64 solution (reliable updates)
   double* cg_s;             // per-system CG scalars (see CG_* below)
   double m_re, m_im;        // fermion mass
+  double pc_re, pc_im;      // mass of the preconditioner M0 (m, or the RMS of c = m + g phi)
   double g_re, g_im;        // Yukawa coupling
   double2* shx;             // multi-shift CG on MdagM: nshift solutions (FP64 planar)
   double2* shp;             //   and nshift search directions
@@ -1405,7 +1406,8 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
       v[2] = double2{k2 * v[2].x, k2 * v[2].y};
       v[3] = double2{0.0, 0.0};
     } else {
-      apply_symbol(sp, S.m_re, S.m_im, sx, sy, sz, st, w, v);
+      const bool m0 = sp.kind == SYM_M0INV || sp.kind == SYM_M0INV_DAG;
+      apply_symbol(sp, m0 ? S.pc_re : S.m_re, m0 ? S.pc_im : S.m_im, sx, sy, sz, st, w, v);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) A[(k * T + kt) * XC + xl] = c2<R>{(R)v[k].x, (R)v[k].y};
@@ -2176,6 +2178,27 @@ __global__ void __launch_bounds__(256) k_force(const SysDev* __restrict__ sys, i
     }
     G[i] = double2{gr, gi};
   }
+}
+
+// Partials of |c_x|^2 = |m + g phi_x|^2 over the sites of each system -> part_c.
+__global__ void __launch_bounds__(256) k_c_norm(const SysDev* __restrict__ sys,
+                                                const int* __restrict__ bmap, int nb_total) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double2 ph = S.phi[i];
+    const double cr = S.m_re + S.g_re * ph.x - S.g_im * ph.y;
+    const double ci = S.m_im + S.g_re * ph.y + S.g_im * ph.x;
+    acc += cr * cr + ci * ci;
+  }
+  const double tot = block_sum(acc, lds);
+  if (threadIdx.x == 0) S.part_c[lb] = tot;
 }
 
 // Re <xi, X> partials (xi AoS complex128 from cg_b, X planar FP64 e_in) -> part_c

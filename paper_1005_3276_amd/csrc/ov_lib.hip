@@ -554,6 +554,8 @@ SysDev base_dev(const SysBuf& b) {
   d.cg_s = b.cg_s;
   d.m_re = p.m_re;
   d.m_im = p.m_im;
+  d.pc_re = p.m_re;  // the free-field operator of the action's mass (ov_apply M0INV)
+  d.pc_im = p.m_im;
   d.g_re = p.g_re;
   d.g_im = p.g_im;
   d.shx = b.shx;
@@ -1129,9 +1131,43 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
   return OV_OK;
 }
 
+// Preconditioner masses (pc_mass = 1): the RMS over the lattice of the site-local
+// coefficient c = m + g phi, in the direction of m (real when m = 0).
+ov_status pc_masses(Engine& E, const std::vector<const void*>& phi, std::vector<double2>& pcm) {
+  ov_ctx* c = E.lead;
+  const int ns = E.nsys;
+  pcm.assign(ns, double2{0.0, 0.0});
+  E.htab.assign((size_t)T_NT * ns, SysDev{});
+  for (int s = 0; s < ns; ++s) {
+    SysDev d = base_dev(E.sb[s]);
+    d.phi = (const double2*)phi[s];
+    E.htab[(size_t)T_APPLY * ns + s] = d;
+  }
+  TRY(upload_tables(E));
+  k_c_norm<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total);
+  TRY(check_launch(c));
+  for (int s = 0; s < ns; ++s) {
+    const SysBuf& b = E.sb[s];
+    std::vector<double> tmp(b.nblk);
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), b.part_c, sizeof(double) * tmp.size(),
+                             hipMemcpyDeviceToHost, E.st));
+    TRY(sync(E));
+    double acc = 0.0;
+    for (double v : tmp) acc += v;
+    const ov_params& p = b.ctx->p;
+    const double rms = std::sqrt(acc / b.V);
+    const double am = std::hypot(p.m_re, p.m_im);
+    pcm[s] = am > 0.0 ? double2{rms * p.m_re / am, rms * p.m_im / am} : double2{rms, 0.0};
+  }
+  return OV_OK;
+}
+
 template <class R>
 ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
                              const std::vector<const void*>& phi) {
+  std::vector<double2> pcm;
+  const bool rms_pc = E.pl.pc && E.lead->p.pc_mass == 1;
+  if (rms_pc) TRY(pc_masses(E, phi, pcm));
   E.htab.assign((size_t)T_NT * E.nsys, SysDev{});
   E.hgwtab.assign(E.pl.gw ? 2 * (size_t)E.nsys : 0, SysDev{});
   E.htrgw.assign(E.pl.gwx ? 2 * (size_t)E.nsys : 0, SysDev{});
@@ -1140,6 +1176,10 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     SysDev d = base_dev(b);
     d.phi = (const double2*)phi[s];
     d.cg_b = (const double2*)bvec[s];
+    if (rms_pc) {
+      d.pc_re = pcm[s].x;
+      d.pc_im = pcm[s].y;
+    }
     // inner M p
     SysDev im = d;
     im.active = b.act_cg;
@@ -1870,6 +1910,10 @@ ov_status validate(const ov_params* p, std::string& err) {
     err = "need 0 < truth_relax <= 1";
     return OV_ERR_INVALID_ARG;
   }
+  if (p->pc_mass != 0 && p->pc_mass != 1) {
+    err = "pc_mass must be 0 or 1";
+    return OV_ERR_INVALID_ARG;
+  }
   if (p->inner_form != 0 && p->inner_form != 1) {
     err = "inner_form must be 0 or 1";
     return OV_ERR_INVALID_ARG;
@@ -2016,6 +2060,7 @@ void ov_params_default(ov_params* p) {
   p->precondition = 1;
   p->truth_relax = 0.01;
   p->inner_form = 1;
+  p->pc_mass = 1;
 }
 
 const char* ov_status_string(ov_status s) {
@@ -2239,7 +2284,8 @@ static bool same_solver(const ov_params& a, const ov_params& b) {
          a.mixed_inner_tol == b.mixed_inner_tol && a.reliable_delta == b.reliable_delta &&
          a.precision == b.precision && a.M0 == b.M0 && a.inner_relax == b.inner_relax &&
          a.inner_tol_max == b.inner_tol_max && a.precondition == b.precondition &&
-         a.dirac == b.dirac && a.truth_relax == b.truth_relax && a.inner_form == b.inner_form;
+         a.dirac == b.dirac && a.truth_relax == b.truth_relax && a.inner_form == b.inner_form &&
+         a.pc_mass == b.pc_mass;
 }
 
 static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,
