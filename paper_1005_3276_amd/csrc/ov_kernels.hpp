@@ -92,7 +92,7 @@ struct MsParams {
   double diag;          // 4 - M0
   double sigma[MAXP];   // shifts b_k
   double coef[MAXP];    // residues a_k
-  int zm;               // > 0: z-marching passes over zm planes per workgroup (zm_march)
+  int zm;               // > 0: z-marching passes over zm planes per workgroup (ZmMarch)
   unsigned long long* tstamp;  // non-null: per workgroup (start, end) wall-clock stamps
 };
 
@@ -353,63 +353,120 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
 }
 
 // H_W of f on the sites of a workgroup that owns zc consecutive z planes of one
-// time slice (X Y == blockDim.x; the block's sites i0 .. i0 + zc X Y - 1), in the
-// z-marching order of k_hw_zm: plane z below and above in registers, the
-// current plane in LDS (sh: 4 X Y values) for the x and y neighbours.  For each
-// site, epi(i, w) receives w = (H_W f)_i and returns a partial sum; the total
-// is returned.  Every thread of the block must call it.
-template <class R, class Epi>
-__device__ __forceinline__ double zm_march(const c2<R>* __restrict__ f, const Geo& g, int i0,
-                                           int zc, R diag, c2<R>* sh, Epi epi) {
-  const int X = g.X, Y = g.Y, Z = g.Z, T = g.T, V = g.V;
-  const int XY = X * Y, XYZ = XY * Z;
-  const int j = threadIdx.x;
-  const int x = j % X, y = j / X;
-  const int p0 = i0 / XY;  // z0 + Z t
-  const int t = p0 / Z, z0 = p0 - Z * t;
-  const int tf_off = (t + 1 < T) ? XYZ : XYZ - V;
-  const int tb_off = (t > 0) ? -XYZ : V - XYZ;
-  const int jxf = y * X + ((x + 1 < X) ? x + 1 : 0);
-  const int jxb = y * X + ((x > 0) ? x - 1 : X - 1);
-  const int jyf = ((y + 1 < Y) ? y + 1 : 0) * X + x;
-  const int jyb = ((y > 0) ? y - 1 : Y - 1) * X + x;
-  const int base = j + XYZ * t;
-  Nbr<R> nb;
-  c2<R> prev[4], cur[4], next[4];
-  load_sp<R>(f, V, base + XY * (z0 > 0 ? z0 - 1 : Z - 1), prev);
-  load_sp<R>(f, V, base + XY * z0, cur);
-  double acc = 0.0;
-  for (int k = 0; k < zc; ++k) {
-    const int z = z0 + k;
-    const int i = base + XY * z;
-    load_sp<R>(f, V, base + XY * (z + 1 < Z ? z + 1 : 0), next);
-    load_sp<R>(f, V, i + tf_off, nb.tf);
-    load_sp<R>(f, V, i + tb_off, nb.tb);
-    __syncthreads();  // reads of the previous plane are done
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sh[q * XY + j] = cur[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      nb.c[q] = cur[q];
-      nb.xf[q] = sh[q * XY + jxf];
-      nb.xb[q] = sh[q * XY + jxb];
-      nb.yf[q] = sh[q * XY + jyf];
-      nb.yb[q] = sh[q * XY + jyb];
-      nb.zf[q] = next[q];
-      nb.zb[q] = prev[q];
-    }
-    c2<R> w[4];
-    hw_compute<R>(nb, g, i, diag, w);
-    acc += epi(i, w);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      prev[q] = cur[q];
-      cur[q] = next[q];
-    }
+// time slice (X Y == blockDim.x; the block's sites i0 .. i0 + zc X Y - 1, zc
+// dividing Z), in the z-marching order of k_hw_zm: plane z below and above in
+// registers, the current plane in LDS (sh: 4 X Y values) for the x and y
+// neighbours.  Next to the stencil operands each site may take one more spinor
+// of its own (the epilogue operand, from ep).  begin() issues the loads of the
+// first plane, so a caller can put them in flight before its scalar work; run()
+// walks the planes with the loads of plane k + 1 issued before plane k is
+// computed.  For each site, epi(i, w, e) receives w = (H_W f)_i and the epilogue
+// operand e and returns a partial sum; run() returns the total.  Every thread of
+// the block must call run().
+template <class R>
+struct ZmMarch {
+  const c2<R>* f;
+  const c2<R>* ep;
+  int V, XY, Z, base, z0, tf_off, tb_off, jxf, jxb, jyf, jyb;
+  c2<R> prev[4], cur[4], next[4], tf[4], tb[4], e[4];
+
+  __device__ __forceinline__ int plane(int z) const { return base + XY * (z < Z ? z : z - Z); }
+
+  __device__ __forceinline__ void begin(const c2<R>* __restrict__ f_, const c2<R>* __restrict__ ep_,
+                                        const Geo& g, int i0) {
+    f = f_;
+    ep = ep_;
+    const int X = g.X, Y = g.Y, T = g.T;
+    V = g.V;
+    Z = g.Z;
+    XY = X * Y;
+    const int XYZ = XY * Z;
+    const int j = threadIdx.x;
+    const int x = j % X, y = j / X;
+    const int p0 = i0 / XY;  // z0 + Z t
+    const int t = p0 / Z;
+    z0 = p0 - Z * t;
+    tf_off = (t + 1 < T) ? XYZ : XYZ - V;
+    tb_off = (t > 0) ? -XYZ : V - XYZ;
+    jxf = y * X + ((x + 1 < X) ? x + 1 : 0);
+    jxb = y * X + ((x > 0) ? x - 1 : X - 1);
+    jyf = ((y + 1 < Y) ? y + 1 : 0) * X + x;
+    jyb = ((y > 0) ? y - 1 : Y - 1) * X + x;
+    base = j + XYZ * t;
+    const int i = plane(z0);
+    load_sp<R>(f, V, plane(z0 > 0 ? z0 - 1 : Z - 1), prev);
+    load_sp<R>(f, V, i, cur);
+    load_sp<R>(f, V, plane(z0 + 1), next);
+    load_sp<R>(f, V, i + tf_off, tf);
+    load_sp<R>(f, V, i + tb_off, tb);
+    if (ep) load_sp<R>(ep, V, i, e);
   }
-  return acc;
-}
+
+  template <bool PIPE, class Epi>
+  __device__ __forceinline__ double run(int zc, const Geo& g, R diag, c2<R>* sh, Epi epi) {
+    const int j = threadIdx.x;
+    double acc = 0.0;
+    for (int k = 0; k < zc; ++k) {
+      const int i = plane(z0 + k);
+      c2<R> next2[4], tf2[4], tb2[4], e2[4];
+      if (PIPE && k + 1 < zc) {
+        const int i2 = i + XY;  // plane z0 + k + 1 < Z
+        load_sp<R>(f, V, plane(z0 + k + 2), next2);
+        load_sp<R>(f, V, i2 + tf_off, tf2);
+        load_sp<R>(f, V, i2 + tb_off, tb2);
+        if (ep) load_sp<R>(ep, V, i2, e2);
+      }
+      __syncthreads();  // reads of the previous plane are done
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh[q * XY + j] = cur[q];
+      __syncthreads();
+      Nbr<R> nb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        nb.c[q] = cur[q];
+        nb.xf[q] = sh[q * XY + jxf];
+        nb.xb[q] = sh[q * XY + jxb];
+        nb.yf[q] = sh[q * XY + jyf];
+        nb.yb[q] = sh[q * XY + jyb];
+        nb.zf[q] = next[q];
+        nb.zb[q] = prev[q];
+        nb.tf[q] = tf[q];
+        nb.tb[q] = tb[q];
+      }
+      c2<R> w[4];
+      hw_compute<R>(nb, g, i, diag, w);
+      acc += epi(i, w, e);
+      if (PIPE) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          prev[q] = cur[q];
+          cur[q] = next[q];
+          next[q] = next2[q];
+          tf[q] = tf2[q];
+          tb[q] = tb2[q];
+          e[q] = e2[q];
+        }
+      } else if (k + 1 < zc) {
+        const int i2 = i + XY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          prev[q] = cur[q];
+          cur[q] = next[q];
+        }
+        load_sp<R>(f, V, plane(z0 + k + 2), next);
+        load_sp<R>(f, V, i2 + tf_off, tf);
+        load_sp<R>(f, V, i2 + tb_off, tb);
+        if (ep) load_sp<R>(ep, V, i2, e);
+      }
+    }
+    return acc;
+  }
+};
+
+// The z-marching passes prefetch the next plane's operands in FP32 only: in FP64 the
+// second register set would halve the co-resident workgroups.
+template <class R>
+constexpr bool ZM_PIPE_FOR = sizeof(R) == sizeof(float);
 
 // ------------------------------------------------------- multi-shift: t pass
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
@@ -420,7 +477,7 @@ __device__ __forceinline__ double zm_march(const c2<R>* __restrict__ f, const Ge
 // is consumed, and each wave finishes the reduction and the shift recurrences
 // on its own (identical bits in every wave), so the only barrier is the final
 // block reduction.
-template <class R>
+template <class R, bool ZM>
 __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const MsParams* mp,
                                            double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
@@ -457,10 +514,13 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   const int i0 = lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
   int i = i0 + threadIdx.x;
-  const bool zm = mp->zm > 0;
-  const bool have = !zm && i < i1;  // z-marching loads inside its own loop
+  constexpr bool zm = ZM;  // z-marching (mp->zm planes per workgroup)
+  constexpr bool ZM_PIPE = ZM_PIPE_FOR<R>;
+  const bool have = !zm && i < i1;
   Nbr<R> nb;
   c2<R> q[4];
+  ZmMarch<R> zmm;
+  if (zm) zmm.begin(rin, n > 0 ? tp : nullptr, g, i0);
   if (have) {
     load_nbr<R>(rin, g, i, nb);
     if (n > 0) load_sp<R>(tp, g.V, i, q);
@@ -508,10 +568,8 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
 
   double acc = 0.0;
   if (zm) {
-    acc = zm_march<R>(rin, g, i0, mp->zm, (R)mp->diag, sh, [&](int ii, c2<R>* o) -> double {
+    acc = zmm.template run<ZM_PIPE>(mp->zm, g, (R)mp->diag, sh, [&](int ii, c2<R>* o, const c2<R>* qq) -> double {
       if (n > 0) {
-        c2<R> qq[4];
-        load_sp<R>(tp, g.V, ii, qq);
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2)
           o[k2] = c2<R>{o[k2].x + beta * qq[k2].x, o[k2].y + beta * qq[k2].y};
@@ -532,7 +590,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
     acc = norm2_sp(o);
   }
   // remaining sites of this block (sites per thread > 1)
-  for (i += blockDim.x; i < i1; i += blockDim.x) {
+  for (i += blockDim.x; !zm && i < i1; i += blockDim.x) {
     c2<R> o[4];
     hw_site<R>(rin, g, i, (R)mp->diag, o);
     if (n > 0) {
@@ -547,7 +605,7 @@ __device__ __forceinline__ void ms_t_block(const SysDev& S, int lb, int n, const
   if (threadIdx.x == 0) S.part_a[lb] = tot;
 }
 
-template <class R>
+template <class R, bool ZM>
 __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const MsParams* mp,
                                            double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
@@ -565,10 +623,13 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   const int i0 = lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
   int i = i0 + threadIdx.x;
-  const bool zm = mp->zm > 0;
+  constexpr bool zm = ZM;
+  constexpr bool ZM_PIPE = ZM_PIPE_FOR<R>;
   const bool have = !zm && i < i1;
   Nbr<R> nb;
   c2<R> r[4];
+  ZmMarch<R> zmm;
+  if (zm) zmm.begin(tn, rin, g, i0);
   if (have) {
     load_nbr<R>(tn, g, i, nb);
     load_sp<R>(rin, g.V, i, r);
@@ -589,9 +650,10 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
   const R alpha = (R)alpha_d;
   double acc = 0.0;
   if (zm) {
-    acc = zm_march<R>(tn, g, i0, mp->zm, (R)mp->diag, sh, [&](int ii, c2<R>* w) -> double {
+    acc = zmm.template run<ZM_PIPE>(mp->zm, g, (R)mp->diag, sh, [&](int ii, c2<R>* w, const c2<R>* r0) -> double {
       c2<R> rr[4];
-      load_sp<R>(rin, g.V, ii, rr);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rr[k] = r0[k];
 #pragma unroll
       for (int k = 0; k < 4; ++k) rr[k] = c2<R>{rr[k].x - alpha * w[k].x, rr[k].y - alpha * w[k].y};
       store_sp_nt<R>(rout, g.V, ii, rr);
@@ -607,7 +669,7 @@ __device__ __forceinline__ void ms_r_block(const SysDev& S, int lb, int n, const
     store_sp_nt<R>(rout, g.V, i, r);
     acc = norm2_sp(r);
   }
-  for (i += blockDim.x; i < i1; i += blockDim.x) {
+  for (i += blockDim.x; !zm && i < i1; i += blockDim.x) {
     c2<R> w[4];
     hw_site<R>(tn, g, i, (R)mp->diag, w);
     load_sp<R>(rin, g.V, i, r);
@@ -639,7 +701,7 @@ __device__ __forceinline__ void stamp_block(unsigned long long* ts, unsigned lon
 // is consumed, and each wave finishes the reduction and the shift recurrences
 // on its own (identical bits in every wave), so the only barrier is the final
 // block reduction.
-template <class R>
+template <class R, bool ZM>
 __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
@@ -649,13 +711,13 @@ __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
   if (mp_.tstamp && threadIdx.x == 0) t0 = wall_clock64();
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  ms_t_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.zm ? (c2<R>*)dyn_lds : nullptr);
+  ms_t_block<R, ZM>(S, L - S.blk0, n, &mp_, lds, ZM ? (c2<R>*)dyn_lds : nullptr);
   if (mp_.tstamp) stamp_block(mp_.tstamp, t0);
 }
 
 // Iteration n, r pass:
 //   alpha_n = rho_n / |t_n|^2;  r_{n+1} = r_n - alpha_n H t_n;  partial |r_{n+1}|^2.
-template <class R>
+template <class R, bool ZM>
 __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
@@ -665,7 +727,7 @@ __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
   if (mp_.tstamp && threadIdx.x == 0) t0 = wall_clock64();
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  ms_r_block<R>(S, L - S.blk0, n, &mp_, lds, mp_.zm ? (c2<R>*)dyn_lds : nullptr);
+  ms_r_block<R, ZM>(S, L - S.blk0, n, &mp_, lds, ZM ? (c2<R>*)dyn_lds : nullptr);
   if (mp_.tstamp) stamp_block(mp_.tstamp, t0);
 }
 
@@ -748,13 +810,13 @@ __global__ void __launch_bounds__(256) k_ms_persistent(const SysDev* __restrict_
   for (int n = 0; n < L; ++n) {
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_t_block<R>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
+      ms_t_block<R, false>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_r_block<R>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
+      ms_r_block<R, false>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;

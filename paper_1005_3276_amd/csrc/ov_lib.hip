@@ -760,11 +760,17 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);
-      k_ms_t<R><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (mps.zm)
+        k_ms_t<R, true><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      else
+        k_ms_t<R, false><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 4 : 1, bytes);
-      k_ms_r<R><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (mps.zm)
+        k_ms_r<R, true><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      else
+        k_ms_r<R, false><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
   }
   k_ms_coef<<<nent, 256, 0, E.st>>>(T, nent, L, mp);
