@@ -30,12 +30,12 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the multi-shift pass code (ov_common.hpp + ms_t_block .. ms_r_block)."""
+    """Hash of the multi-shift pass code (ov_common.hpp + ZmMarch .. ms_r_block)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1005_3276_amd", "csrc")
     common = open(os.path.join(csrc, "ov_common.hpp")).read()
     kern = open(os.path.join(csrc, "ov_kernels.hpp")).read()
-    a = kern.index("__device__ __forceinline__ void ms_t_block(")
+    a = kern.index("struct ZmMarch {")
     b = kern.index("// Iteration n, t pass:")
     return hashlib.sha256((common + kern[a:b]).encode()).hexdigest()[:16]
 
@@ -380,9 +380,9 @@ def main():
     lat.kernel_sampling(0)
     spans = [lat.kernel_spans(k) for k in range(5)]  # (kernel_ms, kcnt, event_ms, cnt, bytes)
     families = {
-        "fp64_truth": ((3, 4), "k_ms_t<double> + k_ms_r<double> (FP64 multi-shift passes of "
+        "fp64_truth": ((3, 4), "k_ms_t<double, *> + k_ms_r<double, *> (FP64 multi-shift passes of "
                                "the true residuals, two sources per launch)"),
-        "fp32_inner": ((0, 1), "k_ms_t<float> + k_ms_r<float> (FP32 multi-shift passes of "
+        "fp32_inner": ((0, 1), "k_ms_t<float, *> + k_ms_r<float, *> (FP32 multi-shift passes of "
                                "the inner CG, two sources per launch)"),
     }
 
