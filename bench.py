@@ -223,6 +223,21 @@ def other_configs(torch, Lattice, inputs):
         "max_true_rel_res": max(s["true_rel_res"] for s in st),
         "outer_iters": [s["outer_iters"] for s in st]}
     log(f"config5: {out['config5_uneven_batch']}")
+    del lats
+    # the same batch with the FP64 solver
+    lats = [Lattice(d, precision="fp64", m=0.05, g=0.3, n_poles=24, lambda_min=1e-4,
+                    lambda_max=8.0, outer_tol=1e-10, inner_tol=1e-8) for d, _ in members]
+    solve_batch(lats, bs, ps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st = solve_batch(lats, bs, ps)
+    torch.cuda.synchronize()
+    e64 = time.perf_counter() - t
+    out["config5_uneven_batch_fp64"] = {
+        "seconds": e64, "rhs_solves_per_s": 11 / e64,
+        "max_true_rel_res": max(s["true_rel_res"] for s in st),
+        "mixed_speedup": e64 / e}
+    log(f"config5 fp64: {out['config5_uneven_batch_fp64']}")
     return out
 
 
