@@ -463,6 +463,27 @@ def main():
             del l64
         best64 = max(extra[k]["solves_per_s"] for k in ("fp64_p1", "fp64_p2", "fp64_p3"))
         extra["mixed_speedup_vs_best_fp64"] = value / best64
+        # ---- the same workload at 8^4 (the smaller lattice of the workload), mixed vs FP64
+        d8 = (8, 8, 8, 8)
+        phi8, src8 = inputs.draw(d8, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2) + 1)
+        b8, p8 = torch.from_numpy(src8).cuda(), torch.from_numpy(phi8).cuda()
+        r8 = {}
+        for name, kw in (("mixed", dict(precision="mixed")),
+                         ("fp64_p3", dict(precision="fp64", inner_tol=1e-8))):
+            l8 = Lattice(d8, **dict(CFG, **kw))
+            l8.solve(b8, p8)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                _, st8 = l8.solve(b8, p8)
+            torch.cuda.synchronize()
+            e8 = (time.perf_counter() - t) / 3
+            r8[name] = {"ms_per_solve": e8 * 1e3, "outer_iters": st8[0]["outer_iters"],
+                        "true_rel_res": st8[0]["true_rel_res"]}
+            del l8
+        r8["mixed_speedup"] = r8["fp64_p3"]["ms_per_solve"] / r8["mixed"]["ms_per_solve"]
+        extra["config2_8x4"] = r8
+        log(f"config2 8^4: {r8}")
         # ---- stencil bandwidth at 16^4
         sweep = stencil_sweep(lat, torch)
         extra["stencil"] = sweep
