@@ -844,6 +844,7 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
                                                  int launched, const MsParams mp_) {
   __shared__ int sh_N;
   __shared__ double sh_res[MAXP];
+  __shared__ int l_nk[MAXP];
   __shared__ double l_rho[COEF_LDS_ITERS + 1];
   __shared__ double l_alpha[COEF_LDS_ITERS + 1];
   __shared__ unsigned int l_act[COEF_LDS_ITERS + 1];
@@ -897,23 +898,55 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
     zeta = l_zeta;
   }
   const double rho0 = rho[0];
-  for (int k = threadIdx.x; k < MAXP; k += blockDim.x) sh_res[k] = 0.0;
+  for (int k = threadIdx.x; k < MAXP; k += blockDim.x) {
+    sh_res[k] = 0.0;
+    l_nk[k] = N;
+  }
   __syncthreads();
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    int Nk = N;
-    for (int j = 0; j < N; ++j)
-      if (!(actv[j] & (1u << k))) { Nk = j; break; }
-    double Sk = 0.0;
-    for (int j = Nk - 1; j >= 0; --j) {
+  if (staged) {
+    // N_k (first iteration with shift k inactive) and the recurrence factors
+    // alpha_{j,k}, beta_{j,k} for every (k, j) at once; the per-shift chains below
+    // are then multiply-adds on LDS operands
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      const unsigned int a = actv[j];
+      for (int k = 0; k < np; ++k)
+        if (!(a & (1u << k))) atomicMin(&l_nk[k], j);
+    }
+    for (int q = threadIdx.x; q < np * N; q += blockDim.x) {
+      const int k = q / N, j = q - k * N;
       const double zj = zeta[(size_t)j * MAXP + k];
       const double zr = zeta[(size_t)(j + 1) * MAXP + k] / zj;
-      const double aj = alph[j] * zr;
-      const double bj = (rho[j + 1] / rho[j]) * zr * zr;
-      Sk = aj + bj * Sk;
-      S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zj * Sk;
+      l_u[k][j] = alph[j] * zr;
+      l_cp[k][j] = (rho[j + 1] / rho[j]) * zr * zr;
     }
-    for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
-    if (rho0 > 0.0) sh_res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      const int Nk = l_nk[k];
+      double Sk = 0.0;
+      for (int j = Nk - 1; j >= 0; --j) {
+        Sk = l_u[k][j] + l_cp[k][j] * Sk;
+        S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zeta[(size_t)j * MAXP + k] * Sk;
+      }
+      for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
+      if (rho0 > 0.0) sh_res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
+    }
+  } else {
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      int Nk = N;
+      for (int j = 0; j < N; ++j)
+        if (!(actv[j] & (1u << k))) { Nk = j; break; }
+      double Sk = 0.0;
+      for (int j = Nk - 1; j >= 0; --j) {
+        const double zj = zeta[(size_t)j * MAXP + k];
+        const double zr = zeta[(size_t)(j + 1) * MAXP + k] / zj;
+        const double aj = alph[j] * zr;
+        const double bj = (rho[j + 1] / rho[j]) * zr * zr;
+        Sk = aj + bj * Sk;
+        S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zj * Sk;
+      }
+      for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
+      if (rho0 > 0.0) sh_res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
@@ -957,17 +990,26 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
     double* u = U + (size_t)k * ld;
     double* cp = CP + (size_t)k * ld;
     const double bk = mp->sigma[k];
-    double cprev = 0.0, dprev = 0.0;
+    // forward elimination; the next row's operands are read ahead of the division
+    double cprev = 0.0, dprev = 0.0, ol = 0.0;
+    double td = TD[0], rhs = from_g ? G[0] : 1.0;
     for (int j = 0; j < N; ++j) {
-      const double ol = j > 0 ? TO[j - 1] : 0.0;
-      const double inv = 1.0 / (TD[j] + bk - ol * cprev);
-      const double cj = j + 1 < N ? TO[j] * inv : 0.0;
-      const double rhs = from_g ? G[j] : (j == 0 ? 1.0 : 0.0);
+      const double to = TO[j];
+      double td_n = 0.0, rhs_n = 0.0;
+      if (j + 1 < N) {
+        td_n = TD[j + 1];
+        rhs_n = from_g ? G[j + 1] : 0.0;
+      }
+      const double inv = 1.0 / (td + bk - ol * cprev);
+      const double cj = j + 1 < N ? to * inv : 0.0;
       const double dj = (rhs - ol * dprev) * inv;
       cp[j] = cj;
       u[j] = dj;
       cprev = cj;
       dprev = dj;
+      ol = to;
+      td = td_n;
+      rhs = rhs_n;
     }
     double un = dprev;
     for (int j = N - 2; j >= 0; --j) {
