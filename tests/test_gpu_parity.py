@@ -497,6 +497,31 @@ def test_batched_equals_unbatched(orc):
         assert o.residual(src[r], xb[r], phi) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_solve_deterministic_bitwise(precision):
+    """Every reduction sums its partials in a fixed order (no atomics on values), so
+    two contexts in the same state give bitwise equal results.  A context learns the
+    multi-shift launch counts from its first solve, so its later solves are compared
+    with a second context's later solves, and with its own first to tolerance."""
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2))
+    kw = dict(precision=precision, outer_tol=1e-10, **CFG2)
+    la, lb = lattice(dims, **kw), lattice(dims, **kw)
+
+    def bits(x):
+        return host(x).view(np.uint64)
+
+    xa1, sta = la.solve(dev(src), dev(phi))
+    xb1, stb = lb.solve(dev(src), dev(phi))
+    assert np.array_equal(bits(xa1), bits(xb1))
+    assert [s["outer_iters"] for s in sta] == [s["outer_iters"] for s in stb]
+    xa2, _ = la.solve(dev(src), dev(phi))
+    xb2, _ = lb.solve(dev(src), dev(phi))
+    assert np.array_equal(bits(xa2), bits(xb2))
+    assert rel(host(xa2), host(xa1)) < 1e-8
+    assert np.array_equal(bits(la.sign(dev(src))[0]), bits(lb.sign(dev(src))[0]))
+
+
 def test_uneven_batch(orc):
     from paper_1005_3276_amd import solve_batch
     kw = dict(precision="mixed", outer_tol=1e-10, m=0.05, g=0.3, n_poles=24,
