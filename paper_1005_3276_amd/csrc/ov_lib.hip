@@ -2059,11 +2059,11 @@ void ov_params_default(ov_params* p) {
   p->outer_tol = 1e-10;
   p->truth_tol = 1e-13;
   p->mixed_inner_tol = 1e-6;
-  p->reliable_delta = 0.03;
+  p->reliable_delta = 0.01;
   p->max_inner = 400;
   p->max_outer = 2000;
   p->precision = OV_MIXED;
-  p->inner_relax = 3e-3;
+  p->inner_relax = 1e-3;
   p->inner_tol_max = 1e-2;
   p->precondition = 1;
   p->truth_relax = 0.01;
