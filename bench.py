@@ -148,12 +148,51 @@ def cpu_baseline(phi, src, outer_iters):
                       f"{per:.2f} s each, scaled by {outer_iters} outer CG iterations"}
 
 
-def other_configs(torch, Lattice, inputs):
-    """Timed runs of the batched (16^3x32, 12 rhs), force (12^4) and uneven-batch
-    workloads; one warm-up and one timed call each."""
-    from paper_1005_3276_amd import solve_batch
-    out = {}
-    # config 3
+# multi-shift pass families: (t-pass kernel id, r-pass kernel id) of the library's
+# event sampling (ov_kernel_sampling): 0/1 FP32 passes, 3/4 FP64 passes
+FAMILIES = {"fp64_truth": (3, 4), "fp32_inner": (0, 1)}
+
+
+def sampled_spans(lat, run):
+    """Run `run()` once with every multi-shift pass launch sampled by HIP events on the
+    library's stream (and device wall-clock stamps of every workgroup)."""
+    lat.kernel_sampling(512)
+    for k in range(5):
+        lat.kernel_spans(k, reset=True)
+    run()
+    lat.kernel_sampling(0)
+    return [lat.kernel_spans(k) for k in range(5)]  # (kernel_ms, kcnt, event_ms, cnt, bytes)
+
+
+def family_roofline(spans, name, kname):
+    """Achieved algorithmic GB/s of one pass family over the sampled launches."""
+    ids = FAMILIES[name]
+    ms_sum = sum(spans[k][2] for k in ids)
+    cnt = sum(spans[k][3] for k in ids)
+    bytes_sum = sum(spans[k][4] for k in ids)
+    per_launch = bytes_sum / max(cnt, 1)
+    achieved = bytes_sum / (ms_sum * 1e-3) / 1e9 if ms_sum > 0 else 0.0
+    r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, per_launch),
+         "kernel": kname, "avg_launch_us": ms_sum / max(cnt, 1) * 1e3,
+         "bytes_per_launch": per_launch, "launches_per_solve": cnt,
+         "event_ms_per_solve": ms_sum,
+         "t_pass_us": spans[ids[0]][2] / max(spans[ids[0]][3], 1) * 1e3,
+         "r_pass_us": spans[ids[1]][2] / max(spans[ids[1]][3], 1) * 1e3}
+    # the same launches, kernel-only: max(end) - min(start) of device wall-clock
+    # stamps taken by every workgroup (what a kernel trace reports; the event
+    # duration above also holds the dispatch gap before each launch)
+    kms = sum(spans[k][0] for k in ids)
+    kcnt = sum(spans[k][1] for k in ids)
+    if kcnt > 0:
+        r["kernel_only_us"] = kms / kcnt * 1e3
+        r["achieved_kernel_only"] = per_launch / (kms / kcnt * 1e-3) / 1e9
+    return r
+
+
+def batched_config3(torch, Lattice, inputs):
+    """The batched workload (12 sources on 16^3 x 32, mixed): timed solve, then one
+    sampled solve giving the pass families' achieved bandwidth at that size."""
     dims = (16, 16, 16, 32)
     phi, src = inputs.draw(dims, nrhs=12, sigma2=0.5, seed=inputs.config_seed(3))
     lat = Lattice(dims, precision="mixed", m=0.02, g=0.5, n_poles=20, lambda_min=1e-3,
@@ -165,12 +204,31 @@ def other_configs(torch, Lattice, inputs):
     _, st = lat.solve(b, p)
     torch.cuda.synchronize()
     e = time.perf_counter() - t
-    out["config3_batched_16x3x32_12rhs"] = {
-        "seconds": e, "rhs_solves_per_s": 12 / e,
-        "max_true_rel_res": max(s["true_rel_res"] for s in st),
-        "outer_iters": [s["outer_iters"] for s in st]}
-    log(f"config3: {out['config3_batched_16x3x32_12rhs']}")
+    spans = sampled_spans(lat, lambda: lat.solve(b, p))
+    out = {"seconds": e, "rhs_solves_per_s": 12 / e,
+           "max_true_rel_res": max(s["true_rel_res"] for s in st),
+           "outer_iters": [s["outer_iters"] for s in st],
+           "pass_rooflines": {
+               n: family_roofline(spans, n, k) for n, k in (
+                   ("fp32_inner", "k_ms_t<float, *> + k_ms_r<float, *> (FP32 inner passes, "
+                                  "12 systems x 2 sources per launch)"),
+                   ("fp64_truth", "k_ms_t<double, *> + k_ms_r<double, *> (FP64 true-residual "
+                                  "passes, the systems due for an update x 2 sources per launch)"))}}
     del lat
+    return out, b, p
+
+
+def other_configs(torch, Lattice, inputs):
+    """Timed runs of the batched (16^3x32, 12 rhs), force (12^4) and uneven-batch
+    workloads; one warm-up and one timed call each."""
+    from paper_1005_3276_amd import solve_batch
+    out = {}
+    # config 3
+    dims = (16, 16, 16, 32)
+    c3, b, p = batched_config3(torch, Lattice, inputs)
+    e = c3["seconds"]
+    out["config3_batched_16x3x32_12rhs"] = c3
+    log(f"config3: {out['config3_batched_16x3x32_12rhs']}")
     # the same batch with the FP64 solver (the mixed solver's algorithm in FP64)
     lat = Lattice(dims, precision="fp64", m=0.02, g=0.5, n_poles=20, lambda_min=1e-3,
                   lambda_max=8.0, outer_tol=1e-10, inner_tol=1e-8)
@@ -330,6 +388,9 @@ def main():
                     help="end with one 512 MiB device copy (reference for traffic counters)")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the 16^4 stencil sweep (one JSON line of its own)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched 12 x 16^3x32 mixed solve with its pass rooflines "
+                         "(one JSON line of its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the batched and "
@@ -353,6 +414,11 @@ def main():
             calibrate_copy(torch)
             out["calibration_copy_bytes"] = 512 << 20
         print(json.dumps(out), flush=True)
+        return
+    if args.batched_only:
+        c3, _, _ = batched_config3(torch, Lattice, inputs)
+        print(json.dumps({"metric": "batched_only", "config3_batched_16x3x32_12rhs": c3}),
+              flush=True)
         return
     phi, src = inputs.draw(DIMS, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
     dphi = torch.from_numpy(phi).cuda()
@@ -385,47 +451,22 @@ def main():
     # multi-shift pass launch of one solve is sampled (the cap applies per host
     # synchronisation, i.e. per outer iteration / reliable update), so the per-family
     # sums below cover the whole solve and decide which pass family dominates.
+    families = {
+        "fp64_truth": "k_ms_t<double, *> + k_ms_r<double, *> (FP64 multi-shift passes of "
+                      "the true residuals, two sources per launch)",
+        "fp32_inner": "k_ms_t<float, *> + k_ms_r<float, *> (FP32 multi-shift passes of "
+                      "the inner CG, two sources per launch)",
+    }
     if args.no_sample:
         lat.kernel_sampling(0)
+        for k in range(5):
+            lat.kernel_spans(k, reset=True)
+        lat.solve(dsrc, dphi)
+        spans = [lat.kernel_spans(k) for k in range(5)]
     else:
-        lat.kernel_sampling(512)
-    for k in range(5):
-        lat.kernel_spans(k, reset=True)
-    lat.solve(dsrc, dphi)
-    lat.kernel_sampling(0)
-    spans = [lat.kernel_spans(k) for k in range(5)]  # (kernel_ms, kcnt, event_ms, cnt, bytes)
-    families = {
-        "fp64_truth": ((3, 4), "k_ms_t<double, *> + k_ms_r<double, *> (FP64 multi-shift passes of "
-                               "the true residuals, two sources per launch)"),
-        "fp32_inner": ((0, 1), "k_ms_t<float, *> + k_ms_r<float, *> (FP32 multi-shift passes of "
-                               "the inner CG, two sources per launch)"),
-    }
+        spans = sampled_spans(lat, lambda: lat.solve(dsrc, dphi))
 
-    def family_roofline(name):
-        ids, kname = families[name]
-        ms_sum = sum(spans[k][2] for k in ids)
-        cnt = sum(spans[k][3] for k in ids)
-        bytes_sum = sum(spans[k][4] for k in ids)
-        per_launch = bytes_sum / max(cnt, 1)
-        achieved = bytes_sum / (ms_sum * 1e-3) / 1e9 if ms_sum > 0 else 0.0
-        r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, per_launch),
-             "kernel": kname, "avg_launch_us": ms_sum / max(cnt, 1) * 1e3,
-             "bytes_per_launch": per_launch, "launches_per_solve": cnt,
-             "event_ms_per_solve": ms_sum,
-             "t_pass_us": spans[ids[0]][2] / max(spans[ids[0]][3], 1) * 1e3,
-             "r_pass_us": spans[ids[1]][2] / max(spans[ids[1]][3], 1) * 1e3}
-        # the same launches, kernel-only: max(end) - min(start) of device wall-clock
-        # stamps taken by every workgroup (what a kernel trace reports; the event
-        # duration above also holds the dispatch gap before each launch)
-        kms = sum(spans[k][0] for k in ids)
-        kcnt = sum(spans[k][1] for k in ids)
-        if kcnt > 0:
-            r["kernel_only_us"] = kms / kcnt * 1e3
-            r["achieved_kernel_only"] = per_launch / (kms / kcnt * 1e-3) / 1e9
-        return r
-
-    fam = {n: family_roofline(n) for n in families}
+    fam = {n: family_roofline(spans, n, families[n]) for n in families}
     dom = max(fam, key=lambda n: fam[n]["event_ms_per_solve"])
     roofline = fam[dom]
     roofline_secondary = fam[[n for n in fam if n != dom][0]]
