@@ -1289,18 +1289,20 @@ __device__ __forceinline__ int find_sys(const SysDev* __restrict__ sys, int nsys
   return s;
 }
 
-__device__ __forceinline__ void twiddles(double2* tw, int L, double sgn) {
+// Twiddle table e^{sgn 2 pi i j / L}, evaluated in FP64 and stored in the transform's
+// precision (an FP32 transform reads 8-byte entries from LDS).
+template <class R>
+__device__ __forceinline__ void twiddles(c2<R>* tw, int L, double sgn) {
   for (int j = threadIdx.x; j < L; j += blockDim.x) {
     double sn, cs;
     sincospi(2.0 * (double)j / (double)L, &sn, &cs);
-    tw[j] = double2{cs, sgn * sn};
+    tw[j] = c2<R>{(R)cs, (R)(sgn * sn)};
   }
 }
 
 template <class R>
-__device__ __forceinline__ c2<R> cmad(c2<R> acc, c2<R> a, double2 w) {
-  const R wr = (R)w.x, wi = (R)w.y;
-  return c2<R>{acc.x + a.x * wr - a.y * wi, acc.y + a.x * wi + a.y * wr};
+__device__ __forceinline__ c2<R> cmad(c2<R> acc, c2<R> a, c2<R> w) {
+  return c2<R>{acc.x + a.x * w.x - a.y * w.y, acc.y + a.x * w.y + a.y * w.x};
 }
 
 // x and y axes of one (z, t, spin) plane.  inv = 0: e_in -> fft_tmp with the
@@ -1310,7 +1312,7 @@ template <class R>
 __global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, int nsys, int inv,
                                                 int periodic) {
   __shared__ c2<R> A[1024], B[1024];
-  __shared__ double2 twx[64], twy[64];
+  __shared__ c2<R> twx[64], twy[64];
   const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 0)];
   if (S.active && *S.active == 0) return;
   const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, T = S.g.T, V = S.g.V;
@@ -1322,8 +1324,8 @@ __global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, 
   const c2<R>* in = (const c2<R>*)(inv ? S.fft_tmp : S.e_in) + (size_t)spin * V + (size_t)zt * XY;
   c2<R>* out = (c2<R>*)(inv ? S.e_out : S.fft_tmp) + (size_t)spin * V + (size_t)zt * XY;
   const double sgn = inv ? 1.0 : -1.0;
-  twiddles(twx, X, sgn);
-  twiddles(twy, Y, sgn);
+  twiddles<R>(twx, X, sgn);
+  twiddles<R>(twy, Y, sgn);
   double tr = 1.0, ti = 0.0;  // twist (forward) / untwist and normalisation (inverse)
   if (S.g.bc < 0 && !periodic) sincospi(sgn * (double)t / (double)T, &ti, &tr);
   if (inv) {
@@ -1365,7 +1367,7 @@ __global__ void __launch_bounds__(256) k_fft_xy(const SysDev* __restrict__ sys, 
 template <class R>
 __global__ void __launch_bounds__(256) k_fft_z(const SysDev* __restrict__ sys, int nsys, int inv) {
   __shared__ c2<R> A[1024];
-  __shared__ double2 tw[64];
+  __shared__ c2<R> tw[64];
   const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 1)];
   if (S.active && *S.active == 0) return;
   const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, V = S.g.V;
@@ -1374,7 +1376,7 @@ __global__ void __launch_bounds__(256) k_fft_z(const SysDev* __restrict__ sys, i
   const int yt = loc >> 2;  // y + Y t
   const int y = yt % Y, t = yt / Y;
   c2<R>* f = (c2<R>*)S.fft_tmp + (size_t)spin * V;
-  twiddles(tw, Z, inv ? 1.0 : -1.0);
+  twiddles<R>(tw, Z, inv ? 1.0 : -1.0);
   const int n = X * Z;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int x = e % X, z = e / X;
@@ -1452,7 +1454,7 @@ template <class R>
 __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sys, int nsys,
                                                    const SymParams sp) {
   __shared__ c2<R> A[1024], B[1024];
-  __shared__ double2 twf[64], twi[64];
+  __shared__ c2<R> twf[64], twi[64];
   const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 2)];
   if (S.active && *S.active == 0) return;
   const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, T = S.g.T, V = S.g.V;
@@ -1463,8 +1465,8 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
   const int yz = loc / nxc;  // y + Y z
   const int y = yz % Y, z = yz / Y;
   c2<R>* f = (c2<R>*)S.fft_tmp;
-  twiddles(twf, T, -1.0);
-  twiddles(twi, T, 1.0);
+  twiddles<R>(twf, T, -1.0);
+  twiddles<R>(twi, T, 1.0);
   const int n = 4 * XC * T;  // element e = (spin T + t) XC + xl
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int xl = e % XC, q = e / XC;
