@@ -79,7 +79,7 @@ struct SysDev {
   int nshift;
   void* fft_tmp;            // momentum-space scratch field (kernel precision)
   int off_xy, off_z, off_t; // first workgroup of this system in each transform pass
-  int xc;                   // x values per workgroup in the t pass (divides X, <= 8)
+  int xc;                   // x values per workgroup in the t pass (divides X, xc T <= 64)
 };
 
 // CG scalar slots
@@ -1455,6 +1455,7 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
                                                    const SymParams sp) {
   __shared__ c2<R> A[1024], B[1024];
   __shared__ c2<R> twf[64], twi[64];
+  __shared__ double2 csx[64], cst[64];  // (sin, cos) of the block's x momenta and of every t momentum
   const SysDev& S = sys[find_sys(sys, nsys, blockIdx.x, 2)];
   if (S.active && *S.active == 0) return;
   const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, T = S.g.T, V = S.g.V;
@@ -1467,6 +1468,17 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
   c2<R>* f = (c2<R>*)S.fft_tmp;
   twiddles<R>(twf, T, -1.0);
   twiddles<R>(twi, T, 1.0);
+  const double tshift = (S.g.bc < 0 && !sp.periodic) ? 1.0 : 0.0;
+  for (int j = threadIdx.x; j < XC + T; j += blockDim.x) {
+    double sn, cs;
+    if (j < XC) {
+      sincospi(2.0 * (double)(xb + j) / (double)X, &sn, &cs);
+      csx[j] = double2{sn, cs};
+    } else {
+      sincospi((2.0 * (j - XC) + tshift) / (double)T, &sn, &cs);
+      cst[j - XC] = double2{sn, cs};
+    }
+  }
   const int n = 4 * XC * T;  // element e = (spin T + t) XC + xl
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int xl = e % XC, q = e / XC;
@@ -1492,9 +1504,7 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
   sincospi(2.0 * (double)z / (double)Z, &sz, &cz);
   for (int q = threadIdx.x; q < XC * T; q += blockDim.x) {  // operator at (kx, ky, kz, kt)
     const int xl = q % XC, kt = q / XC;
-    double sx, cx, st, ct;
-    sincospi(2.0 * (double)(xb + xl) / (double)X, &sx, &cx);
-    sincospi((2.0 * kt + ((S.g.bc < 0 && !sp.periodic) ? 1.0 : 0.0)) / (double)T, &st, &ct);
+    const double sx = csx[xl].x, cx = csx[xl].y, st = cst[kt].x, ct = cst[kt].y;
     const double w = sp.diag - (cx + cy + cz + ct);
     double2 v[4];
 #pragma unroll
