@@ -358,9 +358,9 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
 // registers, the current plane in LDS (sh: 4 X Y values) for the x and y
 // neighbours.  Next to the stencil operands each site may take one more spinor
 // of its own (the epilogue operand, from ep).  begin() issues the loads of the
-// first plane, so a caller can put them in flight before its scalar work; run()
-// walks the planes with the loads of plane k + 1 issued before plane k is
-// computed.  For each site, epi(i, w, e) receives w = (H_W f)_i and the epilogue
+// first plane, so a caller can put them in flight before its scalar work; run<PIPE>()
+// walks the planes, with PIPE loading the operands of plane k + 1 before plane k is
+// computed (else after it).  For each site, epi(i, w, e) receives w = (H_W f)_i and the epilogue
 // operand e and returns a partial sum; run() returns the total.  Every thread of
 // the block must call run().
 template <class R>
