@@ -73,3 +73,32 @@ def test_null_arguments():
     assert lib.ov_force(None, None, None, None, None, 1, None) == L.OV_ERR_INVALID_ARG
     assert lib.ov_zolotarev(0, 0.1, 1.0, None, None, None) == L.OV_ERR_INVALID_ARG
     assert lib.ov_status_string(L.OV_ERR_SPECTRUM).decode().startswith("spectrum")
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py is a one-GPU benchmark: --gpus N > 1 exits with a message and status 2
+    before touching any device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "single-GPU" in msg["error"]
+
+
+def test_traffic_record_gated_by_kernel_source():
+    """The committed HBM-traffic record names the multi-shift pass code it was measured on;
+    bench.py reports it only while that code, and the bytes per launch, are unchanged."""
+    import importlib.util
+    import json
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rec = json.load(open(os.path.join(ROOT, "profiles", "k_ms_passes_16x4_traffic.json")))
+    same = rec["kernel_source_hash"] == bench.kernel_source_hash()
+    for name, fam in rec["families"].items():
+        got = bench.measured_traffic(name, fam["algorithmic_bytes_per_launch"])
+        assert got == (fam["hbm_bytes_per_launch"] if same else None)
+        assert bench.measured_traffic(name, fam["algorithmic_bytes_per_launch"] + 1) is None
