@@ -372,6 +372,21 @@ def test_zero_source_gives_zero():
     assert st[0]["inner_iters"] == 0
 
 
+def test_empty_batch_rejected():
+    """No right-hand side at all: every entry point refuses it with OV_ERR_INVALID_ARG and
+    launches nothing."""
+    from paper_1005_3276_amd import _lib as L
+    dims = (4, 4, 4, 4)
+    lat = lattice(dims, **CFG1)
+    e = torch.zeros((0,) + lat.field_shape, dtype=torch.complex128, device="cuda")
+    phi = torch.zeros(lat.phi_shape, dtype=torch.complex128, device="cuda")
+    for call in (lambda: lat.sign(e), lambda: lat.apply("m", e, phi), lambda: lat.solve(e, phi)):
+        with pytest.raises(L.OvError) as err:
+            call()
+        assert err.value.status == L.OV_ERR_INVALID_ARG
+    lat.sign(torch.ones((1,) + lat.field_shape, dtype=torch.complex128, device="cuda"))
+
+
 # ------------------------------------------------------------------- solves
 
 @pytest.mark.parametrize("form", [1, 0])
