@@ -382,9 +382,10 @@ struct Engine {
   size_t layout(void* base, size_t cap, bool dry) {
     Bump bp(base, cap, dry);
     gbar = (GridBar*)bp.take(sizeof(GridBar));
-    cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys);
-    // counters of entries A, B (inner) and B (true residual)
-    stat_all = (long long*)bp.take(sizeof(long long) * 12 * nsys);
+    // the CG scalars and, right after them, the counters of entries A, B (inner) and
+    // B (true residual): one block, read back with one copy
+    cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys + sizeof(long long) * 12 * nsys);
+    stat_all = dry ? nullptr : (long long*)(cg_all + (size_t)CG_NSLOT * nsys);
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0, nxy = 0, nz = 0, nt = 0;
     long long total_sites = 0;
@@ -826,7 +827,7 @@ ov_status sync(Engine& E) {
   TRY(check_launch(E.lead));
   HIPCHK(E.lead, hipStreamSynchronize(E.st));
   if (!E.lead->ev_use.empty()) collect_samples(E.lead);
-  if (E.gbar) {
+  if (E.gbar && E.lead->persistent) {  // only the persistent kernel uses the grid barrier
     GridBar gb;
     HIPCHK(E.lead, hipMemcpy(&gb, E.gbar, sizeof(gb), hipMemcpyDeviceToHost));
     if (gb.abort) {
@@ -1392,10 +1393,10 @@ ov_status set_flags(Engine& E, const std::vector<int>& cg, const std::vector<int
 }
 
 ov_status read_scalars(Engine& E) {
-  HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all, sizeof(double) * CG_NSLOT * E.nsys,
+  static_assert(sizeof(long long) == sizeof(double), "counters share the scalar block");
+  HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all,
+                                sizeof(double) * CG_NSLOT * E.nsys + sizeof(long long) * 12 * E.nsys,
                                 hipMemcpyDeviceToHost, E.st));
-  HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned + (size_t)CG_NSLOT * E.nsys, E.stat_all,
-                                sizeof(long long) * 12 * E.nsys, hipMemcpyDeviceToHost, E.st));
   return sync(E);
 }
 
