@@ -410,6 +410,24 @@ def test_solve_residual_under_oracle(orc, dims, prec, pc, form):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_periodic_complex_couplings(orc, prec):
+    """Periodic time (bc_t = +1, the preconditioner's t momenta on 2 pi n / T) and complex
+    m and g (Y = (m + g phi) P+ + (m* + g* phi*) P-): the solve meets the 1e-10 true
+    residual under the oracle's operator and agrees with the oracle's solution."""
+    dims = (4, 4, 2, 6)
+    kw = dict(m=0.08 + 0.05j, g=0.3 - 0.2j, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2) + 7)
+    lat = lattice(dims, bc_t=1, precision=prec, outer_tol=1e-10, inner_tol=1e-8, **kw)
+    x, st = lat.solve(dev(src), dev(phi))
+    x = host(x)
+    o = orc.Oracle(dims, bc_t=1, inner_tol=1e-13, **kw)
+    for r in range(2):
+        assert o.residual(src[r], x[r], phi) <= 1e-10
+        xo, _, _ = o.solve(src[r], phi, tol=1e-11)
+        assert rel(x[r], xo) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_solve_8x4_config2(orc, prec):
     dims = (8, 8, 8, 8)
     phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
