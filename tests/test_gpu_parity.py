@@ -51,6 +51,7 @@ def lattice(dims, **kw):
 
 CFG1 = dict(m=0.05, g=0.1, n_poles=16, lambda_min=0.01, lambda_max=8.0)
 CFG2 = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+CFG5 = dict(m=0.05, g=0.3, n_poles=24, lambda_min=1e-4, lambda_max=8.0)  # uneven-batch sign
 
 
 # ------------------------------------------------------------- pack / stencil
@@ -134,7 +135,7 @@ def test_zmarch_multishift_passes(orc, spt):
 # -------------------------------------------------------------- sign / apply
 
 @pytest.mark.parametrize("dims,cfg", [((4, 4, 4, 4), CFG1), ((8, 8, 8, 8), CFG2),
-                                      ((2, 4, 6, 8), CFG2)])
+                                      ((2, 4, 6, 8), CFG2), ((6, 4, 4, 8), CFG5)])
 def test_sign_vs_oracle(orc, dims, cfg):
     print(f"[sign] dims={dims}", flush=True)
     tol = 1e-12
