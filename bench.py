@@ -281,6 +281,18 @@ def other_configs(torch, Lattice, inputs):
         "max_true_rel_res": max(s["true_rel_res"] for s in st),
         "outer_iters": [s["outer_iters"] for s in st]}
     log(f"config5: {out['config5_uneven_batch']}")
+    # the adjoint force on the 16^4 member (its first source)
+    l16 = lats[2]
+    xi16 = bs[2][:1].contiguous()
+    l16.force(xi16, ps[2])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    S16, _, st16 = l16.force(xi16, ps[2])
+    torch.cuda.synchronize()
+    e16 = time.perf_counter() - t
+    out["config5_force_16x4_member"] = {"seconds": e16, "S": S16[0],
+                                        "outer_iters": st16[0]["outer_iters"]}
+    log(f"config5 force: {out['config5_force_16x4_member']}")
     del lats
     # the same batch with the FP64 solver
     lats = [Lattice(d, precision="fp64", m=0.05, g=0.3, n_poles=24, lambda_min=1e-4,
