@@ -162,6 +162,26 @@ def test_sign_config1_vs_exact_rational(orc):
     assert rel(host(e2), src) < 3 * delta + 1e-11
 
 
+@pytest.mark.parametrize("bc", [-1, 1])
+def test_sign_config1_vs_diagonalised(bc):
+    """Config 1 (4^4, 16 poles on [0.01, 8]): the GPU sign and D_ov against H_W
+    diagonalised in momentum space (numpy FFT, no oracle code): within 1e-11 of the
+    rational r(H_W) and within the Zolotarev error delta of sgn(H_W) itself."""
+    import closed_form as cf
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(1))
+    lat = lattice(dims, bc_t=bc, inner_tol=1e-12, **CFG1)
+    a, b, delta = lat.coeffs()
+    eps = host(lat.sign(dev(src))[0])[0]
+    dov = host(lat.apply("dov", dev(src))[0])[0]
+    rat = cf.apply_symbol(cf.rational_symbol(dims, a, b, bc), src[0], dims, bc)
+    exact = cf.apply_symbol(cf.exact_sign_symbol(dims, bc), src[0], dims, bc)
+    assert rel(eps, rat) < 1e-11
+    assert rel(eps, exact) < delta + 1e-11
+    assert rel(dov, cf.apply_symbol(cf.dov_symbol(cf.rational_symbol(dims, a, b, bc)), src[0],
+                                    dims, bc)) < 1e-11
+
+
 @pytest.mark.parametrize("op", ["dov", "dov_dag", "m", "m_dag", "mdagm"])
 def test_apply_ops_vs_oracle(orc, op):
     dims = (4, 4, 4, 4)
