@@ -576,6 +576,25 @@ def test_solve_deterministic_bitwise(precision):
     assert np.array_equal(bits(la.sign(dev(src))[0]), bits(lb.sign(dev(src))[0]))
 
 
+def test_graph_captured_solve_equals_eager(monkeypatch):
+    """OV_GRAPHS=1 (each outer iteration and reliable update captured once and replayed):
+    two solves, each bitwise equal to the eager solve in the same state, with the replays
+    separated by the solver's own synchronisations and eager work."""
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2))
+    kw = dict(precision="mixed", outer_tol=1e-10, **CFG2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b, p = dev(src), dev(phi)
+        le = lattice(dims, **kw)
+        ref = [host(le.solve(b, p)[0]) for _ in range(2)]
+        monkeypatch.setenv("OV_GRAPHS", "1")
+        lg = lattice(dims, **kw)
+        got = [host(lg.solve(b, p)[0]) for _ in range(2)]
+    for r, g in zip(ref, got):
+        assert np.array_equal(r.view(np.uint64), g.view(np.uint64))
+
+
 def test_uneven_batch(orc):
     from paper_1005_3276_amd import solve_batch
     kw = dict(precision="mixed", outer_tol=1e-10, m=0.05, g=0.3, n_poles=24,
