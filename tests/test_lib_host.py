@@ -102,3 +102,25 @@ def test_traffic_record_gated_by_kernel_source():
         got = bench.measured_traffic(name, fam["algorithmic_bytes_per_launch"])
         assert got == (fam["hbm_bytes_per_launch"] if same else None)
         assert bench.measured_traffic(name, fam["algorithmic_bytes_per_launch"] + 1) is None
+
+
+@pytest.mark.parametrize("name", ["k_ms_passes_16x4_traffic.json",
+                                  "k_ms_passes_16x3x32x12_traffic.json"])
+def test_traffic_records_consistent(name):
+    """Each committed HBM-traffic record is internally consistent: the scale factors are
+    the copy calibration's bytes over its counter readings, and each family's bytes per
+    launch are the scaled FETCH_SIZE + WRITE_SIZE medians averaged over its two passes."""
+    import json
+    rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+    cal = rec["calibration"]
+    kib = cal["copy_bytes"] / 1024
+    assert abs(cal["fetch_scale"] - kib / cal["fetch_kib"]) < 1e-3
+    assert abs(cal["write_scale"] - kib / cal["write_kib"]) < 1e-3
+    for fam in rec["families"].values():
+        ks = fam["kernels"]
+        assert len(ks) == 2
+        tot = sum(fam["fetch_kib_per_dispatch"][k] * 1024 * cal["fetch_scale"]
+                  + fam["write_kib_per_dispatch"][k] * 1024 * cal["write_scale"] for k in ks) / 2
+        assert abs(tot - fam["hbm_bytes_per_launch"]) <= 1e-6 * tot + 1
+        assert abs(fam["ratio"] - tot / fam["algorithmic_bytes_per_launch"]) < 1e-3
+        assert fam["hbm_bytes_per_launch"] >= fam["algorithmic_bytes_per_launch"]
