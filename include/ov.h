@@ -166,11 +166,21 @@ void ov_params_default(ov_params *p);
 ov_status ov_ctx_create(const ov_params *p, void *hip_stream, ov_ctx **out);
 ov_status ov_ctx_destroy(ov_ctx *ctx);
 
-/* Device bytes of workspace needed for nrhs right-hand sides. */
+/* Device bytes of workspace that every call on nrhs right-hand sides needs (sign, apply,
+ * solve, force, locality, boson, pack/unpack), whatever launch shape ov_set_launch or
+ * the autotuner selects.  0 for a null context or nrhs < 1. */
 size_t ov_workspace_bytes(const ov_ctx *ctx, int nrhs);
 
-/* Hand the context a caller-owned device buffer (256-byte aligned).  Without
- * one, calls allocate and keep their own workspace (freed by ov_ctx_destroy). */
+/* Device bytes of workspace ov_rational / ov_rational_force need for nrhs right-hand
+ * sides and nshift (1..32) shifted systems (each shift keeps its own solution and search
+ * direction).  0 for invalid arguments. */
+size_t ov_workspace_bytes_rational(const ov_ctx *ctx, int nrhs, int nshift);
+
+/* Hand the context a caller-owned device buffer (256-byte aligned; dev_ptr = NULL
+ * returns to library-owned workspace).  While one is set, a call that needs more than
+ * `bytes` returns OV_ERR_WORKSPACE and launches nothing: the library never adds a
+ * hidden allocation to a caller's workspace.  Without one, calls allocate and keep their
+ * own workspace (freed by ov_ctx_destroy). */
 ov_status ov_set_workspace(ov_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Zolotarev coefficients (n_poles each) and the max error delta on the interval. */

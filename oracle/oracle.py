@@ -74,6 +74,9 @@ def lib():
         L.orc_rhmc_trajectory.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_double, C.c_int,
                                           P, P, C.c_double, C.c_int, P, P, C.c_double,
                                           C.c_double, C.c_int, P, P]
+        L.orc_rhmc_trajectory_ex.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_double,
+                                             C.c_int, P, P, C.c_double, C.c_int, P, P,
+                                             C.c_double, C.c_double, C.c_int, P, P, P, P]
         L.orc_rational_force.argtypes = [P, P, C.c_double, C.c_int, P, P, P, C.c_double,
                                          C.c_int, P, P]
         _lib = L
@@ -254,8 +257,11 @@ class Oracle:
         lib().orc_boson(C.byref(self.p), _ptr(ph), C.byref(S), _ptr(G), _ptr(F))
         return S.value, G.reshape(self.shape[:4]), F.reshape(self.shape[:4])
 
-    def rhmc_trajectory(self, phi, pi, R, nsteps, tau, c18, c14, u, tol=1e-12, maxit=4000):
-        """One RHMC trajectory; returns (phi_end_or_start, dH, accepted)."""
+    def rhmc_trajectory(self, phi, pi, R, nsteps, tau, c18, c14, u, tol=1e-12, maxit=4000,
+                        start=False):
+        """One RHMC trajectory; returns (phi_end_or_start, dH, accepted), and with
+        start=True also (eta, H_parts): the heatbath field eta = r18(MdagM) R and the
+        kinetic, bosonic and pseudofermion parts of H at the start."""
         ph = np.ascontiguousarray(phi, np.complex128).reshape(-1).copy()
         pi = np.ascontiguousarray(pi, np.complex128).reshape(-1)
         R = self._field(R)
@@ -263,13 +269,18 @@ class Oracle:
         a14, al14, be14 = c14[0], np.ascontiguousarray(c14[1], np.float64), np.ascontiguousarray(c14[2], np.float64)
         dH = C.c_double(0.0)
         acc = C.c_int(0)
-        rc = lib().orc_rhmc_trajectory(C.byref(self.p), _ptr(ph), _ptr(pi), _ptr(R), nsteps, tau,
-                                       a18, len(al18), _ptr(al18), _ptr(be18), a14, len(al14),
-                                       _ptr(al14), _ptr(be14), u, tol, maxit, C.byref(dH),
-                                       C.byref(acc))
+        eta = np.zeros_like(R)
+        parts = np.zeros(3)
+        rc = lib().orc_rhmc_trajectory_ex(C.byref(self.p), _ptr(ph), _ptr(pi), _ptr(R), nsteps,
+                                          tau, a18, len(al18), _ptr(al18), _ptr(be18), a14,
+                                          len(al14), _ptr(al14), _ptr(be14), u, tol, maxit,
+                                          C.byref(dH), C.byref(acc), _ptr(eta), _ptr(parts))
         if rc != 0:
             raise RuntimeError(f"orc_rhmc_trajectory: a solve did not converge ({rc})")
-        return ph.reshape(self.shape[:4]), dH.value, bool(acc.value)
+        out = (ph.reshape(self.shape[:4]), dH.value, bool(acc.value))
+        if start:
+            return out + (eta.reshape(self.shape), parts)
+        return out
 
     def locality(self, spin=0):
         """f(r), r = 0 .. sum L/2, of the locality probe of Sec. 3.2 for this D."""

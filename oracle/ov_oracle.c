@@ -543,7 +543,7 @@ static int momentum_apply(const orc_params *p, int dag, const cplx *in, cplx *ou
     }
     const double pm[4] = {momentum(p, 0, kx), momentum(p, 1, ky), momentum(p, 2, kz),
                           momentum(p, 3, kt)};
-    cplx D[4][4];
+    cplx D[4][4] = {{0}};
     if (dirac_symbol(p, pm, dag, D)) bad = 1;
     for (int s = 0; s < 4; ++s) {
       cplx v = 0;
@@ -973,13 +973,14 @@ int orc_boson(const orc_params *p, const cplx *phi, double *S, cplx *G, cplx *F)
  * (r18 ~ x^{1/8}, r14 ~ x^{-1/4}: a0 + sum alpha_i/(x + beta_i)), with
  * dphi/dt = pi and dpi/dt = -G; accepted when u < exp(-dH).  phi is updated in
  * place when accepted.  Momenta pi, the Gaussian R and u are inputs. */
-int orc_rhmc_trajectory(const orc_params *p, cplx *phi, const cplx *pi0, const cplx *R,
-                        int nsteps, double tau, double a18, int n18, const double *al18,
-                        const double *be18, double a14, int n14, const double *al14,
-                        const double *be14, double u, double tol, int maxit, double *dH,
-                        int *accepted) {
+int orc_rhmc_trajectory_ex(const orc_params *p, cplx *phi, const cplx *pi0, const cplx *R,
+                           int nsteps, double tau, double a18, int n18, const double *al18,
+                           const double *be18, double a14, int n14, const double *al14,
+                           const double *be14, double u, double tol, int maxit, double *dH,
+                           int *accepted, cplx *eta_out, double *H_parts) {
   const long long V = volume(p), N = 4 * V;
   cplx *eta = vec_new(N), *ph = vec_new(V), *pi = vec_new(V), *G = vec_new(V), *Gf = vec_new(V);
+  /* pseudofermion heatbath: eta = (MdagM)^{1/8} R through the x^{1/8} rational */
   int rc = orc_rational(p, phi, a18, n18, al18, be18, R, eta, tol, maxit);
   memcpy(ph, phi, (size_t)V * sizeof(cplx));
   memcpy(pi, pi0, (size_t)V * sizeof(cplx));
@@ -989,6 +990,12 @@ int orc_rhmc_trajectory(const orc_params *p, cplx *phi, const cplx *pi0, const c
   orc_boson(p, ph, &Sb, G, NULL);
   rc |= orc_rational_force(p, ph, a14, n14, al14, be14, eta, tol, maxit, &Sf, Gf);
   H0 = 0.5 * vec_norm2(V, pi) + Sb + Sf;
+  if (H_parts) {  /* kinetic, bosonic and pseudofermion parts of H at the start */
+    H_parts[0] = 0.5 * vec_norm2(V, pi);
+    H_parts[1] = Sb;
+    H_parts[2] = Sf;
+  }
+  if (eta_out) memcpy(eta_out, eta, (size_t)N * sizeof(cplx));
   for (int k = 0; k < nsteps; ++k) {
     for (long long x = 0; x < V; ++x) pi[x] -= 0.5 * eps * (G[x] + Gf[x]);
     for (long long x = 0; x < V; ++x) ph[x] += eps * pi[x];
@@ -1002,4 +1009,13 @@ int orc_rhmc_trajectory(const orc_params *p, cplx *phi, const cplx *pi0, const c
   if (*accepted) memcpy(phi, ph, (size_t)V * sizeof(cplx));
   free(eta); free(ph); free(pi); free(G); free(Gf);
   return rc;
+}
+
+int orc_rhmc_trajectory(const orc_params *p, cplx *phi, const cplx *pi0, const cplx *R,
+                        int nsteps, double tau, double a18, int n18, const double *al18,
+                        const double *be18, double a14, int n14, const double *al14,
+                        const double *be14, double u, double tol, int maxit, double *dH,
+                        int *accepted) {
+  return orc_rhmc_trajectory_ex(p, phi, pi0, R, nsteps, tau, a18, n18, al18, be18, a14, n14,
+                                al14, be14, u, tol, maxit, dH, accepted, NULL, NULL);
 }

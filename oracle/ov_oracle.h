@@ -159,6 +159,16 @@ int orc_rhmc_trajectory(const orc_params *p, double complex *phi, const double c
                         const double *al14, const double *be14, double u, double tol,
                         int maxit, double *dH, int *accepted);
 
+/* The same trajectory with its start exposed: eta_out (4 V, may be NULL) receives the
+ * heatbath field eta = r18(MdagM) R, H_parts (3 doubles, may be NULL) the kinetic,
+ * bosonic and pseudofermion parts of H at the start of the trajectory. */
+int orc_rhmc_trajectory_ex(const orc_params *p, double complex *phi, const double complex *pi0,
+                           const double complex *R, int nsteps, double tau, double a18, int n18,
+                           const double *al18, const double *be18, double a14, int n14,
+                           const double *al14, const double *be14, double u, double tol,
+                           int maxit, double *dH, int *accepted, double complex *eta_out,
+                           double *H_parts);
+
 int orc_threads(void);
 
 #endif

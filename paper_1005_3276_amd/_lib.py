@@ -22,6 +22,7 @@ OPS = {"hw": OP_HW, "dov": OP_DOV, "dov_dag": OP_DOV_DAG, "m": OP_M, "m_dag": OP
 
 # every symbol include/ov.h declares
 SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace_bytes",
+           "ov_workspace_bytes_rational",
            "ov_set_workspace", "ov_get_coeffs", "ov_zolotarev", "ov_sign", "ov_apply",
            "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
            "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling",
@@ -78,6 +79,8 @@ def lib():
         L.ov_ctx_destroy.argtypes = [P]
         L.ov_workspace_bytes.argtypes = [P, C.c_int]
         L.ov_workspace_bytes.restype = C.c_size_t
+        L.ov_workspace_bytes_rational.argtypes = [P, C.c_int, C.c_int]
+        L.ov_workspace_bytes_rational.restype = C.c_size_t
         L.ov_set_workspace.argtypes = [P, P, C.c_size_t]
         L.ov_get_coeffs.argtypes = [P, P, P, P]
         L.ov_zolotarev.argtypes = [C.c_int, C.c_double, C.c_double, P, P, P]

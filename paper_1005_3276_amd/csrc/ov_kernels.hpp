@@ -2130,6 +2130,21 @@ __global__ void k_stat3_clear(const SysDev* __restrict__ sys, int nsys) {
     if (sys[s].stat) sys[s].stat[3] = 0;
 }
 
+// h_ctl[3] = 0 (the sticky multi-shift error bits) for the nsys entries, so that the
+// next multi-shift solves can be checked on their own.
+__global__ void k_ctl3_clear(const SysDev* __restrict__ sys, int nsys) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x)
+    if (sys[s].h_ctl) sys[s].h_ctl[3] = 0;
+}
+
+// Zero n 32-bit words (a fill kernel rather than a memset node, so that the clear is
+// an ordinary kernel also when a caller captures the stream into a graph).
+__global__ void __launch_bounds__(256) k_zero32(unsigned int* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // p = r + beta p (beta from cg_s; use_beta = 0 -> p = r); partial |p|^2 -> part_b.
 template <class R>
 __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, const int* __restrict__ bmap,

@@ -270,8 +270,6 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
   s.h_alpha = (double*)bp.take(sizeof(double) * (capmax + 1));
   s.h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
   s.h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
-  s.h_ctl = (int*)bp.take(sizeof(int) * 4);
-  s.dstat = (double*)bp.take(sizeof(double) * 2);
   s.coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
   s.coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
   s.coef_d = (double*)bp.take(sizeof(double) * capmax);
@@ -287,8 +285,6 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.ms_b_h_alpha = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.ms_b_h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
     s.ms_b_h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
-    s.ms_b_h_ctl = (int*)bp.take(sizeof(int) * 4);
-    s.ms_b_dstat = (double*)bp.take(sizeof(double) * 2);
     s.ms_b_coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
     s.ms_b_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.ms_b_coef_d = (double*)bp.take(sizeof(double) * capmax);
@@ -304,8 +300,6 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.tb_h_alpha = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.tb_h_zeta = (double*)bp.take(sizeof(double) * (capmax + 1) * MAXP);
     s.tb_h_active = (unsigned*)bp.take(sizeof(unsigned) * (capmax + 1));
-    s.tb_h_ctl = (int*)bp.take(sizeof(int) * 4);
-    s.tb_dstat = (double*)bp.take(sizeof(double) * 2);
     s.tb_coef_term = (double*)bp.take(sizeof(double) * MAXP * capmax);
     s.tb_coef_c = (double*)bp.take(sizeof(double) * (capmax + 1));
     s.tb_coef_d = (double*)bp.take(sizeof(double) * capmax);
@@ -365,7 +359,13 @@ struct Engine {
   std::vector<void*> hptrs;         // host staging of ptrs (outlives the async copy)
   GridBar* gbar = nullptr;          // device: grid barrier of the persistent kernel
   double* cg_all = nullptr;         // device: nsys * CG_NSLOT scalars (one copy to the host)
-  long long* stat_all = nullptr;    // device: nsys * 4 multi-shift counters
+  long long* stat_all = nullptr;    // device: 3 nsys * 4 multi-shift counters (entries A, B, B')
+  double* dstat_all = nullptr;      // device: 3 nsys * 2 shift residuals
+  int* ctl_all = nullptr;           // device: 3 nsys * 4 control words
+  size_t ctl_words = 0;             // 32-bit words from stat_all to the end of ctl_all
+  std::string geo_key;              // launch geometry of every system (graph cache key)
+  bool size_worst = false;          // sizing only: the smallest workgroup partition any
+                                    // launch shape gives (64 sites per workgroup)
   int* act_all = nullptr;           // device: act_cg[nsys] then act_ru[nsys]
   std::vector<int> last_flags;      // last uploaded flags (upload only on change)
   MsParams mp64{}, mpR{};
@@ -383,9 +383,15 @@ struct Engine {
     Bump bp(base, cap, dry);
     gbar = (GridBar*)bp.take(sizeof(GridBar));
     // the CG scalars and, right after them, the counters of entries A, B (inner) and
-    // B (true residual): one block, read back with one copy
-    cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys + sizeof(long long) * 12 * nsys);
+    // B (true residual) -- read back with one copy -- then the entries' shift residuals
+    // and control words: everything from stat_all on is cleared by one fill kernel
+    const size_t ctl_bytes = sizeof(long long) * 12 * nsys + sizeof(double) * 6 * nsys +
+                             sizeof(int) * 12 * nsys;
+    cg_all = (double*)bp.take(sizeof(double) * CG_NSLOT * nsys + ctl_bytes);
     stat_all = dry ? nullptr : (long long*)(cg_all + (size_t)CG_NSLOT * nsys);
+    dstat_all = dry ? nullptr : (double*)(stat_all + (size_t)12 * nsys);
+    ctl_all = dry ? nullptr : (int*)(dstat_all + (size_t)6 * nsys);
+    ctl_words = ctl_bytes / sizeof(int);
     act_all = (int*)bp.take(sizeof(int) * 2 * nsys);
     int blk = 0, nxy = 0, nz = 0, nt = 0;
     long long total_sites = 0;
@@ -398,7 +404,7 @@ struct Engine {
       b.ctx = ctxs[s];
       const ov_params& p = ctxs[s]->p;
       b.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
-      b.spb = sites_per_block(ctxs[s], b.V, total_sites);
+      b.spb = size_worst ? 64 : sites_per_block(ctxs[s], b.V, total_sites);
       b.nblk = (b.V + b.spb - 1) / b.spb;
       b.blk0 = blk;
       blk += b.nblk;
@@ -415,6 +421,12 @@ struct Engine {
       b.stat = dry ? nullptr : stat_all + (size_t)s * 4;
       b.ms_b_stat = (dry || !pl.gw) ? nullptr : stat_all + (size_t)(nsys + s) * 4;
       b.tb_stat = (dry || !pl.gwx) ? nullptr : stat_all + (size_t)(2 * nsys + s) * 4;
+      b.dstat = dry ? nullptr : dstat_all + (size_t)s * 2;
+      b.h_ctl = dry ? nullptr : ctl_all + (size_t)s * 4;
+      b.ms_b_dstat = (dry || !pl.gw) ? nullptr : dstat_all + (size_t)(nsys + s) * 2;
+      b.ms_b_h_ctl = (dry || !pl.gw) ? nullptr : ctl_all + (size_t)(nsys + s) * 4;
+      b.tb_dstat = (dry || !pl.gwx) ? nullptr : dstat_all + (size_t)(2 * nsys + s) * 2;
+      b.tb_h_ctl = (dry || !pl.gwx) ? nullptr : ctl_all + (size_t)(2 * nsys + s) * 4;
       b.act_cg = dry ? nullptr : act_all + s;
       b.act_ru = dry ? nullptr : act_all + nsys + s;
     }
@@ -422,6 +434,16 @@ struct Engine {
     nb_xy = nxy;
     nb_z = nz;
     nb_t = nt;
+    // everything a captured launch sequence bakes in besides the table and workspace
+    // addresses: per system its lattice, boundary, partition and transform chunking
+    geo_key.clear();
+    for (int s = 0; s < nsys; ++s) {
+      const ov_params& p = ctxs[s]->p;
+      char g[96];
+      std::snprintf(g, sizeof g, "%dx%dx%dx%d/%d/%d/%d;", p.dims[0], p.dims[1], p.dims[2],
+                    p.dims[3], p.bc_t, sb[s].spb, sb[s].xc);
+      geo_key += g;
+    }
     tables = (SysDev*)bp.take(sizeof(SysDev) * T_NT * nsys);
     ftab = pl.nshift > 0 ? (SysDev*)bp.take(sizeof(SysDev) * nsys * pl.nshift) : nullptr;
     gwtab = pl.gw ? (SysDev*)bp.take(sizeof(SysDev) * 2 * nsys) : nullptr;
@@ -451,7 +473,14 @@ void clear_graphs(ov_ctx* c) {
 }
 
 ov_status ensure_ws(ov_ctx* c, size_t need, void** base) {
-  if (c->user_ws && c->user_ws_bytes >= need) {
+  if (c->user_ws) {  // a caller-owned workspace is never supplemented by a hidden allocation
+    if (c->user_ws_bytes < need) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "workspace of %zu bytes is too small: this call needs %zu",
+                    c->user_ws_bytes, need);
+      c->err = buf;
+      return OV_ERR_WORKSPACE;
+    }
     *base = c->user_ws;
     return OV_OK;
   }
@@ -473,7 +502,7 @@ ov_status ensure_pinned(ov_ctx* c, int nsys) {
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   c->pinned = nullptr;
   c->pinned_flags = nullptr;
-  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 12) * nsys));
+  HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 24) * nsys));
   HIPCHK(c, hipHostMalloc((void**)&c->pinned_flags, sizeof(int) * 2 * nsys + 64));
   c->pinned_n = nsys;
   return OV_OK;
@@ -493,16 +522,15 @@ MsParams make_mp(const ov_ctx* c, double tol, int cap) {
 }
 
 // Build the engine for `ctxs` (one entry per system) and carve the workspace.
-ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, bool mixed,
-                      double tol64, double tolR, int nshift = 0) {
+// The plan of a call (buffers, basis capacities, multi-shift parameters) for `ctxs`
+// (one entry per system).  Host only: engine_init carves it, the workspace queries size it.
+void plan_engine(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, bool mixed,
+                 double tol64, double tolR, int nshift) {
   E.ctxs = ctxs;
   E.nsys = (int)ctxs.size();
   E.sb.assign(E.nsys, SysBuf{});
   E.lead = ctxs[0];
   E.st = E.lead->priv;
-  for (int& k : E.lead->ev_call_count) k = 0;
-  HIPCHK(E.lead, hipEventRecord(E.lead->ev_in, E.lead->stream));
-  HIPCHK(E.lead, hipStreamWaitEvent(E.st, E.lead->ev_in, 0));
   E.pl.solve = solve;
   E.pl.mixed = mixed;
   E.pl.nshift = solve ? nshift : 0;
@@ -512,10 +540,13 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   E.pl.gw = solve && !E.pl.fft && nshift == 0 && E.lead->p.inner_form == 1;
   E.pl.gwx = solve && !E.pl.fft && E.lead->p.inner_form == 1;
   // capacities from the loosest spectral bound over the batch (no multi-shift
-  // basis for a momentum-space operator)
+  // basis for a momentum-space operator).  The exact Ginsparg-Wilson product runs its
+  // multi-shift ten times tighter than the tolerance it serves (truth_ms_tol), so the
+  // FP64 basis is sized for that.
+  const double cap_tol64 = E.pl.gwx ? 0.1 * tol64 : tol64;
   int cap64 = 0, capR = 0;
   for (auto* c : ctxs) {
-    cap64 = std::max(cap64, capacity(c, tol64));
+    cap64 = std::max(cap64, capacity(c, cap_tol64));
     if (solve) capR = std::max(capR, capacity(c, tolR));
   }
   E.pl.cap64 = solve && !mixed ? std::max(cap64, capR) : cap64;
@@ -525,11 +556,26 @@ ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, b
   E.mpR = make_mp(E.lead, tolR, solve ? E.pl.capR : E.pl.cap64);
   E.L64 = E.pl.cap64;
   E.LR = solve ? E.pl.capR : E.pl.cap64;
+}
+
+// Tolerances of the solve plan (ov_solve, ov_solve_batch, ov_force).
+double solve_tol64(const ov_ctx* c) { return std::min(c->p.inner_tol, c->p.truth_tol); }
+double solve_tolR(const ov_ctx* c) {
+  return c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol;
+}
+
+// Build the engine for `ctxs` (one entry per system) and carve the workspace.
+ov_status engine_init(Engine& E, const std::vector<ov_ctx*>& ctxs, bool solve, bool mixed,
+                      double tol64, double tolR, int nshift = 0) {
+  plan_engine(E, ctxs, solve, mixed, tol64, tolR, nshift);
+  for (int& k : E.lead->ev_call_count) k = 0;
+  HIPCHK(E.lead, hipEventRecord(E.lead->ev_in, E.lead->stream));
+  HIPCHK(E.lead, hipStreamWaitEvent(E.st, E.lead->ev_in, 0));
   const size_t need = E.layout(nullptr, 0, true);
   void* base = nullptr;
   TRY(ensure_ws(E.lead, need, &base));
   E.layout(base, need, false);
-  HIPCHK(E.lead, hipMemsetAsync(E.gbar, 0, sizeof(GridBar), E.st));
+  k_zero32<<<1, 64, 0, E.st>>>((unsigned int*)E.gbar, sizeof(GridBar) / sizeof(unsigned int));
   TRY(ensure_pinned(E.lead, E.nsys));
   return OV_OK;
 }
@@ -870,23 +916,19 @@ ov_status read_ctl(Engine& E, std::vector<int>& ctl3, std::vector<long long>& st
   return OV_OK;
 }
 
+// Counters, shift residuals and control words of every entry: one fill kernel.
 ov_status reset_stats(Engine& E) {
-  for (int s = 0; s < E.nsys; ++s) {
-    HIPCHK(E.lead, hipMemsetAsync(E.sb[s].h_ctl, 0, sizeof(int) * 4, E.st));
-    HIPCHK(E.lead, hipMemsetAsync(E.sb[s].stat, 0, sizeof(long long) * 4, E.st));
-    HIPCHK(E.lead, hipMemsetAsync(E.sb[s].dstat, 0, sizeof(double) * 2, E.st));
-    if (E.sb[s].ms_b_stat) {
-      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_h_ctl, 0, sizeof(int) * 4, E.st));
-      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_stat, 0, sizeof(long long) * 4, E.st));
-      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].ms_b_dstat, 0, sizeof(double) * 2, E.st));
-    }
-    if (E.sb[s].tb_stat) {
-      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].tb_h_ctl, 0, sizeof(int) * 4, E.st));
-      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].tb_stat, 0, sizeof(long long) * 4, E.st));
-      HIPCHK(E.lead, hipMemsetAsync(E.sb[s].tb_dstat, 0, sizeof(double) * 2, E.st));
-    }
-  }
-  return OV_OK;
+  const size_t n = E.ctl_words;
+  k_zero32<<<(unsigned)std::min<size_t>((n + 255) / 256, 64), 256, 0, E.st>>>(
+      (unsigned int*)E.stat_all, n);
+  return check_launch(E.lead);
+}
+
+// Zero a device buffer (a multiple of 4 bytes) with the fill kernel.
+void zero_dev(const Engine& E, void* p, size_t bytes) {
+  const size_t n = bytes / sizeof(unsigned int);
+  const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 4096));
+  k_zero32<<<nb, 256, 0, E.st>>>((unsigned int*)p, n);
 }
 
 // ABI field pointers -> pack into the planar FP64 buffer chosen by `dst_of`.
@@ -1392,12 +1434,43 @@ ov_status set_flags(Engine& E, const std::vector<int>& cg, const std::vector<int
   return OV_OK;
 }
 
+// CG scalars, multi-shift counters, shift residuals and control words of every entry
+// (the engine's contiguous scalar block) to the pinned host copy, then synchronise.
 ov_status read_scalars(Engine& E) {
   static_assert(sizeof(long long) == sizeof(double), "counters share the scalar block");
   HIPCHK(E.lead, hipMemcpyAsync(E.lead->pinned, E.cg_all,
-                                sizeof(double) * CG_NSLOT * E.nsys + sizeof(long long) * 12 * E.nsys,
+                                sizeof(double) * CG_NSLOT * E.nsys + sizeof(int) * E.ctl_words,
                                 hipMemcpyDeviceToHost, E.st));
   return sync(E);
+}
+
+// Sticky multi-shift error bits (h_ctl[3]: bit 1 breakdown, bit 2 not converged within
+// the launched iterations or the basis) of system s's entries, from the last
+// read_scalars.
+int sticky_bits(const Engine& E, int s) {
+  const int* ctl = (const int*)((const double*)E.lead->pinned + (size_t)CG_NSLOT * E.nsys +
+                                (size_t)18 * E.nsys);
+  int b = 0;
+  for (int e = 0; e < 3; ++e) b |= ctl[(size_t)(e * E.nsys + s) * 4 + 3];
+  return b;
+}
+
+// Clear every entry's control words before multi-shift solves that are checked on their own.
+void clear_ctl(const Engine& E) {
+  k_zero32<<<1, 256, 0, E.st>>>((unsigned int*)E.ctl_all, (size_t)12 * E.nsys);
+}
+
+// OV_OK, or the status a set of sticky bits stands for (with the reason in err).
+ov_status sticky_status(ov_ctx* c, int bits, const char* what) {
+  if (bits & (1 << 1)) {
+    c->err = std::string(what) + ": multi-shift breakdown (non-finite or non-positive scalar)";
+    return OV_ERR_BREAKDOWN;
+  }
+  if (bits & (1 << 2)) {
+    c->err = std::string(what) + ": multi-shift did not converge within its basis (max_inner)";
+    return OV_ERR_NOT_CONVERGED;
+  }
+  return OV_OK;
 }
 
 // Largest iteration count of the FP64 multi-shift solves of the last reliable
@@ -1434,9 +1507,9 @@ ov_status run_graph(Engine& E, const std::string& key, F&& enqueue) {
     return check_launch(c);
   }
   char buf[160];
-  std::snprintf(buf, sizeof buf, "|%p|%p|%d|%d|%d", (void*)E.tables, (void*)E.bmap, E.nb_total,
-                E.nsys, c->block);
-  const std::string k = key + buf;
+  std::snprintf(buf, sizeof buf, "|%p|%p|%p|%d|%d|%d|%d|%d|%d|", (void*)E.tables, (void*)E.bmap,
+                (void*)E.gwtab, E.nb_total, E.nsys, c->block, E.nb_xy, E.nb_z, E.nb_t);
+  const std::string k = key + buf + E.geo_key;
   auto it = c->graphs.find(k);
   if (it == c->graphs.end()) {
     if (c->graphs.size() >= 64) clear_graphs(c);
@@ -1585,6 +1658,7 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
     auto it = c->n_est.find(key);
     if (it != c->n_est.end()) L = std::min(Lfull, it->second + std::max(4, it->second / 8));
   }
+  clear_ctl(E);
   TRY(reliable_update_L<R>(E, tol, scalar_op, L));
   TRY(read_scalars(E));
   int nobs = last_truth_iters(E);
@@ -1592,11 +1666,20 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
     if (ov_log())
       std::fprintf(stderr, "[ov] truth multi-shift at tol %.0e cut at %d of %d: repeated\n", tol, L,
                    Lfull);
+    clear_ctl(E);
     TRY(reliable_update_L<R>(E, tol, scalar_op, Lfull));
     TRY(read_scalars(E));
     nobs = last_truth_iters(E);
   }
   c->n_est[key] = nobs;
+  // The final check certifies the solution: its multi-shift solves must have converged
+  // within their basis (a basis capped by max_inner, or a breakdown, leaves an
+  // uncertified residual).
+  if (tol <= c->p.truth_tol * 1.0000001) {
+    int bits = 0;
+    for (int s = 0; s < E.nsys; ++s) bits |= sticky_bits(E, s);
+    TRY(sticky_status(c, bits, "true residual"));
+  }
   return OV_OK;
 }
 
@@ -2007,7 +2090,7 @@ ov_status tune_run(ov_ctx* c, int nrhs, int iters, float* us) {
   Engine E;
   std::vector<ov_ctx*> v(nrhs, c);
   const bool fp32 = sizeof(R) == sizeof(float);
-  TRY(engine_init(E, v, true, fp32, 1e-13, 1e-13));
+  TRY(engine_init(E, v, true, fp32, solve_tol64(c), fp32 ? c->p.mixed_inner_tol : c->p.inner_tol));
   E.htab.assign((size_t)T_NT * nrhs, SysDev{});
   for (int s = 0; s < nrhs; ++s) {
     SysBuf& b = E.sb[s];
@@ -2160,28 +2243,30 @@ ov_status ov_ctx_destroy(ov_ctx* c) {
   return OV_OK;
 }
 
-size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
-  if (!c || nrhs < 1) return 0;
+// Workspace bytes of a plan for nrhs systems of this context, for any launch shape
+// (the partial-sum arrays are sized for 64 sites per workgroup).
+static size_t plan_bytes(const ov_ctx* c, int nrhs, bool solve, bool mixed, double tol64,
+                         double tolR, int nshift) {
   Engine E;
   std::vector<ov_ctx*> v(nrhs, const_cast<ov_ctx*>(c));
-  E.ctxs = v;
-  E.nsys = nrhs;
-  E.sb.assign(nrhs, SysBuf{});
-  E.lead = v[0];
-  const bool mixed = c->p.precision == OV_MIXED;
-  const double tol64 = std::min(c->p.inner_tol, c->p.truth_tol);
-  const double tolR = mixed ? c->p.mixed_inner_tol : c->p.inner_tol;
-  int cap64 = capacity(c, tol64), capR = capacity(c, tolR);
-  E.pl.solve = true;
-  E.pl.mixed = mixed;
-  E.pl.pc = c->p.precondition != 0;
-  E.pl.fft = c->p.dirac != OV_DIRAC_OVERLAP_MS;
-  E.pl.gw = !E.pl.fft && c->p.inner_form == 1;
-  E.pl.gwx = E.pl.gw;
-  E.pl.cap64 = mixed ? cap64 : std::max(cap64, capR);
-  E.pl.capR = mixed ? capR : E.pl.cap64;
-  if (E.pl.fft) E.pl.cap64 = E.pl.capR = 0;
+  plan_engine(E, v, solve, mixed, tol64, tolR, nshift);
+  E.size_worst = true;
   return E.layout(nullptr, 0, true);
+}
+
+size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
+  if (!c || nrhs < 1) return 0;
+  // the solve plan (solve, force) covers every other call without shifted systems
+  // (sign, apply, locality, boson, pack, the tuning probe in the context's precision)
+  const size_t solve = plan_bytes(c, nrhs, true, c->p.precision == OV_MIXED, solve_tol64(c),
+                                  solve_tolR(c), 0);
+  const size_t apply = plan_bytes(c, nrhs, false, false, c->p.inner_tol, c->p.inner_tol, 0);
+  return std::max(solve, apply);
+}
+
+size_t ov_workspace_bytes_rational(const ov_ctx* c, int nrhs, int nshift) {
+  if (!c || nrhs < 1 || nshift < 1 || nshift > MAXP) return 0;
+  return plan_bytes(c, nrhs, true, false, solve_tol64(c), c->p.inner_tol, nshift);
 }
 
 ov_status ov_set_workspace(ov_ctx* c, void* ptr, size_t bytes) {
@@ -2306,7 +2391,7 @@ static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const v
   const double tolR = mixed ? c->p.mixed_inner_tol : c->p.inner_tol;
   Engine Eloc;
   Engine& E = keep ? *keep : Eloc;
-  TRY(engine_init(E, sysctx, true, mixed, std::min(c->p.inner_tol, c->p.truth_tol), tolR));
+  TRY(engine_init(E, sysctx, true, mixed, solve_tol64(c), tolR));
   const int ns = E.nsys;
   // pack the guesses into x64 (needs a geometry table)
   E.htab.assign((size_t)T_NT * ns, SysDev{});
@@ -2329,6 +2414,7 @@ static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const v
   TRY(unpack64(E, x64v, xv));
   TRY(sync(E));
   fill_stats(st, ns, &E, &so, now_s() - t0, mixed ? 8 : 16);
+  if (rc != OV_OK) return rc;  // x holds the best iterate; err says why
   for (int s = 0; s < ns; ++s)
     if (!so.conv[s]) {
       c->err = "outer CG did not reach outer_tol within max_outer";
@@ -2392,7 +2478,7 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   // zero guess directly in x64
   for (int r = 0; r < nrhs; ++r) {
     bv[r] = (const char*)xi + r * vb;
-    HIPCHK(c, hipMemsetAsync(E.sb[r].x64, 0, vb, E.st));
+    zero_dev(E, E.sb[r].x64, vb);
   }
   SolveOut so;
   const double tolR = c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol;
@@ -2427,6 +2513,7 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   } else {
     MsParams mp = make_mp(c, c->p.truth_tol, E.pl.cap64);
     const int L = std::min(E.pl.cap64, capacity(c, c->p.truth_tol));
+    clear_ctl(E);  // the sticky bits below then belong to the Y = M X multi-shift alone
     k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_APPLY), E.bmap, E.nb_total, 0);
     launch_ms<double>(E, T_APPLY, mp, L);
     launch_combine<double>(E, T_APPLY, EPI_M);
@@ -2436,7 +2523,12 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   // G summed over right-hand sides in order (one launch over the sites)
   k_force<<<E.sb[0].nblk, c->block, 0, E.st>>>(tab(E, T_APPLY), nrhs, E.sb[0].nblk,
                                                (double2*)grad_phi);
-  TRY(sync(E));
+  TRY(read_scalars(E));
+  if (!E.pl.fft) {
+    int bits = 0;
+    for (int s = 0; s < nrhs; ++s) bits |= sticky_bits(E, s);
+    TRY(sticky_status(c, bits, "ov_force, Y = M X"));
+  }
   for (int s = 0; s < nrhs; ++s) {
     std::vector<double> tmp(E.sb[s].nblk);
     HIPCHK(c, hipMemcpy(tmp.data(), E.sb[s].part_c, sizeof(double) * tmp.size(),
@@ -2512,11 +2604,8 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
   for (int s = 0; s < ns; ++s) L = std::max(L, capacity(E.ctxs[s], tol_ms));
   L = std::min(E.pl.cap64, L);
   int Lrun = L;
-  for (int it = 0; it < c->p.max_outer; ++it) {
-    bool any = false;
-    for (int s = 0; s < ns; ++s) any |= fcg[s] != 0;
-    if (!any) break;
-    TRY(set_flags(E, fcg, fru));
+  // w = MdagM p (vR for the multi-shift forms), alpha = rho / Re <p, w>
+  auto product = [&](int Ln) {
     if (E.pl.fft) {
       launch_sym<double>(E, T_F_M, SYM_D);
       k_yuk<double><<<nb, bl, 0, E.st>>>(tab(E, T_F_M), E.bmap, nb, 0);
@@ -2528,25 +2617,49 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
       // (eps^2 p from the Krylov space of p) -> vR, alpha = rho / Re <p, w>
       k_stat3_clear<<<1, 64, 0, E.st>>>(E.trgwtab, 2 * ns);
       k_gw_prep<double><<<nb, bl, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
-      launch_ms_tab<double>(E, E.trgwtab, E.gwbmap, 2 * nb, 2 * ns, mpx, Lrun);
+      launch_ms_tab<double>(E, E.trgwtab, E.gwbmap, 2 * nb, 2 * ns, mpx, Ln);
       k_truth_combine<<<nb, bl, 0, E.st>>>(E.trgwtab, E.trgwtab + ns, E.bmap, nb);
       k_truth_finish<double><<<nb, bl, 0, E.st>>>(E.trgwtab, E.bmap, nb, 4.0 - c->p.M0, 1);
       k_cg_scalar<<<ns, 256, 0, E.st>>>(E.trgwtab, ns, 1);
     } else {
       k_ms_prep<double><<<nb, bl, 0, E.st>>>(tab(E, T_IN_M), E.bmap, nb, 0);
-      launch_ms<double>(E, T_IN_M, mp, Lrun);
+      launch_ms<double>(E, T_IN_M, mp, Ln);
       launch_combine<double>(E, T_IN_M, EPI_M);
       k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
-      launch_ms<double>(E, T_IN_MDAG, mp, Lrun);
+      launch_ms<double>(E, T_IN_MDAG, mp, Ln);
       launch_combine<double>(E, T_IN_MDAG, EPI_MDAG);
+    }
+  };
+  for (int it = 0; it < c->p.max_outer; ++it) {
+    bool any = false;
+    for (int s = 0; s < ns; ++s) any |= fcg[s] != 0;
+    if (!any) break;
+    const std::vector<int> live = fcg;  // the systems this iteration advances
+    TRY(set_flags(E, fcg, fru));
+    if (E.pl.fft) {
+      product(0);
+    } else {
+      // The launch count follows the last iteration's need plus a margin; a product
+      // cut short by it is recomputed with the full count before the CG update uses
+      // it (the product of p is exact to the multi-shift tolerance in every iteration).
+      clear_ctl(E);
+      product(Lrun);
+      TRY(read_scalars(E));
+      int nobs = E.pl.gwx ? last_truth_iters(E) : last_ms_iters(E);
+      if (Lrun < L && nobs >= Lrun - 1) {
+        clear_ctl(E);
+        product(L);
+        TRY(read_scalars(E));
+        nobs = E.pl.gwx ? last_truth_iters(E) : last_ms_iters(E);
+      }
+      int bits = 0;
+      for (int s = 0; s < ns; ++s) bits |= live[s] ? sticky_bits(E, s) : 0;
+      TRY(sticky_status(c, bits, "multi-shift CG on MdagM, product MdagM p"));
+      Lrun = std::min(L, nobs + 4);
     }
     k_cg_misc<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);  // r -= alpha w
     k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);                // rho, beta
     TRY(read_scalars(E));
-    if (!E.pl.fft) {  // launch what the multi-shift needed, plus a margin
-      const int nobs = E.pl.gwx ? last_truth_iters(E) : last_ms_iters(E);
-      Lrun = (nobs >= Lrun - 1) ? L : std::min(L, nobs + 4);
-    }
     for (int s = 0; s < ns; ++s) {
       if (!fcg[s]) continue;
       iters[s]++;
@@ -2557,7 +2670,7 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
         return OV_ERR_BREAKDOWN;
       }
       double* b = blk.data() + (size_t)s * SHC_LEN;
-      bool live = false;
+      bool alive = false;
       for (int k = 0; k < n; ++k) {
         const size_t j = (size_t)s * n + k;
         if (!act[j]) {
@@ -2574,17 +2687,17 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
         zo[j] = zc[j];
         zc[j] = zn;
         if (std::fabs(zn) * std::sqrt(std::max(rho, 0.0)) <= tol * bn[s]) act[j] = 0;
-        live |= act[j] != 0;
+        alive |= act[j] != 0;
       }
       aold[s] = a;
       bold[s] = bt;
-      if (!live) fcg[s] = 0;
+      if (!alive) fcg[s] = 0;
     }
     TRY(upload());
-    // the last update of a shift that just converged still applies (act flag set above)
-    std::vector<int> fupd(ns, 0);
-    for (int s = 0; s < ns; ++s) fupd[s] = iters[s] > 0 ? 1 : 0;
-    TRY(set_flags(E, fupd, fru));
+    // The shifted update of this iteration applies to the systems it advanced (a shift
+    // that converged just now still takes its last step); systems that had converged
+    // before are left alone.
+    TRY(set_flags(E, live, fru));
     k_shift<<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);
     TRY(set_flags(E, fcg, fru));
     k_cg_p<double><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);  // p = r + beta p
@@ -2621,7 +2734,7 @@ ov_status ov_rational(ov_ctx* c, double a0, int n, const double* alpha, const do
     ov[r] = (char*)out + r * vb;
   }
   Engine E;
-  TRY(engine_init(E, sc, true, false, c->p.inner_tol, c->p.inner_tol, n));
+  TRY(engine_init(E, sc, true, false, solve_tol64(c), c->p.inner_tol, n));
   std::vector<int> iters;
   TRY(rational_core(c, E, a0, n, alpha, beta, bv, ph, iters));
   for (int r = 0; r < nrhs; ++r) r64[r] = E.sb[r].r64;
@@ -2654,7 +2767,7 @@ ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
   std::vector<const void*> bv(nrhs), ph(nrhs, phi);
   for (int r = 0; r < nrhs; ++r) bv[r] = (const char*)xi + r * vb;
   Engine E;
-  TRY(engine_init(E, sc, true, false, c->p.inner_tol, c->p.inner_tol, n));
+  TRY(engine_init(E, sc, true, false, solve_tol64(c), c->p.inner_tol, n));
   std::vector<int> iters;
   TRY(rational_core(c, E, a0, n, alpha, beta, bv, ph, iters));
   // S_r = Re xi_r^dag (a0 xi_r + sum_i alpha_i X_i) from the combined field in r64
@@ -2676,6 +2789,7 @@ ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
   const size_t slot = V * 4;
   std::vector<int> on(nrhs, 1), off(nrhs, 0);
   TRY(set_flags(E, on, off));
+  clear_ctl(E);  // the sticky bits checked below then belong to the Y_i multi-shifts
   for (int k = 0; k < n; ++k) {
     for (int s = 0; s < nrhs; ++s) {
       SysDev& d = E.htab[(size_t)T_APPLY * nrhs + s];
@@ -2712,7 +2826,12 @@ ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
                            E.st));
   k_force<<<E.sb[0].nblk, c->block, 0, E.st>>>(E.ftab, nrhs * n, E.sb[0].nblk,
                                                (double2*)grad_phi);
-  TRY(sync(E));
+  TRY(read_scalars(E));
+  if (!E.pl.fft) {
+    int bits = 0;
+    for (int s = 0; s < nrhs; ++s) bits |= sticky_bits(E, s);
+    TRY(sticky_status(c, bits, "ov_rational_force, Y_i = M X_i"));
+  }
   SolveOut so;
   so.outer = iters;
   so.ru.assign(nrhs, 0);
@@ -2849,7 +2968,7 @@ ov_status ov_locality(ov_ctx* c, int spin, double* f, int nr, ov_stats* st) {
   SysBuf& b = E.sb[0];
   const size_t V = b.V;
   // unit point source at the origin: x64 = 0, plane `spin` of site 0 = 1
-  HIPCHK(c, hipMemsetAsync(b.x64, 0, V * 4 * sizeof(double2), E.st));
+  zero_dev(E, b.x64, V * 4 * sizeof(double2));
   static const double2 one = {1.0, 0.0};
   HIPCHK(c, hipMemcpyAsync(b.x64 + (size_t)spin * V, &one, sizeof(double2),
                            hipMemcpyHostToDevice, E.st));

@@ -1,0 +1,160 @@
+"""GPU tests of the failure paths and of the caller-owned workspace.  Every failure is
+forced from the host (an iteration cap, an unreachable tolerance, a small buffer): every
+kernel still runs to its normal end.
+
+* A multi-shift basis capped by max_inner: sign, force, and the rational layers return
+  OV_ERR_NOT_CONVERGED instead of a silently inaccurate result.
+* outer_tol = 1e-30: OV_ERR_NOT_CONVERGED, with the best iterate in x and the stats
+  filled.
+* Workspace: a caller's workspace that is too small gives OV_ERR_WORKSPACE (no hidden
+  allocation); ov_workspace_bytes covers every launch shape; the rational layers need
+  ov_workspace_bytes_rational.
+* Graph capture (OV_GRAPHS=1): batches with members of equal volume but different
+  shapes replay graphs of their own geometry.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_1005_3276_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_util import CFG1, CFG2, bits, check, dev, host, lattice, require_gpu  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    require_gpu(torch)
+
+
+@pytest.fixture(scope="module")
+def rat20():
+    from paper_1005_3276_amd import rational
+    return rational.power_approx(-0.25, 1e-5, 10.0, 20)
+
+
+def _status(call):
+    from paper_1005_3276_amd import _lib as L
+    with pytest.raises(L.OvError) as e:
+        call()
+    return e.value.status, str(e.value)
+
+
+def test_basis_cap_not_converged(rat20):
+    """max_inner = 4 leaves every multi-shift solve short of its tolerance: the sign,
+    the force (its solve and the recomputed Y = M X) and the rational layers report
+    OV_ERR_NOT_CONVERGED."""
+    from paper_1005_3276_amd import _lib as L
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(4))
+    lat = lattice(dims, max_inner=4, max_outer=20, inner_tol=1e-12, outer_tol=1e-10, **CFG1)
+    b, p = dev(src), dev(phi)
+    a0, al, be, _ = rat20
+    for name, call in (("sign", lambda: lat.sign(b)),
+                       ("apply m", lambda: lat.apply("m", b, p)),
+                       ("force", lambda: lat.force(b, p)),
+                       ("rational", lambda: lat.rational(b, p, a0, al, be)),
+                       ("rational_force", lambda: lat.rational_force(b, p, a0, al, be))):
+        st, msg = _status(call)
+        print(f"[cap] {name}: {msg}", flush=True)
+        assert st == L.OV_ERR_NOT_CONVERGED, (name, msg)
+    # the same calls with the default cap succeed
+    ok = lattice(dims, inner_tol=1e-12, outer_tol=1e-10, **CFG1)
+    ok.force(b, p)
+    ok.rational(b, p, a0, al, be)
+
+
+def test_unreachable_tolerance_best_iterate(orc):
+    """outer_tol = 1e-30 cannot be met: OV_ERR_NOT_CONVERGED after max_outer, with the
+    best iterate in x (converged far below 1e-10 under the oracle's operator) and the
+    stats filled."""
+    from paper_1005_3276_amd import _lib as L
+    dims = (4, 4, 4, 4)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    lat = lattice(dims, precision="mixed", outer_tol=1e-30, max_outer=60, **CFG2)
+    x = torch.zeros((1,) + lat.field_shape, dtype=torch.complex128, device="cuda")
+    st = (L.OvStats * 1)()
+    rc = L.lib().ov_solve(lat._h, C.c_void_p(x.data_ptr()), C.c_void_p(dev(src).data_ptr()),
+                          C.c_void_p(dev(phi).data_ptr()), 1, st)
+    torch.cuda.synchronize()
+    msg = L.lib().ov_last_error(lat._h).decode()
+    print(f"[unreachable] rc {rc} ({msg}) {st[0].as_dict()}", flush=True)
+    assert rc == L.OV_ERR_NOT_CONVERGED
+    assert st[0].outer_iters == 60 and st[0].true_rel_res < 1e-10
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    assert o.residual(src[0], host(x)[0], phi) <= 1e-10
+
+
+def test_workspace_too_small_and_sizes(rat20):
+    from paper_1005_3276_amd import _lib as L
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2))
+    b, p = dev(src), dev(phi)
+    lat = lattice(dims, precision="mixed", outer_tol=1e-10, **CFG2)
+    lib = L.lib()
+    # a workspace too small: refused, nothing allocated behind the caller's back
+    tiny = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    L.check(lib.ov_set_workspace(lat._h, C.c_void_p(tiny.data_ptr()), 4096), lat._h)
+    st, msg = _status(lambda: lat.solve(b, p))
+    assert st == L.OV_ERR_WORKSPACE and "too small" in msg
+    st, _ = _status(lambda: lat.sign(b))
+    assert st == L.OV_ERR_WORKSPACE
+    # ov_workspace_bytes is enough for every call without shifted systems, at every
+    # launch shape the autotuner may pick
+    need = lat.use_workspace(2)
+    assert need == lib.ov_workspace_bytes(lat._h, 2) > 0
+    x_ref, _ = lat.solve(b, p)
+    for blk, spt in ((64, 1), (256, 4)):
+        lat.set_launch(blk, spt)
+        x, st2 = lat.solve(b, p)
+        check(host(x), host(x_ref), 1e-8, f"launch {blk}x{spt}")
+    lat.sign(b)
+    lat.force(b[:1], p)
+    # the rational layers need room for their shifted systems
+    a0, al, be, _ = rat20
+    st, _ = _status(lambda: lat.rational(b, p, a0, al, be))
+    assert st == L.OV_ERR_WORKSPACE
+    nb = lib.ov_workspace_bytes_rational(lat._h, 2, len(al))
+    assert nb > need
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) & ~255
+    L.check(lib.ov_set_workspace(lat._h, C.c_void_p(base), nb), lat._h)
+    out, _ = lat.rational(b, p, a0, al, be)
+    L.check(lib.ov_set_workspace(lat._h, None, 0), lat._h)
+    out2, _ = lat.rational(b, p, a0, al, be)
+    assert np.array_equal(bits(host(out)), bits(host(out2)))
+
+
+@pytest.mark.timeout(600)
+def test_graph_cache_equal_volume_members(orc, monkeypatch):
+    """OV_GRAPHS=1, two batched solves under the same lead context whose second members
+    have the same volume (same workspace layout) but different shapes: each solve replays
+    graphs of its own geometry and equals the eager solve bit for bit."""
+    from paper_1005_3276_amd import solve_batch
+    kw = dict(precision="mixed", outer_tol=1e-10, **CFG2)
+    lead_dims = (8, 8, 4, 4)
+    shapes = [(8, 8, 4, 4), (4, 4, 8, 8)]
+    phi0, src0 = inputs.draw(lead_dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2) + 21)
+
+    def run(graphs):
+        monkeypatch.setenv("OV_GRAPHS", "1" if graphs else "0")
+        lead = lattice(lead_dims, **kw)
+        outs = []
+        for k, dims in enumerate(shapes):
+            phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2) + 22 + k)
+            other = lattice(dims, **kw)
+            for rep in range(2):  # the second solve replays the captured graphs
+                xs, _ = solve_batch([lead, other], [dev(src0), dev(src)], [dev(phi0), dev(phi)])
+                outs.append((dims, phi, src, [host(x) for x in xs]))
+        return outs
+
+    eager = run(False)
+    graph = run(True)
+    for (dims, phi, src, xe), (_, _, _, xg) in zip(eager, graph):
+        for a, g in zip(xe, xg):
+            assert np.array_equal(bits(a), bits(g)), dims
+        o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+        assert o.residual(src[0], xg[1][0], phi) <= 1e-10

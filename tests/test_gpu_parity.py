@@ -21,37 +21,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def rel(a, b):
-    a = np.asarray(a).ravel()
-    b = np.asarray(b).ravel()
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+from gpu_util import CFG1, CFG2, CFG5, check, dev, host, lattice, rel, require_gpu
 
 
 @pytest.fixture(scope="module", autouse=True)
 def gpu():
-    if not torch.cuda.is_available():
-        pytest.fail("GPU test run without a visible HIP device")
-    from paper_1005_3276_amd import _lib
-    _lib.lib()  # raises if libov.so is missing: no fallback path exists
-    print(f"[gpu] {torch.cuda.get_device_name(0)}", flush=True)
-
-
-def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-
-
-def host(t):
-    return t.detach().cpu().numpy()
-
-
-def lattice(dims, **kw):
-    from paper_1005_3276_amd import Lattice
-    return Lattice(dims, **kw)
-
-
-CFG1 = dict(m=0.05, g=0.1, n_poles=16, lambda_min=0.01, lambda_max=8.0)
-CFG2 = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
-CFG5 = dict(m=0.05, g=0.3, n_poles=24, lambda_min=1e-4, lambda_max=8.0)  # uneven-batch sign
+    require_gpu(torch)
 
 
 # ------------------------------------------------------------- pack / stencil
@@ -76,7 +51,7 @@ def test_hw_fp64_vs_oracle(orc, dims, bc):
     o = orc.Oracle(dims, bc_t=bc)
     lat = lattice(dims, bc_t=bc)
     out, _ = lat.apply("hw", dev(x))
-    assert rel(host(out), o.hw(x)) < 1e-14
+    check(host(out), o.hw(x), 1e-14)
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 8, 8, 8), (2, 4, 6, 8)])
@@ -88,12 +63,12 @@ def test_hw_fp32_stencil_vs_oracle(orc, dims):
     outp, ms = lat.stencil_bench(xp, 1, reps=2)
     out = host(lat.unpack(outp, 1))
     for r in range(3):
-        assert rel(out[r], o.hw(x[r])) < 2e-6
+        check(out[r], o.hw(x[r]), 2e-6)
     xp64 = lat.pack(dev(x), 0)
     outp64, _ = lat.stencil_bench(xp64, 0, reps=2)
     out64 = host(lat.unpack(outp64, 0))
     for r in range(3):
-        assert rel(out64[r], o.hw(x[r])) < 1e-14
+        check(out64[r], o.hw(x[r]), 1e-14)
 
 
 @pytest.mark.parametrize("dims", [(16, 16, 16, 16), (12, 12, 12, 12), (24, 24, 24, 48)])
@@ -108,7 +83,7 @@ def test_stencil_bench_kernels_full_size(orc, dims):
         outp, _ = lat.stencil_bench(xp, prec, reps=1)
         out = host(lat.unpack(outp, prec))
         for r in range(2):
-            assert rel(out[r], o.hw(x[r])) < tol
+            check(out[r], o.hw(x[r]), tol)
 
 
 @pytest.mark.parametrize("spt", [2, 4])
@@ -125,7 +100,7 @@ def test_zmarch_multishift_passes(orc, spt):
     out = host(out)
     for r in range(2):
         ref, _ = o.sign(src[r])
-        assert rel(out[r], ref) < 1e-11
+        check(out[r], ref, 1e-11)
     x, st = lat.solve(dev(src), dev(phi))
     x = host(x)
     for r in range(2):
@@ -146,7 +121,7 @@ def test_sign_vs_oracle(orc, dims, cfg):
     out = host(out)
     for r in range(2):
         ref, ost = o.sign(x[r])
-        assert rel(out[r], ref) < 1e-11
+        check(out[r], ref, 1e-11)
         assert abs(st[r]["inner_iters"] - ost.iters) <= 2
         assert st[r]["max_shift_res"] <= tol
 
@@ -176,10 +151,10 @@ def test_sign_config1_vs_diagonalised(bc):
     dov = host(lat.apply("dov", dev(src))[0])[0]
     rat = cf.apply_symbol(cf.rational_symbol(dims, a, b, bc), src[0], dims, bc)
     exact = cf.apply_symbol(cf.exact_sign_symbol(dims, bc), src[0], dims, bc)
-    assert rel(eps, rat) < 1e-11
+    check(eps, rat, 1e-11)
     assert rel(eps, exact) < delta + 1e-11
-    assert rel(dov, cf.apply_symbol(cf.dov_symbol(cf.rational_symbol(dims, a, b, bc)), src[0],
-                                    dims, bc)) < 1e-11
+    check(dov, cf.apply_symbol(cf.dov_symbol(cf.rational_symbol(dims, a, b, bc)), src[0],
+                                    dims, bc), 1e-11)
 
 
 @pytest.mark.parametrize("op", ["dov", "dov_dag", "m", "m_dag", "mdagm"])
@@ -193,7 +168,7 @@ def test_apply_ops_vs_oracle(orc, op):
     code = {"dov": orc.OP_DOV, "dov_dag": orc.OP_DOV_DAG, "m": orc.OP_M, "m_dag": orc.OP_M_DAG,
             "mdagm": orc.OP_MDAGM}[op]
     for r in range(2):
-        assert rel(out[r], o.apply(code, src[r], phi)) < 1e-11
+        check(out[r], o.apply(code, src[r], phi), 1e-11)
 
 
 # ---------------------------------------------- free-field preconditioner
@@ -213,7 +188,7 @@ def test_m0inv_vs_oracle(orc, dims, bc, m, op):
     out, _ = lat.apply(op, dev(x))
     out = host(out)
     for r in range(2):
-        assert rel(out[r], o.m0inv(x[r], dag=(op == "m0inv_dag"), tol=1e-13)) < 1e-10
+        check(out[r], o.m0inv(x[r], dag=(op == "m0inv_dag"), tol=1e-13), 1e-10)
 
 
 @pytest.mark.parametrize("dims", [(16, 16, 16, 16), (24, 24, 24, 48), (12, 12, 12, 12)])
@@ -233,8 +208,8 @@ def test_m0inv_full_size_closed_form(dims):
     y, _ = lat.apply("m0inv", dev(x))
     yd, _ = lat.apply("m0inv_dag", dev(x))
     y, yd = host(y), host(yd)
-    assert rel(y[0], cf.apply_symbol(inv, x[0], dims)) < 1e-12
-    assert rel(yd[0], cf.apply_symbol(np.conj(np.swapaxes(inv, -1, -2)), x[0], dims)) < 1e-12
+    check(y[0], cf.apply_symbol(inv, x[0], dims), 1e-12)
+    check(yd[0], cf.apply_symbol(np.conj(np.swapaxes(inv, -1, -2)), x[0], dims), 1e-12)
     lhs = np.vdot(x[1], y[0])
     rhs = np.vdot(yd[1], x[0])
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
@@ -270,7 +245,7 @@ def test_dirac_forms_apply_vs_oracle(orc, dirac, dims):
         out, _ = lat.apply(op, dev(src), dev(phi))
         out = host(out)
         for r in range(2):
-            assert rel(out[r], o.apply(code, src[r], phi)) < 1e-13, op
+            check(out[r], o.apply(code, src[r], phi), 1e-13, op)
 
 
 @pytest.mark.parametrize("pc", [1, 0])
@@ -427,7 +402,7 @@ def test_solve_residual_under_oracle(orc, dims, prec, pc, form):
     assert res <= 1e-10
     assert st[0]["true_rel_res"] <= 1e-10
     xo, ost, rc = o.solve(src[0], phi, tol=1e-11)
-    assert rel(x, xo) < 1e-8
+    check(x, xo, 1e-8)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -445,7 +420,7 @@ def test_solve_periodic_complex_couplings(orc, prec):
     for r in range(2):
         assert o.residual(src[r], x[r], phi) <= 1e-10
         xo, _, _ = o.solve(src[r], phi, tol=1e-11)
-        assert rel(x[r], xo) < 1e-8
+        check(x[r], xo, 1e-8)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -486,7 +461,7 @@ def test_pc_mass_rms_8x4(orc):
         res = o.residual(src[0], xs[pm], phi)
         print(f"[pc_mass] {pm}: outer {outer[pm]} oracle residual {res:.3e}", flush=True)
         assert res <= 1e-10
-    assert rel(xs[1], xs[0]) < 1e-8
+    check(xs[1], xs[0], 1e-8)
     assert outer[1] <= outer[0] + 2
 
 
@@ -513,7 +488,7 @@ def test_inner_forms_agree_8x4(orc, prec):
         print(f"[forms] {prec} inner_form={form} {el * 1e3:.1f} ms oracle residual {res:.3e} "
               f"{st[0]}", flush=True)
         assert res <= 1e-10
-    assert rel(xs[1], xs[0]) < 1e-8
+    check(xs[1], xs[0], 1e-8)
     assert outer[1] <= 1.5 * outer[0] + 5
 
 
@@ -547,7 +522,7 @@ def test_batched_equals_unbatched(orc):
                    lambda_max=8.0)
     for r in range(3):
         xs, _ = lat.solve(dev(src[r:r + 1]), dev(phi))
-        assert rel(xb[r], host(xs)[0]) < 1e-8
+        check(xb[r], host(xs)[0], 1e-8)
         assert o.residual(src[r], xb[r], phi) <= 1e-10
 
 
@@ -572,7 +547,7 @@ def test_solve_deterministic_bitwise(precision):
     xa2, _ = la.solve(dev(src), dev(phi))
     xb2, _ = lb.solve(dev(src), dev(phi))
     assert np.array_equal(bits(xa2), bits(xb2))
-    assert rel(host(xa2), host(xa1)) < 1e-8
+    check(host(xa2), host(xa1), 1e-8)
     assert np.array_equal(bits(la.sign(dev(src))[0]), bits(lb.sign(dev(src))[0]))
 
 
@@ -824,7 +799,7 @@ def test_autotune_choices_agree(tmp_path, monkeypatch):
         if ref is None:
             ref = out
         else:
-            assert rel(out, ref) < 1e-12
+            check(out, ref, 1e-12)
 
 
 def test_autotune_on_solve(tmp_path, monkeypatch):
@@ -876,8 +851,64 @@ def test_rational_vs_oracle(orc, rat_coeffs, dirac, form):
     out = host(out)
     for r in range(2):
         ref = o.rational(src[r], phi, a0, al, be, tol=1e-11)
-        assert rel(out[r], ref) < 1e-9
+        check(out[r], ref, 1e-9)
     print(f"[rational] {st[0]}", flush=True)
+
+
+def _plane_wave(dims):
+    """The lowest antiperiodic-time plane wave in spin 0: an eigenvector of the free
+    MdagM, so that with a weak phi its multi-shift CG converges in fewer iterations than
+    a Gaussian source's."""
+    X, Y, Z, T = dims
+    f = np.zeros((T, Z, Y, X, 4), complex)
+    f[..., 0] = np.exp(1j * np.pi * np.arange(T) / T)[:, None, None, None]
+    return f
+
+
+def test_rational_systems_converging_apart(orc, rat_coeffs):
+    """Two right-hand sides whose multi-shift CG on MdagM needs different iteration counts:
+    the one that converges first must not take further shifted updates while the other
+    iterates.  Each result equals the single-source call bit for bit (same launch shape)
+    and the oracle's one-CG-per-shift result; the same for the rational force."""
+    dims = (4, 4, 4, 4)
+    phi, g = inputs.draw(dims, nrhs=1, sigma2=0.05, seed=73)
+    src = np.stack([g[0], _plane_wave(dims)])
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
+    lat = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, truth_tol=1e-13, **kw)
+    lat.set_launch(256, 1)
+    a0, al, be, _ = rat_coeffs[-0.25]
+    b, p = dev(src), dev(phi)
+    out, st = lat.rational(b, p, a0, al, be)
+    its = [s["outer_iters"] for s in st]
+    print(f"[rational-apart] iterations {its}", flush=True)
+    assert abs(its[0] - its[1]) >= 2
+    out = host(out)
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    for r in range(2):
+        single, _ = lat.rational(b[r:r + 1], p, a0, al, be)
+        assert np.array_equal(out[r].view(np.uint64), host(single)[0].view(np.uint64)), r
+        check(out[r], o.rational(src[r], phi, a0, al, be, tol=1e-11), 1e-9, f"rhs {r}")
+    S, G, _ = lat.rational_force(b, p, a0, al, be)
+    Gs = np.zeros_like(host(G))
+    for r in range(2):
+        Sr, Gr, _ = lat.rational_force(b[r:r + 1], p, a0, al, be)
+        assert S[r] == Sr[0], r
+        Gs += host(Gr)
+    check(host(G), Gs, 1e-14, "G of the pair vs the sum of single-source forces")
+
+
+def test_batched_sign_bitwise():
+    """With one launch shape, a batch of sign applications equals the single-system calls
+    bit for bit: every system reduces its own partial sums in a fixed order and stops on
+    its own shift residuals."""
+    dims = (8, 8, 8, 8)
+    x = inputs.gaussian_field(dims, nrhs=3, seed=41)
+    lat = lattice(dims, inner_tol=1e-12, **CFG2)
+    lat.set_launch(256, 1)
+    xb = host(lat.sign(dev(x))[0])
+    for r in range(3):
+        xs = host(lat.sign(dev(x[r:r + 1]))[0])[0]
+        assert np.array_equal(xb[r].view(np.uint64), xs.view(np.uint64)), r
 
 
 @pytest.mark.parametrize("dirac", [0, 3])
@@ -968,7 +999,7 @@ def test_rhmc_trajectory_vs_oracle(rhmc_setup):
     print(f"[rhmc] dH gpu {dH:.6e} oracle {dH_o:.6e}", flush=True)
     assert acc and acc_o
     assert abs(dH - dH_o) < 1e-7 * max(1.0, abs(dH_o))
-    assert rel(host(ph), end_o) < 1e-10
+    check(host(ph), end_o, 1e-10)
 
 
 def test_rhmc_dh_scaling_16x4():

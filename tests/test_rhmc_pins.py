@@ -99,11 +99,35 @@ def traj_setup(orc):
     lo, hi = 0.3 * lam.min(), 3.0 * lam.max()
     c18 = rational.power_approx(0.125, lo, hi, 12)
     c14 = rational.power_approx(-0.25, lo, hi, 12)
-    return o, phi, pi, R[0], c18, c14
+    return o, phi, pi, R[0], c18, c14, Md
+
+
+def test_trajectory_start_heatbath(traj_setup):
+    """The trajectory's own start (Sec. 7.3): its heatbath field eta equals the dense
+    (MdagM)^{1/8} R (eigendecomposition) to the fit error of the x^{1/8} rational, its
+    pseudofermion action eta^dag r(MdagM)^{-1/4} eta equals R^dag R (the heatbath
+    identity; a trajectory that drew eta with the x^{-1/4} rational would give
+    R^dag A^{-3/4} R instead), and the kinetic and bosonic parts are 1/2 |pi|^2 and S_B."""
+    o, phi, pi, R, c18, c14, Md = traj_setup
+    _, _, _, eta, parts = o.rhmc_trajectory(phi, pi, R, 2, 0.5, c18[:3], c14[:3], u=0.0,
+                                            start=True)
+    A = Md.conj().T @ Md
+    lam, U = np.linalg.eigh(A)
+    r = R.reshape(-1)
+    eta_dense = U @ (lam ** 0.125 * (U.conj().T @ r))
+    err18, err14 = c18[3], c14[3]
+    assert np.linalg.norm(eta.reshape(-1) - eta_dense) <= (4 * err18 + 1e-10) * np.linalg.norm(
+        eta_dense)
+    rr = float(np.vdot(r, r).real)
+    assert abs(parts[2] - rr) <= (4 * (2 * err18 + err14) + 1e-10) * rr
+    wrong = float(np.vdot(r, U @ (lam ** -0.75 * (U.conj().T @ r))).real)
+    assert abs(wrong - rr) > 100 * abs(parts[2] - rr)
+    assert abs(parts[0] - 0.5 * np.vdot(pi, pi).real) <= 1e-13 * parts[0]
+    assert abs(parts[1] - o.boson(phi)[0]) <= 1e-12 * abs(parts[1])
 
 
 def test_leapfrog_dh_scales_as_eps_squared(traj_setup):
-    o, phi, pi, R, c18, c14 = traj_setup
+    o, phi, pi, R, c18, c14, _ = traj_setup
     tau = 0.5
     dh = []
     for nsteps in (5, 10, 20):
@@ -115,7 +139,7 @@ def test_leapfrog_dh_scales_as_eps_squared(traj_setup):
 
 
 def test_metropolis_decision(traj_setup):
-    o, phi, pi, R, c18, c14 = traj_setup
+    o, phi, pi, R, c18, c14, _ = traj_setup
     end, d, acc = o.rhmc_trajectory(phi, pi, R, 5, 0.5, c18[:3], c14[:3], u=0.0)
     assert acc and not np.allclose(end, phi)
     end2, d2, acc2 = o.rhmc_trajectory(phi, pi, R, 5, 0.5, c18[:3], c14[:3], u=np.nextafter(1.0, 2.0))
