@@ -238,7 +238,8 @@ class Lattice:
     def unpack(self, xp, prec):
         nrhs = xp.shape[0]
         out = torch.empty((nrhs,) + self.field_shape, dtype=torch.complex128, device=xp.device)
-        self._check(L.lib().ov_unpack(self._h, prec, _ptr(out), _ptr(xp.contiguous()), nrhs))
+        xp = xp.contiguous()  # held until the call has been enqueued
+        self._check(L.lib().ov_unpack(self._h, prec, _ptr(out), _ptr(xp), nrhs))
         return out
 
 
@@ -247,14 +248,16 @@ def solve_batch(lattices, bs, phis):
     n = len(lattices)
     ctx = (C.c_void_p * n)(*[l._h.value for l in lattices])
     bl, xl, pl, nr = [], [], [], []
-    xs = []
+    xs, held = [], []  # every tensor whose pointer is passed stays referenced until the call
     for lat, b, phi in zip(lattices, bs, phis):
         b, nrhs = lat._fields(b)
+        phi = lat._phi(phi)
         x = torch.zeros_like(b)
         xs.append(x)
+        held += [b, phi]
         bl.append(b.data_ptr())
         xl.append(x.data_ptr())
-        pl.append(lat._phi(phi).data_ptr())
+        pl.append(phi.data_ptr())
         nr.append(nrhs)
     tot = sum(nr)
     st = (L.OvStats * tot)()

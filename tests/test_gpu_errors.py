@@ -77,8 +77,11 @@ def test_unreachable_tolerance_best_iterate(orc):
     lat = lattice(dims, precision="mixed", outer_tol=1e-30, max_outer=60, **CFG2)
     x = torch.zeros((1,) + lat.field_shape, dtype=torch.complex128, device="cuda")
     st = (L.OvStats * 1)()
-    rc = L.lib().ov_solve(lat._h, C.c_void_p(x.data_ptr()), C.c_void_p(dev(src).data_ptr()),
-                          C.c_void_p(dev(phi).data_ptr()), 1, st)
+    # the device copies must outlive the call: a pointer taken from a temporary tensor
+    # goes back to torch's caching allocator at once and is reused by the next copy
+    b, p = dev(src), dev(phi)
+    rc = L.lib().ov_solve(lat._h, C.c_void_p(x.data_ptr()), C.c_void_p(b.data_ptr()),
+                          C.c_void_p(p.data_ptr()), 1, st)
     torch.cuda.synchronize()
     msg = L.lib().ov_last_error(lat._h).decode()
     print(f"[unreachable] rc {rc} ({msg}) {st[0].as_dict()}", flush=True)
@@ -113,12 +116,19 @@ def test_workspace_too_small_and_sizes(rat20):
         check(host(x), host(x_ref), 1e-8, f"launch {blk}x{spt}")
     lat.sign(b)
     lat.force(b[:1], p)
-    # the rational layers need room for their shifted systems
+    # the rational layers size their shifted systems with ov_workspace_bytes_rational:
+    # within the solve-sized workspace only if that query says they fit
     a0, al, be, _ = rat20
+    nb = lib.ov_workspace_bytes_rational(lat._h, 2, len(al))
+    print(f"[workspace] solve {need} B, rational {nb} B", flush=True)
+    if nb > need:
+        st, _ = _status(lambda: lat.rational(b, p, a0, al, be))
+        assert st == L.OV_ERR_WORKSPACE
+    else:
+        lat.rational(b, p, a0, al, be)
+    L.check(lib.ov_set_workspace(lat._h, C.c_void_p(tiny.data_ptr()), 4096), lat._h)
     st, _ = _status(lambda: lat.rational(b, p, a0, al, be))
     assert st == L.OV_ERR_WORKSPACE
-    nb = lib.ov_workspace_bytes_rational(lat._h, 2, len(al))
-    assert nb > need
     ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
     base = (ws.data_ptr() + 255) & ~255
     L.check(lib.ov_set_workspace(lat._h, C.c_void_p(base), nb), lat._h)

@@ -856,9 +856,10 @@ def test_rational_vs_oracle(orc, rat_coeffs, dirac, form):
 
 
 def _plane_wave(dims):
-    """The lowest antiperiodic-time plane wave in spin 0: an eigenvector of the free
-    MdagM, so that with a weak phi its multi-shift CG converges in fewer iterations than
-    a Gaussian source's."""
+    """The lowest antiperiodic-time plane wave in spin 0: with phi = 0 an eigenvector of
+    MdagM up to the rational sign's error (D + D^dag is a scalar per momentum), so its
+    CG on MdagM converges in one or two iterations, a Gaussian source's in about eleven
+    at 4^4 (the oracle's plain CG to 1e-11: 1 and 11)."""
     X, Y, Z, T = dims
     f = np.zeros((T, Z, Y, X, 4), complex)
     f[..., 0] = np.exp(1j * np.pi * np.arange(T) / T)[:, None, None, None]
@@ -872,6 +873,7 @@ def test_rational_systems_converging_apart(orc, rat_coeffs):
     and the oracle's one-CG-per-shift result; the same for the rational force."""
     dims = (4, 4, 4, 4)
     phi, g = inputs.draw(dims, nrhs=1, sigma2=0.05, seed=73)
+    phi = np.zeros_like(phi)  # with a non-zero phi the two counts differ by one at most
     src = np.stack([g[0], _plane_wave(dims)])
     kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0)
     lat = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, truth_tol=1e-13, **kw)
@@ -881,7 +883,7 @@ def test_rational_systems_converging_apart(orc, rat_coeffs):
     out, st = lat.rational(b, p, a0, al, be)
     its = [s["outer_iters"] for s in st]
     print(f"[rational-apart] iterations {its}", flush=True)
-    assert abs(its[0] - its[1]) >= 2
+    assert its[0] - its[1] >= 5
     out = host(out)
     o = orc.Oracle(dims, inner_tol=1e-13, **kw)
     for r in range(2):
