@@ -198,6 +198,26 @@ ov_status ov_sign(ov_ctx *ctx, void *out, const void *in, int nrhs, ov_stats *st
 ov_status ov_apply(ov_ctx *ctx, ov_op op, void *out, const void *in, const void *phi,
                    int nrhs, ov_stats *st);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): ov_apply with every scratch
+ * buffer of the call (multi-shift basis, partial sums, counters, tables) carved from
+ * one library-static device array of OV_NOALLOC_SCRATCH_BYTES per device instead of
+ * a workspace.  Same arguments, kernels and results as ov_apply (bit for bit at the
+ * same launch shape); the caller still owns in, out and phi.  The call allocates
+ * nothing (no hipMalloc/hipFree, no host staging: that is set up by ov_ctx_create for
+ * up to 16 right-hand sides) and ignores any workspace set with ov_set_workspace.
+ * Limits and errors: a call whose buffers exceed the array (ov_workspace_bytes of the
+ * same context and nrhs is an upper bound; e.g. at inner_tol 1e-12 the multi-shift
+ * basis of one 8^4 field takes 30.7 MB, so 8^4 fits 2 right-hand sides), or nrhs > 16,
+ * returns OV_ERR_WORKSPACE and launches nothing; other errors as ov_apply.  The array
+ * keeps the last call's contents; every call clears what must start at zero.  All
+ * contexts on one device share that device's array, so no-allocation calls that
+ * overlap in time on one device (different streams or threads) race: serialise them.
+ * Kernel-duration sampling (ov_kernel_sampling) is suspended during the call. */
+#define OV_NOALLOC_SCRATCH_BYTES (64u << 20)
+ov_status ov_apply_noalloc(ov_ctx *ctx, ov_op op, void *out, const void *in, const void *phi,
+                           int nrhs, ov_stats *st);
+
 /* Solve MdagM x = b for nrhs right-hand sides (all in one batched launch
  * sequence).  x is the initial guess on entry (zero it for a cold start) and
  * the solution on exit.  st may be NULL or an array of nrhs stats. */

@@ -24,7 +24,7 @@ OPS = {"hw": OP_HW, "dov": OP_DOV, "dov_dag": OP_DOV_DAG, "m": OP_M, "m_dag": OP
 SYMBOLS = ["ov_params_default", "ov_ctx_create", "ov_ctx_destroy", "ov_workspace_bytes",
            "ov_workspace_bytes_rational",
            "ov_set_workspace", "ov_get_coeffs", "ov_zolotarev", "ov_sign", "ov_apply",
-           "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
+           "ov_apply_noalloc", "ov_solve", "ov_solve_batch", "ov_force", "ov_stencil_bench", "ov_pack",
            "ov_unpack", "ov_set_launch", "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling",
            "ov_kernel_times", "ov_locality", "ov_rational", "ov_rational_force", "ov_boson",
            "ov_rhmc_trajectory",
@@ -86,6 +86,7 @@ def lib():
         L.ov_zolotarev.argtypes = [C.c_int, C.c_double, C.c_double, P, P, P]
         L.ov_sign.argtypes = [P, P, P, C.c_int, P]
         L.ov_apply.argtypes = [P, C.c_int, P, P, P, C.c_int, P]
+        L.ov_apply_noalloc.argtypes = [P, C.c_int, P, P, P, C.c_int, P]
         L.ov_solve.argtypes = [P, P, P, P, C.c_int, P]
         L.ov_solve_batch.argtypes = [C.c_int, P, P, P, P, P, P]
         L.ov_force.argtypes = [P, P, P, P, P, C.c_int, P]
@@ -108,7 +109,8 @@ def lib():
         L.ov_last_error.argtypes = [P]
         L.ov_last_error.restype = C.c_char_p
         for fn in ("ov_ctx_create", "ov_ctx_destroy", "ov_set_workspace", "ov_get_coeffs",
-                   "ov_zolotarev", "ov_sign", "ov_apply", "ov_solve", "ov_solve_batch",
+                   "ov_zolotarev", "ov_sign", "ov_apply", "ov_apply_noalloc", "ov_solve",
+                   "ov_solve_batch",
                    "ov_force", "ov_stencil_bench", "ov_pack", "ov_unpack", "ov_set_launch",
                    "ov_get_launch", "ov_tune_ms", "ov_kernel_sampling", "ov_kernel_times",
                    "ov_locality", "ov_rational", "ov_rational_force", "ov_boson",

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,7 @@ struct ov_ctx {
   size_t own_ws_bytes = 0;
   double* pinned = nullptr;      // host staging of per-system scalars
   int pinned_n = 0;
+  bool noalloc = false;          // inside ov_apply_noalloc: scratch array, no allocation
   int* pinned_flags = nullptr;
   // kernel-duration sampling (see ov_kernel_sampling)
   int sample_max = 0;
@@ -68,7 +70,20 @@ struct ov_ctx {
   double wall_khz = 0;                   // wall-clock rate of the stamps
 };
 
+// Scratch of ov_apply_noalloc: one array per device, held until the process ends.
+// Host code never uses its name as an address (on the host it is only a stand-in for
+// the symbol); the device address comes from hipGetSymbolAddress, once per device,
+// at context creation (noalloc_scratch_setup).
+static __device__ __align__(256) unsigned char scratch[OV_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` per device
+// Host staging (pinned scalars) allocated at context creation, so that the
+// no-allocation entry point never allocates it: systems it serves per call.
+constexpr int kNoAllocSystems = 16;
 
 thread_local std::string g_err;
 
@@ -473,6 +488,23 @@ void clear_graphs(ov_ctx* c) {
 }
 
 ov_status ensure_ws(ov_ctx* c, size_t need, void** base) {
+  if (c->noalloc) {  // ov_apply_noalloc: the device's scratch array, never an allocation
+    void* p = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_dev[c->device] : nullptr;
+    if (!p) {
+      c->err = "no-allocation scratch has no device address on this device";
+      return OV_ERR_DEVICE;
+    }
+    if (need > (size_t)OV_NOALLOC_SCRATCH_BYTES) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "no-allocation scratch of %zu bytes is too small: this call needs %zu",
+                    (size_t)OV_NOALLOC_SCRATCH_BYTES, need);
+      c->err = buf;
+      return OV_ERR_WORKSPACE;
+    }
+    *base = p;
+    return OV_OK;
+  }
   if (c->user_ws) {  // a caller-owned workspace is never supplemented by a hidden allocation
     if (c->user_ws_bytes < need) {
       char buf[160];
@@ -498,6 +530,13 @@ ov_status ensure_ws(ov_ctx* c, size_t need, void** base) {
 
 ov_status ensure_pinned(ov_ctx* c, int nsys) {
   if (c->pinned_n >= nsys) return OV_OK;
+  if (c->noalloc) {
+    char buf[120];
+    std::snprintf(buf, sizeof buf, "no-allocation calls take at most %d right-hand sides",
+                  c->pinned_n);
+    c->err = buf;
+    return OV_ERR_WORKSPACE;
+  }
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   c->pinned = nullptr;
@@ -505,6 +544,26 @@ ov_status ensure_pinned(ov_ctx* c, int nsys) {
   HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(double) * (CG_NSLOT + 24) * nsys));
   HIPCHK(c, hipHostMalloc((void**)&c->pinned_flags, sizeof(int) * 2 * nsys + 64));
   c->pinned_n = nsys;
+  return OV_OK;
+}
+
+// Device address of the no-allocation scratch array on the context's device: looked
+// up once per device (with that device current: contexts are created on the current
+// device) and kept for the life of the process.
+ov_status noalloc_scratch_setup(ov_ctx* c) {
+  if (c->device < 0 || c->device >= kMaxDevices) {
+    c->err = "device ordinal beyond the no-allocation scratch table";
+    return OV_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[c->device]) return OV_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    c->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return OV_ERR_DEVICE;
+  }
+  g_scratch_dev[c->device] = ptr;
   return OV_OK;
 }
 
@@ -2217,6 +2276,17 @@ ov_status ov_ctx_create(const ov_params* p, void* hip_stream, ov_ctx** out) {
     delete c;
     return OV_ERR_DEVICE;
   }
+  // set-up of the no-allocation entry point: the scratch array's device address and
+  // host staging for kNoAllocSystems systems
+  if (noalloc_scratch_setup(c) != OV_OK || ensure_pinned(c, kNoAllocSystems) != OV_OK) {
+    g_err = c->err;
+    (void)hipEventDestroy(c->ev_in);
+    (void)hipStreamDestroy(c->priv);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
+    delete c;
+    return OV_ERR_DEVICE;
+  }
   const char* eg = std::getenv("OV_GRAPHS");
   c->use_graphs = (eg && *eg == '1');
   // The persistent cooperative multi-shift kernel is opt-in: its grid barriers
@@ -2370,6 +2440,26 @@ ov_status ov_apply(ov_ctx* c, ov_op op, void* out, const void* in, const void* p
   if (c && (op == OV_OP_M0INV || op == OV_OP_M0INV_DAG) && !fft_ok(&c->p, c->err))
     return OV_ERR_INVALID_ARG;
   return apply_impl(c, (int)op, out, in, phi, nrhs, st);
+}
+
+ov_status ov_apply_noalloc(ov_ctx* c, ov_op op, void* out, const void* in, const void* phi,
+                           int nrhs, ov_stats* st) {
+  if (!c || nrhs < 1) return OV_ERR_INVALID_ARG;
+  if (nrhs > c->pinned_n) {
+    char buf[120];
+    std::snprintf(buf, sizeof buf, "no-allocation calls take at most %d right-hand sides",
+                  c->pinned_n);
+    c->err = buf;
+    return OV_ERR_WORKSPACE;
+  }
+  // kernel-duration sampling creates events and stamp buffers: off for this call
+  const int sample_max = c->sample_max;
+  c->sample_max = 0;
+  c->noalloc = true;
+  const ov_status rc = ov_apply(c, op, out, in, phi, nrhs, st);
+  c->noalloc = false;
+  c->sample_max = sample_max;
+  return rc;
 }
 
 static bool same_solver(const ov_params& a, const ov_params& b) {

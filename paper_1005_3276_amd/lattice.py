@@ -198,6 +198,18 @@ class Lattice:
                                      _ptr(phi) if phi is not None else None, nrhs, st))
         return out, [s.as_dict() for s in st]
 
+    def apply_noalloc(self, op, x, phi=None):
+        """apply() through ov_apply_noalloc: the library allocates nothing (its scratch
+        is a static device array of OV_NOALLOC_SCRATCH_BYTES; see include/ov.h)."""
+        x, nrhs = self._fields(x)
+        phi = self._phi(phi)
+        out = torch.empty_like(x)
+        st = (L.OvStats * nrhs)()
+        code = L.OPS[op] if isinstance(op, str) else int(op)
+        self._check(L.lib().ov_apply_noalloc(self._h, code, _ptr(out), _ptr(x),
+                                             _ptr(phi) if phi is not None else None, nrhs, st))
+        return out, [s.as_dict() for s in st]
+
     def solve(self, b, phi, x0=None):
         b, nrhs = self._fields(b)
         phi = self._phi(phi)
