@@ -120,36 +120,67 @@ def copy_bandwidth(torch):
     return out
 
 
-def cpu_baseline(phi, src, outer_iters):
-    """Oracle FP64 M^dag M applications at 16^4 on the host cores; scaled to one
-    solve of the oracle's (unpreconditioned) CG by the outer-iteration count of
-    the unpreconditioned GPU FP64 solve."""
-    from oracle import oracle as O
-    o = O.Oracle(DIMS, m=CFG["m"], g=CFG["g"], n_poles=CFG["n_poles"],
-                 lambda_min=CFG["lambda_min"], lambda_max=CFG["lambda_max"], inner_tol=1e-12)
-    t = time.perf_counter()
-    napp = 0
-    v = src[0]
-    while True:
-        v = o.apply(O.OP_MDAGM, v, phi)
-        v = v / (abs(v).max())
-        napp += 1
-        if time.perf_counter() - t > 10.0 or napp >= 3:
-            break
-    el = time.perf_counter() - t
-    per = el / napp
-    model = "unknown CPU"
+def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": 1.0 / (per * outer_iters), "unit": "solves/s", "cores": O.threads(),
-            "kind": "oracle", "cpu": model,
-            "sample": f"{napp} MdagM applications (FP64 oracle, multi-shift tol 1e-12) at 16^4, "
-                      f"{per:.2f} s each, scaled by {outer_iters} outer CG iterations"}
+    return "unknown CPU"
+
+
+def oracle_solve_timed(dims, phi, b, m=0.05, g=0.3, inner_tol=1e-12):
+    """One complete solve of MdagM x = b by the FP64 oracle (its plain CG on MdagM,
+    multi-shift tolerance inner_tol, stop on the true residual 1e-10), timed."""
+    from oracle import oracle as O
+    o = O.Oracle(dims, m=m, g=g, n_poles=CFG["n_poles"], lambda_min=CFG["lambda_min"],
+                 lambda_max=CFG["lambda_max"], inner_tol=inner_tol)
+    t = time.perf_counter()
+    _, st, rc = o.solve(b, phi, tol=CFG["outer_tol"], maxit=2000)
+    el = time.perf_counter() - t
+    return el, {"seconds": el, "outer_iters": st.iters, "inner_iters": st.inner_iters,
+                "true_rel_res": st.true_rel_res, "converged": rc == 0}
+
+
+def cpu_baseline(phi, src):
+    """The oracle on the host cores: one complete solve of the benchmark's own system
+    (16^4, same inputs), timed whole."""
+    from oracle import oracle as O
+    el, st = oracle_solve_timed(DIMS, phi, src[0])
+    return {"value": 1.0 / el, "unit": "solves/s", "cores": O.threads(), "kind": "oracle",
+            "cpu": cpu_model(), "timed": "complete solve",
+            "sample": f"one complete solve of the benchmark's system at 16^4 by the FP64 oracle "
+                      f"(plain CG on MdagM, no preconditioner, multi-shift tol 1e-12): "
+                      f"{st['outer_iters']} CG iterations, true residual "
+                      f"{st['true_rel_res']:.2e}, {el:.1f} s",
+            "solve": st}
+
+
+def cpu_suite(full16):
+    """--cpu-only: the oracle timed on the config-2 solves (8^4, and 16^4 with full16)
+    and the config-4 force (12^4), with the threads OMP_NUM_THREADS gives it."""
+    from oracle import oracle as O
+    from paper_1005_3276_amd import inputs
+    out = {"metric": "cpu_oracle", "cores": O.threads(), "cpu": cpu_model()}
+    phi, src = inputs.draw((8, 8, 8, 8), nrhs=1, sigma2=0.25, seed=inputs.config_seed(2) + 1)
+    out["solve_8x4"] = oracle_solve_timed((8, 8, 8, 8), phi, src[0])[1]
+    log(f"oracle 8^4 solve: {out['solve_8x4']}")
+    if full16:
+        phi, src = inputs.draw(DIMS, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+        out["solve_16x4"] = oracle_solve_timed(DIMS, phi, src[0])[1]
+        log(f"oracle 16^4 solve: {out['solve_16x4']}")
+    d12 = (12, 12, 12, 12)
+    phi, xi = inputs.draw(d12, nrhs=1, sigma2=0.25, seed=inputs.config_seed(4))
+    o = O.Oracle(d12, m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0,
+                 inner_tol=1e-12)
+    t = time.perf_counter()
+    S, _, st, rc = o.force(phi, xi[0], tol=CFG["outer_tol"])
+    el = time.perf_counter() - t
+    out["force_12x4"] = {"seconds": el, "S": S, "outer_iters": st.iters,
+                         "true_rel_res": st.true_rel_res, "converged": rc == 0}
+    log(f"oracle 12^4 force: {out['force_12x4']}")
+    return out
 
 
 # multi-shift pass families: (t-pass kernel id, r-pass kernel id) of the library's
@@ -404,6 +435,11 @@ def main():
                     help="end with one 512 MiB device copy (reference for traffic counters)")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the 16^4 stencil sweep (one JSON line of its own)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only the oracle timings on the host (config-2 solve at 8^4, config-4 "
+                         "force at 12^4; no GPU); one JSON line")
+    ap.add_argument("--cpu-16", action="store_true",
+                    help="with --cpu-only: also the config-2 solve at 16^4")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched 12 x 16^3x32 mixed solve with its pass rooflines "
                          "(one JSON line of its own)")
@@ -413,6 +449,10 @@ def main():
                                    "multi-lattice work shards across GPUs without "
                                    "communication; that path is not part of this build)"}))
         sys.exit(2)
+
+    if args.cpu_only:
+        print(json.dumps(cpu_suite(args.cpu_16)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -492,7 +532,6 @@ def main():
     log(f"roofline: {roofline}")
 
     extra = {}
-    fp64_outer = stats[0]["outer_iters"]
     if not args.quick:
         # ---- plain FP64 paths (P2: inner 1e-8 + reliable updates; P1: inner 1e-12)
         # P1: plain nested FP64 CG, inner sign at 1e-12, no reliable updates
@@ -517,8 +556,6 @@ def main():
                            "outer_iters": st64[0]["outer_iters"],
                            "inner_iters": st64[0]["inner_iters"],
                            "true_rel_res": st64[0]["true_rel_res"]}
-            if name == "fp64_p3_unpreconditioned":
-                fp64_outer = st64[0]["outer_iters"]
             log(f"{name}: {extra[name]}")
             del l64
         best64 = max(extra[k]["solves_per_s"] for k in ("fp64_p1", "fp64_p2", "fp64_p3"))
@@ -557,7 +594,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(phi, src, fp64_outer)
+        cpu = cpu_baseline(phi, src)
         log(f"cpu: {cpu}")
 
     out = {
