@@ -66,6 +66,7 @@ struct SysDev {
   void* cg_x;               // CG vectors (kernel precision)
   void* cg_p;
   void* cg_r;
+  void* cg_z;               // preconditioned residual z = P r (PCG); null: z = r
   const double2* cg_b;      // FP64 right-hand side (true residual)
   void* cg_r64;             // FP64 true residual out
   void* cg_x64;             // FP64 solution (reliable updates)
@@ -83,7 +84,9 @@ struct SysDev {
 };
 
 // CG scalar slots
-enum { CG_RR = 0, CG_RR_OLD, CG_PAP, CG_ALPHA, CG_BETA, CG_BB, CG_RTRUE, CG_RYT, CG_NSLOT = 8 };
+// CG_RR holds rho = <r, z> (= |r|^2 without a preconditioner); CG_R2 holds |r|^2 of
+// the preconditioned recursion.
+enum { CG_RR = 0, CG_RR_OLD, CG_PAP, CG_ALPHA, CG_BETA, CG_BB, CG_RTRUE, CG_R2, CG_NSLOT = 8 };
 
 struct MsParams {
   int np;               // poles
@@ -1266,7 +1269,10 @@ __global__ void __launch_bounds__(256) k_fill(const SysDev* __restrict__ sys,
 // inverse e^{+2 pi i j k/L} with 1/V.  Antiperiodic time is handled by the
 // twist e^{-i pi t/T} before the forward and e^{+i pi t/T} after the inverse
 // transform, which puts p_t on (2n+1) pi / T.
-enum SymKind { SYM_D = 0, SYM_D_DAG = 1, SYM_M0INV = 2, SYM_M0INV_DAG = 3, SYM_BOSON = 4 };
+// SYM_PCG: the scalar (M0^dag M0)^-1 = M0^-1 M0^-dag of the free-field operator, the
+// preconditioner of CG on MdagM (Sec. 7.3 in its split form; same iterates).
+enum SymKind { SYM_D = 0, SYM_D_DAG = 1, SYM_M0INV = 2, SYM_M0INV_DAG = 3, SYM_BOSON = 4,
+               SYM_PCG = 5 };
 enum DiracForm { DIRAC_RATIONAL = 0, DIRAC_EXACT = 1, DIRAC_DSLASH = 2 };
 
 struct SymParams {
@@ -1417,6 +1423,13 @@ __device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, d
     a0 = 1.0 + Rr * w;
     c = Rr;
   }
+  if (sp.kind == SYM_PCG) {  // M0^dag M0 = (a^2 + mu^2 + c^2 |s|^2) 1: a scalar per momentum
+    const double A = a0 + m_re;
+    const double sc = 1.0 / (A * A + m_im * m_im + c * c * s2sin);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = double2{v[k].x * sc, v[k].y * sc};
+    return;
+  }
   // out = (A v + i (cg gamma.s v + c5 g5 v)) * scale
   double A = a0, cg = c, c5 = 0.0, scale = 1.0;
   if (sp.kind == SYM_D_DAG) {
@@ -1522,7 +1535,7 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
       v[2] = double2{k2 * v[2].x, k2 * v[2].y};
       v[3] = double2{0.0, 0.0};
     } else {
-      const bool m0 = sp.kind == SYM_M0INV || sp.kind == SYM_M0INV_DAG;
+      const bool m0 = sp.kind == SYM_M0INV || sp.kind == SYM_M0INV_DAG || sp.kind == SYM_PCG;
       apply_symbol(sp, m0 ? S.pc_re : S.m_re, m0 ? S.pc_im : S.m_im, sx, sy, sz, st, w, v);
     }
 #pragma unroll
@@ -2082,20 +2095,27 @@ __global__ void __launch_bounds__(256) k_md_axpy(double2* __restrict__ y, double
 }
 
 // ------------------------------------------------------------ CG kernels
-// Sum part_c into cg_s[slot]; op 0: store, 1: alpha = rr/pap, 2: beta + rr update.
+// CG scalars of system s from partial sums (part_c; part_b for rho = <r, z>):
+//   op 0: start, rho = |r|^2;  1: alpha = rho / <p, w>;  2: beta, rho = |r|^2;
+//   3 / 7: reliable update (true |r|^2 replaces the recursive one; 7 restarts);
+//   4: |b|^2;  5: true |r|^2 only;
+//   preconditioned (PCG, z = P r):  9: beta, rho = <r, z>, |r|^2;  10: start;
+//   11 / 12: reliable update from the true residual (|r|^2 set by op 5; 12 restarts).
 __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
   __shared__ double lds[17];
   const int s = blockIdx.x;
   if (s >= nsys) return;
   const SysDev& S = sys[s];
   if (S.active && *S.active == 0) return;
-  const double v = sum_partials(S.part_c, S.nblk, lds);
+  const double v = (op >= 10) ? 0.0 : sum_partials(S.part_c, S.nblk, lds);
+  const double rz = (op >= 9) ? sum_partials(S.part_b, S.nblk, lds) : 0.0;
   if (threadIdx.x == 0) {
     double* c = S.cg_s;
     if (op == 0) {
       c[CG_RR] = v;
       c[CG_RR_OLD] = v;
       c[CG_BETA] = 0.0;
+      c[CG_R2] = v;
     } else if (op == 1) {
       c[CG_PAP] = v;
       c[CG_ALPHA] = c[CG_RR] / v;
@@ -2103,6 +2123,7 @@ __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
       c[CG_RR_OLD] = c[CG_RR];
       c[CG_RR] = v;
       c[CG_BETA] = v / c[CG_RR_OLD];
+      c[CG_R2] = v;
     } else if (op == 3 || op == 7) {  // reliable update: recursive |r|^2 -> true one
       // Keep the search direction unless the true residual exceeds the recursive
       // one by more than 2x (the recursion drifted) or a restart is forced (op 7,
@@ -2110,14 +2131,26 @@ __global__ void k_cg_scalar(const SysDev* __restrict__ sys, int nsys, int op) {
       const double rec = c[CG_RR];
       c[CG_RTRUE] = v;
       c[CG_RR] = v;
+      c[CG_R2] = v;
       c[CG_BETA] = (op == 7 || v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
     } else if (op == 5) {  // true residual only (no CG state change)
       c[CG_RTRUE] = v;
-    } else if (op == 6 || op == 8) {  // the same for the preconditioned recursion (|r~|^2)
-      const double rec = c[CG_RR];
-      c[CG_RYT] = v;
-      c[CG_RR] = v;
-      c[CG_BETA] = (op == 8 || v > 4.0 * rec) ? 0.0 : v / c[CG_RR_OLD];
+    } else if (op == 9) {
+      c[CG_RR_OLD] = c[CG_RR];
+      c[CG_RR] = rz;
+      c[CG_BETA] = rz / c[CG_RR_OLD];
+      c[CG_R2] = v;
+    } else if (op == 10) {  // start from r = b (|b|^2 set by op 4)
+      c[CG_RR] = rz;
+      c[CG_RR_OLD] = rz;
+      c[CG_BETA] = 0.0;
+      c[CG_R2] = c[CG_BB];
+    } else if (op == 11 || op == 12) {
+      const double rec = c[CG_R2];
+      const double rt = c[CG_RTRUE];
+      c[CG_R2] = rt;
+      c[CG_RR] = rz;
+      c[CG_BETA] = (op == 12 || rt > 4.0 * rec) ? 0.0 : rz / c[CG_RR_OLD];
     } else if (op == 4) {  // norm of b
       c[CG_BB] = v;
     }
@@ -2145,7 +2178,8 @@ __global__ void __launch_bounds__(256) k_zero32(unsigned int* __restrict__ p, si
     p[i] = 0u;
 }
 
-// p = r + beta p (beta from cg_s; use_beta = 0 -> p = r); partial |p|^2 -> part_b.
+// p = z + beta p (z = cg_z, or r without a preconditioner; beta from cg_s;
+// use_beta = 0 -> p = z); partial |p|^2 -> part_b.
 template <class R>
 __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                int nb_total, int use_beta) {
@@ -2164,7 +2198,7 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
   double acc = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     c2<R> r[4], p[4];
-    load_sp<R>((const c2<R>*)S.cg_r, V, i, r);
+    load_sp<R>((const c2<R>*)(S.cg_z ? S.cg_z : S.cg_r), V, i, r);
     if (use_beta) {
       load_sp<R>((const c2<R>*)S.cg_p, V, i, p);
 #pragma unroll
@@ -2189,6 +2223,7 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
 //   op 3: x64 += e_out (low precision), x = 0        (preconditioned fold-in)
 //   op 4: partial |r|^2 -> part_c
 //   op 5: x += alpha p, r -= alpha e_in, partial |r|^2 -> part_c
+//   op 6: partial Re <r, z> -> part_b  (z = cg_z)
 template <class R>
 __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                   int nb_total, int op) {
@@ -2263,11 +2298,21 @@ __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys,
       store_sp<R>((c2<R>*)S.cg_x, V, i, xv);
       store_sp<R>((c2<R>*)S.cg_r, V, i, rv);
       acc += norm2_sp(rv);
+    } else if (op == 6) {
+      c2<R> rv[4], zv[4];
+      load_sp<R>((const c2<R>*)S.cg_r, V, i, rv);
+      load_sp<R>((const c2<R>*)S.cg_z, V, i, zv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        acc += (double)rv[k].x * (double)zv[k].x + (double)rv[k].y * (double)zv[k].y;
     }
   }
   if (op == 1 || op == 4 || op == 5) {
     const double tot = block_sum(acc, lds);
     if (threadIdx.x == 0) S.part_c[lb] = tot;
+  } else if (op == 6) {
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) S.part_b[lb] = tot;
   }
 }
 

@@ -325,11 +325,8 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
 
 enum Table {
   T_APPLY = 0, T_APPLY2, T_IN_M, T_IN_MDAG, T_TR_M, T_TR_MDAG, T_CG, T_CG_RU,
-  T_PC_P,     // v = M0^-1 p
-  T_PC_Q,     // q = M0^-dag (M^dag u), in place on v
-  T_PC_FOLD,  // M0^-1 x~ for the fold-in x64 += M0^-1 x~
-  T_PC_RES,   // r~ = M0^-dag r64
-  T_PC_B,     // r~ = M0^-dag b, in place
+  T_PC_Z,     // z = P r, P = (M0^dag M0)^-1 (systems iterating)
+  T_PC_ZRU,   // the same for the systems taking a reliable update
   T_F_M,      // momentum-space D: inner M v
   T_F_MD,     // inner M^dag u
   T_F_TM,     // FP64 true residual: M x64
@@ -1184,17 +1181,13 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
             need(t, s, T[t]->cg_x64, "cg_x64") && need(t, s, T[t]->src, "src");
     ok &= need(T_CG_RU, s, T[T_CG_RU]->cg_r64, "cg_r64");
     if (E.pl.pc) {
-      // momentum-space passes, EPI_MDAG into v, k_cg_misc ops 3-5
-      for (int t : {T_PC_P, T_PC_Q, T_PC_FOLD, T_PC_RES, T_PC_B})
+      // z = P r (momentum-space passes), EPI_MDAG into w, k_cg_misc ops 5 and 6
+      for (int t : {T_PC_Z, T_PC_ZRU})
         ok &= need(t, s, T[t]->e_in, "e_in") && need(t, s, T[t]->e_out, "e_out") &&
               need(t, s, T[t]->fft_tmp, "fft_tmp") && need(t, s, T[t]->active, "active");
       if (!E.pl.fft) ok &= need(T_IN_MDAG, s, T[T_IN_MDAG]->e_out, "e_out");
       ok &= need(T_CG, s, T[T_CG]->e_in, "e_in");
-      ok &= need(T_PC_FOLD, s, T[T_PC_FOLD]->cg_x, "cg_x") &&
-            need(T_PC_FOLD, s, T[T_PC_FOLD]->cg_x64, "cg_x64");
-      for (int t : {T_PC_RES, T_PC_B})
-        ok &= need(t, s, T[t]->cg_r, "cg_r") && need(t, s, T[t]->part_c, "part_c") &&
-              need(t, s, T[t]->cg_s, "cg_s");
+      for (int t : {T_CG, T_CG_RU}) ok &= need(t, s, T[t]->cg_z, "cg_z");
     }
     if (E.pl.gw) {
       // k_gw_prep / multi-shift / k_gw_combine over both entries, k_cg_scalar on A
@@ -1295,8 +1288,8 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     im.active = b.act_cg;
     im.basis = b.basisR;
     im.r = b.rR;
-    im.src = E.pl.pc ? b.vR : b.pR;  // preconditioned: M (M0^-1 p)
-    im.e_in = E.pl.pc ? b.vR : b.pR;
+    im.src = b.pR;
+    im.e_in = b.pR;
     im.e_out = b.uR;
     im.e_out2 = b.srcR2;
     // inner M^dag u with the CG update
@@ -1309,7 +1302,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     imd.cg_x = b.xR;
     imd.cg_p = b.pR;
     imd.cg_r = b.rcgR;
-    imd.e_out = b.vR;  // preconditioned: M^dag u -> v (EPI_MDAG), then M0^-dag
+    imd.e_out = b.vR;  // preconditioned: w = M^dag u -> v (EPI_MDAG), then the CG update
     // FP64 true residual: M x64, then r64 = b - M^dag (M x64)
     SysDev tm = d;
     tm.active = b.act_ru;
@@ -1326,9 +1319,8 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     tmd.src = b.src64b;
     tmd.e_in = b.u64;
     tmd.cg_r64 = b.r64;
-    // FP64 inner solver: copy of r64 in cg_r; FP32: k_r64_to_r32; preconditioned:
-    // the recursion restarts from M0^-dag r64 instead
-    tmd.cg_r = (sizeof(R) == sizeof(double) && !E.pl.pc) ? b.rcgR : nullptr;
+    // FP64 inner solver: copy of r64 in cg_r; FP32: k_r64_to_r32
+    tmd.cg_r = (sizeof(R) == sizeof(double)) ? b.rcgR : nullptr;
     // CG vector ops
     SysDev cg = d;
     cg.active = b.act_cg;
@@ -1337,45 +1329,27 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     cg.cg_r = b.rcgR;
     cg.cg_x64 = b.x64;
     cg.src = b.x64;
-    cg.e_in = b.vR;  // q of the preconditioned update
+    cg.e_in = b.vR;   // w = MdagM p of the update (preconditioned and GW forms)
+    cg.cg_z = E.pl.pc ? b.vR : nullptr;  // z = P r, in v once w has been used
     SysDev cgr = cg;
     cgr.active = b.act_ru;
     cgr.cg_r64 = b.r64;
-    if (E.pl.pc) {
-      SysDev pp = d;
-      pp.active = b.act_cg;
-      pp.fft_tmp = b.fftR;
-      pp.e_in = b.pR;
-      pp.e_out = b.vR;
-      SysDev pq = pp;
-      pq.e_in = b.vR;
-      SysDev pf = d;
-      pf.active = b.act_ru;
-      pf.fft_tmp = b.fftR;
-      pf.e_in = b.xR;
-      pf.e_out = b.vR;
-      pf.cg_x = b.xR;
-      pf.cg_x64 = b.x64;
-      SysDev pr = d;
-      pr.active = b.act_ru;
-      pr.fft_tmp = b.fftR;
-      pr.e_in = (sizeof(R) == sizeof(double)) ? (const void*)b.r64 : (const void*)b.rcgR;
-      pr.e_out = b.rcgR;
-      pr.cg_r = b.rcgR;
-      SysDev pb = pr;
-      pb.active = b.act_cg;
-      pb.e_in = b.rcgR;
-      E.htab[(size_t)T_PC_P * E.nsys + s] = pp;
-      E.htab[(size_t)T_PC_Q * E.nsys + s] = pq;
-      E.htab[(size_t)T_PC_FOLD * E.nsys + s] = pf;
-      E.htab[(size_t)T_PC_RES * E.nsys + s] = pr;
-      E.htab[(size_t)T_PC_B * E.nsys + s] = pb;
+    if (E.pl.pc) {  // z = P r: rcgR -> vR through the transform scratch
+      SysDev pz = d;
+      pz.active = b.act_cg;
+      pz.fft_tmp = b.fftR;
+      pz.e_in = b.rcgR;
+      pz.e_out = b.vR;
+      SysDev pzr = pz;
+      pzr.active = b.act_ru;
+      E.htab[(size_t)T_PC_Z * E.nsys + s] = pz;
+      E.htab[(size_t)T_PC_ZRU * E.nsys + s] = pzr;
     }
     if (E.pl.fft) {
-      SysDev fm = d;  // inner: u = D v + Y v (v = M0^-1 p when preconditioned)
+      SysDev fm = d;  // inner: u = D p + Y p
       fm.active = b.act_cg;
       fm.fft_tmp = b.fftR;
-      fm.e_in = E.pl.pc ? b.vR : b.pR;
+      fm.e_in = b.pR;
       fm.e_out = b.uR;
       SysDev fmd = fm;  // inner: w = D^dag u + Y^dag u -> v
       fmd.e_in = b.uR;
@@ -1389,7 +1363,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
       ftmd.e_in = b.u64;
       ftmd.e_out = b.r64ms;
       ftmd.cg_r64 = b.r64;
-      ftmd.cg_r = (sizeof(R) == sizeof(double) && !E.pl.pc) ? b.rcgR : nullptr;
+      ftmd.cg_r = (sizeof(R) == sizeof(double)) ? b.rcgR : nullptr;
       E.htab[(size_t)T_F_M * E.nsys + s] = fm;
       E.htab[(size_t)T_F_MD * E.nsys + s] = fmd;
       E.htab[(size_t)T_F_TM * E.nsys + s] = ftm;
@@ -1473,7 +1447,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     SysDev ap = d;  // pack/unpack geometry
     E.htab[(size_t)T_APPLY * E.nsys + s] = ap;
   }
-  TRY(check_roles(E, sizeof(R) == sizeof(double) && !E.pl.pc));
+  TRY(check_roles(E, sizeof(R) == sizeof(double)));
   return upload_tables(E);
 }
 
@@ -1646,15 +1620,11 @@ ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
   return run_graph(E, key, [&]() {
     if (!E.pl.fft)  // per-update maximum of the FP64 multi-shift iteration counts
       k_stat3_clear<<<1, 64, 0, E.st>>>(tab(E, T_TR_M), E.nsys);
-    if (pc) {  // x64 += M0^-1 x~, x~ = 0
-      launch_sym<R>(E, T_PC_FOLD, SYM_M0INV);
-      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_PC_FOLD), E.bmap, E.nb_total, 3);
-    } else {
-      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total, 0);
-    }
+    // x64 += x, x = 0
+    k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total, 0);
     // the residual table: EPI_MDAG_RES (multi-shift) or k_yuk mode 2 (momentum
-    // space) writes r64 (FP64) and, for an unpreconditioned FP64 inner solver,
-    // its copy in cg_r; an FP32 inner solver gets its copy from k_r64_to_r32.
+    // space) writes r64 (FP64) and, for an FP64 inner solver, its copy in cg_r; an
+    // FP32 inner solver gets its copy from k_r64_to_r32.
     const int tres = E.pl.fft ? T_F_TMD : T_TR_MDAG;
     if (E.pl.fft) {
       launch_sym<double>(E, T_F_TM, SYM_D);
@@ -1676,15 +1646,16 @@ ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
       launch_combine<double>(E, T_TR_MDAG, EPI_MDAG_RES);
     }
     if (pc) {
-      // |r64|^2 of the original system, then the recursion restarts from
-      // r~ = M0^-dag r64 with |r~|^2 in the CG state
+      // |r64|^2, then the recursion restarts from r = r64 with z = P r and
+      // rho = <r, z> in the CG state
       k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, tres), E.nsys, 5);
       if (sizeof(R) != sizeof(double))
         k_r64_to_r32<<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total);
-      launch_sym<R>(E, T_PC_RES, SYM_M0INV_DAG);
-      k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_PC_RES), E.bmap, E.nb_total, 4);
-      if (scalar_op == 3 || scalar_op == 7)
-        k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_PC_RES), E.nsys, scalar_op == 3 ? 6 : 8);
+      if (scalar_op == 3 || scalar_op == 7) {
+        launch_sym<R>(E, T_PC_ZRU, SYM_PCG);
+        k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG_RU), E.bmap, E.nb_total, 6);
+        k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, T_CG_RU), E.nsys, scalar_op == 3 ? 11 : 12);
+      }
     } else {
       k_cg_scalar<<<E.nsys, 256, 0, E.st>>>(tab(E, tres), E.nsys, scalar_op);
       if (sizeof(R) != sizeof(double))
@@ -1771,11 +1742,13 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 1);
   k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 4);  // BB
   const bool pc = E.pl.pc;
-  if (pc) {  // the preconditioned recursion starts from b~ = M0^-dag b (Sec. 7.3)
-    launch_sym<R>(E, T_PC_B, SYM_M0INV_DAG);
-    k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 4);
+  if (pc) {  // z = P b, rho = <b, z>, beta = 0
+    launch_sym<R>(E, T_PC_Z, SYM_PCG);
+    k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 6);
+    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 10);
+  } else {
+    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);  // rho = |b|^2, beta = 0
   }
-  k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);  // RR = |b|^2 (|b~|^2), beta = 0
   // |x0|^2 -> part_b via prep on x64 (src = x64 in T_CG)
   k_ms_prep<double><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 0);
   std::vector<double> x0n(ns);
@@ -1789,10 +1762,9 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     x0n[s] = acc;
   }
   TRY(read_scalars(E));
-  // rmax: recursion residual norm at the last restart (of r~ when
-  // preconditioned); kap: |r| / |r~| there, which turns the recursive |r~| into
-  // an estimate of the original residual for the stopping test.
-  std::vector<double> bn(ns), rmax(ns), kap(ns, 1.0);
+  // rmax: residual norm at the last restart (the recursion's |r| is slot CG_R2,
+  // with or without the preconditioner).
+  std::vector<double> bn(ns), rmax(ns);
   std::vector<int> last_ru(ns, 0);  // outer iteration of the last reliable update
   constexpr int kStall = 250;
   out.outer.assign(ns, 0);
@@ -1813,26 +1785,15 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     fru[s] = (x0n[s] > 0.0 && fcg[s]) ? 1 : 0;
     if (fru[s]) any_guess = true;
     rmax[s] = bn[s];
-    if (pc && fcg[s]) {
-      rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RR]);
-      kap[s] = rmax[s] > 0.0 ? bn[s] / rmax[s] : 1.0;
-    }
   }
-  if (any_guess) {  // r = b - A x0 for warm starts
+  if (any_guess) {  // r = b - A x0 for warm starts; the recursion restarts from it
     TRY(set_flags(E, fcg, fru));
-    TRY(reliable_update<R>(E, P.truth_tol, 3));
+    TRY(reliable_update<R>(E, P.truth_tol, 7));
     for (int s = 0; s < ns; ++s)
       if (fru[s]) {
-        const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
-        rmax[s] = rt;
-        if (pc) {
-          rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RYT]);
-          kap[s] = rmax[s] > 0.0 ? rt / rmax[s] : 1.0;
-        }
+        rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
         out.ru[s]++;
       }
-    // restart the recurrence from the true residual
-    k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 0);
   }
   int iter = 0;
   while (true) {
@@ -1851,7 +1812,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       double t = P.inner_tol_max;
       for (int s = 0; s < ns; ++s) {
         if (!fcg[s]) continue;
-        const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_RR];
+        const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_R2];
         const double rn = std::sqrt(std::max(rr, 0.0));
         t = std::min(t, rn > 0.0 ? P.inner_relax * rmax[s] / rn : P.inner_tol_max);
       }
@@ -1870,53 +1831,47 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     char ikey[96];
     std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d|%d|%d|%d", sizeof(R), tol_it, LR, (int)pc,
                   (int)E.pl.fft, (int)E.pl.gw);
-    // p = r + beta p (beta = 0 right after a (re)start) ; M p ; alpha ;
-    // M^dag u with the CG update ; beta -- one captured graph per iteration.
-    // Preconditioned (M~ = M M0^-1): M (M0^-1 p), and M0^-dag (M^dag u) feeds
-    // the update.
+    // p = z + beta p (beta = 0 right after a (re)start; z = P r preconditioned, else
+    // r) ; w = MdagM p ; alpha ; x += alpha p, r -= alpha w ; z = P r ; beta -- one
+    // captured graph per iteration.  Preconditioned CG with P = (M0^dag M0)^-1, a
+    // scalar per momentum: the iterates of CG on (M M0^-1)^dag (M M0^-1) x~ = M0^-dag b,
+    // x = M0^-1 x~ (Sec. 7.3), with one transform per iteration instead of two.
     TRY(run_graph(E, ikey, [&]() {
-      k_cg_p<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 1);
+      const int nb = E.nb_total, bl = c->block;
+      k_cg_p<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);
+      bool fused_update = false;  // EPI_MDAG_CG did the update and the beta scalar
       if (E.pl.fft) {  // momentum-space D: M = D + Y exactly, no inner solve
-        const int nb = E.nb_total, bl = c->block;
-        if (pc) launch_sym<R>(E, T_PC_P, SYM_M0INV);
         launch_sym<R>(E, T_F_M, SYM_D);
         k_yuk<R><<<nb, bl, 0, E.st>>>(tab(E, T_F_M), E.bmap, nb, 0);
         k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_F_M), ns, 1);
         launch_sym<R>(E, T_F_MD, SYM_D_DAG);
         k_yuk<R><<<nb, bl, 0, E.st>>>(tab(E, T_F_MD), E.bmap, nb, 1);
-        if (pc) launch_sym<R>(E, T_PC_Q, SYM_M0INV_DAG);
-        k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);
-        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
-        return;
-      }
-      if (E.pl.gw) {  // w = MdagM v in Ginsparg-Wilson form: both signs in one multi-shift
-        const int nb = E.nb_total, bl = c->block;
-        if (pc) launch_sym<R>(E, T_PC_P, SYM_M0INV);
+      } else if (E.pl.gw) {  // w = MdagM p in Ginsparg-Wilson form: both signs in one multi-shift
         k_gw_prep<R><<<nb, bl, 0, E.st>>>(E.gwtab, E.gwtab + ns, E.bmap, nb);
         launch_ms_tab<R>(E, E.gwtab, E.gwbmap, 2 * nb, 2 * ns, mpR, LR);
         k_gw_combine<R><<<nb, bl, 0, E.st>>>(E.gwtab, E.gwtab + ns, E.bmap, nb);
-        k_cg_scalar<<<ns, 256, 0, E.st>>>(E.gwtab, ns, 1);  // alpha = rr / Re<v, w>
-        if (pc) launch_sym<R>(E, T_PC_Q, SYM_M0INV_DAG);
-        k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);
-        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
-        return;
-      }
-      if (pc) {
-        launch_sym<R>(E, T_PC_P, SYM_M0INV);
-        k_ms_prep<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_IN_M), E.bmap, E.nb_total, 0);
-      }
-      launch_ms<R>(E, T_IN_M, mpR, LR);
-      launch_combine<R>(E, T_IN_M, EPI_M);
-      k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
-      launch_ms<R>(E, T_IN_MDAG, mpR, LR);
-      if (pc) {
-        launch_combine<R>(E, T_IN_MDAG, EPI_MDAG);
-        launch_sym<R>(E, T_PC_Q, SYM_M0INV_DAG);
-        k_cg_misc<R><<<E.nb_total, c->block, 0, E.st>>>(tab(E, T_CG), E.bmap, E.nb_total, 5);
-        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(E.gwtab, ns, 1);  // alpha = rho / Re<p, w>
       } else {
-        launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
-        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+        launch_ms<R>(E, T_IN_M, mpR, LR);
+        launch_combine<R>(E, T_IN_M, EPI_M);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_M), ns, 1);
+        launch_ms<R>(E, T_IN_MDAG, mpR, LR);
+        if (pc) {
+          launch_combine<R>(E, T_IN_MDAG, EPI_MDAG);
+        } else {
+          launch_combine<R>(E, T_IN_MDAG, EPI_MDAG_CG);
+          k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_IN_MDAG), ns, 2);
+          fused_update = true;
+        }
+      }
+      if (fused_update) return;
+      k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);
+      if (pc) {
+        launch_sym<R>(E, T_PC_Z, SYM_PCG);
+        k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 6);
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 9);
+      } else {
+        k_cg_scalar<<<ns, 256, 0, E.st>>>(tab(E, T_CG), ns, 2);
       }
     }));
     TRY(read_scalars(E));
@@ -1939,7 +1894,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       for (int s = 0; s < ns; ++s)
         if (fcg[s])
           std::fprintf(stderr, " s%d rec=%.3e pap=%.3e", s,
-                       kap[s] * std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RR]) / bn[s],
+                       std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_R2]) / bn[s],
                        c->pinned[(size_t)s * CG_NSLOT + CG_PAP]);
       std::fprintf(stderr, "\n");
     }
@@ -1947,12 +1902,13 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       if (!fcg[s]) continue;
       out.outer[s]++;
       const double* cs = c->pinned + (size_t)s * CG_NSLOT;
-      const double rr = cs[CG_RR];
-      if (!std::isfinite(rr) || !std::isfinite(cs[CG_ALPHA]) || cs[CG_PAP] <= 0.0) {
+      const double rr = cs[CG_R2];
+      if (!std::isfinite(rr) || !std::isfinite(cs[CG_RR]) || !std::isfinite(cs[CG_ALPHA]) ||
+          cs[CG_PAP] <= 0.0 || cs[CG_RR] < 0.0) {
         c->err = "CG breakdown (non-finite or non-positive scalar)";
         return OV_ERR_BREAKDOWN;
       }
-      const double rec = kap[s] * std::sqrt(rr) / bn[s];
+      const double rec = std::sqrt(rr) / bn[s];
       const bool at_target = rec <= P.outer_tol;
       const bool dropped = delta > 0.0 && std::sqrt(rr) < delta * rmax[s];
       // a recursion that has not dropped by delta for kStall iterations has
@@ -1974,10 +1930,10 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
       const double half = std::sqrt(delta);
       for (int s = 0; s < ns; ++s) {
         if (!fcg[s] || fru[s]) continue;
-        const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_RR];
+        const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_R2];
         if (std::sqrt(rr) < half * rmax[s]) {
           fru[s] = 1;
-          best_rec = std::min(best_rec, kap[s] * std::sqrt(rr) / bn[s]);
+          best_rec = std::min(best_rec, std::sqrt(rr) / bn[s]);
         }
       }
     }
@@ -1995,10 +1951,6 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         last_ru[s] = iter;
         const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
         rmax[s] = rt;
-        if (pc) {
-          rmax[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RYT]);
-          kap[s] = rmax[s] > 0.0 ? rt / rmax[s] : 1.0;
-        }
         out.res[s] = rt / bn[s];
         if (ov_log())
           std::fprintf(stderr, "[ov] reliable update s%d at iter %d: true res %.3e (ms tol %.1e)\n",
