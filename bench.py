@@ -541,8 +541,12 @@ def main():
         for name, kw in (("fp64_p1", dict(inner_tol=1e-12, reliable_delta=0.0, inner_relax=0.0)),
                          ("fp64_p2", dict(inner_tol=1e-8, reliable_delta=0.1, inner_relax=0.0)),
                          ("fp64_p3", dict(inner_tol=1e-8)),
-                         ("fp64_p3_unpreconditioned", dict(inner_tol=1e-8, precondition=0)),
-                         ("mixed_unpreconditioned", dict(precision="mixed", precondition=0))):
+                         # without the preconditioner CG on MdagM converges unevenly and
+                         # long FP32 cycles lose accuracy: reliable updates every 100x
+                         ("fp64_p3_unpreconditioned", dict(inner_tol=1e-8, precondition=0,
+                                                           reliable_delta=0.01, inner_relax=1e-3)),
+                         ("mixed_unpreconditioned", dict(precision="mixed", precondition=0,
+                                                         reliable_delta=0.01, inner_relax=1e-3))):
             cfg = dict(CFG, precision="fp64")
             cfg.update(kw)
             l64 = Lattice(DIMS, **cfg)

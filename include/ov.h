@@ -102,11 +102,20 @@ typedef struct {
   double outer_tol;        /* solve stop: true ||b - MdagM x|| / ||b|| */
   double truth_tol;        /* FP64 multi-shift tolerance of true residuals (1e-12) */
   double mixed_inner_tol;  /* FP32 multi-shift tolerance of the mixed solver */
-  double reliable_delta;   /* reliable update when ||r|| drops below delta * ||r_true|| */
+  double reliable_delta;   /* reliable update when ||r|| drops below delta * ||r_true||
+                              (default 3e-4, for the preconditioned solver; without the
+                              preconditioner 0.01 with inner_relax 1e-3 converges in
+                              about half the iterations); also, in preconditioned solves,
+                              at a stagnating recursion (no new
+                              minimum of ||r|| in 8 iterations, or under a quarter of the
+                              decades its best 8-iteration window gained), and a relaxed
+                              inner sign is tightened tenfold for a system whose true
+                              residual comes back 10x above the recursive one */
   int max_inner;           /* multi-shift iteration cap (<= basis capacity) */
   int max_outer;           /* outer CG iteration cap */
   ov_precision precision;  /* OV_FP64 or OV_MIXED for ov_solve / ov_force */
-  double inner_relax;      /* inexact-Krylov relaxation of the solver's inner sign:
+  double inner_relax;      /* inexact-Krylov relaxation of the solver's inner sign
+                              (default 3e-4):
                               tol_j = inner_relax * ||r_cycle|| / ||r_j||, clamped to
                               [inner tolerance, inner_tol_max]; 0 keeps it fixed */
   double inner_tol_max;    /* loosest inner multi-shift tolerance the relaxation uses */
@@ -152,6 +161,12 @@ typedef struct {
   double max_shift_res;    /* max_k |zeta_k| ||r|| / ||src|| of the last multi-shift */
   double seconds;          /* wall time of the call (host clock, stream synchronised) */
   double model_bytes;      /* algorithmic HBM bytes moved (byte model) */
+  int stagnations;         /* reliable updates forced by a recursion that made no progress
+                              for 8 iterations (restarted with p = z) */
+  int fp64_fallback;       /* 1: the mixed solve's true residual fell by less than half in
+                              two reliable-update cycles in a row, and the FP64 solver (fixed
+                              inner tolerance inner_tol, no relaxation) finished the system
+                              from the mixed iterate (ov_force: solved again in FP64) */
 } ov_stats;
 
 typedef struct ov_ctx ov_ctx;

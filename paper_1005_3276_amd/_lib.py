@@ -49,7 +49,8 @@ class OvStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("reliable_updates", C.c_int),
                 ("inner_iters", C.c_longlong), ("stencil_apps", C.c_longlong),
                 ("true_rel_res", C.c_double), ("max_shift_res", C.c_double),
-                ("seconds", C.c_double), ("model_bytes", C.c_double)]
+                ("seconds", C.c_double), ("model_bytes", C.c_double),
+                ("stagnations", C.c_int), ("fp64_fallback", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -102,6 +102,13 @@ thread_local std::string g_err;
     if (s_ != OV_OK) return s_; \
   } while (0)
 
+// Test hook: every mixed solve hands its systems to the FP64 solver at the first
+// reliable update (exercises the stagnation fallback).
+bool force_fallback_env() {
+  const char* e = std::getenv("OV_FORCE_FALLBACK");
+  return e && *e == '1';
+}
+
 bool ov_log() {
   static int v = -1;
   if (v < 0) {
@@ -382,6 +389,11 @@ struct Engine {
   std::vector<int> last_flags;      // last uploaded flags (upload only on change)
   MsParams mp64{}, mpR{};
   int L64 = 0, LR = 0;              // multi-shift launch counts
+  bool no_relax = false;            // fixed inner tolerance (the FP64 fallback solver)
+  int max_outer = 0;                // > 0: outer iteration cap instead of max_outer (the
+                                    // fallback solver gets what the mixed one left)
+  bool force_fallback = false;      // hand every system to the FP64 solver at its first
+                                    // reliable update (OV_FORCE_FALLBACK=1; tests)
   int nb_xy = 0, nb_z = 0, nb_t = 0;  // workgroups of the momentum-space passes
   SysDev* ftab = nullptr;           // device: (system, shift) table of the rational force
   SysDev* gwtab = nullptr;          // device: 2 nsys multi-shift entries of the GW inner operator
@@ -1717,6 +1729,8 @@ struct SolveOut {
   std::vector<int> outer, ru;
   std::vector<double> res;
   std::vector<int> conv;
+  std::vector<int> stag;      // restarts forced by a stagnating recursion
+  std::vector<int> fallback;  // mixed solve handed to the FP64 solver (stagnating cycles)
 };
 
 // Reliable-update CG on MdagM x = b.  Inner iterations run in precision R with
@@ -1733,6 +1747,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   ov_ctx* c = E.lead;
   const ov_params& P = c->p;
   const int ns = E.nsys;
+  const int max_outer = E.max_outer > 0 ? E.max_outer : P.max_outer;
   TRY((build_solve_tables<R>(E, bvec, phi)));
   TRY(reset_stats(E));
   std::vector<int> fcg(ns, 1), fru(ns, 1);
@@ -1766,11 +1781,33 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   // with or without the preconditioner).
   std::vector<double> bn(ns), rmax(ns);
   std::vector<int> last_ru(ns, 0);  // outer iteration of the last reliable update
-  constexpr int kStall = 250;
+  // Stagnation.  Within a cycle: a recursion that has not dropped by delta in kStall
+  // iterations, or, under a relaxed (inexact) inner sign in a preconditioned solve,
+  // has made no new minimum of
+  // |r| for kStagnate iterations or gained less than kCrawl of the decades its best
+  // kStagnate-iteration window of this solve gained -> reliable update and restart.  At an update: a true
+  // residual more than 10x the recursive one (the inexact sign's error has decoupled
+  // the recursion) tightens that system's relaxation tenfold.  Across cycles: a true
+  // residual that fell by less than half since the last update, kCycleStag times in a
+  // row -> a mixed solve hands the system to the FP64 solver (fixed inner tolerance).
+  constexpr int kStall = 250, kStagnate = 8, kCycleStag = 2;
+  constexpr double kCrawl = 0.25;
+  const bool relaxed = !E.pl.fft && P.inner_relax > 0.0 && !E.no_relax;
+  // the within-cycle checks need an even convergence rate: preconditioned solves only
+  // (unpreconditioned CG on MdagM has plateaus that a restart would throw away)
+  const bool watch = relaxed && E.pl.pc;
+  std::vector<double> rbest(ns, 1e300), rt_prev(ns, 0.0), rec_last(ns, 1.0);
+  std::vector<double> relax_scale(ns, 1.0);
+  std::vector<int> it_best(ns, 0), nstag(ns, 0);
+  std::vector<std::vector<double>> hist(ns);  // recursive |r| since the last update
+  std::vector<double> gain_best(ns, 0.0);     // most decades gained in kStagnate iterations
+  const bool can_fall_back = sizeof(R) != sizeof(double);
   out.outer.assign(ns, 0);
   out.ru.assign(ns, 0);
   out.res.assign(ns, 1.0);
   out.conv.assign(ns, 0);
+  out.stag.assign(ns, 0);
+  out.fallback.assign(ns, 0);
   bool any_guess = false;
   for (int s = 0; s < ns; ++s) {
     bn[s] = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_BB]);
@@ -1808,13 +1845,14 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     // van den Eshof & Sleijpen's inexact-Krylov bound); the tightest system
     // sets it, rounded down to a power of ten.
     double tol_it = tol_in;
-    if (P.inner_relax > 0.0) {
+    if (P.inner_relax > 0.0 && !E.no_relax) {
       double t = P.inner_tol_max;
       for (int s = 0; s < ns; ++s) {
         if (!fcg[s]) continue;
         const double rr = c->pinned[(size_t)s * CG_NSLOT + CG_R2];
         const double rn = std::sqrt(std::max(rr, 0.0));
-        t = std::min(t, rn > 0.0 ? P.inner_relax * rmax[s] / rn : P.inner_tol_max);
+        t = std::min(t, rn > 0.0 ? P.inner_relax * relax_scale[s] * rmax[s] / rn
+                                 : P.inner_tol_max);
       }
       tol_it = std::max(tol_in, std::pow(10.0, std::floor(std::log10(t) + 1e-9)));
     }
@@ -1909,16 +1947,36 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         return OV_ERR_BREAKDOWN;
       }
       const double rec = std::sqrt(rr) / bn[s];
+      rec_last[s] = rec;
       const bool at_target = rec <= P.outer_tol;
       const bool dropped = delta > 0.0 && std::sqrt(rr) < delta * rmax[s];
-      // a recursion that has not dropped by delta for kStall iterations has
-      // stalled (lost conjugacy in the inner precision): update and restart
-      const bool stalled = delta > 0.0 && iter - last_ru[s] >= kStall;
-      if (stalled) restart = true;
-      if (at_target || dropped || stalled || iter >= P.max_outer) {
+      if (std::sqrt(rr) < rbest[s]) {
+        rbest[s] = std::sqrt(rr);
+        it_best[s] = iter;
+      }
+      hist[s].push_back(std::sqrt(rr));
+      const size_t nh = hist[s].size();
+      bool crawling = false;
+      if (watch && nh > (size_t)kStagnate && hist[s][nh - 1] > 0.0) {
+        // decades the recursion gained over the last kStagnate iterations, against the
+        // best such window of this solve: far slower than before is a crawl
+        const double gain = std::log10(hist[s][nh - 1 - kStagnate] / hist[s][nh - 1]);
+        crawling = gain < kCrawl * gain_best[s];
+        gain_best[s] = std::max(gain_best[s], gain);
+      }
+      // a recursion that has made no progress for kStagnate iterations, or has not
+      // dropped by delta in kStall, has stalled (lost conjugacy in the inner precision
+      // or under the inexact inner sign): update and restart
+      const bool stalled = delta > 0.0 && ((watch && iter - it_best[s] >= kStagnate) ||
+                                           crawling || iter - last_ru[s] >= kStall);
+      if (stalled) {
+        restart = true;
+        out.stag[s]++;
+      }
+      if (at_target || dropped || stalled || iter >= max_outer) {
         fru[s] = 1;
         need_ru = true;
-        if (at_target || iter >= P.max_outer) final_check = true;
+        if (at_target || iter >= max_outer) final_check = true;
         best_rec = std::min(best_rec, rec);
       }
     }
@@ -1950,20 +2008,32 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         out.ru[s]++;
         last_ru[s] = iter;
         const double rt = std::sqrt(c->pinned[(size_t)s * CG_NSLOT + CG_RTRUE]);
+        if (relaxed && rt > 10.0 * rec_last[s] * bn[s]) relax_scale[s] *= 0.1;
+        // cycles whose true residual fell by less than half
+        nstag[s] = (rt_prev[s] > 0.0 && rt > 0.5 * rt_prev[s]) ? nstag[s] + 1 : 0;
+        rt_prev[s] = rt;
         rmax[s] = rt;
+        rbest[s] = rt;
+        it_best[s] = iter;
+        hist[s].clear();
         out.res[s] = rt / bn[s];
         if (ov_log())
-          std::fprintf(stderr, "[ov] reliable update s%d at iter %d: true res %.3e (ms tol %.1e)\n",
-                       s, iter, out.res[s], ttol);
+          std::fprintf(stderr,
+                       "[ov] reliable update s%d at iter %d: true res %.3e (ms tol %.1e, %d "
+                       "FP64 multi-shift iterations)\n",
+                       s, iter, out.res[s], ttol, last_truth_iters(E));
         if (out.res[s] <= P.outer_tol) {
           // a momentum-space operator is exact at every tolerance
           if (E.pl.fft || ttol <= P.truth_tol * 1.0000001) {
             out.conv[s] = 1;
             fcg[s] = 0;
           }
+        } else if (can_fall_back && (nstag[s] >= kCycleStag || E.force_fallback)) {
+          out.fallback[s] = 1;  // x64 holds the best iterate; the FP64 solver finishes
+          fcg[s] = 0;
         }
       }
-      if (iter >= P.max_outer) break;
+      if (iter >= max_outer) break;
     }
   }
   return OV_OK;
@@ -2088,6 +2158,7 @@ void fill_stats(ov_stats* st, int n, Engine* E, const SolveOut* so, double secs,
       o.outer_iters = so->outer[s];
       o.reliable_updates = so->ru[s];
       o.true_rel_res = so->res[s];
+      o.stagnations = so->stag.empty() ? 0 : so->stag[s];
     }
     o.seconds = secs;
   }
@@ -2154,11 +2225,11 @@ void ov_params_default(ov_params* p) {
   p->outer_tol = 1e-10;
   p->truth_tol = 1e-13;
   p->mixed_inner_tol = 1e-6;
-  p->reliable_delta = 0.01;
+  p->reliable_delta = 3e-4;
   p->max_inner = 400;
   p->max_outer = 2000;
   p->precision = OV_MIXED;
-  p->inner_relax = 1e-3;
+  p->inner_relax = 3e-4;
   p->inner_tol_max = 1e-2;
   p->precondition = 1;
   p->truth_relax = 0.01;
@@ -2283,7 +2354,11 @@ size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
   const size_t solve = plan_bytes(c, nrhs, true, c->p.precision == OV_MIXED, solve_tol64(c),
                                   solve_tolR(c), 0);
   const size_t apply = plan_bytes(c, nrhs, false, false, c->p.inner_tol, c->p.inner_tol, 0);
-  return std::max(solve, apply);
+  // a mixed solve whose cycles stagnate is finished by the FP64 solver
+  const size_t fallback = c->p.precision == OV_MIXED
+                              ? plan_bytes(c, nrhs, true, false, solve_tol64(c), c->p.inner_tol, 0)
+                              : 0;
+  return std::max(std::max(solve, apply), fallback);
 }
 
 size_t ov_workspace_bytes_rational(const ov_ctx* c, int nrhs, int nshift) {
@@ -2426,15 +2501,15 @@ static bool same_solver(const ov_params& a, const ov_params& b) {
 
 static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const void*>& bv,
                                std::vector<void*>& xv, std::vector<const void*>& phv,
-                               ov_stats* st, Engine* keep = nullptr) {
+                               ov_stats* st) {
   ov_ctx* c = sysctx[0];
   const double t0 = now_s();
   const bool mixed = c->p.precision == OV_MIXED;
   const double tolR = mixed ? c->p.mixed_inner_tol : c->p.inner_tol;
-  Engine Eloc;
-  Engine& E = keep ? *keep : Eloc;
+  Engine E;
   TRY(engine_init(E, sysctx, true, mixed, solve_tol64(c), tolR));
   const int ns = E.nsys;
+  E.force_fallback = mixed && force_fallback_env();
   // pack the guesses into x64 (needs a geometry table)
   E.htab.assign((size_t)T_NT * ns, SysDev{});
   for (int s = 0; s < ns; ++s) E.htab[(size_t)T_APPLY * ns + s] = base_dev(E.sb[s]);
@@ -2457,6 +2532,64 @@ static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const v
   TRY(sync(E));
   fill_stats(st, ns, &E, &so, now_s() - t0, mixed ? 8 : 16);
   if (rc != OV_OK) return rc;  // x holds the best iterate; err says why
+  // Systems whose mixed-precision cycles stagnated: the FP64 solver (fixed inner
+  // tolerance inner_tol, no relaxation) finishes them from the iterate just written to x.
+  std::vector<int> fb;
+  int used = 0;  // outer iterations the mixed solver spent on the systems handed over
+  for (int s = 0; s < ns; ++s)
+    if (so.fallback[s]) {
+      fb.push_back(s);
+      used = std::max(used, so.outer[s]);
+    }
+  if (!fb.empty() && used < c->p.max_outer) {
+    if (ov_log()) std::fprintf(stderr, "[ov] %zu system(s) handed to the FP64 solver\n", fb.size());
+    std::vector<ov_ctx*> c2;
+    std::vector<const void*> b2, p2, x2in;
+    std::vector<void*> x2;
+    for (int s : fb) {
+      c2.push_back(sysctx[s]);
+      b2.push_back(bv[s]);
+      p2.push_back(phv[s]);
+      x2.push_back(xv[s]);
+      x2in.push_back(xv[s]);
+    }
+    Engine F;
+    TRY(engine_init(F, c2, true, false, solve_tol64(c), c->p.inner_tol));
+    F.no_relax = true;
+    F.max_outer = c->p.max_outer - used;
+    F.htab.assign((size_t)T_NT * F.nsys, SysDev{});
+    for (int k = 0; k < F.nsys; ++k) F.htab[(size_t)T_APPLY * F.nsys + k] = base_dev(F.sb[k]);
+    TRY(upload_tables(F));
+    std::vector<void*> fx(F.nsys);
+    for (int k = 0; k < F.nsys; ++k) fx[k] = F.sb[k].x64;
+    TRY(pack64(F, x2in, fx));
+    SolveOut so2;
+    rc = solve_engine<double>(F, b2, p2, c->p.inner_tol, delta, so2);
+    if (rc != OV_OK && rc != OV_ERR_NOT_CONVERGED) return rc;
+    TRY(unpack64(F, fx, x2));
+    TRY(sync(F));
+    std::vector<ov_stats> st2(F.nsys);
+    fill_stats(st2.data(), F.nsys, &F, &so2, now_s() - t0, 16);
+    for (int k = 0; k < F.nsys; ++k) {
+      const int s = fb[k];
+      so.conv[s] = so2.conv[k];
+      so.res[s] = so2.res[k];
+      if (st) {
+        st[s].outer_iters += st2[k].outer_iters;
+        st[s].reliable_updates += st2[k].reliable_updates;
+        st[s].inner_iters += st2[k].inner_iters;
+        st[s].stencil_apps += st2[k].stencil_apps;
+        st[s].model_bytes += st2[k].model_bytes;
+        st[s].true_rel_res = st2[k].true_rel_res;
+        st[s].max_shift_res = st2[k].max_shift_res;
+        st[s].stagnations += so2.stag[k];
+        st[s].fp64_fallback = 1;
+      }
+    }
+    if (st)
+      for (int s = 0; s < ns; ++s) st[s].seconds = now_s() - t0;
+    if (rc != OV_OK) return rc;
+  }
   for (int s = 0; s < ns; ++s)
     if (!so.conv[s]) {
       c->err = "outer CG did not reach outer_tol within max_outer";
@@ -2513,21 +2646,43 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
   std::vector<const void*> bv(nrhs), ph(nrhs, phi);
   std::vector<void*> xv(nrhs);
   // X = (MdagM)^-1 xi, cold start, kept in the engine's x64 buffers
+  const bool mixed = c->p.precision == OV_MIXED;
   Engine E;
-  TRY(engine_init(E, sc, true, c->p.precision == OV_MIXED,
-                  std::min(c->p.inner_tol, c->p.truth_tol),
-                  c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol));
+  TRY(engine_init(E, sc, true, mixed, std::min(c->p.inner_tol, c->p.truth_tol),
+                  mixed ? c->p.mixed_inner_tol : c->p.inner_tol));
+  E.force_fallback = mixed && force_fallback_env();
   // zero guess directly in x64
   for (int r = 0; r < nrhs; ++r) {
     bv[r] = (const char*)xi + r * vb;
     zero_dev(E, E.sb[r].x64, vb);
   }
   SolveOut so;
-  const double tolR = c->p.precision == OV_MIXED ? c->p.mixed_inner_tol : c->p.inner_tol;
-  ov_status rc = c->p.precision == OV_MIXED
-                     ? solve_engine<float>(E, bv, ph, tolR, c->p.reliable_delta, so)
-                     : solve_engine<double>(E, bv, ph, tolR, c->p.reliable_delta, so);
+  const double tolR = mixed ? c->p.mixed_inner_tol : c->p.inner_tol;
+  ov_status rc = mixed ? solve_engine<float>(E, bv, ph, tolR, c->p.reliable_delta, so)
+                       : solve_engine<double>(E, bv, ph, tolR, c->p.reliable_delta, so);
   if (rc != OV_OK) return rc;
+  bool fell_back = false;
+  for (int r = 0; r < nrhs; ++r) fell_back |= so.fallback[r] != 0;
+  if (fell_back) {
+    // the force's FP64 solve starts cold: it gets the whole max_outer
+    // a stagnating mixed solve: the FP64 solver (fixed inner tolerance) solves again
+    // from a cold start in an engine of its own (X must sit in that engine's buffers)
+    if (ov_log()) std::fprintf(stderr, "[ov] force solve handed to the FP64 solver\n");
+    E = Engine{};
+    TRY(engine_init(E, sc, true, false, std::min(c->p.inner_tol, c->p.truth_tol),
+                    c->p.inner_tol));
+    E.no_relax = true;
+    for (int r = 0; r < nrhs; ++r) zero_dev(E, E.sb[r].x64, vb);
+    SolveOut so2;
+    rc = solve_engine<double>(E, bv, ph, c->p.inner_tol, c->p.reliable_delta, so2);
+    if (rc != OV_OK) return rc;
+    for (int r = 0; r < nrhs; ++r) {
+      so2.outer[r] += so.outer[r];
+      so2.ru[r] += so.ru[r];
+      so2.stag[r] += so.stag[r];
+    }
+    so = so2;
+  }
   for (int r = 0; r < nrhs; ++r)
     if (!so.conv[r]) {
       c->err = "force solve did not converge";
@@ -2579,7 +2734,9 @@ ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, co
     for (double v : tmp) acc += v;
     S_host[s] = acc;
   }
-  fill_stats(st, nrhs, &E, &so, now_s() - t0, c->p.precision == OV_MIXED ? 8 : 16);
+  fill_stats(st, nrhs, &E, &so, now_s() - t0, (mixed && !fell_back) ? 8 : 16);
+  if (st && fell_back)
+    for (int r = 0; r < nrhs; ++r) st[r].fp64_fallback = 1;
   return OV_OK;
 }
 

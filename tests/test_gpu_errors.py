@@ -168,3 +168,50 @@ def test_graph_cache_equal_volume_members(orc, monkeypatch):
             assert np.array_equal(bits(a), bits(g)), dims
         o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
         assert o.residual(src[0], xg[1][0], phi) <= 1e-10
+
+
+@pytest.mark.timeout(300)
+def test_fp64_fallback_forced(orc, monkeypatch):
+    """OV_FORCE_FALLBACK=1 hands every mixed system to the FP64 solver at its first
+    reliable update (the path a stagnating mixed solve takes): ov_solve finishes from the
+    mixed iterate, ov_force solves again in FP64; both certified under the oracle and
+    flagged in the stats."""
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=inputs.config_seed(2) + 31)
+    b, p = dev(src), dev(phi)
+    kw = dict(outer_tol=1e-10, **CFG2)
+    lat = lattice(dims, precision="mixed", **kw)
+    x_ref, st_ref = lat.solve(b, p)
+    assert all(s["fp64_fallback"] == 0 for s in st_ref)
+    monkeypatch.setenv("OV_FORCE_FALLBACK", "1")
+    x, st = lat.solve(b, p)
+    print(f"[fallback] solve {st}", flush=True)
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    for r in range(2):
+        assert st[r]["fp64_fallback"] == 1
+        assert o.residual(src[r], host(x)[r], phi) <= 1e-10
+    check(host(x), host(x_ref), 1e-7, "fallback vs mixed solution")
+    S, G, stf = lat.force(b[:1], p)
+    print(f"[fallback] force {stf}", flush=True)
+    assert stf[0]["fp64_fallback"] == 1
+    monkeypatch.setenv("OV_FORCE_FALLBACK", "0")
+    S0, G0, st0 = lat.force(b[:1], p)
+    assert st0[0]["fp64_fallback"] == 0
+    assert abs(S[0] - S0[0]) <= 1e-9 * abs(S0[0])
+    check(host(G), host(G0), 1e-7, "force after fallback")
+
+
+@pytest.mark.timeout(300)
+def test_loose_inner_sign_still_certified(orc):
+    """A mixed solve whose inner sign is held at tolerance 0.1 throughout (relaxation
+    clamped at inner_tol_max = 0.5): the recursion follows the wrong operator, the
+    reliable updates and the stagnation checks still bring the true residual to 1e-10
+    under the oracle's operator."""
+    dims = (8, 8, 8, 8)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2) + 32)
+    lat = lattice(dims, precision="mixed", outer_tol=1e-10, inner_relax=10.0, inner_tol_max=0.5,
+                  max_outer=400, **CFG2)
+    x, st = lat.solve(dev(src), dev(phi))
+    print(f"[loose] {st}", flush=True)
+    o = orc.Oracle(dims, inner_tol=1e-13, **CFG2)
+    assert o.residual(src[0], host(x)[0], phi) <= 1e-10
