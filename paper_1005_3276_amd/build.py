@@ -28,7 +28,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    srcs = [("ov_lib.hip", True), ("ov_zolotarev.cpp", False)]
+    srcs = [("ov_lib.hip", True), ("ov_zolotarev.cpp", False), ("ov_host.cpp", False)]
     for name, device in srcs:
         src = os.path.join(CSRC, name)
         obj = os.path.join(build_dir, name + ".o")
@@ -40,7 +40,8 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    link = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", SO + ".tmp"] + objs
+    link = ([cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", SO + ".tmp"] + objs +
+            ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

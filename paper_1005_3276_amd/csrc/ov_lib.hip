@@ -4,6 +4,7 @@
 //   kernels (ov_kernels.hpp)  -> Engine (batched systems, tables, launch
 //   sequences for sign / apply / solve / force)  -> extern "C" ov_* (ov.h).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -17,13 +18,11 @@
 #include <vector>
 
 #include "../../include/ov.h"
+#include "ov_host.hpp"
 #include "ov_kernels.hpp"
 
-namespace ov {
-int zolotarev_coeffs(int n, double lmin, double lmax, double* a, double* b, double* delta);
-}
-
 using namespace ov;
+static_assert(ov::HOST_MAXP == ov::MAXP, "host and kernel pole limits");
 
 struct ov_ctx {
   ov_params p;
@@ -109,6 +108,15 @@ bool force_fallback_env() {
   return e && *e == '1';
 }
 
+// ROCTX range for the life of a scope: the phases of a call show up in a marker trace
+// (rocprofv3 --marker-trace); without a tool attached the calls return at once.
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 bool ov_log() {
   static int v = -1;
   if (v < 0) {
@@ -133,16 +141,6 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Iterations CG on H_W^2 needs, in the worst case, to bring every shifted
-// residual |zeta_k| |r| below tol |src|: Chebyshev bound with kappa =
-// (smax/smin)^2 and the sqrt(kappa) factor between error and residual norms.
-int cg_bound(double smin, double smax, double tol) {
-  const double kap = (smax / smin) * (smax / smin);
-  const double sk = std::sqrt(kap);
-  const double q = (sk - 1.0) / (sk + 1.0);
-  if (q <= 0.0) return 2;
-  return (int)std::ceil(std::log(2.0 * sk / tol) / std::log(1.0 / q));
-}
 
 int capacity(const ov_ctx* c, double tol) {
   const int cap = cg_bound(c->smin, c->smax, tol) + 6;
@@ -352,15 +350,6 @@ int pick_xc(int X, int T) {
 }
 
 // Lattices the momentum-space kernels handle (LDS tiles of <= 1024 complex values).
-bool fft_ok(const ov_params* p, std::string& why) {
-  const int X = p->dims[0], Y = p->dims[1], Z = p->dims[2], T = p->dims[3];
-  if (X > 64 || Y > 64 || Z > 64 || T > 64 || X * Y > 1024 || X * Z > 1024) {
-    why = "momentum-space kernels need every extent <= 64, X*Y <= 1024 and X*Z <= 1024";
-    return false;
-  }
-  return true;
-}
-
 // A batch of systems sharing poles, tolerances and precision.
 struct Engine {
   std::vector<ov_ctx*> ctxs;        // per system
@@ -1685,6 +1674,7 @@ ov_status reliable_update_L(Engine& E, double tol, int scalar_op, int L) {
 template <class R>
 ov_status reliable_update(Engine& E, double tol, int scalar_op) {
   ov_ctx* c = E.lead;
+  Range range("ov reliable update (FP64 true residual)");
   tol = std::pow(10.0, std::floor(std::log10(tol) + 1e-9));
   int Lfull = 0;
   for (int s = 0; s < E.nsys; ++s)
@@ -1748,6 +1738,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   const ov_params& P = c->p;
   const int ns = E.nsys;
   const int max_outer = E.max_outer > 0 ? E.max_outer : P.max_outer;
+  Range range(sizeof(R) == sizeof(double) ? "ov solve engine FP64" : "ov solve engine mixed");
   TRY((build_solve_tables<R>(E, bvec, phi)));
   TRY(reset_stats(E));
   std::vector<int> fcg(ns, 1), fru(ns, 1);
@@ -1874,6 +1865,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     // captured graph per iteration.  Preconditioned CG with P = (M0^dag M0)^-1, a
     // scalar per momentum: the iterates of CG on (M M0^-1)^dag (M M0^-1) x~ = M0^-dag b,
     // x = M0^-1 x~ (Sec. 7.3), with one transform per iteration instead of two.
+    Range it_range("ov CG iteration");
     TRY(run_graph(E, ikey, [&]() {
       const int nb = E.nb_total, bl = c->block;
       k_cg_p<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);
@@ -2039,104 +2031,6 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   return OV_OK;
 }
 
-ov_status validate(const ov_params* p, std::string& err) {
-  for (int d = 0; d < 4; ++d)
-    if (p->dims[d] < 2 || (p->dims[d] & 1)) {
-      err = "every extent must be even and >= 2";
-      return OV_ERR_INVALID_ARG;
-    }
-  const long long V = (long long)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
-  if (V > (1LL << 28)) {
-    err = "lattice too large";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->bc_t != 1 && p->bc_t != -1) {
-    err = "bc_t must be +1 or -1";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->n_poles < 1 || p->n_poles > MAXP) {
-    err = "n_poles must be in 1..32";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (!(p->lambda_min > 0) || !(p->lambda_max > p->lambda_min)) {
-    err = "need 0 < lambda_min < lambda_max";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (!(p->inner_tol > 0) || !(p->outer_tol > 0) || !(p->truth_tol > 0) ||
-      !(p->mixed_inner_tol > 0) || p->reliable_delta < 0 || p->reliable_delta >= 1) {
-    err = "tolerances must be positive (0 <= reliable_delta < 1)";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->inner_relax < 0 || !(p->inner_tol_max > 0) || p->inner_tol_max >= 1) {
-    err = "need inner_relax >= 0 and 0 < inner_tol_max < 1";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->max_inner < 4 || p->max_outer < 1) {
-    err = "max_inner >= 4 and max_outer >= 1 required";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->precision != OV_FP64 && p->precision != OV_MIXED) {
-    err = "precision must be OV_FP64 or OV_MIXED";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (!(p->truth_relax > 0) || p->truth_relax > 1) {
-    err = "need 0 < truth_relax <= 1";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->pc_mass != 0 && p->pc_mass != 1) {
-    err = "pc_mass must be 0 or 1";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->inner_form != 0 && p->inner_form != 1) {
-    err = "inner_form must be 0 or 1";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->precondition != 0 && p->precondition != 1) {
-    err = "precondition must be 0 or 1";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->precondition && !fft_ok(p, err)) {
-    err += " (set precondition = 0 for larger lattices)";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->dirac < OV_DIRAC_OVERLAP_MS || p->dirac > OV_DIRAC_DSLASH) {
-    err = "dirac must be one of OV_DIRAC_*";
-    return OV_ERR_INVALID_ARG;
-  }
-  if (p->dirac != OV_DIRAC_OVERLAP_MS && !fft_ok(p, err)) return OV_ERR_INVALID_ARG;
-  if (p->dirac == OV_DIRAC_DSLASH && p->bc_t != -1) {
-    err = "Dslash needs antiperiodic time (1 - D/2 is singular at the doublers otherwise)";
-    return OV_ERR_INVALID_ARG;
-  }
-  return OV_OK;
-}
-
-// free |H_W| spectrum on the lattice: s(p)^2 = sum sin^2 p + (M0' )^2 with
-// the Wilson mass term 4 - M0 - sum cos p (antiperiodic time: p_t = (2n+1) pi/T)
-void free_spectrum(const ov_params* p, double& smin, double& smax) {
-  smin = 1e300;
-  smax = 0;
-  std::vector<double> cx[4], sx[4];
-  for (int d = 0; d < 4; ++d) {
-    const int L = p->dims[d];
-    for (int n = 0; n < L; ++n) {
-      double ph = 2.0 * M_PI * n / L;
-      if (d == 3 && p->bc_t < 0) ph += M_PI / L;
-      cx[d].push_back(std::cos(ph));
-      sx[d].push_back(std::sin(ph) * std::sin(ph));
-    }
-  }
-  for (size_t a = 0; a < cx[0].size(); ++a)
-    for (size_t b = 0; b < cx[1].size(); ++b)
-      for (size_t c = 0; c < cx[2].size(); ++c)
-        for (size_t d = 0; d < cx[3].size(); ++d) {
-          const double w = 4.0 - p->M0 - (cx[0][a] + cx[1][b] + cx[2][c] + cx[3][d]);
-          const double s2 = sx[0][a] + sx[1][b] + sx[2][c] + sx[3][d] + w * w;
-          const double s = std::sqrt(s2);
-          smin = std::min(smin, s);
-          smax = std::max(smax, s);
-        }
-}
 
 void fill_stats(ov_stats* st, int n, Engine* E, const SolveOut* so, double secs, int prec_bytes) {
   if (!st) return;
@@ -2458,11 +2352,13 @@ static ov_status apply_impl(ov_ctx* c, int op, void* out, const void* in, const 
 }
 
 ov_status ov_sign(ov_ctx* c, void* out, const void* in, int nrhs, ov_stats* st) {
+  Range range("ov_sign");
   return apply_impl(c, -1, out, in, nullptr, nrhs, st);
 }
 
 ov_status ov_apply(ov_ctx* c, ov_op op, void* out, const void* in, const void* phi, int nrhs,
                    ov_stats* st) {
+  Range range("ov_apply");
   if ((int)op < 0 || (int)op > OV_OP_M0INV_DAG) return OV_ERR_INVALID_ARG;
   if (c && (op == OV_OP_M0INV || op == OV_OP_M0INV_DAG) && !fft_ok(&c->p, c->err))
     return OV_ERR_INVALID_ARG;
@@ -2471,6 +2367,7 @@ ov_status ov_apply(ov_ctx* c, ov_op op, void* out, const void* in, const void* p
 
 ov_status ov_apply_noalloc(ov_ctx* c, ov_op op, void* out, const void* in, const void* phi,
                            int nrhs, ov_stats* st) {
+  Range range("ov_apply_noalloc");
   if (!c || nrhs < 1) return OV_ERR_INVALID_ARG;
   if (nrhs > c->pinned_n) {
     char buf[120];
@@ -2599,6 +2496,7 @@ static ov_status solve_systems(std::vector<ov_ctx*>& sysctx, std::vector<const v
 }
 
 ov_status ov_solve(ov_ctx* c, void* x, const void* b, const void* phi, int nrhs, ov_stats* st) {
+  Range range("ov_solve");
   if (!c || !x || !b || !phi || nrhs < 1) return OV_ERR_INVALID_ARG;
   const size_t vb = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3] * 4 *
                     sizeof(double2);
@@ -2614,6 +2512,7 @@ ov_status ov_solve(ov_ctx* c, void* x, const void* b, const void* phi, int nrhs,
 
 ov_status ov_solve_batch(int n, ov_ctx* const* ctx, void* const* x, const void* const* b,
                          const void* const* phi, const int* nrhs, ov_stats* st) {
+  Range range("ov_solve_batch");
   if (n < 1 || !ctx || !x || !b || !phi || !nrhs) return OV_ERR_INVALID_ARG;
   std::vector<ov_ctx*> sc;
   std::vector<const void*> bv, ph;
@@ -2638,6 +2537,7 @@ ov_status ov_solve_batch(int n, ov_ctx* const* ctx, void* const* x, const void* 
 
 ov_status ov_force(ov_ctx* c, void* grad_phi, double* S_host, const void* xi, const void* phi,
                    int nrhs, ov_stats* st) {
+  Range range("ov_force");
   if (!c || !grad_phi || !S_host || !xi || !phi || nrhs < 1) return OV_ERR_INVALID_ARG;
   const double t0 = now_s();
   const size_t V = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3];
@@ -2915,6 +2815,7 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
 
 ov_status ov_rational(ov_ctx* c, double a0, int n, const double* alpha, const double* beta,
                       void* out, const void* in, const void* phi, int nrhs, ov_stats* st) {
+  Range range("ov_rational");
   if (!c || !alpha || !beta || !out || !in || !phi || nrhs < 1 || n < 1 || n > MAXP)
     return OV_ERR_INVALID_ARG;
   for (int k = 0; k < n; ++k)
@@ -2951,6 +2852,7 @@ ov_status ov_rational(ov_ctx* c, double a0, int n, const double* alpha, const do
 ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
                             const double* beta, void* grad_phi, double* S_host, const void* xi,
                             const void* phi, int nrhs, ov_stats* st) {
+  Range range("ov_rational_force");
   if (!c || !alpha || !beta || !grad_phi || !S_host || !xi || !phi || nrhs < 1 || n < 1 ||
       n > MAXP)
     return OV_ERR_INVALID_ARG;
@@ -3042,6 +2944,7 @@ ov_status ov_rational_force(ov_ctx* c, double a0, int n, const double* alpha,
 
 // ------------------------------------------------------------ RHMC (Sec. 7.3)
 ov_status ov_boson(ov_ctx* c, const void* phi, double* S_host, void* G, void* F) {
+  Range range("ov_boson");
   if (!c || !phi || !S_host) return OV_ERR_INVALID_ARG;
   std::string why;
   if (!fft_ok(&c->p, why)) {
@@ -3097,6 +3000,7 @@ ov_status ov_rhmc_trajectory(ov_ctx* c, void* phi, const void* pi0, const void* 
                              const double* be18, double a14, int n14, const double* al14,
                              const double* be14, double u, double* dH, int* accepted,
                              ov_stats* st) {
+  Range range("ov_rhmc_trajectory");
   if (!c || !phi || !pi0 || !R || nsteps < 1 || !(tau > 0) || !al18 || !be18 || !al14 ||
       !be14 || !dH || !accepted)
     return OV_ERR_INVALID_ARG;
@@ -3151,6 +3055,7 @@ ov_status ov_rhmc_trajectory(ov_ctx* c, void* phi, const void* pi0, const void* 
 }
 
 ov_status ov_locality(ov_ctx* c, int spin, double* f, int nr, ov_stats* st) {
+  Range range("ov_locality");
   if (!c || !f || spin < 0 || spin > 3) return OV_ERR_INVALID_ARG;
   const int* d = c->p.dims;
   const int rmax = d[0] / 2 + d[1] / 2 + d[2] / 2 + d[3] / 2;
