@@ -409,6 +409,31 @@ def momentum_forms(torch, Lattice, inputs, dphi, dsrc):
             "fit_rel_err": [c18[3], c14[3]]}
         log(f"rhmc {dirac}: {out[f'rhmc_heatbath_action_{dirac}_16x4']}")
         del lat
+    # the paper's heatbath workload (Sec. 7.3, Table heattab1, context only): eta =
+    # (MdagM)^{1/8} R with the Dslash fermion matrix at m = 1, g = 0.1, degree 20 on the
+    # free spectrum of M0^dag M0 ([1.01, 8.2e4] on these lattices: fit on [1, 1e5]); shifts
+    # beta_i <= 100 by the preconditioned solver (the paper's cutoff), the rest by one
+    # multi-shift CG; iterations summed over the 20 shifts, as the table counts them
+    c18p = rational.power_approx(0.125, 1.0, 1e5, 20)
+    for dims in ((8, 8, 8, 32), (16, 16, 16, 32)):
+        phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2) + 7)
+        b, p = torch.from_numpy(src).cuda(), torch.from_numpy(phi).cuda()
+        tag = "x".join(str(d) for d in dims)
+        for prec in ("mixed", "fp64"):
+            for cut in (100.0, 0.0):
+                lat = Lattice(dims, precision=prec, dirac="dslash", m=1.0, g=0.1, outer_tol=1e-10,
+                              shift_pc_cutoff=cut)
+                lat.rational(b, p, *c18p[:3])
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, st = lat.rational(b, p, *c18p[:3])
+                torch.cuda.synchronize()
+                e = time.perf_counter() - t
+                key = f"heatbath_dslash_{prec}_{'pc100' if cut else 'multishift'}_{tag}_m1_g0.1"
+                out[key] = {"seconds": e, "iterations_summed": st[0]["outer_iters"],
+                            "fit_rel_err": c18p[3]}
+                log(f"heatbath {tag} {prec} cutoff {cut}: {out[key]}")
+                del lat
     # locality probe of Dslash on 16^4 (Sec. 3.2, Fig. rfig)
     lat = Lattice(DIMS, dirac="dslash")
     lat.locality(0)

@@ -150,6 +150,14 @@ typedef struct {
                               m; real when m = 0), the free-field operator closest to M
                               on average; 0: the action's mass m, the phi = 0 operator
                               of Sec. 7.3.  OV_OP_M0INV(_DAG) of ov_apply always use m. */
+  double shift_pc_cutoff;  /* ov_rational (heatbath / action, Sec. 7.3): shifts beta_i <=
+                              this cutoff are solved one at a time, (MdagM + beta_i) X =
+                              b by the preconditioned solver (context precision, reliable
+                              updates, free shifted preconditioner (M0^dag M0 + beta_i)^-1)
+                              and the rest by one multi-shift CG; 0 (default): every shift
+                              by the multi-shift CG.  The paper's cutoff is 100.  Needs
+                              precondition = 1 and inner_form = 1 or a momentum-space
+                              dirac (else every shift takes the multi-shift CG). */
 } ov_params;
 
 typedef struct {

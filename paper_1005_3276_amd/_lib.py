@@ -42,7 +42,7 @@ class OvParams(C.Structure):
                 ("max_outer", C.c_int), ("precision", C.c_int),
                 ("inner_relax", C.c_double), ("inner_tol_max", C.c_double),
                 ("precondition", C.c_int), ("dirac", C.c_int), ("truth_relax", C.c_double),
-                ("inner_form", C.c_int), ("pc_mass", C.c_int)]
+                ("inner_form", C.c_int), ("pc_mass", C.c_int), ("shift_pc_cutoff", C.c_double)]
 
 
 class OvStats(C.Structure):

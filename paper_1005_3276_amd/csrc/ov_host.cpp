@@ -78,6 +78,10 @@ ov_status validate(const ov_params* p, std::string& err) {
     err = "need 0 < truth_relax <= 1";
     return OV_ERR_INVALID_ARG;
   }
+  if (!(p->shift_pc_cutoff >= 0.0) || !std::isfinite(p->shift_pc_cutoff)) {
+    err = "shift_pc_cutoff must be finite and >= 0";
+    return OV_ERR_INVALID_ARG;
+  }
   if (p->pc_mass != 0 && p->pc_mass != 1) {
     err = "pc_mass must be 0 or 1";
     return OV_ERR_INVALID_ARG;

@@ -73,6 +73,7 @@ struct SysDev {
   double* cg_s;             // per-system CG scalars (see CG_* below)
   double m_re, m_im;        // fermion mass
   double pc_re, pc_im;      // mass of the preconditioner M0 (m, or the RMS of c = m + g phi)
+  double shift;             // sigma of a shifted solve (MdagM + sigma) x = b; 0 otherwise
   double g_re, g_im;        // Yukawa coupling
   double2* shx;             // multi-shift CG on MdagM: nshift solutions (FP64 planar)
   double2* shp;             //   and nshift search directions
@@ -147,6 +148,39 @@ __global__ void k_unpack(const SysDev* __restrict__ sys, const int* __restrict__
     for (int k = 0; k < 4; ++k) {
       const c2<R> v = in[(size_t)k * V + i];
       out[(size_t)i * 4 + k] = double2{(double)v.x, (double)v.y};
+    }
+  }
+}
+
+// out = a * in over n complex128 values (ABI layout).
+__global__ void k_scale_copy(double2* __restrict__ out, const double2* __restrict__ in, double a,
+                             size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = in[i];
+    out[i] = double2{a * v.x, a * v.y};
+  }
+}
+
+// dst += a * src: planar FP64 src (spin-planar) added into the ABI's complex128 AoS dst.
+__global__ void k_unpack_axpy(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+                              int nb_total, void* const* __restrict__ src,
+                              double2* const* __restrict__ dst, double a) {
+  const int L = xcd_logical_block(nb_total);
+  const int s = bmap[L];
+  const SysDev& S = sys[s];
+  const int V = S.g.V;
+  const int lb = L - S.blk0;
+  const double2* in = (const double2*)src[s];
+  double2* out = dst[s];
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 v = in[(size_t)k * V + i];
+      double2& o = out[(size_t)i * 4 + k];
+      o = double2{o.x + a * v.x, o.y + a * v.y};
     }
   }
 }
@@ -1404,8 +1438,8 @@ __global__ void __launch_bounds__(256) k_fft_z(const SysDev* __restrict__ sys, i
 
 // Momentum-space operator on the four spin components v of one momentum.
 __device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, double m_im,
-                                             double sx, double sy, double sz, double st, double w,
-                                             double2 v[4]) {
+                                             double shift, double sx, double sy, double sz,
+                                             double st, double w, double2 v[4]) {
   const double s2sin = sx * sx + sy * sy + sz * sz + st * st;
   const double s2 = w * w + s2sin;
   double a0, c;
@@ -1424,8 +1458,9 @@ __device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, d
     c = Rr;
   }
   if (sp.kind == SYM_PCG) {  // M0^dag M0 = (a^2 + mu^2 + c^2 |s|^2) 1: a scalar per momentum
+    // (a shifted solve takes the free shifted operator, M0^dag M0 + sigma)
     const double A = a0 + m_re;
-    const double sc = 1.0 / (A * A + m_im * m_im + c * c * s2sin);
+    const double sc = 1.0 / (A * A + m_im * m_im + c * c * s2sin + shift);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = double2{v[k].x * sc, v[k].y * sc};
     return;
@@ -1536,7 +1571,8 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
       v[3] = double2{0.0, 0.0};
     } else {
       const bool m0 = sp.kind == SYM_M0INV || sp.kind == SYM_M0INV_DAG || sp.kind == SYM_PCG;
-      apply_symbol(sp, m0 ? S.pc_re : S.m_re, m0 ? S.pc_im : S.m_im, sx, sy, sz, st, w, v);
+      apply_symbol(sp, m0 ? S.pc_re : S.m_re, m0 ? S.pc_im : S.m_im, S.shift, sx, sy, sz, st, w,
+                   v);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) A[(k * T + kt) * XC + xl] = c2<R>{(R)v[k].x, (R)v[k].y};
@@ -1594,12 +1630,26 @@ __global__ void __launch_bounds__(256) k_yuk(const SysDev* __restrict__ sys, con
       const double pr = (double)p[k].x, pi = (double)p[k].y;
       o[k] = double2{(double)w[k].x + cr * pr - ci * pi, (double)w[k].y + cr * pi + ci * pr};
     }
+    if (S.shift != 0.0 && mode == 1) {  // (MdagM + sigma) p: p = cg_p
+      c2<R> q[4];
+      load_sp<R>((const c2<R>*)S.cg_p, V, i, q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        o[k] = double2{o[k].x + S.shift * (double)q[k].x, o[k].y + S.shift * (double)q[k].y};
+    }
     if (mode == 2) {
       double2 rr[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double2 bv = S.cg_b[(size_t)i * 4 + k];
         rr[k] = double2{bv.x - o[k].x, bv.y - o[k].y};
+      }
+      if (S.shift != 0.0) {  // (MdagM + sigma) x: x = cg_x64
+        double2 x[4];
+        load_sp<double>((const double2*)S.cg_x64, V, i, x);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          rr[k] = double2{rr[k].x - S.shift * x[k].x, rr[k].y - S.shift * x[k].y};
       }
       store_sp<double>((double2*)S.cg_r64, V, i, rr);
       if (S.cg_r) {
@@ -1615,7 +1665,7 @@ __global__ void __launch_bounds__(256) k_yuk(const SysDev* __restrict__ sys, con
 #pragma unroll
     for (int k = 0; k < 4; ++k) ov[k] = c2<R>{(R)o[k].x, (R)o[k].y};
     store_sp<R>((c2<R>*)S.e_out, V, i, ov);
-    if (mode == 0) acc += norm2_sp(ov);
+    if (mode == 0) acc += norm2_sp(ov) + S.shift * norm2_sp(p);  // <p, (MdagM + sigma) p>
   }
   if (mode != 1) {
     const double tot = block_sum(acc, lds);
@@ -1887,7 +1937,7 @@ __global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ t
     for (int k = 0; k < 4; ++k) {
       const double cr = cpr, ci = (k < 2) ? -cpi : cpi;
       const double g5 = k < 2 ? -1.0 : 1.0;
-      const double a = 1.0 + (1.0 + cr) * (1.0 + cr) + ci * ci;  // 1 + |1 + c|^2
+      const double a = 1.0 + (1.0 + cr) * (1.0 + cr) + ci * ci + A.shift;  // 1 + |1 + c|^2 + sigma
       // (1 + c*) g5 e1
       const double br = 1.0 + cr, bi = -ci;
       const double fr = g5 * (br * e1[k].x - bi * e1[k].y);
@@ -1998,6 +2048,13 @@ __global__ void __launch_bounds__(256) k_truth_finish(const SysDev* __restrict__
     for (int k = 0; k < 4; ++k) {
       const double2 bv = S.cg_b[(size_t)i * 4 + k];
       rr[k] = double2{bv.x - P[k].x - hw[k].x, bv.y - P[k].y - hw[k].y};
+    }
+    if (S.shift != 0.0) {  // (MdagM + sigma) x: x = e_in
+      double2 x[4];
+      load_sp<double>((const double2*)S.e_in, V, i, x);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        rr[k] = double2{rr[k].x - S.shift * x[k].x, rr[k].y - S.shift * x[k].y};
     }
     store_sp<double>((double2*)S.cg_r64, V, i, rr);
     if (S.cg_r) {

@@ -379,6 +379,7 @@ struct Engine {
   MsParams mp64{}, mpR{};
   int L64 = 0, LR = 0;              // multi-shift launch counts
   bool no_relax = false;            // fixed inner tolerance (the FP64 fallback solver)
+  double shift = 0.0;               // solve (MdagM + shift) x = b (rational layers)
   int max_outer = 0;                // > 0: outer iteration cap instead of max_outer (the
                                     // fallback solver gets what the mixed one left)
   bool force_fallback = false;      // hand every system to the FP64 solver at its first
@@ -1280,6 +1281,7 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
     SysDev d = base_dev(b);
     d.phi = (const double2*)phi[s];
     d.cg_b = (const double2*)bvec[s];
+    d.shift = E.shift;
     if (rms_pc) {
       d.pc_re = pcm[s].x;
       d.pc_im = pcm[s].y;
@@ -1352,16 +1354,18 @@ ov_status build_solve_tables(Engine& E, const std::vector<const void*>& bvec,
       fm.fft_tmp = b.fftR;
       fm.e_in = b.pR;
       fm.e_out = b.uR;
-      SysDev fmd = fm;  // inner: w = D^dag u + Y^dag u -> v
+      SysDev fmd = fm;  // inner: w = D^dag u + Y^dag u (+ shift p) -> v
       fmd.e_in = b.uR;
       fmd.e_out = b.vR;
+      fmd.cg_p = b.pR;
       SysDev ftm = d;  // FP64 truth: u64 = M x64
       ftm.active = b.act_ru;
       ftm.fft_tmp = b.src64b;
       ftm.e_in = b.x64;
       ftm.e_out = b.u64;
-      SysDev ftmd = ftm;  // r64 = b - M^dag u64
+      SysDev ftmd = ftm;  // r64 = b - M^dag u64 (- shift x64)
       ftmd.e_in = b.u64;
+      ftmd.cg_x64 = b.x64;
       ftmd.e_out = b.r64ms;
       ftmd.cg_r64 = b.r64;
       ftmd.cg_r = (sizeof(R) == sizeof(double)) ? b.rcgR : nullptr;
@@ -2255,9 +2259,14 @@ size_t ov_workspace_bytes(const ov_ctx* c, int nrhs) {
   return std::max(std::max(solve, apply), fallback);
 }
 
+static bool shifted_pc_on(const ov_ctx* c);
+
 size_t ov_workspace_bytes_rational(const ov_ctx* c, int nrhs, int nshift) {
   if (!c || nrhs < 1 || nshift < 1 || nshift > MAXP) return 0;
-  return plan_bytes(c, nrhs, true, false, solve_tol64(c), c->p.inner_tol, nshift);
+  size_t need = plan_bytes(c, nrhs, true, false, solve_tol64(c), c->p.inner_tol, nshift);
+  if (shifted_pc_on(c))  // shifts solved one by one: the solve plans (and the FP64 retry)
+    need = std::max(need, ov_workspace_bytes(c, nrhs));
+  return need;
 }
 
 ov_status ov_set_workspace(ov_ctx* c, void* ptr, size_t bytes) {
@@ -2813,6 +2822,74 @@ static ov_status rational_core(ov_ctx* c, Engine& E, double a0, int n, const dou
   return check_launch(c);
 }
 
+// Whether a context's rational layers solve their small shifts one by one with the
+// preconditioned solver (shift_pc_cutoff): the shifted operator needs the Ginsparg-Wilson
+// inner form or a momentum-space D.
+static bool shifted_pc_on(const ov_ctx* c) {
+  return c->p.shift_pc_cutoff > 0.0 && c->p.precondition != 0 &&
+         (c->p.inner_form == 1 || c->p.dirac != OV_DIRAC_OVERLAP_MS);
+}
+
+// (MdagM + sigma) X = b for every right-hand side bv (cold start) with the solver of the
+// context's precision and the free shifted preconditioner, then outs[r] += alpha X_r (ABI
+// layout).  A mixed solve whose cycles stagnate is solved again in FP64.  Adds the outer
+// iterations, reliable updates and multi-shift iterations to the totals.
+static ov_status shifted_solve_acc(ov_ctx* c, double sigma, double alpha,
+                                   const std::vector<const void*>& bv,
+                                   const std::vector<const void*>& ph,
+                                   const std::vector<void*>& outs, std::vector<int>& outer,
+                                   std::vector<int>& ru, std::vector<long long>& inner) {
+  const int ns = (int)bv.size();
+  const size_t vb = (size_t)c->p.dims[0] * c->p.dims[1] * c->p.dims[2] * c->p.dims[3] * 4 *
+                    sizeof(double2);
+  std::vector<ov_ctx*> sc(ns, c);
+  const bool mixed = c->p.precision == OV_MIXED;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const bool m = mixed && attempt == 0;
+    const double tolR = m ? c->p.mixed_inner_tol : c->p.inner_tol;
+    Engine F;
+    TRY(engine_init(F, sc, true, m, solve_tol64(c), tolR));
+    F.shift = sigma;
+    F.no_relax = attempt == 1;
+    for (int r = 0; r < ns; ++r) zero_dev(F, F.sb[r].x64, vb);
+    SolveOut so;
+    ov_status rc = m ? solve_engine<float>(F, bv, ph, tolR, c->p.reliable_delta, so)
+                     : solve_engine<double>(F, bv, ph, tolR, c->p.reliable_delta, so);
+    if (rc != OV_OK) return rc;
+    std::vector<int> ctl;
+    std::vector<long long> st0;
+    std::vector<double> ds;
+    TRY(read_ctl(F, ctl, st0, ds));
+    bool fell_back = false;
+    for (int r = 0; r < ns; ++r) {
+      outer[r] += so.outer[r];
+      ru[r] += so.ru[r];
+      inner[r] += st0[r];
+      fell_back |= so.fallback[r] != 0;
+    }
+    if (fell_back && m) continue;
+    for (int r = 0; r < ns; ++r)
+      if (!so.conv[r]) {
+        c->err = "shifted solve of the rational layer did not converge within max_outer";
+        return OV_ERR_NOT_CONVERGED;
+      }
+    TRY(sync(F));  // the pointer staging feeds the copy below
+    std::vector<void*>& h = F.hptrs;
+    h.assign(2 * ns, nullptr);
+    for (int r = 0; r < ns; ++r) {
+      h[r] = F.sb[r].x64;
+      h[ns + r] = outs[r];
+    }
+    HIPCHK(c, hipMemcpyAsync(F.ptrs, h.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice,
+                             F.st));
+    k_unpack_axpy<<<F.nb_total, c->block, 0, F.st>>>(tab(F, T_APPLY), F.bmap, F.nb_total, F.ptrs,
+                                                     (double2* const*)(F.ptrs + ns), alpha);
+    return sync(F);
+  }
+  c->err = "shifted solve of the rational layer: FP64 retry did not finish";
+  return OV_ERR_NOT_CONVERGED;
+}
+
 ov_status ov_rational(ov_ctx* c, double a0, int n, const double* alpha, const double* beta,
                       void* out, const void* in, const void* phi, int nrhs, ov_stats* st) {
   Range range("ov_rational");
@@ -2833,19 +2910,55 @@ ov_status ov_rational(ov_ctx* c, double a0, int n, const double* alpha, const do
     bv[r] = (const char*)in + r * vb;
     ov[r] = (char*)out + r * vb;
   }
-  Engine E;
-  TRY(engine_init(E, sc, true, false, solve_tol64(c), c->p.inner_tol, n));
-  std::vector<int> iters;
-  TRY(rational_core(c, E, a0, n, alpha, beta, bv, ph, iters));
-  for (int r = 0; r < nrhs; ++r) r64[r] = E.sb[r].r64;
-  TRY(unpack64(E, r64, ov));
-  TRY(sync(E));
-  SolveOut so;
-  so.outer = iters;
-  so.ru.assign(nrhs, 0);
-  so.res.assign(nrhs, 0.0);
-  so.conv.assign(nrhs, 1);
-  fill_stats(st, nrhs, &E, &so, now_s() - t0, 16);
+  // Shifts at or below shift_pc_cutoff: one preconditioned solve each (the paper's
+  // heatbath, Sec. 7.3); the rest: one multi-shift CG on MdagM.
+  std::vector<double> al_hi, be_hi, al_lo, be_lo;
+  const bool split = shifted_pc_on(c);
+  for (int k = 0; k < n; ++k) {
+    const bool lo = split && beta[k] <= c->p.shift_pc_cutoff;
+    (lo ? al_lo : al_hi).push_back(alpha[k]);
+    (lo ? be_lo : be_hi).push_back(beta[k]);
+  }
+  std::vector<int> outer(nrhs, 0), ru(nrhs, 0);
+  std::vector<long long> inner(nrhs, 0);
+  std::vector<double> shift_res(nrhs, 0.0);
+  if (!al_hi.empty()) {
+    Engine E;
+    TRY(engine_init(E, sc, true, false, solve_tol64(c), c->p.inner_tol, (int)al_hi.size()));
+    std::vector<int> iters;
+    TRY(rational_core(c, E, a0, (int)al_hi.size(), al_hi.data(), be_hi.data(), bv, ph, iters));
+    for (int r = 0; r < nrhs; ++r) r64[r] = E.sb[r].r64;
+    TRY(unpack64(E, r64, ov));
+    TRY(sync(E));
+    std::vector<int> ctl;
+    std::vector<long long> st0;
+    TRY(read_ctl(E, ctl, st0, shift_res));
+    for (int r = 0; r < nrhs; ++r) {
+      outer[r] += iters[r];
+      inner[r] += st0[r];
+    }
+  } else {  // out = a0 in, ordered after the caller's stream like every other launch
+    HIPCHK(c, hipEventRecord(c->ev_in, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->priv, c->ev_in, 0));
+    const size_t nel = (size_t)nrhs * vb / sizeof(double2);
+    k_scale_copy<<<(unsigned)std::min<size_t>((nel + 255) / 256, 4096), 256, 0, c->priv>>>(
+        (double2*)out, (const double2*)in, a0, nel);
+    TRY(check_launch(c));
+  }
+  for (size_t k = 0; k < al_lo.size(); ++k)
+    TRY(shifted_solve_acc(c, be_lo[k], al_lo[k], bv, ph, ov, outer, ru, inner));
+  if (st) {
+    for (int r = 0; r < nrhs; ++r) {
+      ov_stats& o = st[r];
+      std::memset(&o, 0, sizeof(o));
+      o.outer_iters = outer[r];
+      o.reliable_updates = ru[r];
+      o.inner_iters = inner[r];
+      o.stencil_apps = 2 * inner[r];
+      o.max_shift_res = shift_res[r];
+      o.seconds = now_s() - t0;
+    }
+  }
   return OV_OK;
 }
 

@@ -855,6 +855,37 @@ def test_rational_vs_oracle(orc, rat_coeffs, dirac, form):
     print(f"[rational] {st[0]}", flush=True)
 
 
+@pytest.mark.parametrize("dirac,prec,cutoff", [(0, "mixed", 100.0), (0, "fp64", 100.0),
+                                                (2, "mixed", 100.0), (0, "mixed", 1e9)])
+def test_rational_shifted_pc_vs_oracle(orc, rat_coeffs, dirac, prec, cutoff):
+    """shift_pc_cutoff (Sec. 7.3, the paper's preconditioned heatbath): shifts beta_i <=
+    cutoff are solved one by one by the preconditioned solver, the rest by the multi-shift
+    CG (cutoff 1e9: every shift preconditioned, out = a0 in + sum).  Heatbath (x^1/8) and
+    action (x^-1/4) layers at 4^4 against the oracle's one CG per shift and against the
+    all-multi-shift result."""
+    dims = (4, 4, 4, 4)
+    print(f"[rational-pc] dirac={dirac} prec={prec} cutoff={cutoff}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=2, sigma2=0.25, seed=71)
+    kw = dict(m=0.05, g=0.3, n_poles=20, lambda_min=1e-3, lambda_max=8.0, dirac=dirac)
+    lat = lattice(dims, precision=prec, inner_tol=1e-13, outer_tol=1e-11, shift_pc_cutoff=cutoff,
+                  **kw)
+    ms = lattice(dims, inner_tol=1e-13, outer_tol=1e-11, **kw)
+    o = orc.Oracle(dims, inner_tol=1e-13, **kw)
+    b, p = dev(src), dev(phi)
+    for power in (0.125, -0.25):
+        a0, al, be, _ = rat_coeffs[power]
+        out, st = lat.rational(b, p, a0, al, be)
+        ref_ms, st_ms = ms.rational(b, p, a0, al, be)
+        out, ref_ms = host(out), host(ref_ms)
+        for r in range(2):
+            check(out[r], o.rational(src[r], phi, a0, al, be, tol=1e-11), 1e-9, f"rhs {r}")
+            check(out[r], ref_ms[r], 1e-9, f"vs multi-shift rhs {r}")
+        n_pc = int(np.sum(np.asarray(be) <= cutoff))
+        print(f"[rational-pc] x^{power}: {n_pc} preconditioned shifts, iterations "
+              f"{[s['outer_iters'] for s in st]} (multi-shift alone "
+              f"{[s['outer_iters'] for s in st_ms]})", flush=True)
+
+
 def _plane_wave(dims):
     """The lowest antiperiodic-time plane wave in spin 0: with phi = 0 an eigenvector of
     MdagM up to the rational sign's error (D + D^dag is a scalar per momentum), so its
