@@ -43,10 +43,10 @@ def kernel_source_hash():
 TRAFFIC_RECORDS = ("k_ms_passes_16x4_traffic.json", "k_ms_passes_16x3x32x12_traffic.json")
 
 
-def measured_traffic(family, bytes_per_launch):
-    """HBM bytes per launch of a pass family from the committed counter runs (one record
-    per workload, told apart by the algorithmic bytes per launch), if the kernels and the
-    launch composition are unchanged."""
+def measured_traffic(family, full_launch_bytes):
+    """Mean HBM bytes per launch of a pass family and their ratio to the mean algorithmic
+    bytes, from the committed counter runs (one record per workload, told apart by the
+    algorithmic bytes of a full launch), if the kernels are unchanged; else (None, None)."""
     for name in TRAFFIC_RECORDS:
         try:
             rec = json.load(open(os.path.join(ROOT, "profiles", name)))
@@ -55,9 +55,9 @@ def measured_traffic(family, bytes_per_launch):
         if rec.get("kernel_source_hash") != kernel_source_hash():
             continue
         f = rec.get("families", {}).get(family)
-        if f and abs(f.get("algorithmic_bytes_per_launch", -1) - bytes_per_launch) <= 0.5:
-            return f.get("hbm_bytes_per_launch")
-    return None
+        if f and abs(f.get("full_launch_algorithmic_bytes", -1) - full_launch_bytes) <= 0.5:
+            return f.get("hbm_bytes_per_launch"), f.get("ratio")
+    return None, None
 
 
 def stencil_bandwidth(lat, torch, nrhs, prec, reps=20):
@@ -85,6 +85,67 @@ def stencil_sweep(lat, torch):
         sweep.append(stencil_bandwidth(lat, torch, nrhs, prec))
         log(f"stencil {sweep[-1]}")
     return sweep
+
+
+def record_traffic(out_path, fetch_csv, write_csv, workload, systems, sources, volume):
+    """Host only: the HBM traffic record of the multi-shift pass families from two rocprofv3
+    --pmc runs of one command (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), scaled by the
+    largest device copy in the same program (run with --calibrate-copy: 512 MiB each way).
+    The two runs dispatch the same deterministic sequence, so the n-th dispatch of a kernel
+    in one is the n-th in the other.  Writes are exact (one output field per source taking
+    part), so each dispatch's WRITE_SIZE gives the share of the launch's systems that took
+    part, and with it the dispatch's algorithmic bytes (3 fields per source).  Records the
+    mean HBM bytes per launch against the mean algorithmic bytes per launch and their ratio
+    (sums over every dispatch), the full launch's algorithmic bytes (every system and source
+    taking part: the key bench.py matches on) and the per-kernel medians.  Writes the JSON
+    that measured_traffic reads."""
+    import csv
+    import statistics
+
+    def per_kernel(path):
+        by = {}
+        for r in csv.DictReader(open(path)):
+            by.setdefault(r["Kernel_Name"], []).append(
+                (int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        return {k: [v for _, v in sorted(x)] for k, x in by.items()}
+
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy = [k for k in fetch if "copyBuffer" in k]
+    cf = max(max(fetch[k]) for k in copy)
+    cw = max(max(write[k]) for k in copy)
+    copy_kib = 512 * 1024
+    fs, ws = copy_kib / cf, copy_kib / cw
+    rec = {"kernel_source_hash": kernel_source_hash(),
+           "hash_covers": "ov_common.hpp + ov_kernels.hpp from struct ZmMarch to the k_ms_t comment",
+           "workload": workload,
+           "calibration": {"copy_bytes": copy_kib * 1024, "fetch_kib": cf, "write_kib": cw,
+                           "fetch_scale": fs, "write_scale": ws},
+           "families": {}}
+    for fam, prec, esize in (("fp32_inner", "float", 8), ("fp64_truth", "double", 16)):
+        ks = [f"k_ms_t<{prec}, true>", f"k_ms_r<{prec}, true>"]
+        full = {k: next((n for n in fetch if k in n), None) for k in ks}
+        if not all(full.values()) or not all(full[k] in write for k in ks):
+            continue
+        field = systems * sources * 4 * volume * esize  # one field per source, whole launch
+        alg_full = 3 * field
+        hbm, alg, n = 0.0, 0.0, 0
+        for k in ks:
+            for f_kib, w_kib in zip(fetch[full[k]], write[full[k]]):
+                hbm += (f_kib * fs + w_kib * ws) * 1024
+                alg += alg_full * min(1.0, w_kib * ws * 1024 / field)
+                n += 1
+        rec["families"][fam] = {
+            "kernels": ks, "sources_per_launch": sources * systems,
+            "fetch_kib_median": {k: statistics.median(fetch[full[k]]) for k in ks},
+            "write_kib_median": {k: statistics.median(write[full[k]]) for k in ks},
+            "dispatches": {k: min(len(fetch[full[k]]), len(write[full[k]])) for k in ks},
+            "hbm_bytes_per_launch": round(hbm / n),
+            "algorithmic_bytes_per_launch": round(alg / n),
+            "full_launch_algorithmic_bytes": alg_full,
+            "ratio": round(hbm / alg, 3)}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=2)
+    print(json.dumps(rec["families"], indent=1))
 
 
 def calibrate_copy(torch):
@@ -183,6 +244,14 @@ def cpu_suite(full16):
     return out
 
 
+def full_bytes(family, systems, volume):
+    """Algorithmic bytes of one multi-shift pass launch with every system taking part: two
+    sources per system (the Ginsparg-Wilson forms), three fields each (two read, one
+    written), 4 spins of 8 B (FP32) or 16 B (FP64) per site."""
+    esize = 8 if family == "fp32_inner" else 16
+    return 3 * 2 * systems * 4 * volume * esize
+
+
 # multi-shift pass families: (t-pass kernel id, r-pass kernel id) of the library's
 # event sampling (ov_kernel_sampling): 0/1 FP32 passes, 3/4 FP64 passes
 FAMILIES = {"fp64_truth": (3, 4), "fp32_inner": (0, 1)}
@@ -199,18 +268,22 @@ def sampled_spans(lat, run):
     return [lat.kernel_spans(k) for k in range(5)]  # (kernel_ms, kcnt, event_ms, cnt, bytes)
 
 
-def family_roofline(spans, name, kname):
-    """Achieved algorithmic GB/s of one pass family over the sampled launches."""
+def family_roofline(spans, name, kname, full_launch_bytes):
+    """Achieved algorithmic GB/s of one pass family over the sampled launches.  The bytes
+    of a launch are those of the systems that took part (the library counts the sites its
+    workgroups processed); full_launch_bytes is a launch with every system taking part."""
     ids = FAMILIES[name]
     ms_sum = sum(spans[k][2] for k in ids)
     cnt = sum(spans[k][3] for k in ids)
     bytes_sum = sum(spans[k][4] for k in ids)
     per_launch = bytes_sum / max(cnt, 1)
     achieved = bytes_sum / (ms_sum * 1e-3) / 1e9 if ms_sum > 0 else 0.0
+    traffic, ratio = measured_traffic(name, full_launch_bytes)
     r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, per_launch),
+         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_ratio": ratio,
          "kernel": kname, "avg_launch_us": ms_sum / max(cnt, 1) * 1e3,
-         "bytes_per_launch": per_launch, "launches_per_solve": cnt,
+         "bytes_per_launch": per_launch, "full_launch_bytes": full_launch_bytes,
+         "active_share": per_launch / full_launch_bytes, "launches_per_solve": cnt,
          "event_ms_per_solve": ms_sum,
          "t_pass_us": spans[ids[0]][2] / max(spans[ids[0]][3], 1) * 1e3,
          "r_pass_us": spans[ids[1]][2] / max(spans[ids[1]][3], 1) * 1e3}
@@ -244,7 +317,7 @@ def batched_config3(torch, Lattice, inputs):
            "max_true_rel_res": max(s["true_rel_res"] for s in st),
            "outer_iters": [s["outer_iters"] for s in st],
            "pass_rooflines": {
-               n: family_roofline(spans, n, k) for n, k in (
+               n: family_roofline(spans, n, k, full_bytes(n, 12, 16 * 16 * 16 * 32)) for n, k in (
                    ("fp32_inner", "k_ms_t<float, *> + k_ms_r<float, *> (FP32 inner passes, "
                                   "12 systems x 2 sources per launch)"),
                    ("fp64_truth", "k_ms_t<double, *> + k_ms_r<double, *> (FP64 true-residual "
@@ -468,7 +541,16 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched 12 x 16^3x32 mixed solve with its pass rooflines "
                          "(one JSON line of its own)")
+    ap.add_argument("--record-traffic", nargs=7,
+                    metavar=("OUT_JSON", "FETCH_CSV", "WRITE_CSV", "WORKLOAD", "SYSTEMS",
+                             "SOURCES", "VOLUME"),
+                    help="host only: write the pass families' traffic record from two "
+                         "rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE)")
     args = ap.parse_args()
+    if args.record_traffic:
+        o, fc, wc, wl, nsys, nsrc, vol = args.record_traffic
+        record_traffic(o, fc, wc, wl, int(nsys), int(nsrc), int(vol))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the batched and "
                                    "multi-lattice work shards across GPUs without "
@@ -550,7 +632,7 @@ def main():
     else:
         spans = sampled_spans(lat, lambda: lat.solve(dsrc, dphi))
 
-    fam = {n: family_roofline(spans, n, families[n]) for n in families}
+    fam = {n: family_roofline(spans, n, families[n], full_bytes(n, 1, lat.V)) for n in families}
     dom = max(fam, key=lambda n: fam[n]["event_ms_per_solve"])
     roofline = fam[dom]
     roofline_secondary = fam[[n for n in fam if n != dom][0]]

@@ -57,6 +57,8 @@ struct ov_ctx {
     double bytes;          // bytes of the launch, or bytes per iteration when n_dev is set
     const int* n_dev;      // device iteration count of a persistent launch
     int ts_blocks;         // workgroups that stamped region ts_index (0: none)
+    double sites;          // sites of the launch (all systems): its stamped site count
+                           // scales bytes to the systems that took part
   };
   std::vector<EvUse> ev_use;
   // kernels: 0 / 1 FP32 t / r pass, 2 persistent, 3 / 4 FP64 t / r pass
@@ -714,7 +716,7 @@ struct Sample {
       c->ev_pool.push_back(a);
       c->ev_pool.push_back(b);
     }
-    c->ev_use.push_back({k, bytes, n_dev, 0});
+    c->ev_use.push_back({k, bytes, n_dev, 0, 0.0});
     c->ev_call_count[k]++;
     on = hipEventRecord(c->ev_pool[2 * idx], c->priv) == hipSuccess;
   }
@@ -726,10 +728,29 @@ struct Sample {
 // Collect the sampled durations after the stream has been synchronised.
 void collect_samples(ov_ctx* c) {
   for (size_t i = 0; i < c->ev_use.size(); ++i) {
+    const auto& u = c->ev_use[i];
+    // device stamps: (start, end, sites processed) per workgroup
+    double frac = 1.0;  // share of the launch's sites that were processed
+    if (u.ts_blocks > 0 && c->ts_dev && c->wall_khz > 0 && i < c->ts_regions) {
+      std::vector<unsigned long long> h(3 * (size_t)u.ts_blocks);
+      if (hipMemcpy(h.data(), c->ts_dev + i * c->ts_region, sizeof(unsigned long long) * h.size(),
+                    hipMemcpyDeviceToHost) == hipSuccess) {
+        unsigned long long lo = ~0ull, hi = 0, sites = 0;
+        for (int b = 0; b < u.ts_blocks; ++b) {
+          lo = std::min(lo, h[3 * b]);
+          hi = std::max(hi, h[3 * b + 1]);
+          sites += h[3 * b + 2];
+        }
+        if (u.sites > 0) frac = std::min(1.0, (double)sites / u.sites);
+        if (hi > lo) {
+          c->ksum_kernel_ms[u.kernel] += (double)(hi - lo) / c->wall_khz;
+          c->kcount_kernel[u.kernel]++;
+        }
+      }
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]) == hipSuccess) {
-      const auto& u = c->ev_use[i];
-      double bytes = u.bytes;
+      double bytes = u.bytes * frac;
       if (u.n_dev) {  // persistent launch: bytes per iteration x iterations run
         int n = 0;
         if (hipMemcpy(&n, u.n_dev, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) n = 0;
@@ -738,22 +759,6 @@ void collect_samples(ov_ctx* c) {
       c->ksum_ms[u.kernel] += ms;
       c->ksum_bytes[u.kernel] += bytes;
       c->kcount[u.kernel]++;
-    }
-    const auto& u = c->ev_use[i];
-    if (u.ts_blocks > 0 && c->ts_dev && c->wall_khz > 0 && i < c->ts_regions) {
-      std::vector<unsigned long long> h(2 * (size_t)u.ts_blocks);
-      if (hipMemcpy(h.data(), c->ts_dev + i * c->ts_region, sizeof(unsigned long long) * h.size(),
-                    hipMemcpyDeviceToHost) == hipSuccess) {
-        unsigned long long lo = ~0ull, hi = 0;
-        for (int b = 0; b < u.ts_blocks; ++b) {
-          lo = std::min(lo, h[2 * b]);
-          hi = std::max(hi, h[2 * b + 1]);
-        }
-        if (hi > lo) {
-          c->ksum_kernel_ms[u.kernel] += (double)(hi - lo) / c->wall_khz;
-          c->kcount_kernel[u.kernel]++;
-        }
-      }
     }
   }
   c->ev_use.clear();
@@ -836,7 +841,7 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
     shb = ok ? (size_t)4 * c->block * sizeof(c2<R>) : 0;
   }
   if (c->sample_max > 0) {  // stamp regions for the sampled launches of this call
-    const size_t region = 2 * (size_t)nbt_;
+    const size_t region = 3 * (size_t)nbt_;  // (start, end, sites) per workgroup
     const size_t regions = 4 * (size_t)c->sample_max + 2;
     if (c->ts_region < region || c->ts_regions < regions) {
       if (c->ts_dev) (void)hipFree(c->ts_dev);  // synchronises the device
@@ -861,6 +866,7 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
     if (smp.on && c->ts_dev && idx < c->ts_regions) {
       m.tstamp = c->ts_dev + idx * c->ts_region;
       c->ev_use[idx].ts_blocks = nbt_;
+      c->ev_use[idx].sites = vol;
     }
     return m;
   };

@@ -90,7 +90,7 @@ def test_bench_refuses_several_gpus():
 
 def test_traffic_record_gated_by_kernel_source():
     """The committed HBM-traffic record names the multi-shift pass code it was measured on;
-    bench.py reports it only while that code, and the bytes per launch, are unchanged."""
+    bench.py reports it only while that code, and the size of a full launch, are unchanged."""
     import importlib.util
     import json
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
@@ -99,28 +99,32 @@ def test_traffic_record_gated_by_kernel_source():
     rec = json.load(open(os.path.join(ROOT, "profiles", "k_ms_passes_16x4_traffic.json")))
     same = rec["kernel_source_hash"] == bench.kernel_source_hash()
     for name, fam in rec["families"].items():
-        got = bench.measured_traffic(name, fam["algorithmic_bytes_per_launch"])
-        assert got == (fam["hbm_bytes_per_launch"] if same else None)
-        assert bench.measured_traffic(name, fam["algorithmic_bytes_per_launch"] + 1) is None
+        got = bench.measured_traffic(name, fam["full_launch_algorithmic_bytes"])
+        assert got == ((fam["hbm_bytes_per_launch"], fam["ratio"]) if same else (None, None))
+        assert bench.measured_traffic(name, fam["full_launch_algorithmic_bytes"] + 1) == (None, None)
+        # the full launch of the benchmark's 16^4 system: two sources, three fields
+        assert fam["full_launch_algorithmic_bytes"] == bench.full_bytes(name, 1, 16 ** 4)
 
 
 @pytest.mark.parametrize("name", ["k_ms_passes_16x4_traffic.json",
                                   "k_ms_passes_16x3x32x12_traffic.json"])
 def test_traffic_records_consistent(name):
     """Each committed HBM-traffic record is internally consistent: the scale factors are
-    the copy calibration's bytes over its counter readings, and each family's bytes per
-    launch are the scaled FETCH_SIZE + WRITE_SIZE medians averaged over its two passes."""
+    the copy calibration's bytes over its counter readings, the mean algorithmic bytes per
+    launch lie within a full launch's, and the ratio is the mean HBM bytes over them."""
     import json
     rec = json.load(open(os.path.join(ROOT, "profiles", name)))
     cal = rec["calibration"]
     kib = cal["copy_bytes"] / 1024
     assert abs(cal["fetch_scale"] - kib / cal["fetch_kib"]) < 1e-3
     assert abs(cal["write_scale"] - kib / cal["write_kib"]) < 1e-3
+    assert rec["families"]
     for fam in rec["families"].values():
-        ks = fam["kernels"]
-        assert len(ks) == 2
-        tot = sum(fam["fetch_kib_per_dispatch"][k] * 1024 * cal["fetch_scale"]
-                  + fam["write_kib_per_dispatch"][k] * 1024 * cal["write_scale"] for k in ks) / 2
-        assert abs(tot - fam["hbm_bytes_per_launch"]) <= 1e-6 * tot + 1
-        assert abs(fam["ratio"] - tot / fam["algorithmic_bytes_per_launch"]) < 1e-3
-        assert fam["hbm_bytes_per_launch"] >= fam["algorithmic_bytes_per_launch"]
+        assert len(fam["kernels"]) == 2
+        assert 0 < fam["algorithmic_bytes_per_launch"] <= fam["full_launch_algorithmic_bytes"]
+        assert abs(fam["ratio"] - fam["hbm_bytes_per_launch"] / fam["algorithmic_bytes_per_launch"]) < 1e-3
+        for k in fam["kernels"]:
+            assert fam["dispatches"][k] > 0
+            # medians of whole dispatches: written bytes never exceed a full launch's field
+            field = fam["full_launch_algorithmic_bytes"] / 3
+            assert fam["write_kib_median"][k] * 1024 * cal["write_scale"] <= field * 1.01
