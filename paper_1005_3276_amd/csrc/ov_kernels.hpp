@@ -82,6 +82,7 @@ struct SysDev {
   void* fft_tmp;            // momentum-space scratch field (kernel precision)
   int off_xy, off_z, off_t; // first workgroup of this system in each transform pass
   int xc;                   // x values per workgroup in the t pass (divides X, xc T <= 64)
+  double* pcs;              // [V] preconditioner scale per momentum (k_pcg_table), or null
 };
 
 // CG scalar slots
@@ -400,22 +401,33 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
 // registers, the current plane in LDS (sh: 4 X Y values) for the x and y
 // neighbours.  Next to the stencil operands each site may take one more spinor
 // of its own (the epilogue operand, from ep).  begin() issues the loads of the
-// first plane, so a caller can put them in flight before its scalar work; run<PIPE>()
-// walks the planes, with PIPE loading the operands of plane k + 1 before plane k is
-// computed (else after it).  For each site, epi(i, w, e) receives w = (H_W f)_i and the epilogue
-// operand e and returns a partial sum; run() returns the total.  Every thread of
-// the block must call run().
-template <class R>
+// first plane, and with PIPE those of the second one as well, so that a caller puts
+// them in flight before its scalar work and a two-plane workgroup waits for memory
+// once; with PIPE, run() then loads the operands of plane k + 1 while plane k is
+// computed (two register sets), else after it.  For each site, epi(i, w, e) receives
+// w = (H_W f)_i and the epilogue operand e and returns a partial sum; run() returns
+// the total.  Every thread of the block must call run().
+template <class R, bool PIPE>
 struct ZmMarch {
   const c2<R>* f;
   const c2<R>* ep;
   int V, XY, Z, base, z0, tf_off, tb_off, jxf, jxb, jyf, jyb;
   c2<R> prev[4], cur[4], next[4], tf[4], tb[4], e[4];
+  c2<R> next2[4], tf2[4], tb2[4], e2[4];  // PIPE: operands of the following plane
 
   __device__ __forceinline__ int plane(int z) const { return base + XY * (z < Z ? z : z - Z); }
 
+  // operands of the plane after the one at site index i (z index z of that plane)
+  __device__ __forceinline__ void load_ahead(int i, int z) {
+    const int i2 = i + XY;  // plane z + 1 < Z
+    load_sp<R>(f, V, plane(z + 2), next2);
+    load_sp<R>(f, V, i2 + tf_off, tf2);
+    load_sp<R>(f, V, i2 + tb_off, tb2);
+    if (ep) load_sp<R>(ep, V, i2, e2);
+  }
+
   __device__ __forceinline__ void begin(const c2<R>* __restrict__ f_, const c2<R>* __restrict__ ep_,
-                                        const Geo& g, int i0) {
+                                        const Geo& g, int i0, int zc) {
     f = f_;
     ep = ep_;
     const int X = g.X, Y = g.Y, T = g.T;
@@ -442,22 +454,16 @@ struct ZmMarch {
     load_sp<R>(f, V, i + tf_off, tf);
     load_sp<R>(f, V, i + tb_off, tb);
     if (ep) load_sp<R>(ep, V, i, e);
+    if (PIPE && zc > 1) load_ahead(i, z0);
   }
 
-  template <bool PIPE, class Epi>
+  template <class Epi>
   __device__ __forceinline__ double run(int zc, const Geo& g, R diag, c2<R>* sh, Epi epi) {
     const int j = threadIdx.x;
     double acc = 0.0;
     for (int k = 0; k < zc; ++k) {
       const int i = plane(z0 + k);
-      c2<R> next2[4], tf2[4], tb2[4], e2[4];
-      if (PIPE && k + 1 < zc) {
-        const int i2 = i + XY;  // plane z0 + k + 1 < Z
-        load_sp<R>(f, V, plane(z0 + k + 2), next2);
-        load_sp<R>(f, V, i2 + tf_off, tf2);
-        load_sp<R>(f, V, i2 + tb_off, tb2);
-        if (ep) load_sp<R>(ep, V, i2, e2);
-      }
+      if (PIPE && k > 0 && k + 1 < zc) load_ahead(i, z0 + k);
       __syncthreads();  // reads of the previous plane are done
 #pragma unroll
       for (int q = 0; q < 4; ++q) sh[q * XY + j] = cur[q];
@@ -517,10 +523,10 @@ __device__ __forceinline__ int zm_first_site(const SysDev& S, int lb) {
   return lb * S.spb;
 }
 
-// The z-marching passes prefetch the next plane's operands in FP32 only: in FP64 the
-// second register set would halve the co-resident workgroups.
-template <class R>
-constexpr bool ZM_PIPE_FOR = sizeof(R) == sizeof(float);
+// The z-marching passes prefetch the next plane's operands in FP32 always; in FP64
+// (template flag PIPE) only for launches too small to fill the chip twice over, where
+// the second register set costs no co-resident workgroups and the second plane's
+// loads would otherwise wait for the first plane's compute.
 
 // ------------------------------------------------------- multi-shift: t pass
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
@@ -531,7 +537,8 @@ constexpr bool ZM_PIPE_FOR = sizeof(R) == sizeof(float);
 // is consumed, and each wave finishes the reduction and the shift recurrences
 // on its own (identical bits in every wave), so the only barrier is the final
 // block reduction.
-template <class R, bool ZM>
+// ZM: 0 plain passes, 1 z-marching, 2 z-marching with the next plane prefetched.
+template <class R, int ZM>
 __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const MsParams* mp,
                                           double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
@@ -568,13 +575,12 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
   const int i0 = ZM ? zm_first_site<R>(S, lb) : lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
   int i = i0 + threadIdx.x;
-  constexpr bool zm = ZM;  // z-marching (mp->zm planes per workgroup)
-  constexpr bool ZM_PIPE = ZM_PIPE_FOR<R>;
+  constexpr bool zm = ZM > 0;  // z-marching (mp->zm planes per workgroup)
   const bool have = !zm && i < i1;
   Nbr<R> nb;
   c2<R> q[4];
-  ZmMarch<R> zmm;
-  if (zm) zmm.begin(rin, n > 0 ? tp : nullptr, g, i0);
+  ZmMarch<R, ZM == 2> zmm;
+  if (zm) zmm.begin(rin, n > 0 ? tp : nullptr, g, i0, mp->zm);
   if (have) {
     load_nbr<R>(rin, g, i, nb);
     if (n > 0) load_sp<R>(tp, g.V, i, q);
@@ -622,7 +628,7 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
 
   double acc = 0.0;
   if (zm) {
-    acc = zmm.template run<ZM_PIPE>(mp->zm, g, (R)mp->diag, sh, [&](int ii, c2<R>* o, const c2<R>* qq) -> double {
+    acc = zmm.run(mp->zm, g, (R)mp->diag, sh, [&](int ii, c2<R>* o, const c2<R>* qq) -> double {
       if (n > 0) {
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2)
@@ -660,7 +666,7 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
   return i1 - i0;
 }
 
-template <class R, bool ZM>
+template <class R, int ZM>
 __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const MsParams* mp,
                                           double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
@@ -678,13 +684,12 @@ __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const 
   const int i0 = ZM ? zm_first_site<R>(S, lb) : lb * S.spb;
   const int i1 = min(g.V, i0 + S.spb);
   int i = i0 + threadIdx.x;
-  constexpr bool zm = ZM;
-  constexpr bool ZM_PIPE = ZM_PIPE_FOR<R>;
+  constexpr bool zm = ZM > 0;
   const bool have = !zm && i < i1;
   Nbr<R> nb;
   c2<R> r[4];
-  ZmMarch<R> zmm;
-  if (zm) zmm.begin(tn, rin, g, i0);
+  ZmMarch<R, ZM == 2> zmm;
+  if (zm) zmm.begin(tn, rin, g, i0, mp->zm);
   if (have) {
     load_nbr<R>(tn, g, i, nb);
     load_sp<R>(rin, g.V, i, r);
@@ -705,7 +710,7 @@ __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const 
   const R alpha = (R)alpha_d;
   double acc = 0.0;
   if (zm) {
-    acc = zmm.template run<ZM_PIPE>(mp->zm, g, (R)mp->diag, sh, [&](int ii, c2<R>* w, const c2<R>* r0) -> double {
+    acc = zmm.run(mp->zm, g, (R)mp->diag, sh, [&](int ii, c2<R>* w, const c2<R>* r0) -> double {
       c2<R> rr[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) rr[k] = r0[k];
@@ -760,7 +765,7 @@ __device__ __forceinline__ void stamp_block(unsigned long long* ts, unsigned lon
 // is consumed, and each wave finishes the reduction and the shift recurrences
 // on its own (identical bits in every wave), so the only barrier is the final
 // block reduction.
-template <class R, bool ZM>
+template <class R, int ZM>
 __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
@@ -776,7 +781,7 @@ __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
 
 // Iteration n, r pass:
 //   alpha_n = rho_n / |t_n|^2;  r_{n+1} = r_n - alpha_n H t_n;  partial |r_{n+1}|^2.
-template <class R, bool ZM>
+template <class R, int ZM>
 __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
@@ -869,13 +874,13 @@ __global__ void __launch_bounds__(256) k_ms_persistent(const SysDev* __restrict_
   for (int n = 0; n < L; ++n) {
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_t_block<R, false>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
+      ms_t_block<R, 0>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_r_block<R, false>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
+      ms_r_block<R, 0>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;
@@ -1458,13 +1463,11 @@ __global__ void __launch_bounds__(256) k_fft_z(const SysDev* __restrict__ sys, i
   }
 }
 
-// Momentum-space operator on the four spin components v of one momentum.
-__device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, double m_im,
-                                             double shift, double sx, double sy, double sz,
-                                             double st, double w, double2 v[4]) {
-  const double s2sin = sx * sx + sy * sy + sz * sz + st * st;
+// Free-field Dirac operator at one momentum: D = a0 + i c gamma.s (s_mu = sin p_mu,
+// w the Wilson term), for the form's sign function.
+__device__ __forceinline__ void free_symbol(const SymParams& sp, double s2sin, double w,
+                                            double& a0, double& c) {
   const double s2 = w * w + s2sin;
-  double a0, c;
   if (sp.form == DIRAC_DSLASH) {
     const double sq = sqrt(s2);
     a0 = 0.0;
@@ -1479,14 +1482,32 @@ __device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, d
     a0 = 1.0 + Rr * w;
     c = Rr;
   }
-  if (sp.kind == SYM_PCG) {  // M0^dag M0 = (a^2 + mu^2 + c^2 |s|^2) 1: a scalar per momentum
-    // (a shifted solve takes the free shifted operator, M0^dag M0 + sigma)
-    const double A = a0 + m_re;
-    const double sc = 1.0 / (A * A + m_im * m_im + c * c * s2sin + shift);
+}
+
+// The preconditioner of CG on MdagM at one momentum: M0^dag M0 = (a^2 + mu^2 + c^2 |s|^2) 1
+// is a scalar (a shifted solve takes the free shifted operator, M0^dag M0 + sigma), so
+// P = (M0^dag M0 + sigma)^-1 is one number per momentum.
+__device__ __forceinline__ double pcg_scale(const SymParams& sp, double m_re, double m_im,
+                                            double shift, double s2sin, double w) {
+  double a0, c;
+  free_symbol(sp, s2sin, w, a0, c);
+  const double A = a0 + m_re;
+  return 1.0 / (A * A + m_im * m_im + c * c * s2sin + shift);
+}
+
+// Momentum-space operator on the four spin components v of one momentum.
+__device__ __forceinline__ void apply_symbol(const SymParams& sp, double m_re, double m_im,
+                                             double shift, double sx, double sy, double sz,
+                                             double st, double w, double2 v[4]) {
+  const double s2sin = sx * sx + sy * sy + sz * sz + st * st;
+  if (sp.kind == SYM_PCG) {
+    const double sc = pcg_scale(sp, m_re, m_im, shift, s2sin, w);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = double2{v[k].x * sc, v[k].y * sc};
     return;
   }
+  double a0, c;
+  free_symbol(sp, s2sin, w, a0, c);
   // out = (A v + i (cg gamma.s v + c5 g5 v)) * scale
   double A = a0, cg = c, c5 = 0.0, scale = 1.0;
   if (sp.kind == SYM_D_DAG) {
@@ -1612,6 +1633,233 @@ __global__ void __launch_bounds__(256) k_fft_t_sym(const SysDev* __restrict__ sy
     }
     f[(size_t)spin * V + (xb + xl) + X * (y + Y * (z + Z * t))] = acc;
   }
+}
+
+// ------------------------------------------- transforms of fixed length
+// Lines of compile-time length N (N = 2^a 3^b) transformed in registers: mixed-radix
+// Cooley-Tukey, decimation in time, every index a constant after unrolling, twiddles
+// e^{sgn 2 pi i m / N} folded into the code from a constant table.
+
+// cos and sin of 2 pi j / n at compile time: reduction to |r| <= pi/4 by quadrants,
+// then the Taylor series (terms to r^25: below 1e-17 there).
+struct CS {
+  double c, s;
+};
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr CS ce_cossin(long long j, long long n) {
+  j %= n;
+  if (j < 0) j += n;
+  // quadrant q = round(4 j / n), r = 2 pi (j / n - q / 4)
+  const long long q = (8 * j + n) / (2 * n);
+  const double r = kTwoPi * ((double)(4 * j - q * n) / (double)(4 * n));
+  const double r2 = r * r;
+  double sn = r, cs = 1.0, ts = r, tc = 1.0;
+  for (int k = 1; k <= 12; ++k) {
+    ts *= -r2 / (double)((2 * k) * (2 * k + 1));
+    tc *= -r2 / (double)((2 * k - 1) * (2 * k));
+    sn += ts;
+    cs += tc;
+  }
+  switch (q & 3) {
+    case 0: return CS{cs, sn};
+    case 1: return CS{-sn, cs};
+    case 2: return CS{-cs, -sn};
+    default: return CS{sn, -cs};
+  }
+}
+
+template <int N>
+struct TwTable {
+  double c[N], s[N];
+  constexpr TwTable() : c(), s() {
+    for (int j = 0; j < N; ++j) {
+      const CS v = ce_cossin(j, N);
+      c[j] = v.c;
+      s[j] = v.s;
+    }
+  }
+};
+template <int N>
+constexpr TwTable<N> kTw{};
+
+template <class R>
+__host__ __device__ __forceinline__ c2<R> cmul(c2<R> a, R wr, R wi) {
+  return c2<R>{a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+}
+
+// out[k] = sum_j a[j] e^{SGN 2 pi i j k / N}, in place, natural order in and out.
+template <class R, int N, int SGN>
+struct LineFft {
+  static_assert(N >= 1, "length");
+  static constexpr int P = (N % 2 == 0) ? 2 : 3;
+  static constexpr int Q = N / P;
+  static_assert(N == 1 || N % P == 0, "lengths are 2^a 3^b");
+  __host__ __device__ static __forceinline__ void run(c2<R> (&a)[N]) {
+    if constexpr (N == 1) {
+      return;
+    } else {
+      c2<R> sub[P][Q];
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sub[p][q] = a[q * P + p];
+#pragma unroll
+      for (int p = 0; p < P; ++p) LineFft<R, Q, SGN>::run(sub[p]);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        c2<R> t[P];
+        t[0] = sub[0][k];
+#pragma unroll
+        for (int p = 1; p < P; ++p) {
+          const int m = (p * k) % N;
+          t[p] = cmul<R>(sub[p][k], (R)kTw<N>.c[m], (R)(SGN * kTw<N>.s[m]));
+        }
+        if constexpr (P == 2) {
+          a[k] = c2<R>{t[0].x + t[1].x, t[0].y + t[1].y};
+          a[k + Q] = c2<R>{t[0].x - t[1].x, t[0].y - t[1].y};
+        } else {
+          // radix 3: w3 = e^{SGN 2 pi i / 3} = -1/2 + SGN i sqrt(3)/2
+          const R h = (R)0.8660254037844386467637231707529 * (R)SGN;
+          const c2<R> sp{t[1].x + t[2].x, t[1].y + t[2].y};
+          const c2<R> sm{t[1].x - t[2].x, t[1].y - t[2].y};
+          const c2<R> m0{t[0].x - (R)0.5 * sp.x, t[0].y - (R)0.5 * sp.y};
+          a[k] = c2<R>{t[0].x + sp.x, t[0].y + sp.y};
+          a[k + Q] = c2<R>{m0.x - h * sm.y, m0.y + h * sm.x};
+          a[k + 2 * Q] = c2<R>{m0.x + h * sm.y, m0.y - h * sm.x};
+        }
+      }
+    }
+  }
+};
+
+// Forward (inverse) transform of the x, y and z axes of one (time slice, spin) of a
+// system, through LDS: e_in -> fft_tmp with the time twist (fft_tmp -> e_out with the
+// untwist and 1/V).  Replaces k_fft_xy + k_fft_z for lattices whose spatial extents
+// have templates.  Workgroup b of the run starting at system s0: system s0 + b / (4 T),
+// spin b % 4, time slice (b / 4) % T.  LDS rows padded by one value against bank
+// conflicts of the x lines.
+template <class R, int NX, int NY, int NZ, int INV>
+__global__ void __launch_bounds__(256) k_fft_xyz(const SysDev* __restrict__ sys, int s0,
+                                                 int periodic) {
+  constexpr int PX = NX + 1;
+  constexpr int NV = NX * NY * NZ;
+  constexpr int SGN = INV ? 1 : -1;
+  __shared__ c2<R> A[PX * NY * NZ];
+  const int T = sys[s0].g.T;
+  const int b = blockIdx.x;
+  const SysDev& S = sys[s0 + b / (4 * T)];
+  if (S.active && *S.active == 0) return;
+  const int spin = b & 3;
+  const int t = (b >> 2) % T;
+  const int V = S.g.V;
+  const size_t off = (size_t)spin * V + (size_t)t * NV;
+  const c2<R>* in = (const c2<R>*)(INV ? S.fft_tmp : S.e_in) + off;
+  c2<R>* out = (c2<R>*)(INV ? S.e_out : S.fft_tmp) + off;
+  double tr = 1.0, ti = 0.0;  // twist (forward) / untwist and normalisation (inverse)
+  if (S.g.bc < 0 && !periodic) sincospi((double)SGN * (double)t / (double)T, &ti, &tr);
+  if (INV) {
+    tr /= (double)V;
+    ti /= (double)V;
+  }
+  const R rr = (R)tr, ri = (R)ti;
+  for (int i = threadIdx.x; i < NV; i += blockDim.x) {
+    const c2<R> v = in[i];
+    A[i % NX + PX * (i / NX)] = INV ? v : cmul<R>(v, rr, ri);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < NY * NZ; l += blockDim.x) {  // x lines
+    c2<R> a[NX];
+#pragma unroll
+    for (int x = 0; x < NX; ++x) a[x] = A[x + PX * l];
+    LineFft<R, NX, SGN>::run(a);
+#pragma unroll
+    for (int x = 0; x < NX; ++x) A[x + PX * l] = a[x];
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < NX * NZ; l += blockDim.x) {  // y lines
+    const int x = l % NX, z = l / NX;
+    c2<R> a[NY];
+#pragma unroll
+    for (int y = 0; y < NY; ++y) a[y] = A[x + PX * (y + NY * z)];
+    LineFft<R, NY, SGN>::run(a);
+#pragma unroll
+    for (int y = 0; y < NY; ++y) A[x + PX * (y + NY * z)] = a[y];
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < NX * NY; l += blockDim.x) {  // z lines
+    c2<R> a[NZ];
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) a[z] = A[l % NX + PX * (l / NX + NY * z)];
+    LineFft<R, NZ, SGN>::run(a);
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) A[l % NX + PX * (l / NX + NY * z)] = a[z];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NV; i += blockDim.x) {
+    const c2<R> v = A[i % NX + PX * (i / NX)];
+    out[i] = INV ? cmul<R>(v, rr, ri) : v;
+  }
+}
+
+// The preconditioner's scale per momentum of every system (sites of the table's
+// partition; momentum (kx, ky, kz, kt) at the site index of (x, y, z, t)), for
+// k_fft_t_pcg: the same arithmetic as the SYM_PCG symbol.
+__global__ void __launch_bounds__(256) k_pcg_table(const SysDev* __restrict__ sys,
+                                                   const int* __restrict__ bmap, int nb_total,
+                                                   const SymParams sp) {
+  const int L = xcd_logical_block(nb_total);
+  const SysDev& S = sys[bmap[L]];
+  const int lb = L - S.blk0;
+  const int X = S.g.X, Y = S.g.Y, Z = S.g.Z, T = S.g.T, V = S.g.V;
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  const double tshift = (S.g.bc < 0 && !sp.periodic) ? 1.0 : 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    int r = i;
+    const int kx = r % X; r /= X;
+    const int ky = r % Y; r /= Y;
+    const int kz = r % Z;
+    const int kt = r / Z;
+    double sx, cx, sy, cy, sz, cz, st, ct;
+    sincospi(2.0 * (double)kx / (double)X, &sx, &cx);
+    sincospi(2.0 * (double)ky / (double)Y, &sy, &cy);
+    sincospi(2.0 * (double)kz / (double)Z, &sz, &cz);
+    sincospi((2.0 * kt + tshift) / (double)T, &st, &ct);
+    const double w = sp.diag - (cx + cy + cz + ct);
+    const double s2sin = sx * sx + sy * sy + sz * sz + st * st;
+    S.pcs[i] = pcg_scale(sp, S.pc_re, S.pc_im, S.shift, s2sin, w);
+  }
+}
+
+// t axis forward, the preconditioner's scale, t axis inverse, in place on fft_tmp: the
+// t pass of z = P r.  P does not mix spins, so one thread owns one (site, spin) line of
+// NT values in registers; a wave reads 64 consecutive sites of one time slice per load
+// (coalesced), and no LDS is needed.  Workgroup (64 threads) b of the run starting at
+// system s0: system s0 + b / (4 nchunk), chunk of 64 sites (b / 4) % nchunk, spin b % 4
+// (the four spins of a chunk are neighbours, so they share the scale lines in L2).
+template <class R, int NT>
+__global__ void __launch_bounds__(64) k_fft_t_pcg(const SysDev* __restrict__ sys, int s0,
+                                                  int nchunk) {
+  const int b = blockIdx.x;
+  const SysDev& S = sys[s0 + b / (4 * nchunk)];
+  if (S.active && *S.active == 0) return;
+  const int XYZ = S.g.X * S.g.Y * S.g.Z;
+  const int site = ((b >> 2) % nchunk) * 64 + (int)threadIdx.x;
+  if (site >= XYZ) return;
+  c2<R>* f = (c2<R>*)S.fft_tmp + (size_t)(b & 3) * S.g.V + site;
+  const double* sc = S.pcs + site;
+  c2<R> a[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) a[t] = f[(size_t)t * XYZ];
+  LineFft<R, NT, -1>::run(a);
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const double m = sc[(size_t)k * XYZ];
+    a[k] = c2<R>{(R)((double)a[k].x * m), (R)((double)a[k].y * m)};
+  }
+  LineFft<R, NT, 1>::run(a);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) f[(size_t)t * XYZ] = a[t];
 }
 
 // Yukawa epilogue of a momentum-space D (psi = e_in, D psi already in e_out):

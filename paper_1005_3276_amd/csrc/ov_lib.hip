@@ -34,6 +34,7 @@ struct ov_ctx {
   int persistent = 0;            // cooperative persistent multi-shift kernel (0: per-pass kernels)
   std::map<long long, int> n_est;  // (precision, tolerance) -> iterations the last multi-shift needed
   int coop_cap[2] = {0, 0};      // co-resident workgroups of k_ms_persistent<double/float>
+  int n_cu = 0;                   // compute units of the device (0: not queried yet)
   int device = 0;
   std::string err;
   double a[MAXP], b[MAXP], delta = 0;
@@ -176,6 +177,7 @@ struct SysBuf {
   long long* stat;
   double* dstat;
   double *coef_term, *coef_c, *coef_d, *cg_s;
+  double* pcs = nullptr;  // preconditioner scale per momentum (preconditioned solves)
   int *act_cg, *act_ru;
   void *vR, *fftR;              // preconditioned solve: M0^-1 p / M^dag u, transform scratch
   // second multi-shift entry of the inner operator in Ginsparg-Wilson form (ms_b*)
@@ -277,6 +279,7 @@ void carve(Bump& bp, SysBuf& s, const Plan& pl) {
     s.vR = bp.take(pl.mixed ? v32 : v64);
     s.fftR = bp.take(pl.mixed ? v32 : v64);
   }
+  s.pcs = (pl.solve && pl.pc) ? (double*)bp.take(sizeof(double) * s.V) : nullptr;
   s.shx = s.shp = nullptr;
   s.shc = nullptr;
   s.nshift = (pl.solve && pl.nshift > 0) ? pl.nshift : 0;
@@ -671,6 +674,7 @@ SysDev base_dev(const SysBuf& b) {
   d.shp = b.shp;
   d.shc = b.shc;
   d.nshift = b.nshift;
+  d.pcs = b.pcs;
   d.xc = b.xc;
   d.off_xy = b.off_xy;
   d.off_z = b.off_z;
@@ -763,6 +767,18 @@ void collect_samples(ov_ctx* c) {
   }
   c->ev_use.clear();
   for (int& k : c->ev_call_count) k = 0;
+}
+
+// Compute units of the context's device.
+int cu_count(ov_ctx* c) {
+  if (c->n_cu <= 0) {
+    int cus = 0;
+    c->n_cu = (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) ==
+                   hipSuccess && cus > 0)
+                  ? cus
+                  : 256;
+  }
+  return c->n_cu;
 }
 
 // Co-resident workgroups of k_ms_persistent<R> on this device (0: no cooperative launch).
@@ -870,20 +886,28 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
     }
     return m;
   };
+  // z-marching with the next plane prefetched: always in FP32; in FP64 when the launch
+  // holds at most one workgroup per compute unit (its second register set would
+  // otherwise halve the co-resident workgroups)
+  const int zmode = !mps.zm ? 0 : (sizeof(R) == sizeof(float) || nbt_ <= cu_count(c)) ? 2 : 1;
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);
-      if (mps.zm)
-        k_ms_t<R, true><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (zmode == 2)
+        k_ms_t<R, 2><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      else if (zmode == 1)
+        k_ms_t<R, 1><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
       else
-        k_ms_t<R, false><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+        k_ms_t<R, 0><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 4 : 1, bytes);
-      if (mps.zm)
-        k_ms_r<R, true><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (zmode == 2)
+        k_ms_r<R, 2><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      else if (zmode == 1)
+        k_ms_r<R, 1><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
       else
-        k_ms_r<R, false><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+        k_ms_r<R, 0><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
   }
   k_ms_coef<<<nent, 256, 0, E.st>>>(T, nent, L, mp);
@@ -899,11 +923,7 @@ void launch_combine(const Engine& E, int t, int mode) {
   k_ms_combine<R><<<E.nb_total, E.lead->block, 0, E.st>>>(tab(E, t), E.bmap, E.nb_total, mode);
 }
 
-// e_out = op(e_in) for a momentum-space operator (forward DFTs, symbol, inverse
-// DFTs through fft_tmp); e_out may alias e_in.
-template <class R>
-void launch_sym(const Engine& E, int t, int kind) {
-  const ov_ctx* c = E.lead;
+SymParams sym_params(const ov_ctx* c, int kind) {
   SymParams sp{};
   sp.kind = kind;
   sp.form = c->p.dirac == OV_DIRAC_OVERLAP_EXACT ? DIRAC_EXACT
@@ -916,6 +936,131 @@ void launch_sym(const Engine& E, int t, int kind) {
     sp.b[k] = k < sp.np ? c->b[k] : 0.0;
   }
   sp.periodic = kind == SYM_BOSON ? 1 : 0;  // scalar fields are periodic in time
+  return sp;
+}
+
+// x, y, z transforms of systems [s0, s0 + ns) of spatial extents d through one
+// fixed-length kernel; false when no kernel has these extents (FP64 24^3 does not fit
+// in LDS).
+template <class R, int NX, int NY, int NZ>
+void xyz_launch(const Engine& E, const SysDev* T, int s0, int ns, int nt, int inv, int periodic) {
+  const unsigned grid = (unsigned)(4 * nt * ns);
+  if (inv)
+    k_fft_xyz<R, NX, NY, NZ, 1><<<grid, 256, 0, E.st>>>(T, s0, periodic);
+  else
+    k_fft_xyz<R, NX, NY, NZ, 0><<<grid, 256, 0, E.st>>>(T, s0, periodic);
+}
+
+template <class R>
+bool xyz_fixed(const Engine* E, const SysDev* T, int s0, int ns, const int* d, int inv,
+               int periodic) {
+  struct Shape {
+    int x, y, z;
+    void (*go)(const Engine&, const SysDev*, int, int, int, int, int);
+  };
+  static const Shape shapes[] = {
+      {4, 4, 4, xyz_launch<R, 4, 4, 4>},       {8, 8, 8, xyz_launch<R, 8, 8, 8>},
+      {12, 12, 12, xyz_launch<R, 12, 12, 12>}, {16, 16, 16, xyz_launch<R, 16, 16, 16>},
+      {16, 16, 8, xyz_launch<R, 16, 16, 8>},
+  };
+  for (const Shape& sh : shapes)
+    if (d[0] == sh.x && d[1] == sh.y && d[2] == sh.z) {
+      if (E) sh.go(*E, T, s0, ns, d[3], inv, periodic);
+      return true;
+    }
+  if (sizeof(R) == sizeof(float) && d[0] == 24 && d[1] == 24 && d[2] == 24) {
+    if (E) xyz_launch<float, 24, 24, 24>(*E, T, s0, ns, d[3], inv, periodic);
+    return true;
+  }
+  return false;
+}
+
+template <class R, int NT>
+void tpcg_launch(const Engine& E, const SysDev* T, int s0, int ns, int xyz) {
+  const int nchunk = (xyz + 63) / 64;
+  k_fft_t_pcg<R, NT><<<(unsigned)(4 * nchunk * ns), 64, 0, E.st>>>(T, s0, nchunk);
+}
+
+template <class R>
+bool tpcg_fixed(const Engine* E, const SysDev* T, int s0, int ns, const int* d) {
+  const int xyz = d[0] * d[1] * d[2];
+  switch (d[3]) {
+    case 4: if (E) tpcg_launch<R, 4>(*E, T, s0, ns, xyz); return true;
+    case 8: if (E) tpcg_launch<R, 8>(*E, T, s0, ns, xyz); return true;
+    case 12: if (E) tpcg_launch<R, 12>(*E, T, s0, ns, xyz); return true;
+    case 16: if (E) tpcg_launch<R, 16>(*E, T, s0, ns, xyz); return true;
+    case 24: if (E) tpcg_launch<R, 24>(*E, T, s0, ns, xyz); return true;
+    case 32: if (E) tpcg_launch<R, 32>(*E, T, s0, ns, xyz); return true;
+    case 48:
+      if (sizeof(R) != sizeof(float)) return false;  // 48 FP64 values per thread spill
+      if (E) tpcg_launch<float, 48>(*E, T, s0, ns, xyz);
+      return true;
+    default: return false;
+  }
+}
+
+// OV_FFT_FIXED=0 keeps every momentum-space operator on the generic passes.
+bool fft_fixed_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("OV_FFT_FIXED");
+    v = (e && *e == '0') ? 0 : 1;
+  }
+  return v == 1;
+}
+
+// Runs of consecutive systems on one lattice (same extents and time boundary).
+void lattice_runs(const Engine& E, std::vector<std::pair<int, int>>& runs) {
+  runs.clear();
+  for (int s = 0; s < E.nsys; ++s) {
+    const ov_params& p = E.sb[s].ctx->p;
+    if (!runs.empty()) {
+      const ov_params& q = E.sb[runs.back().first].ctx->p;
+      if (std::equal(p.dims, p.dims + 4, q.dims) && p.bc_t == q.bc_t) {
+        ++runs.back().second;
+        continue;
+      }
+    }
+    runs.push_back({s, 1});
+  }
+}
+
+// z = P r of the preconditioned CG by the fixed-length kernels (three passes: x y z,
+// t with the scale table, x y z inverse) when every system's extents have one.
+template <class R>
+bool pcg_fixed(const Engine& E, int t) {
+  if (!fft_fixed_enabled()) return false;
+  std::vector<std::pair<int, int>> runs;
+  lattice_runs(E, runs);
+  for (const auto& r : runs) {
+    const int* d = E.sb[r.first].ctx->p.dims;
+    if (!E.sb[r.first].pcs || !xyz_fixed<R>(nullptr, nullptr, 0, 0, d, 0, 0) ||
+        !tpcg_fixed<R>(nullptr, nullptr, 0, 0, d))
+      return false;
+  }
+  const SysDev* T = tab(E, t);
+  for (const auto& r : runs)
+    xyz_fixed<R>(&E, T, r.first, r.second, E.sb[r.first].ctx->p.dims, 0, 0);
+  for (const auto& r : runs) tpcg_fixed<R>(&E, T, r.first, r.second, E.sb[r.first].ctx->p.dims);
+  for (const auto& r : runs)
+    xyz_fixed<R>(&E, T, r.first, r.second, E.sb[r.first].ctx->p.dims, 1, 0);
+  return true;
+}
+
+// The preconditioner's scale per momentum of every system (once per solve: it depends
+// on the preconditioner mass and the shift only).
+void pcg_table(const Engine& E) {
+  if (!E.pl.pc) return;
+  k_pcg_table<<<E.nb_total, E.lead->block, 0, E.st>>>(tab(E, T_PC_Z), E.bmap, E.nb_total,
+                                                      sym_params(E.lead, SYM_PCG));
+}
+
+// e_out = op(e_in) for a momentum-space operator (forward DFTs, symbol, inverse
+// DFTs through fft_tmp); e_out may alias e_in.
+template <class R>
+void launch_sym(const Engine& E, int t, int kind) {
+  if (kind == SYM_PCG && pcg_fixed<R>(E, t)) return;
+  const SymParams sp = sym_params(E.lead, kind);
   const SysDev* T = tab(E, t);
   k_fft_xy<R><<<E.nb_xy, 256, 0, E.st>>>(T, E.nsys, 0, sp.periodic);
   k_fft_z<R><<<E.nb_z, 256, 0, E.st>>>(T, E.nsys, 0);
@@ -1750,6 +1895,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
   const int max_outer = E.max_outer > 0 ? E.max_outer : P.max_outer;
   Range range(sizeof(R) == sizeof(double) ? "ov solve engine FP64" : "ov solve engine mixed");
   TRY((build_solve_tables<R>(E, bvec, phi)));
+  pcg_table(E);
   TRY(reset_stats(E));
   std::vector<int> fcg(ns, 1), fru(ns, 1);
   TRY(set_flags(E, fcg, fru));
