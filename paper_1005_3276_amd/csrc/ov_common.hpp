@@ -19,6 +19,31 @@ template <class R> using c2 = typename cplx_of<R>::type;
 
 template <class V> __device__ __forceinline__ V cmul_i(V a) { return V{-a.y, a.x}; }  // i*a
 
+// Global-memory access.  Field and scalar buffers are reached through plain pointers held
+// in descriptors, which the compiler accesses with flat instructions; a flat access counts
+// on the LDS/scalar wait counter as well, so every LDS access, cross-lane reduction or
+// scalar load after it would also wait for all loads in flight.  These helpers access the
+// buffers in address space 1 (global instructions, vector memory counter only).
+#define OV_GLOBAL __attribute__((address_space(1)))
+template <class R>
+using ev2 = R __attribute__((ext_vector_type(2)));
+
+template <class R>
+__device__ __forceinline__ c2<R> ldg2(const c2<R>* p, size_t k) {
+  const ev2<R> e = ((const OV_GLOBAL ev2<R>*)p)[k];
+  return c2<R>{e.x, e.y};
+}
+
+template <class R>
+__device__ __forceinline__ void stg2(c2<R>* p, size_t k, c2<R> v) {
+  ((OV_GLOBAL ev2<R>*)p)[k] = ev2<R>{v.x, v.y};
+}
+
+template <class T>
+__device__ __forceinline__ T ldg(const T* p, size_t k) {
+  return ((const OV_GLOBAL T*)p)[k];
+}
+
 // Per-system geometry.  bc is the time-boundary phase of the fermion (+1/-1).
 struct Geo {
   int X, Y, Z, T;
@@ -40,13 +65,13 @@ struct Geo {
 template <class R>
 __device__ __forceinline__ void load_sp(const c2<R>* __restrict__ f, int V, int i, c2<R> v[4]) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) v[s] = f[(size_t)s * V + i];
+  for (int s = 0; s < 4; ++s) v[s] = ldg2<R>(f, (size_t)s * V + i);
 }
 
 template <class R>
 __device__ __forceinline__ void store_sp(c2<R>* __restrict__ f, int V, int i, const c2<R> v[4]) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) f[(size_t)s * V + i] = v[s];
+  for (int s = 0; s < 4; ++s) stg2<R>(f, (size_t)s * V + i, v[s]);
 }
 
 // The nine spinors the stencil reads at site i, loaded in one batch so that

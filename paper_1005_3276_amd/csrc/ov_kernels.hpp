@@ -300,11 +300,10 @@ __global__ void __launch_bounds__(256) k_hw_lds(const SysDev* __restrict__ sys, 
 // not push the input planes, which neighbouring workgroups still read, out of L2.
 template <class R>
 __device__ __forceinline__ void store_sp_nt(c2<R>* __restrict__ f, int V, int i, const c2<R> v[4]) {
-  using E = R __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const E e = {v[s].x, v[s].y};
-    __builtin_nontemporal_store(e, (E*)(f + (size_t)s * V + i));
+    const ev2<R> e = {v[s].x, v[s].y};
+    __builtin_nontemporal_store(e, (OV_GLOBAL ev2<R>*)(f + (size_t)s * V + i));
   }
 }
 
@@ -550,7 +549,7 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
   const int done = (n > 0) ? S.h_ctl[0] : 0;
   // partials of rho_n (this lane's share, summed in a fixed order)
   double pr = 0.0;
-  for (int j = lane; j < nblk; j += 64) pr += S.part_b[j];
+  for (int j = lane; j < nblk; j += 64) pr += ldg(S.part_b, j);
   // scalar history for lane k = shift k
   const int k = lane;
   double zk1 = 1.0, zk2 = 1.0, a1 = 0.0, a2 = 1.0, rho_m1 = 1.0, rho_m2 = 1.0, rho0 = 0.0;
@@ -675,7 +674,7 @@ __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const 
   const int act_sys = S.active ? *S.active : 1;
   const int done = S.h_ctl[0];
   double pg = 0.0;
-  for (int j = lane; j < nblk; j += 64) pg += S.part_a[j];
+  for (int j = lane; j < nblk; j += 64) pg += ldg(S.part_a, j);
   const double rho = S.h_rho[n];
   const size_t slot = (size_t)4 * g.V;
   const c2<R>* tn = (const c2<R>*)S.basis + (size_t)n * slot;
@@ -904,147 +903,35 @@ __global__ void k_bar_reset(GridBar* gb) {
 //   eps = H acc = sum_j d_j t_j,  d_j = c_j - beta_j c_{j+1}   (H r_j = t_j - beta_{j-1} t_{j-1}).
 constexpr int COEF_LDS_ITERS = 160;  // history rows staged in LDS (larger N reads global)
 
-__global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys, int nsys,
-                                                 int launched, const MsParams mp_) {
-  __shared__ int sh_N;
-  __shared__ double sh_res[MAXP];
-  __shared__ int l_nk[MAXP];
-  __shared__ double l_rho[COEF_LDS_ITERS + 1];
-  __shared__ double l_alpha[COEF_LDS_ITERS + 1];
-  __shared__ unsigned int l_act[COEF_LDS_ITERS + 1];
-  __shared__ double l_zeta[(COEF_LDS_ITERS + 1) * MAXP];
-  // second-function coefficients (entries with coef_d2): tridiagonal solves per shift
-  __shared__ double l_u[MAXP][COEF_LDS_ITERS + 1];
-  __shared__ double l_cp[MAXP][COEF_LDS_ITERS + 1];
-  __shared__ double l_g[COEF_LDS_ITERS + 1], l_td[COEF_LDS_ITERS + 1], l_to[COEF_LDS_ITERS + 1];
-  const int s = blockIdx.x;
-  if (s >= nsys) return;
-  const SysDev& S = sys[s];
-  if (S.active && *S.active == 0) return;
-  const MsParams* mp = &mp_;
+// LDS of k_ms_coef.  The staged path works on these arrays only (no pointer that may
+// point to either LDS or global memory: such accesses compile to flat instructions, and
+// each of them waits for every global store in flight).
+struct CoefLds {
+  int N;
+  int nk[MAXP];
+  double res[MAXP];
+  double rho[COEF_LDS_ITERS + 1], alpha[COEF_LDS_ITERS + 1], c[COEF_LDS_ITERS + 1];
+  unsigned int act[COEF_LDS_ITERS + 1];
+  double zeta[(COEF_LDS_ITERS + 1) * MAXP];
+  double u[MAXP][COEF_LDS_ITERS + 1];   // recurrence factors, then the terms (k, j)
+  double cp[MAXP][COEF_LDS_ITERS + 1];
+  double g[COEF_LDS_ITERS + 1], td[COEF_LDS_ITERS + 1], to[COEF_LDS_ITERS + 1];
+};
+
+// Second function of the same Krylov space (entries with coef_d2 set):
+//   w = H r(A)^2 psi = sum_j d2_j t_j,   so that eps^2 psi = A r(A)^2 psi = H w.
+// The CG scalars give the Lanczos tridiagonal of A on v_j = (-1)^j r_j / |r_j|:
+//   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_j,j+1 = sqrt(beta_j)/alpha_j,
+// and r(A)^2 psi ~ |psi| V r(T)^2 e_1 with r(T)^2 e_1 = sum_l a_l (T + b_l)^-1 g,
+// g = sum_k a_k (T + b_k)^-1 e_1: 2 np tridiagonal solves (T + b is positive definite,
+// elimination without pivoting is stable), one thread per shift.  Coefficients on r_j:
+// c2_j = |psi| (-1)^j h_j / |r_j|; on t_j: d2_j = c2_j - beta_j c2_{j+1}.
+// Work arrays U, CP ([MAXP][ld]), G, TD, TO ([N]) all in LDS or all in global memory.
+__device__ __forceinline__ void coef_second(const SysDev& S, const MsParams* mp, int N,
+                                            const double* rho, const double* alph, double* U,
+                                            double* CP, double* G, double* TD, double* TO,
+                                            int ld) {
   const int np = mp->np;
-  const int cap = mp->cap;
-  if (threadIdx.x == 0) {
-    int N;
-    if (S.h_ctl[0]) {
-      N = S.h_ctl[1];
-      if (S.h_ctl[2]) S.h_ctl[3] |= 1 << S.h_ctl[2];
-    } else {  // not finished within the launched iterations: use what exists
-      N = launched > 0 ? launched - 1 : 0;
-      S.h_ctl[1] = N;
-      S.h_ctl[3] |= 1 << 2;
-    }
-    sh_N = N;
-    S.stat[0] += N;
-    S.stat[1] += 1;
-    if (N > S.stat[2]) S.stat[2] = N;
-    if (N > S.stat[3]) S.stat[3] = N;  // max N since the host last cleared it
-  }
-  __syncthreads();
-  const int N = sh_N;
-  // stage rows 0..N of the history (coalesced) when they fit
-  const bool staged = N <= COEF_LDS_ITERS;
-  const double* rho = S.h_rho;
-  const double* alph = S.h_alpha;
-  const unsigned int* actv = S.h_active;
-  const double* zeta = S.h_zeta;
-  if (staged) {
-    for (int j = threadIdx.x; j <= N; j += blockDim.x) {
-      l_rho[j] = S.h_rho[j];
-      l_alpha[j] = S.h_alpha[j];
-      l_act[j] = S.h_active[j];
-    }
-    for (int q = threadIdx.x; q < (N + 1) * MAXP; q += blockDim.x) l_zeta[q] = S.h_zeta[q];
-    __syncthreads();
-    rho = l_rho;
-    alph = l_alpha;
-    actv = l_act;
-    zeta = l_zeta;
-  }
-  const double rho0 = rho[0];
-  for (int k = threadIdx.x; k < MAXP; k += blockDim.x) {
-    sh_res[k] = 0.0;
-    l_nk[k] = N;
-  }
-  __syncthreads();
-  if (staged) {
-    // N_k (first iteration with shift k inactive) and the recurrence factors
-    // alpha_{j,k}, beta_{j,k} for every (k, j) at once; the per-shift chains below
-    // are then multiply-adds on LDS operands
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-      const unsigned int a = actv[j];
-      for (int k = 0; k < np; ++k)
-        if (!(a & (1u << k))) atomicMin(&l_nk[k], j);
-    }
-    for (int q = threadIdx.x; q < np * N; q += blockDim.x) {
-      const int k = q / N, j = q - k * N;
-      const double zj = zeta[(size_t)j * MAXP + k];
-      const double zr = zeta[(size_t)(j + 1) * MAXP + k] / zj;
-      l_u[k][j] = alph[j] * zr;
-      l_cp[k][j] = (rho[j + 1] / rho[j]) * zr * zr;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < np; k += blockDim.x) {
-      const int Nk = l_nk[k];
-      double Sk = 0.0;
-      for (int j = Nk - 1; j >= 0; --j) {
-        Sk = l_u[k][j] + l_cp[k][j] * Sk;
-        S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zeta[(size_t)j * MAXP + k] * Sk;
-      }
-      for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
-      if (rho0 > 0.0) sh_res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
-    }
-  } else {
-    for (int k = threadIdx.x; k < np; k += blockDim.x) {
-      int Nk = N;
-      for (int j = 0; j < N; ++j)
-        if (!(actv[j] & (1u << k))) { Nk = j; break; }
-      double Sk = 0.0;
-      for (int j = Nk - 1; j >= 0; --j) {
-        const double zj = zeta[(size_t)j * MAXP + k];
-        const double zr = zeta[(size_t)(j + 1) * MAXP + k] / zj;
-        const double aj = alph[j] * zr;
-        const double bj = (rho[j + 1] / rho[j]) * zr * zr;
-        Sk = aj + bj * Sk;
-        S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zj * Sk;
-      }
-      for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
-      if (rho0 > 0.0) sh_res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
-    }
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    double c = 0.0;
-    for (int k = 0; k < np; ++k) c += S.coef_term[(size_t)k * cap + j];
-    S.coef_c[j] = c;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    const double cn = (j + 1 < N) ? S.coef_c[j + 1] : 0.0;
-    S.coef_d[j] = S.coef_c[j] - (rho[j + 1] / rho[j]) * cn;
-  }
-  if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int k = 0; k < np; ++k) mx = fmax(mx, sh_res[k]);
-    S.dstat[0] = mx;
-  }
-  if (!S.coef_d2 || N == 0) return;
-  // Second function of the same Krylov space (entries with coef_d2 set):
-  //   w = H r(A)^2 psi = sum_j d2_j t_j,   so that eps^2 psi = A r(A)^2 psi = H w.
-  // The CG scalars give the Lanczos tridiagonal of A on v_j = (-1)^j r_j / |r_j|:
-  //   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_j,j+1 = sqrt(beta_j)/alpha_j,
-  // and r(A)^2 psi ~ |psi| V r(T)^2 e_1 with r(T)^2 e_1 = sum_l a_l (T + b_l)^-1 g,
-  // g = sum_k a_k (T + b_k)^-1 e_1: 2 np tridiagonal solves (T + b is positive definite,
-  // elimination without pivoting is stable), one thread per shift.  Coefficients on r_j:
-  // c2_j = |psi| (-1)^j h_j / |r_j|; on t_j: d2_j = c2_j - beta_j c2_{j+1}.
-  // Work arrays in LDS while the history is staged there (N <= COEF_LDS_ITERS), else
-  // in the entry's global scratch coef_sq; T's entries are computed once.
-  const int ld = staged ? COEF_LDS_ITERS + 1 : cap;
-  double* U = staged ? &l_u[0][0] : S.coef_sq;                                // [MAXP][ld]
-  double* CP = staged ? &l_cp[0][0] : S.coef_sq + (size_t)MAXP * cap;          // [MAXP][ld]
-  double* G = staged ? l_g : S.coef_sq + (size_t)2 * MAXP * cap;              // [ld]
-  double* TD = staged ? l_td : S.coef_sq + (size_t)2 * MAXP * cap + cap;      // [ld]
-  double* TO = staged ? l_to : S.coef_term;  // the shifts' terms are consumed by now
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     TD[j] = 1.0 / alph[j] + (j > 0 ? (rho[j] / rho[j - 1]) / alph[j - 1] : 0.0);
     TO[j] = sqrt(rho[j + 1] / rho[j]) / alph[j];
@@ -1101,6 +988,142 @@ __global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys,
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     const double cn = (j + 1 < N) ? G[j + 1] : 0.0;
     S.coef_d2[j] = G[j] - (rho[j + 1] / rho[j]) * cn;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ms_coef(const SysDev* __restrict__ sys, int nsys,
+                                                 int launched, const MsParams mp_) {
+  __shared__ CoefLds L;
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  const SysDev& S = sys[s];
+  if (S.active && *S.active == 0) return;
+  const MsParams* mp = &mp_;
+  const int np = mp->np;
+  const int cap = mp->cap;
+  if (threadIdx.x == 0) {
+    int N;
+    if (S.h_ctl[0]) {
+      N = S.h_ctl[1];
+      if (S.h_ctl[2]) S.h_ctl[3] |= 1 << S.h_ctl[2];
+    } else {  // not finished within the launched iterations: use what exists
+      N = launched > 0 ? launched - 1 : 0;
+      S.h_ctl[1] = N;
+      S.h_ctl[3] |= 1 << 2;
+    }
+    L.N = N;
+  }
+  for (int k = threadIdx.x; k < MAXP; k += blockDim.x) L.res[k] = 0.0;
+  __syncthreads();
+  const int N = L.N;
+  if (N <= COEF_LDS_ITERS) {
+    // stage rows 0..N of the history (coalesced)
+    for (int j = threadIdx.x; j <= N; j += blockDim.x) {
+      L.rho[j] = S.h_rho[j];
+      L.alpha[j] = S.h_alpha[j];
+      L.act[j] = S.h_active[j];
+    }
+    for (int q = threadIdx.x; q < (N + 1) * MAXP; q += blockDim.x) L.zeta[q] = S.h_zeta[q];
+    __syncthreads();
+    // N_k, the first iteration with shift k inactive: one wave per shift, a ballot per
+    // 64 iterations
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int k = threadIdx.x >> 6; k < np; k += nw) {
+      int nk = N;
+      for (int j0 = 0; j0 < N; j0 += 64) {
+        const int j = j0 + lane;
+        const unsigned long long m = __ballot(j < N && !(L.act[j] & (1u << k)));
+        if (m) {
+          nk = j0 + __ffsll((long long)m) - 1;
+          break;
+        }
+      }
+      if (lane == 0) L.nk[k] = nk;
+    }
+    // the recurrence factors alpha_{j,k}, beta_{j,k} for every (k, j) at once; the
+    // per-shift chains below are then multiply-adds on LDS operands
+    for (int q = threadIdx.x; q < np * N; q += blockDim.x) {
+      const int k = q / N, j = q - k * N;
+      const double zj = L.zeta[j * MAXP + k];
+      const double zr = L.zeta[(j + 1) * MAXP + k] / zj;
+      L.u[k][j] = L.alpha[j] * zr;
+      L.cp[k][j] = (L.rho[j + 1] / L.rho[j]) * zr * zr;
+    }
+    __syncthreads();
+    const double rho0 = L.rho[0];
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      const int Nk = L.nk[k];
+      double Sk = 0.0;
+      for (int j = Nk - 1; j >= 0; --j) {
+        Sk = L.u[k][j] + L.cp[k][j] * Sk;
+        L.u[k][j] = mp->coef[k] * L.zeta[j * MAXP + k] * Sk;  // term (k, j)
+      }
+      for (int j = Nk; j < N; ++j) L.u[k][j] = 0.0;
+      if (rho0 > 0.0) L.res[k] = fabs(L.zeta[Nk * MAXP + k]) * sqrt(L.rho[Nk] / rho0);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      double c = 0.0;
+      for (int k = 0; k < np; ++k) c += L.u[k][j];
+      L.c[j] = c;
+      S.coef_c[j] = c;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      const double cn = (j + 1 < N) ? L.c[j + 1] : 0.0;
+      S.coef_d[j] = L.c[j] - (L.rho[j + 1] / L.rho[j]) * cn;
+    }
+    if (S.coef_d2 && N > 0)
+      coef_second(S, mp, N, L.rho, L.alpha, &L.u[0][0], &L.cp[0][0], L.g, L.td, L.to,
+                  COEF_LDS_ITERS + 1);
+  } else {
+    // long histories read global memory (terms through the entry's coef_term)
+    const double* rho = S.h_rho;
+    const double* alph = S.h_alpha;
+    const double* zeta = S.h_zeta;
+    const double rho0 = rho[0];
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      int Nk = N;
+      for (int j = 0; j < N; ++j)
+        if (!(S.h_active[j] & (1u << k))) { Nk = j; break; }
+      double Sk = 0.0;
+      for (int j = Nk - 1; j >= 0; --j) {
+        const double zj = zeta[(size_t)j * MAXP + k];
+        const double zr = zeta[(size_t)(j + 1) * MAXP + k] / zj;
+        const double aj = alph[j] * zr;
+        const double bj = (rho[j + 1] / rho[j]) * zr * zr;
+        Sk = aj + bj * Sk;
+        S.coef_term[(size_t)k * cap + j] = mp->coef[k] * zj * Sk;
+      }
+      for (int j = Nk; j < N; ++j) S.coef_term[(size_t)k * cap + j] = 0.0;
+      if (rho0 > 0.0) L.res[k] = fabs(zeta[(size_t)Nk * MAXP + k]) * sqrt(rho[Nk] / rho0);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      double c = 0.0;
+      for (int k = 0; k < np; ++k) c += S.coef_term[(size_t)k * cap + j];
+      S.coef_c[j] = c;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      const double cn = (j + 1 < N) ? S.coef_c[j + 1] : 0.0;
+      S.coef_d[j] = S.coef_c[j] - (rho[j + 1] / rho[j]) * cn;
+    }
+    if (S.coef_d2 && N > 0) {
+      __syncthreads();  // the terms are consumed: coef_term becomes TO
+      coef_second(S, mp, N, rho, alph, S.coef_sq, S.coef_sq + (size_t)MAXP * cap,
+                  S.coef_sq + (size_t)2 * MAXP * cap, S.coef_sq + (size_t)2 * MAXP * cap + cap,
+                  S.coef_term, cap);
+    }
+  }
+  if (threadIdx.x == 0) {  // statistics, off the critical path
+    double mx = 0.0;
+    for (int k = 0; k < np; ++k) mx = fmax(mx, L.res[k]);
+    S.dstat[0] = mx;
+    S.stat[0] += N;
+    S.stat[1] += 1;
+    if (N > S.stat[2]) S.stat[2] = N;
+    if (N > S.stat[3]) S.stat[3] = N;  // max N since the host last cleared it
   }
 }
 
@@ -1763,7 +1786,7 @@ __global__ void __launch_bounds__(256) k_fft_xyz(const SysDev* __restrict__ sys,
   }
   const R rr = (R)tr, ri = (R)ti;
   for (int i = threadIdx.x; i < NV; i += blockDim.x) {
-    const c2<R> v = in[i];
+    const c2<R> v = ldg2<R>(in, i);
     A[i % NX + PX * (i / NX)] = INV ? v : cmul<R>(v, rr, ri);
   }
   __syncthreads();
@@ -1797,7 +1820,7 @@ __global__ void __launch_bounds__(256) k_fft_xyz(const SysDev* __restrict__ sys,
   __syncthreads();
   for (int i = threadIdx.x; i < NV; i += blockDim.x) {
     const c2<R> v = A[i % NX + PX * (i / NX)];
-    out[i] = INV ? cmul<R>(v, rr, ri) : v;
+    stg2<R>(out, i, INV ? cmul<R>(v, rr, ri) : v);
   }
 }
 
@@ -1850,16 +1873,16 @@ __global__ void __launch_bounds__(64) k_fft_t_pcg(const SysDev* __restrict__ sys
   const double* sc = S.pcs + site;
   c2<R> a[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) a[t] = f[(size_t)t * XYZ];
+  for (int t = 0; t < NT; ++t) a[t] = ldg2<R>(f, (size_t)t * XYZ);
   LineFft<R, NT, -1>::run(a);
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
-    const double m = sc[(size_t)k * XYZ];
+    const double m = ldg(sc, (size_t)k * XYZ);
     a[k] = c2<R>{(R)((double)a[k].x * m), (R)((double)a[k].y * m)};
   }
   LineFft<R, NT, 1>::run(a);
 #pragma unroll
-  for (int t = 0; t < NT; ++t) f[(size_t)t * XYZ] = a[t];
+  for (int t = 0; t < NT; ++t) stg2<R>(f, (size_t)t * XYZ, a[t]);
 }
 
 // Yukawa epilogue of a momentum-space D (psi = e_in, D psi already in e_out):
