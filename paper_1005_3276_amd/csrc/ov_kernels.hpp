@@ -2198,7 +2198,8 @@ __device__ __forceinline__ void basis_sum(const c2<R>* __restrict__ basis,
 
 // combine: e1 = sum_j dA_j tA_j (entry A: eps(v)), e23 = sum_j dB_j tB_j (entry
 // B: eps(g5 (1 + Y) v)), w = (1 + |1 + c|^2) v + (1 + c*) g5 e1 + e23 -> A.e_out;
-// partial Re <v, w> -> A.part_c.  v = A.e_in.
+// partial Re <v, w> -> A.part_a (the passes' partials are dead by then; k_cg_misc op 7
+// reduces them while it writes part_c).  v = A.e_in.
 template <class R>
 __global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ ta,
                                                      const SysDev* __restrict__ tb,
@@ -2243,7 +2244,7 @@ __global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ t
     store_sp<R>((c2<R>*)A.e_out, V, i, w);
   }
   const double tot = block_sum(acc, lds);
-  if (threadIdx.x == 0) A.part_c[lb] = tot;
+  if (threadIdx.x == 0) A.part_a[lb] = tot;  // part_a: free once the passes are done
 }
 
 // ------------------------ FP64 true residual in Ginsparg-Wilson form (Sec. 2.2)
@@ -2566,6 +2567,71 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
   if (threadIdx.x == 0) S.part_b[lb] = tot;
 }
 
+// k_cg_p followed by k_gw_prep in one pass (the Ginsparg-Wilson inner operator):
+// p = z + beta p -> cg_p; the second multi-shift source g5 (1 + Y) p -> B.src; partials
+// |p|^2 -> part_b (the CG table's and entry A's, one buffer) and |g5 (1 + Y) p|^2 ->
+// B.part_b.  S: CG table, A and B: the two entries of the inner multi-shift.
+template <class R>
+__global__ void __launch_bounds__(256) k_cg_p_gw(const SysDev* __restrict__ sys,
+                                                 const SysDev* __restrict__ ta,
+                                                 const SysDev* __restrict__ tb,
+                                                 const int* __restrict__ bmap, int nb_total,
+                                                 int use_beta) {
+  __shared__ double lds[17];
+  const int L = xcd_logical_block(nb_total);
+  const int s = bmap[L];
+  const SysDev& S = sys[s];
+  const SysDev& A = ta[s];
+  const SysDev& B = tb[s];
+  if (S.active && *S.active == 0) return;
+  const int lb = L - S.blk0;
+  const int V = S.g.V;
+  const double beta = use_beta ? S.cg_s[CG_BETA] : 0.0;
+  use_beta = use_beta && beta != 0.0;  // restart: p = z, the old p is never read
+  if (lb == 0 && threadIdx.x == 0) {
+    S.stat[3] = 0;
+    B.stat[3] = 0;
+  }
+  const int i0 = lb * S.spb;
+  const int i1 = min(V, i0 + S.spb);
+  double av = 0.0, as = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    c2<R> r[4], p[4];
+    load_sp<R>((const c2<R>*)(S.cg_z ? S.cg_z : S.cg_r), V, i, r);
+    if (use_beta) {
+      load_sp<R>((const c2<R>*)S.cg_p, V, i, p);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        p[k] = c2<R>{(R)((double)r[k].x + beta * (double)p[k].x),
+                     (R)((double)r[k].y + beta * (double)p[k].y)};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] = r[k];
+    }
+    store_sp<R>((c2<R>*)S.cg_p, V, i, p);
+    const double2 ph = A.phi[i];
+    const double cpr = A.m_re + A.g_re * ph.x - A.g_im * ph.y;
+    const double cpi = A.m_im + A.g_re * ph.y + A.g_im * ph.x;
+    c2<R> o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double cr = cpr, ci = (k < 2) ? -cpi : cpi;  // c- = conj(c+)
+      const double vr = (double)p[k].x, vi = (double)p[k].y;
+      const double g5 = k < 2 ? -1.0 : 1.0;
+      o[k] = c2<R>{(R)(g5 * (vr + cr * vr - ci * vi)), (R)(g5 * (vi + cr * vi + ci * vr))};
+    }
+    store_sp<R>((c2<R>*)B.src, V, i, o);
+    av += norm2_sp(p);
+    as += norm2_sp(o);
+  }
+  const double tv = block_sum(av, lds);
+  const double ts = block_sum(as, lds);
+  if (threadIdx.x == 0) {
+    S.part_b[lb] = tv;
+    B.part_b[lb] = ts;
+  }
+}
+
 // Fill / axpy helpers used by the reliable-update solver.
 //   op 0: x64 += x (low precision), x = 0
 //   op 1: r = b (FP64 AoS -> planar R), partial |b|^2 -> part_c
@@ -2574,6 +2640,9 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
 //   op 4: partial |r|^2 -> part_c
 //   op 5: x += alpha p, r -= alpha e_in, partial |r|^2 -> part_c
 //   op 6: partial Re <r, z> -> part_b  (z = cg_z)
+//   op 7: op 5 with alpha = rho / Re <p, w> from the partials in part_a, reduced by every
+//         workgroup in the fixed order of k_cg_scalar (identical bits everywhere);
+//         workgroup 0 records PAP and ALPHA
 template <class R>
 __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                   int nb_total, int op) {
@@ -2586,6 +2655,17 @@ __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys,
   const int V = S.g.V;
   const int i0 = lb * S.spb;
   const int i1 = min(V, i0 + S.spb);
+  double alpha7 = 0.0;
+  const bool own_alpha = op == 7;
+  if (own_alpha) {
+    const double pap = sum_partials(S.part_a, S.nblk, lds);
+    alpha7 = S.cg_s[CG_RR] / pap;
+    if (lb == 0 && threadIdx.x == 0) {
+      S.cg_s[CG_PAP] = pap;
+      S.cg_s[CG_ALPHA] = alpha7;
+    }
+    op = 5;
+  }
   double acc = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     if (op == 0) {
@@ -2632,7 +2712,7 @@ __global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys,
       load_sp<R>((const c2<R>*)S.cg_r, V, i, rv);
       acc += norm2_sp(rv);
     } else if (op == 5) {
-      const double alpha = S.cg_s[CG_ALPHA];
+      const double alpha = own_alpha ? alpha7 : S.cg_s[CG_ALPHA];
       c2<R> xv[4], pv[4], rv[4], qv[4];
       load_sp<R>((const c2<R>*)S.cg_x, V, i, xv);
       load_sp<R>((const c2<R>*)S.cg_p, V, i, pv);

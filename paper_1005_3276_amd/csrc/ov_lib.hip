@@ -1343,7 +1343,7 @@ ov_status check_roles(Engine& E, bool fp64_inner) {
       for (int t : {T_CG, T_CG_RU}) ok &= need(t, s, T[t]->cg_z, "cg_z");
     }
     if (E.pl.gw) {
-      // k_gw_prep / multi-shift / k_gw_combine over both entries, k_cg_scalar on A
+      // k_cg_p_gw / multi-shift / k_gw_combine over both entries
       for (int e = 0; e < 2; ++e) {
         const SysDev* G = &E.hgwtab[(size_t)e * E.nsys + s];
         const int t = 100 + e;
@@ -2024,8 +2024,12 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     Range it_range("ov CG iteration");
     TRY(run_graph(E, ikey, [&]() {
       const int nb = E.nb_total, bl = c->block;
-      k_cg_p<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);
+      if (E.pl.gw && !E.pl.fft)  // p = z + beta p and the second inner source in one pass
+        k_cg_p_gw<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.gwtab, E.gwtab + ns, E.bmap, nb, 1);
+      else
+        k_cg_p<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 1);
       bool fused_update = false;  // EPI_MDAG_CG did the update and the beta scalar
+      int update_op = 5;          // k_cg_misc: x += alpha p, r -= alpha w
       if (E.pl.fft) {  // momentum-space D: M = D + Y exactly, no inner solve
         launch_sym<R>(E, T_F_M, SYM_D);
         k_yuk<R><<<nb, bl, 0, E.st>>>(tab(E, T_F_M), E.bmap, nb, 0);
@@ -2033,10 +2037,9 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         launch_sym<R>(E, T_F_MD, SYM_D_DAG);
         k_yuk<R><<<nb, bl, 0, E.st>>>(tab(E, T_F_MD), E.bmap, nb, 1);
       } else if (E.pl.gw) {  // w = MdagM p in Ginsparg-Wilson form: both signs in one multi-shift
-        k_gw_prep<R><<<nb, bl, 0, E.st>>>(E.gwtab, E.gwtab + ns, E.bmap, nb);
         launch_ms_tab<R>(E, E.gwtab, E.gwbmap, 2 * nb, 2 * ns, mpR, LR);
         k_gw_combine<R><<<nb, bl, 0, E.st>>>(E.gwtab, E.gwtab + ns, E.bmap, nb);
-        k_cg_scalar<<<ns, 256, 0, E.st>>>(E.gwtab, ns, 1);  // alpha = rho / Re<p, w>
+        update_op = 7;  // alpha = rho / Re<p, w> inside the update
       } else {
         launch_ms<R>(E, T_IN_M, mpR, LR);
         launch_combine<R>(E, T_IN_M, EPI_M);
@@ -2051,7 +2054,7 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
         }
       }
       if (fused_update) return;
-      k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 5);
+      k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, update_op);
       if (pc) {
         launch_sym<R>(E, T_PC_Z, SYM_PCG);
         k_cg_misc<R><<<nb, bl, 0, E.st>>>(tab(E, T_CG), E.bmap, nb, 6);
