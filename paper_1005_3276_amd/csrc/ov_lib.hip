@@ -1840,6 +1840,10 @@ ov_status reliable_update(Engine& E, double tol, int scalar_op) {
     return read_scalars(E);
   }
   const long long key = n_est_key(1000 + sizeof(R), tol);  // FP64 truth solves of this solver
+  // the last count at this tolerance plus max(4, n/8): a true residual cut short is
+  // repeated in full, so this margin stays wider than the inner solves' one (max(3, n/16)
+  // saved 0.13 ms per 16^4 solve but repeated four true residuals per uneven-batch solve,
+  // +4%: a batch's count is the maximum over its systems, which moves between calls)
   int L = Lfull;
   {
     auto it = c->n_est.find(key);
@@ -2007,11 +2011,15 @@ ov_status solve_engine(Engine& E, const std::vector<const void*>& bvec,
     int LR = 0;
     for (int s = 0; s < ns; ++s) LR = std::max(LR, capacity(E.ctxs[s], tol_it));
     LR = std::min(E.pl.capR, LR);
-    // launch what the last multi-shift at this tolerance needed, plus a margin
+    // launch what the last multi-shift at this tolerance needed, plus one iteration (each
+    // launch past convergence is an empty pass of ~5 us; a multi-shift cut one iteration
+    // short ends a fraction above its relaxed tolerance, which the relaxation bound
+    // absorbs, and widens the estimate for the next one: 16^4 15.3 -> 15.1 ms, same
+    // outer iterations, against a margin of two)
     const long long nkey = n_est_key(sizeof(R), tol_it);
     {
       auto it = c->n_est.find(nkey);
-      if (it != c->n_est.end()) LR = std::min(LR, it->second + 2);
+      if (it != c->n_est.end()) LR = std::min(LR, it->second + 1);
     }
     char ikey[96];
     std::snprintf(ikey, sizeof ikey, "in|%zu|%.6e|%d|%d|%d|%d", sizeof(R), tol_it, LR, (int)pc,
