@@ -12,6 +12,7 @@ Prints ONE JSON line.  Only one GPU is supported: --gpus N > 1 exits.
 """
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -122,9 +123,14 @@ def record_traffic(out_path, fetch_csv, write_csv, workload, systems, sources, v
                            "fetch_scale": fs, "write_scale": ws},
            "families": {}}
     for fam, prec, esize in (("fp32_inner", "float", 8), ("fp64_truth", "double", 16)):
-        ks = [f"k_ms_t<{prec}, true>", f"k_ms_r<{prec}, true>"]
-        full = {k: next((n for n in fetch if k in n), None) for k in ks}
-        if not all(full.values()) or not all(full[k] in write for k in ks):
+        # every launch form of the family's two passes (plain / z-marching variants)
+        full = {}
+        for n in fetch:
+            m = re.search(r"(k_ms_[tr]<%s, \d+>)" % prec, n)
+            if m and n in write:
+                full[m.group(1)] = n
+        ks = sorted(full)
+        if not any(k.startswith("k_ms_t") for k in ks) or not any(k.startswith("k_ms_r") for k in ks):
             continue
         field = systems * sources * 4 * volume * esize  # one field per source, whole launch
         alg_full = 3 * field

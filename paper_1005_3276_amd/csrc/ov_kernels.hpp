@@ -400,12 +400,12 @@ __global__ void __launch_bounds__(256) k_hw_zm(const SysDev* __restrict__ sys, d
 // registers, the current plane in LDS (sh: 4 X Y values) for the x and y
 // neighbours.  Next to the stencil operands each site may take one more spinor
 // of its own (the epilogue operand, from ep).  begin() issues the loads of the
-// first plane, and with PIPE those of the second one as well, so that a caller puts
-// them in flight before its scalar work and a two-plane workgroup waits for memory
-// once; with PIPE, run() then loads the operands of plane k + 1 while plane k is
-// computed (two register sets), else after it.  For each site, epi(i, w, e) receives
-// w = (H_W f)_i and the epilogue operand e and returns a partial sum; run() returns
-// the total.  Every thread of the block must call run().
+// first plane, so that a caller puts them in flight before its scalar work (a
+// workgroup whose system has converged reads no more than that); with PIPE, run()
+// loads the operands of plane k + 1 while plane k is computed (two register sets),
+// else after it.  For each site, epi(i, w, e) receives w = (H_W f)_i and the epilogue
+// operand e and returns a partial sum; run() returns the total.  Every thread of the
+// block must call run().
 template <class R, bool PIPE>
 struct ZmMarch {
   const c2<R>* f;
@@ -426,7 +426,7 @@ struct ZmMarch {
   }
 
   __device__ __forceinline__ void begin(const c2<R>* __restrict__ f_, const c2<R>* __restrict__ ep_,
-                                        const Geo& g, int i0, int zc) {
+                                        const Geo& g, int i0) {
     f = f_;
     ep = ep_;
     const int X = g.X, Y = g.Y, T = g.T;
@@ -453,7 +453,6 @@ struct ZmMarch {
     load_sp<R>(f, V, i + tf_off, tf);
     load_sp<R>(f, V, i + tb_off, tb);
     if (ep) load_sp<R>(ep, V, i, e);
-    if (PIPE && zc > 1) load_ahead(i, z0);
   }
 
   template <class Epi>
@@ -462,7 +461,7 @@ struct ZmMarch {
     double acc = 0.0;
     for (int k = 0; k < zc; ++k) {
       const int i = plane(z0 + k);
-      if (PIPE && k > 0 && k + 1 < zc) load_ahead(i, z0 + k);
+      if (PIPE && k + 1 < zc) load_ahead(i, z0 + k);
       __syncthreads();  // reads of the previous plane are done
 #pragma unroll
       for (int q = 0; q < 4; ++q) sh[q * XY + j] = cur[q];
@@ -522,10 +521,9 @@ __device__ __forceinline__ int zm_first_site(const SysDev& S, int lb) {
   return lb * S.spb;
 }
 
-// The z-marching passes prefetch the next plane's operands in FP32 always; in FP64
-// (template flag PIPE) only for launches too small to fill the chip twice over, where
-// the second register set costs no co-resident workgroups and the second plane's
-// loads would otherwise wait for the first plane's compute.
+// The z-marching passes prefetch the next plane's operands in FP32 only (ZM = 2): in
+// FP64 the second register set would halve the co-resident workgroups of large launches
+// and measured no faster on small ones.
 
 // ------------------------------------------------------- multi-shift: t pass
 // Iteration n.  Finishes rho_n = |r_n|^2 (partials of the previous kernel),
@@ -579,7 +577,7 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
   Nbr<R> nb;
   c2<R> q[4];
   ZmMarch<R, ZM == 2> zmm;
-  if (zm) zmm.begin(rin, n > 0 ? tp : nullptr, g, i0, mp->zm);
+  if (zm) zmm.begin(rin, n > 0 ? tp : nullptr, g, i0);
   if (have) {
     load_nbr<R>(rin, g, i, nb);
     if (n > 0) load_sp<R>(tp, g.V, i, q);
@@ -688,7 +686,7 @@ __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const 
   Nbr<R> nb;
   c2<R> r[4];
   ZmMarch<R, ZM == 2> zmm;
-  if (zm) zmm.begin(tn, rin, g, i0, mp->zm);
+  if (zm) zmm.begin(tn, rin, g, i0);
   if (have) {
     load_nbr<R>(tn, g, i, nb);
     load_sp<R>(rin, g.V, i, r);
@@ -1785,9 +1783,20 @@ __global__ void __launch_bounds__(256) k_fft_xyz(const SysDev* __restrict__ sys,
     ti /= (double)V;
   }
   const R rr = (R)tr, ri = (R)ti;
-  for (int i = threadIdx.x; i < NV; i += blockDim.x) {
-    const c2<R> v = ldg2<R>(in, i);
-    A[i % NX + PX * (i / NX)] = INV ? v : cmul<R>(v, rr, ri);
+  {
+    // every load of the volume in flight before the first LDS store (256 threads)
+    constexpr int NL = (NV + 255) / 256;
+    c2<R> v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int i = q * 256 + (int)threadIdx.x;
+      if (i < NV) v[q] = ldg2<R>(in, i);
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int i = q * 256 + (int)threadIdx.x;
+      if (i < NV) A[i % NX + PX * (i / NX)] = INV ? v[q] : cmul<R>(v[q], rr, ri);
+    }
   }
   __syncthreads();
   for (int l = threadIdx.x; l < NY * NZ; l += blockDim.x) {  // x lines

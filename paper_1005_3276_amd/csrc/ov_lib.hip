@@ -34,7 +34,6 @@ struct ov_ctx {
   int persistent = 0;            // cooperative persistent multi-shift kernel (0: per-pass kernels)
   std::map<long long, int> n_est;  // (precision, tolerance) -> iterations the last multi-shift needed
   int coop_cap[2] = {0, 0};      // co-resident workgroups of k_ms_persistent<double/float>
-  int n_cu = 0;                   // compute units of the device (0: not queried yet)
   int device = 0;
   std::string err;
   double a[MAXP], b[MAXP], delta = 0;
@@ -769,18 +768,6 @@ void collect_samples(ov_ctx* c) {
   for (int& k : c->ev_call_count) k = 0;
 }
 
-// Compute units of the context's device.
-int cu_count(ov_ctx* c) {
-  if (c->n_cu <= 0) {
-    int cus = 0;
-    c->n_cu = (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) ==
-                   hipSuccess && cus > 0)
-                  ? cus
-                  : 256;
-  }
-  return c->n_cu;
-}
-
 // Co-resident workgroups of k_ms_persistent<R> on this device (0: no cooperative launch).
 template <class R>
 int coop_capacity(ov_ctx* c) {
@@ -886,10 +873,8 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
     }
     return m;
   };
-  // z-marching with the next plane prefetched: always in FP32; in FP64 when the launch
-  // holds at most one workgroup per compute unit (its second register set would
-  // otherwise halve the co-resident workgroups)
-  const int zmode = !mps.zm ? 0 : (sizeof(R) == sizeof(float) || nbt_ <= cu_count(c)) ? 2 : 1;
+  // z-marching, with the next plane prefetched in FP32
+  const int zmode = !mps.zm ? 0 : (sizeof(R) == sizeof(float) ? 2 : 1);
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);

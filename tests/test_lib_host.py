@@ -120,7 +120,8 @@ def test_traffic_records_consistent(name):
     assert abs(cal["write_scale"] - kib / cal["write_kib"]) < 1e-3
     assert rec["families"]
     for fam in rec["families"].values():
-        assert len(fam["kernels"]) == 2
+        assert any(k.startswith("k_ms_t<") for k in fam["kernels"])
+        assert any(k.startswith("k_ms_r<") for k in fam["kernels"])
         assert 0 < fam["algorithmic_bytes_per_launch"] <= fam["full_launch_algorithmic_bytes"]
         assert abs(fam["ratio"] - fam["hbm_bytes_per_launch"] / fam["algorithmic_bytes_per_launch"]) < 1e-3
         for k in fam["kernels"]:
