@@ -2132,7 +2132,7 @@ __global__ void __launch_bounds__(256) k_scale(const SysDev* __restrict__ sys, c
 // source partials |v|^2 -> A.part_b and |B.src|^2 -> B.part_b (rho_0 of both
 // multi-shift solves), and B's per-outer-iteration counter stat[3] cleared.
 template <class R>
-__global__ void __launch_bounds__(256) k_gw_prep(const SysDev* __restrict__ ta,
+__global__ void __launch_bounds__(512) k_gw_prep(const SysDev* __restrict__ ta,
                                                   const SysDev* __restrict__ tb,
                                                   const int* __restrict__ bmap, int nb_total) {
   __shared__ double lds[17];
@@ -2210,7 +2210,7 @@ __device__ __forceinline__ void basis_sum(const c2<R>* __restrict__ basis,
 // partial Re <v, w> -> A.part_a (the passes' partials are dead by then; k_cg_misc op 7
 // reduces them while it writes part_c).  v = A.e_in.
 template <class R>
-__global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ ta,
+__global__ void __launch_bounds__(512) k_gw_combine(const SysDev* __restrict__ ta,
                                                      const SysDev* __restrict__ tb,
                                                      const int* __restrict__ bmap, int nb_total) {
   __shared__ double lds[17];
@@ -2264,7 +2264,7 @@ __global__ void __launch_bounds__(256) k_gw_combine(const SysDev* __restrict__ t
 // space of x, w = H r(A)^2 x (coef_d2), with eps^2 x = H w: the true residual needs one
 // multi-shift depth instead of two (M, then M^dag).
 // combine: P = |1 + c|^2 x + (1 + c*) g5 e1 + e23 -> A.e_out, w -> A.e_out2; x = A.e_in.
-__global__ void __launch_bounds__(256) k_truth_combine(const SysDev* __restrict__ ta,
+__global__ void __launch_bounds__(512) k_truth_combine(const SysDev* __restrict__ ta,
                                                        const SysDev* __restrict__ tb,
                                                        const int* __restrict__ bmap, int nb_total) {
   const int L = xcd_logical_block(nb_total);
@@ -2319,7 +2319,7 @@ __global__ void __launch_bounds__(256) k_truth_combine(const SysDev* __restrict_
 //          copy in cg_r when set, partial |r64|^2 -> part_c;
 //   mode 1 (product): W = P + H w = MdagM x -> cg_r64, partial Re <x, W> -> part_c, x = e_in.
 template <class R>
-__global__ void __launch_bounds__(256) k_truth_finish(const SysDev* __restrict__ sys,
+__global__ void __launch_bounds__(512) k_truth_finish(const SysDev* __restrict__ sys,
                                                       const int* __restrict__ bmap, int nb_total,
                                                       double diag, int mode) {
   __shared__ double lds[17];
@@ -2541,7 +2541,7 @@ __global__ void __launch_bounds__(256) k_zero32(unsigned int* __restrict__ p, si
 // p = z + beta p (z = cg_z, or r without a preconditioner; beta from cg_s;
 // use_beta = 0 -> p = z); partial |p|^2 -> part_b.
 template <class R>
-__global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+__global__ void __launch_bounds__(512) k_cg_p(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                int nb_total, int use_beta) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
@@ -2581,7 +2581,7 @@ __global__ void __launch_bounds__(256) k_cg_p(const SysDev* __restrict__ sys, co
 // |p|^2 -> part_b (the CG table's and entry A's, one buffer) and |g5 (1 + Y) p|^2 ->
 // B.part_b.  S: CG table, A and B: the two entries of the inner multi-shift.
 template <class R>
-__global__ void __launch_bounds__(256) k_cg_p_gw(const SysDev* __restrict__ sys,
+__global__ void __launch_bounds__(512) k_cg_p_gw(const SysDev* __restrict__ sys,
                                                  const SysDev* __restrict__ ta,
                                                  const SysDev* __restrict__ tb,
                                                  const int* __restrict__ bmap, int nb_total,
@@ -2653,7 +2653,7 @@ __global__ void __launch_bounds__(256) k_cg_p_gw(const SysDev* __restrict__ sys,
 //         workgroup in the fixed order of k_cg_scalar (identical bits everywhere);
 //         workgroup 0 records PAP and ALPHA
 template <class R>
-__global__ void __launch_bounds__(256) k_cg_misc(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
+__global__ void __launch_bounds__(512) k_cg_misc(const SysDev* __restrict__ sys, const int* __restrict__ bmap,
                                                   int nb_total, int op) {
   __shared__ double lds[17];
   const int L = xcd_logical_block(nb_total);
