@@ -31,6 +31,8 @@ struct ov_ctx {
   hipEvent_t ev_in = nullptr;    // caller-stream marker the private stream waits for
   std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
   bool use_graphs = false;
+  bool fft_fixed = true;          // fixed-length transforms for z = P r (OV_FFT_FIXED=0 at
+                                  // context creation: the generic passes)
   int persistent = 0;            // cooperative persistent multi-shift kernel (0: per-pass kernels)
   std::map<long long, int> n_est;  // (precision, tolerance) -> iterations the last multi-shift needed
   int coop_cap[2] = {0, 0};      // co-resident workgroups of k_ms_persistent<double/float>
@@ -984,16 +986,6 @@ bool tpcg_fixed(const Engine* E, const SysDev* T, int s0, int ns, const int* d) 
   }
 }
 
-// OV_FFT_FIXED=0 keeps every momentum-space operator on the generic passes.
-bool fft_fixed_enabled() {
-  static int v = -1;
-  if (v < 0) {
-    const char* e = std::getenv("OV_FFT_FIXED");
-    v = (e && *e == '0') ? 0 : 1;
-  }
-  return v == 1;
-}
-
 // Runs of consecutive systems on one lattice (same extents and time boundary).
 void lattice_runs(const Engine& E, std::vector<std::pair<int, int>>& runs) {
   runs.clear();
@@ -1014,7 +1006,7 @@ void lattice_runs(const Engine& E, std::vector<std::pair<int, int>>& runs) {
 // t with the scale table, x y z inverse) when every system's extents have one.
 template <class R>
 bool pcg_fixed(const Engine& E, int t) {
-  if (!fft_fixed_enabled()) return false;
+  if (!E.lead->fft_fixed) return false;
   std::vector<std::pair<int, int>> runs;
   lattice_runs(E, runs);
   for (const auto& r : runs) {
@@ -2369,6 +2361,8 @@ ov_status ov_ctx_create(const ov_params* p, void* hip_stream, ov_ctx** out) {
   }
   const char* eg = std::getenv("OV_GRAPHS");
   c->use_graphs = (eg && *eg == '1');
+  const char* ef = std::getenv("OV_FFT_FIXED");
+  c->fft_fixed = !(ef && *ef == '0');
   // The persistent cooperative multi-shift kernel is opt-in: its grid barriers
   // (one L2 write-back and invalidate per workgroup) cost more than a kernel
   // boundary at these sizes.

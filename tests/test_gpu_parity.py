@@ -570,6 +570,28 @@ def test_graph_captured_solve_equals_eager(monkeypatch):
         assert np.array_equal(r.view(np.uint64), g.view(np.uint64))
 
 
+@pytest.mark.parametrize("dims,prec", [((8, 8, 8, 8), "mixed"), ((8, 8, 8, 8), "fp64"),
+                                       ((12, 12, 12, 12), "mixed"), ((16, 16, 8, 4), "mixed"),
+                                       ((16, 16, 16, 16), "mixed")])
+def test_pcg_fixed_transforms_match_generic(monkeypatch, dims, prec):
+    """z = P r through the fixed-length transforms (k_fft_xyz, k_fft_t_pcg with the scale
+    table) against the generic five passes (OV_FFT_FIXED=0 at context creation).  PCG
+    converges with any positive definite preconditioner, so the residual checks alone would
+    not catch a wrong P; both paths apply the same P up to rounding, so the outer iteration
+    counts agree and the solutions agree within the solve tolerance."""
+    print(f"[pcg-fixed] dims={dims} prec={prec}", flush=True)
+    phi, src = inputs.draw(dims, nrhs=1, sigma2=0.25, seed=inputs.config_seed(2))
+    kw = dict(precision=prec, outer_tol=1e-10, **CFG2)
+    b, p = dev(src), dev(phi)
+    monkeypatch.setenv("OV_FFT_FIXED", "1")
+    xf, sf = lattice(dims, **kw).solve(b, p)
+    monkeypatch.setenv("OV_FFT_FIXED", "0")
+    xg, sg = lattice(dims, **kw).solve(b, p)
+    assert abs(sf[0]["outer_iters"] - sg[0]["outer_iters"]) <= 1, (sf[0], sg[0])
+    assert sf[0]["true_rel_res"] <= 1e-10 and sg[0]["true_rel_res"] <= 1e-10
+    assert rel(host(xf), host(xg)) < 1e-6
+
+
 def test_uneven_batch(orc):
     from paper_1005_3276_amd import solve_batch
     kw = dict(precision="mixed", outer_tol=1e-10, m=0.05, g=0.3, n_poles=24,
