@@ -875,24 +875,21 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
     }
     return m;
   };
-  // z-marching, with the next plane prefetched in FP32
-  const int zmode = !mps.zm ? 0 : (sizeof(R) == sizeof(float) ? 2 : 1);
+  // z-marching (with the next plane prefetched in FP32), else the plain passes
+  const bool zmode = mps.zm > 0;
+  constexpr int ZMF = sizeof(R) == sizeof(float) ? 2 : 1;  // the z-marching form of R
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);
-      if (zmode == 2)
-        k_ms_t<R, 2><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
-      else if (zmode == 1)
-        k_ms_t<R, 1><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (zmode)
+        k_ms_t<R, ZMF><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
       else
         k_ms_t<R, 0><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 4 : 1, bytes);
-      if (zmode == 2)
-        k_ms_r<R, 2><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
-      else if (zmode == 1)
-        k_ms_r<R, 1><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (zmode)
+        k_ms_r<R, ZMF><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
       else
         k_ms_r<R, 0><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
