@@ -126,7 +126,7 @@ def record_traffic(out_path, fetch_csv, write_csv, workload, systems, sources, v
         # every launch form of the family's two passes (plain / z-marching variants)
         full = {}
         for n in fetch:
-            m = re.search(r"(k_ms_[tr]<%s, \d+>)" % prec, n)
+            m = re.search(r"(k_ms_[tr]<%s, [^>]*>)" % prec, n)
             if m and n in write:
                 full[m.group(1)] = n
         ks = sorted(full)

@@ -535,7 +535,11 @@ __device__ __forceinline__ int zm_first_site(const SysDev& S, int lb) {
 // on its own (identical bits in every wave), so the only barrier is the final
 // block reduction.
 // ZM: 0 plain passes, 1 z-marching, 2 z-marching with the next plane prefetched.
-template <class R, int ZM>
+// CF: read the system's on/off flag and the done word before the stencil operands, so
+// that a workgroup with nothing to do returns without reading them (large batched
+// launches, where other workgroups hide the extra round trip); else the operands go out
+// first and the check follows (a single system's launch waits for memory once).
+template <class R, int ZM, bool CF>
 __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const MsParams* mp,
                                           double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
@@ -577,6 +581,7 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
   Nbr<R> nb;
   c2<R> q[4];
   ZmMarch<R, ZM == 2> zmm;
+  if (CF && (!act_sys || done)) return 0;
   if (zm) zmm.begin(rin, n > 0 ? tp : nullptr, g, i0);
   if (have) {
     load_nbr<R>(rin, g, i, nb);
@@ -663,7 +668,7 @@ __device__ __forceinline__ int ms_t_block(const SysDev& S, int lb, int n, const 
   return i1 - i0;
 }
 
-template <class R, int ZM>
+template <class R, int ZM, bool CF>
 __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const MsParams* mp,
                                           double* lds, c2<R>* sh) {
   const int lane = threadIdx.x & 63;
@@ -686,6 +691,7 @@ __device__ __forceinline__ int ms_r_block(const SysDev& S, int lb, int n, const 
   Nbr<R> nb;
   c2<R> r[4];
   ZmMarch<R, ZM == 2> zmm;
+  if (CF && (!act_sys || done)) return 0;
   if (zm) zmm.begin(tn, rin, g, i0);
   if (have) {
     load_nbr<R>(tn, g, i, nb);
@@ -762,7 +768,7 @@ __device__ __forceinline__ void stamp_block(unsigned long long* ts, unsigned lon
 // is consumed, and each wave finishes the reduction and the shift recurrences
 // on its own (identical bits in every wave), so the only barrier is the final
 // block reduction.
-template <class R, int ZM>
+template <class R, int ZM, bool CF>
 __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
@@ -772,13 +778,13 @@ __global__ void __launch_bounds__(256) k_ms_t(const SysDev* __restrict__ sys,
   if (mp_.tstamp && threadIdx.x == 0) t0 = wall_clock64();
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  const int sites = ms_t_block<R, ZM>(S, L - S.blk0, n, &mp_, lds, ZM ? (c2<R>*)dyn_lds : nullptr);
+  const int sites = ms_t_block<R, ZM, CF>(S, L - S.blk0, n, &mp_, lds, ZM ? (c2<R>*)dyn_lds : nullptr);
   if (mp_.tstamp) stamp_block(mp_.tstamp, t0, sites);
 }
 
 // Iteration n, r pass:
 //   alpha_n = rho_n / |t_n|^2;  r_{n+1} = r_n - alpha_n H t_n;  partial |r_{n+1}|^2.
-template <class R, int ZM>
+template <class R, int ZM, bool CF>
 __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
                                               const int* __restrict__ bmap, int nb_total, int n,
                                               const MsParams mp_) {
@@ -788,7 +794,7 @@ __global__ void __launch_bounds__(256) k_ms_r(const SysDev* __restrict__ sys,
   if (mp_.tstamp && threadIdx.x == 0) t0 = wall_clock64();
   const int L = xcd_logical_block(nb_total);
   const SysDev& S = sys[bmap[L]];
-  const int sites = ms_r_block<R, ZM>(S, L - S.blk0, n, &mp_, lds, ZM ? (c2<R>*)dyn_lds : nullptr);
+  const int sites = ms_r_block<R, ZM, CF>(S, L - S.blk0, n, &mp_, lds, ZM ? (c2<R>*)dyn_lds : nullptr);
   if (mp_.tstamp) stamp_block(mp_.tstamp, t0, sites);
 }
 
@@ -871,13 +877,13 @@ __global__ void __launch_bounds__(256) k_ms_persistent(const SysDev* __restrict_
   for (int n = 0; n < L; ++n) {
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_t_block<R, 0>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
+      ms_t_block<R, 0, false>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;
     for (int Lb = j0; Lb < nb_total; Lb += grid) {
       const SysDev& S = sys[bmap[Lb]];
-      ms_r_block<R, 0>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
+      ms_r_block<R, 0, false>(S, Lb - S.blk0, n, &mp_, lds, (c2<R>*)nullptr);
       __syncthreads();
     }
     if (!grid_sync(gb, grid)) return;

@@ -131,6 +131,17 @@ bool ov_log() {
 }
 
 // z-marching multi-shift passes (OV_MS_ZM=0 switches them off).
+// Large multi-shift launches read their flags before their operands; OV_MS_CF=0 keeps
+// the operands first everywhere.
+bool ms_cf_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("OV_MS_CF");
+    v = (e && *e == '0') ? 0 : 1;
+  }
+  return v == 1;
+}
+
 bool ms_zm_enabled() {
   static int v = -1;
   if (v < 0) {
@@ -878,20 +889,26 @@ void launch_ms_tab(const Engine& E, const SysDev* T, const int* bmap_, int nbt_,
   // z-marching (with the next plane prefetched in FP32), else the plain passes
   const bool zmode = mps.zm > 0;
   constexpr int ZMF = sizeof(R) == sizeof(float) ? 2 : 1;  // the z-marching form of R
+  // large (batched) launches check their flags before reading operands
+  const bool cf = nbt_ >= 2048 && ms_cf_enabled();
   for (int n = 0; n < L; ++n) {
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 3 : 0, bytes);
-      if (zmode)
-        k_ms_t<R, ZMF><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (zmode && cf)
+        k_ms_t<R, ZMF, true><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      else if (zmode)
+        k_ms_t<R, ZMF, false><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
       else
-        k_ms_t<R, 0><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+        k_ms_t<R, 0, false><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
     {
       Sample smp(c, sizeof(R) == sizeof(double) ? 4 : 1, bytes);
-      if (zmode)
-        k_ms_r<R, ZMF><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      if (zmode && cf)
+        k_ms_r<R, ZMF, true><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+      else if (zmode)
+        k_ms_r<R, ZMF, false><<<nbt_, c->block, shb, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
       else
-        k_ms_r<R, 0><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
+        k_ms_r<R, 0, false><<<nbt_, c->block, 0, E.st>>>(T, bmap_, nbt_, n, stamped(smp));
     }
   }
   k_ms_coef<<<nent, 256, 0, E.st>>>(T, nent, L, mp);
