@@ -129,3 +129,53 @@ def test_traffic_records_consistent(name):
             # medians of whole dispatches: written bytes never exceed a full launch's field
             field = fam["full_launch_algorithmic_bytes"] / 3
             assert fam["write_kib_median"][k] * 1024 * cal["write_scale"] <= field * 1.01
+
+
+def test_record_traffic_sums_every_launch_form(tmp_path):
+    """bench.py --record-traffic on a synthetic counter pair: the copy calibrates the scale
+    factors, every launch form of a pass family (operands-first and check-first variants)
+    is summed, each dispatch's algorithmic bytes follow from its exact writes, and the ratio
+    is total HBM bytes over total algorithmic bytes."""
+    import csv
+    import importlib.util
+    import json
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    V, systems, sources = 4096, 1, 2
+    field = systems * sources * 4 * V * 8              # bytes of one FP32 output field
+    fkib = field / 1024
+    rows_f, rows_w = [], []
+    did = 0
+
+    def add(name, fetch_kib, write_kib):
+        nonlocal did
+        did += 1
+        rows_f.append({"Dispatch_Id": did, "Kernel_Name": name, "Counter_Value": fetch_kib})
+        rows_w.append({"Dispatch_Id": did, "Kernel_Name": name, "Counter_Value": write_kib})
+
+    copy = "__amd_rocclr_copyBuffer"
+    add(copy, 512 * 1024 / 2.0, 512 * 1024)            # fetch counts half the copy's bytes
+    t0 = "void ov::k_ms_t<float, 2, false>(ov::SysDev const*, int const*, int, int, ov::MsParams)"
+    r0 = "void ov::k_ms_r<float, 2, false>(ov::SysDev const*, int const*, int, int, ov::MsParams)"
+    t1 = "void ov::k_ms_t<float, 2, true>(ov::SysDev const*, int const*, int, int, ov::MsParams)"
+    add(t0, 2.0 * fkib / 2.0, fkib)                    # full launch: reads 2 fields
+    add(r0, 2.6 * fkib / 2.0, fkib)                    # full launch: reads 2.6 fields
+    add(t1, 1.0 * fkib / 2.0, 0.5 * fkib)              # half the entries: reads 1 field
+    for path, rows in (("f.csv", rows_f), ("w.csv", rows_w)):
+        with open(tmp_path / path, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Value"])
+            w.writeheader()
+            w.writerows(rows)
+    out = tmp_path / "rec.json"
+    bench.record_traffic(str(out), str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "synthetic",
+                         systems, sources, V)
+    fam = json.load(open(out))["families"]["fp32_inner"]
+    assert sorted(fam["kernels"]) == ["k_ms_r<float, 2, false>", "k_ms_t<float, 2, false>",
+                                      "k_ms_t<float, 2, true>"]
+    hbm = (2.0 + 1 + 2.6 + 1 + 1.0 + 0.5) * field      # reads + writes of the three dispatches
+    alg = (3 + 3 + 1.5) * field                        # three fields per source taking part
+    assert abs(fam["hbm_bytes_per_launch"] - hbm / 3) <= 1
+    assert abs(fam["algorithmic_bytes_per_launch"] - alg / 3) <= 1
+    assert abs(fam["ratio"] - round(hbm / alg, 3)) < 1e-9
+    assert fam["full_launch_algorithmic_bytes"] == 3 * field
