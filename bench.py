@@ -558,9 +558,9 @@ def main():
         record_traffic(o, fc, wc, wl, int(nsys), int(nsrc), int(vol))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the batched and "
-                                   "multi-lattice work shards across GPUs without "
-                                   "communication; that path is not part of this build)"}))
+        print(json.dumps({"error": "single-GPU benchmark: run with --gpus 1 (the batched "
+                                   "and multi-lattice work would shard across GPUs without "
+                                   "communication; no multi-GPU path is implemented)"}))
         sys.exit(2)
 
     if args.cpu_only:
